@@ -1,0 +1,224 @@
+/*
+ * kb.h -- C ABI of libkbatch: iteration-batched graph execution of
+ * iterative GPU solvers on one MI355X (gfx950).
+ *
+ * The library implements the method of "Boosting Performance of Iterative
+ * Applications on GPUs: Kernel Batching with CUDA Graphs" (Ekelund,
+ * Markidis, Peng, arXiv 2501.09398) with HIP graphs: an iterative solver
+ * runs either one launch per kernel per iteration (the baseline loop of
+ * Sec. III-A, Listings 1-2) or in iteration batches of b iterations that are
+ * unrolled into one static graph, instantiated, uploaded and replayed
+ * (Sec. III-A, Listing 3), with the remainder n mod b run per launch (the
+ * loop peeling named in Sec. VI).
+ *
+ * Conventions
+ *   - Every entry point returns an int status: 0 = OK, < 0 = error,
+ *     > 0 = warning (the call did its work).  kb_last_error() gives the
+ *     message of the last failing call on the calling thread.
+ *   - No C++ exception crosses this boundary.
+ *   - Device memory is owned by the caller: kb_create() receives one
+ *     workspace of at least kb_workspace_bytes() bytes (device pointer,
+ *     256-byte aligned) and keeps using it until kb_destroy().  The library
+ *     allocates no device memory of its own for problem state.
+ *   - All device work of a handle is enqueued on the one HIP stream given
+ *     to kb_create() (borrowed, never destroyed by the library).  Calls are
+ *     asynchronous unless stated otherwise.
+ *   - A handle must not be used by two threads at once.
+ */
+#ifndef KB_H
+#define KB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define KB_OK          0
+#define KB_EINVAL     -1   /* bad argument (shape, coefficient, field, size) */
+#define KB_ENOMEM     -2   /* workspace smaller than kb_workspace_bytes()    */
+#define KB_EHIP       -3   /* a HIP runtime call failed; see kb_last_error() */
+#define KB_ESTATE     -4   /* call not valid in the handle's current state  */
+#define KB_WFALLBACK   1   /* graph build failed; the steps ran per launch  */
+
+/* ---- problems ---------------------------------------------------------- */
+/* Each problem is one iterative application of Sec. III-C (or the batched
+ * many-grid variant).  shape and coeffs per problem:
+ *
+ * KB_HEAT2D  (Hotspot-style explicit thermal update, one kernel per step)
+ *   shape  = {ny, nx}                 grid rows, columns (>= 1 each)
+ *   coeffs = {c, Rx, Ry, Rz, Tamb}    per step, with clamped neighbours:
+ *            T' = T + c*(P + (Tn+Ts-2T)/Ry + (Te+Tw-2T)/Rx + (Tamb-T)/Rz)
+ *            Requires c*(2/Rx + 2/Ry + 1/Rz) < 1 (monotone update).
+ *   fields : KB_F_T (ny*nx float, row-major), KB_F_P (ny*nx float)
+ *   initial: T ~ U[323,343), P ~ U[0,1) from the seed.
+ *
+ * KB_HEAT3D  (Hotspot3D-style layered update, one kernel per step)
+ *   shape  = {nz, ny, nx}; coeffs as KB_HEAT2D.  Adds (Tu+Td-2T)/Rz with a
+ *            clamped layer index; ambient term on every layer; the power P
+ *            is nonzero only in layer z = 0 and stored as one ny*nx plane.
+ *            Requires c*(2/Rx + 2/Ry + 3/Rz) < 1.
+ *   fields : KB_F_T (nz*ny*nx float, [z][y][x]), KB_F_P (ny*nx float)
+ *
+ * KB_SKELETON  (the skeleton application: K small element-wise kernels per
+ *   iteration; kernel k computes x <- a_k*x + b_k with one rounding)
+ *   shape  = {n}                      vector length (>= 1)
+ *   coeffs = {K} or {K, a_1..a_K, b_1..b_K}; 1 <= K <= 16.  With K alone the
+ *            a_k ~ U[0.9,1), b_k ~ U[-0.01,0.01) come from the seed.
+ *   fields : KB_F_X (n float), KB_F_A (K float), KB_F_B (K float)
+ *   initial: x ~ U[-1,1).
+ *
+ * KB_FDTD3D  (FDTD Maxwell solver of a PEC cavity, three kernels per step:
+ *   H update, E update, soft source)
+ *   shape  = {N}                      cells per edge (4 <= N <= 1024)
+ *   coeffs = {courant, width, delay, probe_capacity
+ *             [, src_i, src_j, src_k]}
+ *            dt = courant (dx = 1, eps = mu = 1; needs courant < 1/sqrt(3));
+ *            source Ez(src) += exp(-((n - delay)/width)^2) at absolute step n
+ *            (zero for width <= 0); the cell is drawn from the seed unless
+ *            given; probe_capacity steps of Ez(src) are recorded.
+ *   fields : KB_F_EX..KB_F_HZ ((N+1)^3 float each, index (k*(N+1)+j)*(N+1)+i),
+ *            KB_F_PROBE (probe_capacity float), KB_F_STEP (one int64).
+ *
+ * KB_HEAT2D_MULTI  (many independent 2D grids of uneven sizes advanced
+ *   together, one kernel per step over all grids)
+ *   shape  = {G, ny_0, nx_0, ny_1, nx_1, ...}; coeffs as KB_HEAT2D.
+ *   fields : KB_F_T, KB_F_P as the concatenation of the grids, row-major each.
+ *   initial: grid g draws its cells at flat offset sum_{h<g} ny_h*nx_h of the
+ *            same streams as KB_HEAT2D.
+ */
+#define KB_HEAT2D        1
+#define KB_HEAT3D        2
+#define KB_SKELETON      3
+#define KB_FDTD3D        4
+#define KB_HEAT2D_MULTI  5
+
+/* ---- fields (kb_read / kb_write) --------------------------------------- */
+#define KB_F_T      1
+#define KB_F_P      2
+#define KB_F_X      3
+#define KB_F_A      4
+#define KB_F_B      5
+#define KB_F_EX    10
+#define KB_F_EY    11
+#define KB_F_EZ    12
+#define KB_F_HX    13
+#define KB_F_HY    14
+#define KB_F_HZ    15
+#define KB_F_PROBE 16
+#define KB_F_STEP  17   /* int64 count of steps advanced on the device */
+
+/* ---- options (kb_set_option) ------------------------------------------- */
+/* KB_OPT_BUILDER: how a batch graph is built.
+ *   0 = explicit kernel nodes (hipGraphAddKernelNode chain, Listing 3)
+ *   1 = stream capture of the per-launch loop (Sec. II)                   */
+#define KB_OPT_BUILDER   1
+/* KB_OPT_TILE: kernel variant of the stencil problems (0 = library default).
+ *   KB_HEAT2D/KB_HEAT2D_MULTI: 1 = direct (one thread per cell, 64x4
+ *   blocks), 2 = LDS halo tile.                                          */
+#define KB_OPT_TILE      2
+/* KB_OPT_TDEPTH: temporal-blocking depth t >= 1 for KB_HEAT2D: one launch
+ *   of the LDS tile kernel advances t steps (1 <= t <= 16).                */
+#define KB_OPT_TDEPTH    3
+/* KB_OPT_GRAPH_CACHE: 1 = keep instantiated batch graphs between kb_run
+ *   calls (default), 0 = rebuild every call (each call then pays T_C).    */
+#define KB_OPT_GRAPH_CACHE 4
+/* KB_OPT_MAX_NODES: refuse graphs with more kernel nodes (default 65536). */
+#define KB_OPT_MAX_NODES 5
+
+typedef struct kb_problem kb_problem;
+
+/* Timing of the most recent kb_run() (Sec. III-B, Eqs. 1-2): the host wall
+ * time spent building, instantiating and uploading graphs (T_C, including
+ * the upload, as in Sec. IV-A), and the device time of the launches
+ * measured with HIP events around them (T_E).                             */
+typedef struct kb_timing {
+    double t_create_s;        /* T_C of graphs built by this call          */
+    double t_exec_s;          /* T_E: events around all launches of the call */
+    int64_t n_graph_launches; /* graph launches                            */
+    int64_t n_nodes;          /* kernel nodes per batch graph (K*b)       */
+    int64_t n_peeled;         /* iterations run per launch (remainder)     */
+    int64_t n_kernel_launches;/* individual kernel launches                */
+    int64_t n_graphs_built;   /* graphs built by this call (cache misses)  */
+} kb_timing;
+
+/* Device bytes kb_create() needs for this problem and shape; 0 if the
+ * problem or shape is invalid.  Pure; no HIP call.                         */
+size_t kb_workspace_bytes(int problem, const int64_t *shape, int ndim);
+
+/* Create a problem on the current HIP device.
+ *   workspace: device pointer of >= kb_workspace_bytes() bytes, 256-B
+ *              aligned, owned by the caller and kept alive until destroy.
+ *   stream   : hipStream_t (as void*) to enqueue on; NULL = null stream.
+ *   Fills the initial state on the device from seed (counter-based
+ *   SplitMix64, one draw per cell), enqueued on the stream.
+ * Errors: KB_EINVAL (problem, shape, coefficients, unstable c or dt),
+ *         KB_ENOMEM (workspace too small or misaligned), KB_EHIP.          */
+int kb_create(int problem, const int64_t *shape, int ndim,
+              const double *coeffs, int ncoeffs, uint64_t seed,
+              void *workspace, size_t ws_bytes, void *stream,
+              kb_problem **out);
+
+/* Set an option (KB_OPT_*).  Invalidates cached graphs when it changes
+ * the kernels.  KB_EINVAL for an unknown option or value.                 */
+int kb_set_option(kb_problem *h, int option, int64_t value);
+
+/* Advance the state by exactly n_steps time steps (Sec. III-A).
+ *   batch_b == 0 : per-launch loop, one launch per kernel per iteration
+ *                  (Listings 1-2).
+ *   batch_b >= 1 : floor(n_iter / b) launches of a graph that unrolls b
+ *                  iterations as a linear chain of kernel nodes (Listing 3),
+ *                  then n_iter mod b iterations per launch (loop peeling,
+ *                  Sec. VI).  An iteration is the problem's K kernels;
+ *                  with temporal depth t, one iteration advances t steps
+ *                  and n_steps mod t steps run as depth-1 iterations.
+ *   Graphs are built on first use per (b, t, buffer parity) and cached.
+ *   The result is bit-identical for every b (the same kernels run in the
+ *   same order on the same arguments).
+ * Errors: KB_EINVAL (n_steps < 0, batch_b < 0, K*b > max nodes), KB_EHIP.
+ * Warning: KB_WFALLBACK if a graph could not be built and the iterations
+ *          ran per launch instead.                                        */
+int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b);
+
+/* Copy one field out.  Synchronises the stream first.  dst is host memory
+ * (dst_on_device = 0) or device memory (1); bytes must equal the field's
+ * size.  Errors: KB_EINVAL (field or size), KB_EHIP.                      */
+int kb_read(kb_problem *h, int field, void *dst, size_t bytes,
+            int dst_on_device);
+
+/* Overwrite one field (for resume and for prescribed initial states).
+ * Synchronises the stream after the copy.  Same errors as kb_read.        */
+int kb_write(kb_problem *h, int field, const void *src, size_t bytes,
+             int src_on_device);
+
+/* Deterministic device reduction of the current state (fixed-order wave64
+ * tree, double accumulation across blocks), synchronous.
+ *   KB_HEAT2D/3D/MULTI: out[0] = sum of T
+ *   KB_SKELETON       : out[0] = sum of x
+ *   KB_FDTD3D         : out[0] = sum of E.E, out[1] = sum of H.H
+ * Errors: KB_EINVAL, KB_EHIP.                                              */
+int kb_reduce(kb_problem *h, double *out, int nout);
+
+/* Timing of the last kb_run() (synchronises the stream).                   */
+int kb_last_timing(kb_problem *h, kb_timing *out);
+
+/* Number of kernels per iteration (K) of the problem, or < 0 on error.    */
+int kb_kernels_per_iter(const kb_problem *h);
+
+/* Destroy graphs, events and the handle; the workspace stays the caller's.
+ * Synchronises the stream.  NULL is accepted.                              */
+int kb_destroy(kb_problem *h);
+
+/* Message of the last failing call on this thread ("" if none).  Valid
+ * until the next kb_* call on the same thread.                             */
+const char *kb_last_error(void);
+
+/* ABI version of this header (increments on incompatible change).         */
+int kb_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KB_H */

@@ -1,0 +1,149 @@
+"""CPU oracle of the iterative solvers (test infrastructure).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps liboracle.so (plain C, oracle.c) with numpy
+arrays and shares no code with the GPU library.
+
+Every function returns new arrays and leaves its inputs untouched.  The
+``dtype`` argument picks the float32 or the float64 instantiation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        _lib = C.CDLL(_build.LIB)
+        _setup(_lib)
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _setup(L):
+    L.or_abi_version.restype = C.c_int
+    for sfx in ("f32", "f64"):
+        f = getattr(L, "or_heat2d_" + sfx)
+        f.argtypes = [C.c_void_p, C.c_void_p, C.c_long, C.c_long] + [C.c_double] * 5 + [C.c_long, C.c_void_p]
+        f.restype = C.c_int
+        f = getattr(L, "or_heat3d_" + sfx)
+        f.argtypes = [C.c_void_p, C.c_void_p, C.c_long, C.c_long, C.c_long] + [C.c_double] * 5 + [C.c_long, C.c_void_p]
+        f.restype = C.c_int
+        f = getattr(L, "or_skeleton_" + sfx)
+        f.argtypes = [C.c_void_p, C.c_long, C.c_void_p, C.c_void_p, C.c_int, C.c_long, C.c_void_p]
+        f.restype = C.c_int
+        f = getattr(L, "or_fdtd_" + sfx)
+        f.argtypes = [C.c_void_p] * 6 + [C.c_long, C.c_double, C.c_void_p, C.c_void_p, C.c_long, C.c_long, C.c_void_p]
+        f.restype = C.c_int
+    L.or_fdtd_pulse.argtypes = [C.c_double, C.c_double, C.c_long, C.c_void_p, C.c_void_p]
+    L.or_fdtd_pulse.restype = None
+
+
+def _sfx(dtype):
+    dt = np.dtype(dtype)
+    if dt == np.float32:
+        return "f32", np.float32
+    if dt == np.float64:
+        return "f64", np.float64
+    raise ValueError("dtype must be float32 or float64")
+
+
+HEAT_COEFFS = dict(c=1e-3, Rx=1.0, Ry=1.0, Rz=10.0, Tamb=300.0)
+
+
+def heat2d(T0, P, nsteps, c=1e-3, Rx=1.0, Ry=1.0, Rz=10.0, Tamb=300.0, dtype=np.float64):
+    """T after nsteps explicit 2D thermal steps (clamped neighbours)."""
+    sfx, dt = _sfx(dtype)
+    T0 = np.ascontiguousarray(T0, dtype=dt)
+    P = np.ascontiguousarray(P, dtype=dt)
+    ny, nx = T0.shape
+    assert P.shape == (ny, nx)
+    out = np.empty_like(T0)
+    rc = getattr(lib(), "or_heat2d_" + sfx)(_ptr(T0), _ptr(P), ny, nx, c, Rx, Ry, Rz, Tamb, int(nsteps), _ptr(out))
+    if rc:
+        raise MemoryError("oracle heat2d")
+    return out
+
+
+def heat3d(T0, P, nsteps, c=1e-3, Rx=1.0, Ry=1.0, Rz=10.0, Tamb=300.0, dtype=np.float64):
+    """T after nsteps layered 3D steps.  P is dense [nz][ny][nx] or one
+    [ny][nx] plane (then layer 0 gets it and the other layers get zero)."""
+    sfx, dt = _sfx(dtype)
+    T0 = np.ascontiguousarray(T0, dtype=dt)
+    nz, ny, nx = T0.shape
+    P = np.asarray(P, dtype=dt)
+    if P.shape == (ny, nx):
+        Pd = np.zeros_like(T0)
+        Pd[0] = P
+        P = Pd
+    P = np.ascontiguousarray(P)
+    assert P.shape == T0.shape
+    out = np.empty_like(T0)
+    rc = getattr(lib(), "or_heat3d_" + sfx)(_ptr(T0), _ptr(P), nz, ny, nx, c, Rx, Ry, Rz, Tamb, int(nsteps), _ptr(out))
+    if rc:
+        raise MemoryError("oracle heat3d")
+    return out
+
+
+def skeleton(x0, a, b, iters, dtype=np.float64):
+    """x after iters iterations of the chain x <- a_k*x + b_k, k = 1..K."""
+    sfx, dt = _sfx(dtype)
+    x0 = np.ascontiguousarray(x0, dtype=dt)
+    a = np.ascontiguousarray(a, dtype=dt)
+    b = np.ascontiguousarray(b, dtype=dt)
+    assert a.shape == b.shape and a.ndim == 1
+    out = np.empty_like(x0)
+    getattr(lib(), "or_skeleton_" + sfx)(_ptr(x0), x0.size, _ptr(a), _ptr(b), a.size, int(iters), _ptr(out))
+    return out
+
+
+def fdtd_pulse(count, width=20.0, delay=80.0):
+    """(g64, g32): soft-source amplitudes exp(-((n-delay)/width)^2), n < count."""
+    g64 = np.empty(count, np.float64)
+    g32 = np.empty(count, np.float32)
+    lib().or_fdtd_pulse(float(delay), float(width), int(count), _ptr(g64), _ptr(g32))
+    return g64, g32
+
+
+FDTD_FIELDS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+
+
+def fdtd_zero_fields(N, dtype=np.float64):
+    M = N + 1
+    return {k: np.zeros((M, M, M), dtype=dtype) for k in FDTD_FIELDS}
+
+
+def fdtd(fields, N, nsteps, dt=0.5, src=None, g=None, n_start=0, dtype=np.float64):
+    """Advance the Yee fields (dict of (N+1)^3 arrays indexed [k][j][i]) by
+    nsteps steps from absolute step n_start.  Returns (new_fields, probe).
+    g: per-absolute-step source amplitudes (length >= n_start+nsteps) or None.
+    """
+    sfx, dtp = _sfx(dtype)
+    M = N + 1
+    f = {k: np.ascontiguousarray(np.array(fields[k], dtype=dtp, copy=True)) for k in FDTD_FIELDS}
+    for k in FDTD_FIELDS:
+        assert f[k].shape == (M, M, M)
+    probe = np.zeros(max(nsteps, 1), dtype=dtp)
+    src_arr = np.asarray(src if src is not None else (0, 0, 0), dtype=np.int64)
+    gp = None
+    if g is not None:
+        g = np.ascontiguousarray(g, dtype=dtp)
+        assert g.size >= n_start + nsteps
+        gp = _ptr(g)
+    getattr(lib(), "or_fdtd_" + sfx)(*[_ptr(f[k]) for k in FDTD_FIELDS], N, float(dt),
+                                     _ptr(src_arr), gp, int(n_start), int(nsteps),
+                                     _ptr(probe) if src is not None else None)
+    return f, probe[:nsteps]
