@@ -72,15 +72,20 @@ extern "C" {
  *
  * KB_FDTD3D  (FDTD Maxwell solver of a PEC cavity, three kernels per step:
  *   H update, E update, soft source)
- *   shape  = {N}                      cells per edge (4 <= N <= 1024)
- *   coeffs = {courant, width, delay, probe_capacity
- *             [, src_i, src_j, src_k]}
+ *   shape  = {N} or {N, probe_capacity}: cells per edge (4 <= N <= 1024)
+ *            and the number of steps of Ez(src) recorded (default 16384).
+ *   coeffs = {courant, width, delay} or {courant, width, delay, i, j, k}
  *            dt = courant (dx = 1, eps = mu = 1; needs courant < 1/sqrt(3));
- *            source Ez(src) += exp(-((n - delay)/width)^2) at absolute step n
- *            (zero for width <= 0); the cell is drawn from the seed unless
- *            given; probe_capacity steps of Ez(src) are recorded.
+ *            after the E update of absolute step n (counted from 0),
+ *            Ez(src) += float(exp(-((n - delay)/width)^2)) (no source for
+ *            width <= 0; delay + 10.2*width must stay below 4095 steps).
+ *            The source is the Ez node (i, j, k+1/2); it is drawn from the
+ *            seed (2 <= i, j <= N-2, 1 <= k <= N-2) unless given, and must
+ *            be an interior Ez node (1 <= i, j <= N-1, 0 <= k <= N-1).
  *   fields : KB_F_EX..KB_F_HZ ((N+1)^3 float each, index (k*(N+1)+j)*(N+1)+i),
- *            KB_F_PROBE (probe_capacity float), KB_F_STEP (one int64).
+ *            KB_F_PROBE (probe_capacity float: Ez(src) after step n),
+ *            KB_F_STEP (one int64: steps done).
+ *   initial: all fields zero.
  *
  * KB_HEAT2D_MULTI  (many independent 2D grids of uneven sizes advanced
  *   together, one kernel per step over all grids)
@@ -203,6 +208,14 @@ int kb_reduce(kb_problem *h, double *out, int nout);
 
 /* Timing of the last kb_run() (synchronises the stream).                   */
 int kb_last_timing(kb_problem *h, kb_timing *out);
+
+/* Device duration of each of the K kernels of one iteration: runs `reps`
+ * iterations per launch (1 <= reps <= 256), each kernel with start/stop
+ * events bound to its own dispatch (hipExtLaunchKernel), and writes the
+ * mean seconds of kernel k to out[k] (nout >= K).  Advances the state by
+ * reps iterations exactly like kb_run(h, reps*t, 0).  Synchronous.
+ * Errors: KB_EINVAL, KB_EHIP.                                              */
+int kb_kernel_time(kb_problem *h, int64_t reps, double *out, int nout);
 
 /* Number of kernels per iteration (K) of the problem, or < 0 on error.    */
 int kb_kernels_per_iter(const kb_problem *h);

@@ -1,0 +1,721 @@
+// libkbatch C ABI: problem objects, the per-launch driver, the graph
+// builders (explicit kernel nodes, stream capture), graph replay with loop
+// peeling, timing, reads, writes and reductions.
+//
+// The method (Sec. III-A): an iterative application runs `n` iterations of
+// a fixed sequence of K kernels.  The baseline enqueues every kernel of
+// every iteration separately (Listings 1-2).  The batched form unrolls an
+// iteration batch of b iterations into one static graph -- a linear chain of
+// K*b kernel nodes, each depending on the previous one (Listing 3) --
+// instantiates and uploads it once, and launches it n/b times.  Sec. VI names
+// loop peeling for n not divisible by b; here the n mod b leftover
+// iterations run per launch after the replays.
+//
+// Kernel arguments are baked into graph nodes.  For the ping-pong stencils
+// the input buffer alternates each iteration, so a batch graph is specific
+// to the buffer parity it starts from; with odd b successive replays
+// alternate between two graphs.  State that must change with the absolute
+// step (the FDTD source time) lives on the device instead.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+
+#include "kb_internal.h"
+
+using namespace kb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(KB_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kGCap = 4096;           // FDTD source table capacity (steps)
+constexpr int64_t kDefaultProbe = 16384;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    size_t off = total;
+    total = align_up(total + bytes);
+    return off;
+  }
+};
+
+bool heat_shape_ok(int64_t v) { return v >= 1 && v <= (int64_t)1 << 20; }
+
+// Workspace offsets of every buffer of a problem.  Returns false on a bad
+// shape.  Offsets are written to off[] in the order documented per problem.
+bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off) {
+  if (!shape || ndim < 1) return false;
+  const size_t red = (size_t)reduce_max_blocks() * sizeof(double);
+  switch (problem) {
+    case KB_HEAT2D: {
+      if (ndim != 2 || !heat_shape_ok(shape[0]) || !heat_shape_ok(shape[1])) return false;
+      const int64_t n = shape[0] * shape[1];
+      if (n > ((int64_t)1 << 31) - 1) return false;
+      off[0] = L.add(n * 4); off[1] = L.add(n * 4); off[2] = L.add(n * 4);
+      off[3] = L.add(red); off[4] = L.add(64);
+      return true;
+    }
+    case KB_HEAT3D: {
+      if (ndim != 3 || !heat_shape_ok(shape[0]) || !heat_shape_ok(shape[1]) || !heat_shape_ok(shape[2])) return false;
+      const int64_t plane = shape[1] * shape[2];
+      const int64_t n = shape[0] * plane;
+      if (n > ((int64_t)1 << 31) - 1) return false;
+      off[0] = L.add(n * 4); off[1] = L.add(n * 4); off[2] = L.add(plane * 4);
+      off[3] = L.add(red); off[4] = L.add(64);
+      return true;
+    }
+    case KB_SKELETON: {
+      if (ndim != 1 || shape[0] < 1 || shape[0] > ((int64_t)1 << 31) - 1) return false;
+      off[0] = L.add(shape[0] * 4);
+      off[3] = L.add(red); off[4] = L.add(64);
+      return true;
+    }
+    case KB_FDTD3D: {
+      if (ndim < 1 || ndim > 2 || shape[0] < 4 || shape[0] > 1024) return false;
+      const int64_t pcap = ndim == 2 ? shape[1] : kDefaultProbe;
+      if (pcap < 0 || pcap > ((int64_t)1 << 28)) return false;
+      const int64_t M = shape[0] + 1;
+      for (int f = 0; f < 6; ++f) off[5 + f] = L.add(M * M * M * 4);
+      off[11] = L.add(kGCap * 4);
+      off[12] = L.add((pcap > 0 ? pcap : 1) * 4);
+      off[13] = L.add(8);
+      off[3] = L.add(red); off[4] = L.add(64);
+      return true;
+    }
+    case KB_HEAT2D_MULTI: {
+      if (ndim < 3) return false;
+      const int64_t G = shape[0];
+      if (G < 1 || G > 65536 || ndim != 1 + 2 * G) return false;
+      int64_t total = 0;
+      for (int64_t g = 0; g < G; ++g) {
+        if (!heat_shape_ok(shape[1 + 2 * g]) || !heat_shape_ok(shape[2 + 2 * g])) return false;
+        total += shape[1 + 2 * g] * shape[2 + 2 * g];
+      }
+      if (total > ((int64_t)1 << 31) - 1) return false;
+      off[0] = L.add(total * 4); off[1] = L.add(total * 4); off[2] = L.add(total * 4);
+      off[14] = L.add(G * sizeof(GridDesc)); off[15] = L.add((G + 1) * sizeof(int));
+      off[3] = L.add(red); off[4] = L.add(64);
+      return true;
+    }
+    default:
+      return false;
+  }
+}
+
+bool pingpong(const kb_problem *h) {
+  return h->kind == KB_HEAT2D || h->kind == KB_HEAT3D || h->kind == KB_HEAT2D_MULTI;
+}
+
+int heat2d_variant(const kb_problem *h) { return h->tile == 0 ? 1 : h->tile; }
+
+// Temporal depth of one iteration.
+int iter_depth(const kb_problem *h) {
+  return (h->kind == KB_HEAT2D && heat2d_variant(h) >= 2) ? h->tdepth : 1;
+}
+
+// Fill the K launch descriptors of one iteration that starts from buffer
+// parity `cur` and advances `depth` steps.
+int fill_iter(const kb_problem *h, int cur, int depth, Launch *L) {
+  switch (h->kind) {
+    case KB_HEAT2D: {
+      Heat2DArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, (int)h->ny, (int)h->nx, h->hk, depth};
+      const int v = heat2d_variant(h);
+      if (v == 1 || (depth == 1 && h->tile == 0)) {
+        make_heat2d_direct(L[0], a);
+        return 1;
+      }
+      if (!make_heat2d_tile(L[0], a, v)) return -1;
+      return 1;
+    }
+    case KB_HEAT3D: {
+      Heat3DArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, (int)h->nz, (int)h->ny, (int)h->nx, h->hk};
+      make_heat3d(L[0], a);
+      return 1;
+    }
+    case KB_HEAT2D_MULTI: {
+      MultiArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids_d, h->block_start_d, h->G, h->hk};
+      make_multi(L[0], a, h->total_blocks);
+      return 1;
+    }
+    case KB_SKELETON: {
+      for (int k = 0; k < h->K; ++k) {
+        SkelArgs a{h->x, (long long)h->n, h->a[k], h->b[k]};
+        make_skeleton(L[k], a, h->tile == 0 ? 1 : h->tile);
+      }
+      return h->K;
+    }
+    case KB_FDTD3D: {
+      FdtdArgs f{h->F[0], h->F[1], h->F[2], h->F[3], h->F[4], h->F[5], h->N, h->dt};
+      make_fdtd_h(L[0], f);
+      make_fdtd_e(L[1], f);
+      SrcArgs s{h->F[2], h->src, h->g, h->glen, h->probe, h->pcap, h->step};
+      make_fdtd_src(L[2], s);
+      return 3;
+    }
+  }
+  return -1;
+}
+
+constexpr int kMaxK = 16;
+
+// Enqueue one iteration per launch on stream s; returns a KB status.
+int launch_iter(kb_problem *h, int depth, hipStream_t s) {
+  Launch L[kMaxK];
+  const int k = fill_iter(h, h->cur, depth, L);
+  if (k < 0) return fail(KB_EINVAL, "invalid kernel variant %d / depth %d", h->tile, depth);
+  for (int q = 0; q < k; ++q) {
+    HIPCHK(hipLaunchKernel(L[q].func, L[q].grid, L[q].block, L[q].params(), L[q].lds, s));
+  }
+  if (pingpong(h)) h->cur ^= 1;
+  return KB_OK;
+}
+
+void clear_cache(kb_problem *h) {
+  for (auto &kv : h->cache_map) (void)hipGraphExecDestroy(kv.second);
+  h->cache_map.clear();
+}
+
+// Build, instantiate and upload the graph of b iterations starting from
+// buffer parity `parity` (Listing 3, "Building").
+int build_graph(kb_problem *h, int64_t b, int depth, int parity, hipGraphExec_t *out) {
+  hipGraph_t g = nullptr;
+  const int saved = h->cur;
+  if (h->builder == 0) {
+    HIPCHK(hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    int c = parity;
+    Launch L[kMaxK];
+    for (int64_t j = 0; j < b; ++j) {
+      const int k = fill_iter(h, c, depth, L);
+      if (k < 0) { (void)hipGraphDestroy(g); return fail(KB_EINVAL, "invalid kernel variant"); }
+      for (int q = 0; q < k; ++q) {
+        hipKernelNodeParams np{};
+        np.func = const_cast<void *>(L[q].func);
+        np.gridDim = L[q].grid;
+        np.blockDim = L[q].block;
+        np.sharedMemBytes = L[q].lds;
+        np.kernelParams = L[q].params();
+        np.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+        if (e != hipSuccess) {
+          (void)hipGraphDestroy(g);
+          return fail(KB_EHIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+        }
+        prev = node;
+      }
+      if (pingpong(h)) c ^= 1;
+    }
+  } else {
+    HIPCHK(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+    h->cur = parity;
+    int rc = KB_OK;
+    for (int64_t j = 0; j < b && rc == KB_OK; ++j) rc = launch_iter(h, depth, h->capture_stream);
+    hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
+    h->cur = saved;
+    if (rc != KB_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(KB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiateWithFlags(&exec, g, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(KB_EHIP, "hipGraphInstantiateWithFlags: %s", hipGetErrorString(e));
+  e = hipGraphUpload(exec, h->stream);
+  if (e != hipSuccess) { (void)hipGraphExecDestroy(exec); return fail(KB_EHIP, "hipGraphUpload: %s", hipGetErrorString(e)); }
+  *out = exec;
+  return KB_OK;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int enqueue_init(kb_problem *h, float *dst, long long n, uint64_t seed, uint64_t tag, uint64_t offset, double lo,
+                 double hi) {
+  if (n <= 0) return KB_OK;
+  Launch L;
+  InitArgs a{dst, n, seed, tag, offset, lo, hi - lo};
+  make_init(L, a);
+  HIPCHK(hipLaunchKernel(L.func, L.grid, L.block, L.params(), 0, h->stream));
+  return KB_OK;
+}
+
+bool field_info(const kb_problem *h, int field, float **dev, size_t *bytes, bool *host_vec) {
+  *host_vec = false;
+  switch (field) {
+    case KB_F_T:
+      if (!pingpong(h)) return false;
+      *dev = h->Tbuf[h->cur];
+      *bytes = (h->kind == KB_HEAT2D_MULTI ? h->total_cells : h->nz * h->ny * h->nx) * 4;
+      return true;
+    case KB_F_P:
+      if (!pingpong(h)) return false;
+      *dev = h->P;
+      *bytes = (h->kind == KB_HEAT2D_MULTI ? h->total_cells : h->ny * h->nx) * 4;
+      return true;
+    case KB_F_X:
+      if (h->kind != KB_SKELETON) return false;
+      *dev = h->x; *bytes = h->n * 4; return true;
+    case KB_F_A: case KB_F_B:
+      if (h->kind != KB_SKELETON) return false;
+      *dev = nullptr; *bytes = h->K * 4; *host_vec = true; return true;
+    case KB_F_EX: case KB_F_EY: case KB_F_EZ: case KB_F_HX: case KB_F_HY: case KB_F_HZ: {
+      if (h->kind != KB_FDTD3D) return false;
+      const int64_t M = h->N + 1;
+      *dev = h->F[field - KB_F_EX]; *bytes = M * M * M * 4; return true;
+    }
+    case KB_F_PROBE:
+      if (h->kind != KB_FDTD3D) return false;
+      *dev = h->probe; *bytes = (size_t)h->pcap * 4; return true;
+    case KB_F_STEP:
+      if (h->kind != KB_FDTD3D) return false;
+      *dev = reinterpret_cast<float *>(h->step); *bytes = 8; return true;
+  }
+  return false;
+}
+
+int check_heat_coeffs(const double *c, int nc, int layers3d, HeatCoef *k) {
+  double cc = 1e-3, Rx = 1, Ry = 1, Rz = 10, Tamb = 300;
+  if (nc != 0 && nc != 5) return fail(KB_EINVAL, "heat coefficients: expected 5 (c, Rx, Ry, Rz, Tamb), got %d", nc);
+  if (nc == 5) { cc = c[0]; Rx = c[1]; Ry = c[2]; Rz = c[3]; Tamb = c[4]; }
+  if (!(cc > 0) || !(Rx > 0) || !(Ry > 0) || !(Rz > 0) || !std::isfinite(Tamb))
+    return fail(KB_EINVAL, "heat coefficients must be positive and finite");
+  const double diag = cc * (2 / Rx + 2 / Ry + (layers3d ? 3 : 1) / Rz);
+  if (!(diag < 1)) return fail(KB_EINVAL, "unstable heat step: c*(2/Rx+2/Ry+%s/Rz) = %g >= 1", layers3d ? "3" : "1", diag);
+  k->cP = (float)cc;
+  k->cx = (float)(cc / Rx);
+  k->cy = (float)(cc / Ry);
+  k->cz = (float)(cc / Rz);
+  k->Tamb = (float)Tamb;
+  return KB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kb_abi_version(void) { return 1; }
+
+const char *kb_last_error(void) { return g_err.c_str(); }
+
+size_t kb_workspace_bytes(int problem, const int64_t *shape, int ndim) {
+  Layout L;
+  size_t off[16] = {0};
+  if (!layout(problem, shape, ndim, L, off)) return 0;
+  return L.total;
+}
+
+int kb_kernels_per_iter(const kb_problem *h) { return h ? h->K : fail(KB_EINVAL, "null handle"); }
+
+int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs, int ncoeffs, uint64_t seed,
+              void *workspace, size_t ws_bytes, void *stream, kb_problem **out) {
+  g_err.clear();
+  if (!out) return fail(KB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (ncoeffs < 0 || (ncoeffs > 0 && !coeffs)) return fail(KB_EINVAL, "bad coefficient array");
+  Layout Lay;
+  size_t off[16] = {0};
+  if (!layout(problem, shape, ndim, Lay, off)) return fail(KB_EINVAL, "invalid problem %d or shape", problem);
+  if (!workspace || ws_bytes < Lay.total)
+    return fail(KB_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, Lay.total);
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(KB_ENOMEM, "workspace must be %zu-byte aligned", kAlign);
+
+  kb_problem *h = new (std::nothrow) kb_problem();
+  if (!h) return fail(KB_ENOMEM, "host allocation failed");
+  h->kind = problem;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  h->ws = static_cast<unsigned char *>(workspace);
+  h->ws_bytes = ws_bytes;
+  auto P = [&](size_t o) { return reinterpret_cast<float *>(h->ws + o); };
+  h->partials = reinterpret_cast<double *>(h->ws + off[3]);
+  h->red = reinterpret_cast<double *>(h->ws + off[4]);
+
+  int rc = KB_OK;
+  auto bail = [&](int code) { kb_destroy(h); return code; };
+  if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(KB_EHIP, "hipGetDevice failed"));
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+    return bail(fail(KB_EHIP, "hipEventCreate failed"));
+  if (hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(KB_EHIP, "hipStreamCreateWithFlags failed"));
+
+  switch (problem) {
+    case KB_HEAT2D:
+    case KB_HEAT3D: {
+      const bool d3 = problem == KB_HEAT3D;
+      if ((rc = check_heat_coeffs(coeffs, ncoeffs, d3, &h->hk)) != KB_OK) return bail(rc);
+      h->nz = d3 ? shape[0] : 1;
+      h->ny = shape[d3 ? 1 : 0];
+      h->nx = shape[d3 ? 2 : 1];
+      h->Tbuf[0] = P(off[0]); h->Tbuf[1] = P(off[1]); h->P = P(off[2]);
+      h->K = 1;
+      if ((rc = enqueue_init(h, h->Tbuf[0], h->nz * h->ny * h->nx, seed, kTagT0, 0, 323.0, 343.0)) ||
+          (rc = enqueue_init(h, h->P, h->ny * h->nx, seed, kTagP, 0, 0.0, 1.0)))
+        return bail(rc);
+      break;
+    }
+    case KB_HEAT2D_MULTI: {
+      if ((rc = check_heat_coeffs(coeffs, ncoeffs, 0, &h->hk)) != KB_OK) return bail(rc);
+      h->G = (int)shape[0];
+      h->grid_shape.assign(shape, shape + ndim);
+      h->Tbuf[0] = P(off[0]); h->Tbuf[1] = P(off[1]); h->P = P(off[2]);
+      h->grids_d = reinterpret_cast<GridDesc *>(h->ws + off[14]);
+      h->block_start_d = reinterpret_cast<int *>(h->ws + off[15]);
+      std::vector<GridDesc> gd(h->G);
+      std::vector<int> bs(h->G + 1);
+      long long offc = 0;
+      int blocks = 0;
+      for (int g = 0; g < h->G; ++g) {
+        const int ny = (int)shape[1 + 2 * g], nx = (int)shape[2 + 2 * g];
+        const int tx = (nx + kMultiBX - 1) / kMultiBX, ty = (ny + kMultiBY - 1) / kMultiBY;
+        gd[g] = GridDesc{offc, ny, nx, tx, blocks};
+        bs[g] = blocks;
+        blocks += tx * ty;
+        offc += (long long)ny * nx;
+      }
+      bs[h->G] = blocks;
+      h->total_blocks = blocks;
+      h->total_cells = offc;
+      h->K = 1;
+      if (hipMemcpy(h->grids_d, gd.data(), gd.size() * sizeof(GridDesc), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(h->block_start_d, bs.data(), bs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(KB_EHIP, "grid table upload failed"));
+      if ((rc = enqueue_init(h, h->Tbuf[0], offc, seed, kTagT0, 0, 323.0, 343.0)) ||
+          (rc = enqueue_init(h, h->P, offc, seed, kTagP, 0, 0.0, 1.0)))
+        return bail(rc);
+      break;
+    }
+    case KB_SKELETON: {
+      if (ncoeffs < 1) return bail(fail(KB_EINVAL, "skeleton needs coeffs {K[, a_1..a_K, b_1..b_K]}"));
+      const int K = (int)coeffs[0];
+      if ((double)K != coeffs[0] || K < 1 || K > kMaxK) return bail(fail(KB_EINVAL, "skeleton K must be 1..%d", kMaxK));
+      if (ncoeffs != 1 && ncoeffs != 1 + 2 * K) return bail(fail(KB_EINVAL, "skeleton coeffs: 1 or 1+2K values"));
+      h->K = K;
+      h->n = shape[0];
+      h->x = P(off[0]);
+      h->a.resize(K);
+      h->b.resize(K);
+      for (int k = 0; k < K; ++k) {
+        h->a[k] = ncoeffs > 1 ? (float)coeffs[1 + k] : host_uniform(seed, kTagA, k, 0.9, 1.0);
+        h->b[k] = ncoeffs > 1 ? (float)coeffs[1 + K + k] : host_uniform(seed, kTagB, k, -0.01, 0.01);
+      }
+      if ((rc = enqueue_init(h, h->x, h->n, seed, kTagX0, 0, -1.0, 1.0))) return bail(rc);
+      break;
+    }
+    case KB_FDTD3D: {
+      if (ncoeffs != 3 && ncoeffs != 6)
+        return bail(fail(KB_EINVAL, "fdtd coeffs: {courant, width, delay[, i, j, k]}"));
+      const int N = (int)shape[0];
+      const double courant = coeffs[0], width = coeffs[1], delay = coeffs[2];
+      if (!(courant > 0) || !(courant < 1.0 / std::sqrt(3.0)))
+        return bail(fail(KB_EINVAL, "courant number %g outside (0, 1/sqrt(3))", courant));
+      h->N = N;
+      h->dt = (float)courant;
+      h->K = 3;
+      for (int f = 0; f < 6; ++f) h->F[f] = P(off[5 + f]);
+      h->g = P(off[11]);
+      h->probe = P(off[12]);
+      h->pcap = (int)(ndim == 2 ? shape[1] : kDefaultProbe);
+      h->step = reinterpret_cast<long long *>(h->ws + off[13]);
+      int si, sj, sk;
+      if (ncoeffs == 6) {
+        si = (int)coeffs[3]; sj = (int)coeffs[4]; sk = (int)coeffs[5];
+        if (si < 1 || si > N - 1 || sj < 1 || sj > N - 1 || sk < 0 || sk > N - 1)
+          return bail(fail(KB_EINVAL, "source node (%d,%d,%d) is not an interior Ez node", si, sj, sk));
+      } else {
+        si = 2 + (int)host_randint(seed, kTagSrc, 0, N - 3);
+        sj = 2 + (int)host_randint(seed, kTagSrc, 1, N - 3);
+        sk = 1 + (int)host_randint(seed, kTagSrc, 2, N - 2);
+      }
+      h->src_ijk[0] = si; h->src_ijk[1] = sj; h->src_ijk[2] = sk;
+      const long long M = N + 1;
+      h->src = ((long long)sk * M + sj) * M + si;
+      // amplitude table: g(n) = exp(-((n - delay)/width)^2) rounded to float,
+      // up to the first step after which every value rounds to zero.
+      std::vector<float> gt;
+      if (width > 0) {
+        const double last = delay + width * std::sqrt(104.0);
+        if (!(last < kGCap - 1)) return bail(fail(KB_EINVAL, "source pulse longer than %d steps", kGCap));
+        const int len = (int)std::ceil(last) + 1;
+        gt.resize(len);
+        for (int n = 0; n < len; ++n) {
+          const double x = ((double)n - delay) / width;
+          gt[n] = (float)std::exp(-(x * x));
+        }
+      }
+      h->glen = (int)gt.size();
+      for (int f = 0; f < 6; ++f)
+        if (hipMemsetAsync(h->F[f], 0, M * M * M * 4, h->stream) != hipSuccess)
+          return bail(fail(KB_EHIP, "hipMemsetAsync failed"));
+      if (hipMemsetAsync(h->probe, 0, (size_t)(h->pcap > 0 ? h->pcap : 1) * 4, h->stream) != hipSuccess ||
+          hipMemsetAsync(h->step, 0, 8, h->stream) != hipSuccess)
+        return bail(fail(KB_EHIP, "hipMemsetAsync failed"));
+      if (h->glen > 0 && hipMemcpyAsync(h->g, gt.data(), gt.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return bail(fail(KB_EHIP, "source table upload failed"));
+      if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(KB_EHIP, "hipStreamSynchronize failed"));
+      break;
+    }
+  }
+  *out = h;
+  return KB_OK;
+}
+
+int kb_set_option(kb_problem *h, int option, int64_t value) {
+  if (!h) return fail(KB_EINVAL, "null handle");
+  switch (option) {
+    case KB_OPT_BUILDER:
+      if (value != 0 && value != 1) return fail(KB_EINVAL, "builder must be 0 or 1");
+      h->builder = (int)value;
+      break;
+    case KB_OPT_TILE: {
+      bool ok = false;
+      if (h->kind == KB_HEAT2D) ok = value >= 0 && value <= 7;
+      else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
+      else ok = value == 0;
+      if (!ok) return fail(KB_EINVAL, "kernel variant %lld not available for this problem", (long long)value);
+      if (h->tile != value) clear_cache(h);
+      h->tile = (int)value;
+      break;
+    }
+    case KB_OPT_TDEPTH:
+      if (h->kind != KB_HEAT2D && value != 1) return fail(KB_EINVAL, "temporal depth > 1 only for KB_HEAT2D");
+      if (value < 1 || value > heat2d_tile_max_depth()) return fail(KB_EINVAL, "temporal depth must be 1..%d", heat2d_tile_max_depth());
+      if (h->tdepth != value) clear_cache(h);
+      h->tdepth = (int)value;
+      break;
+    case KB_OPT_GRAPH_CACHE:
+      if (value != 0 && value != 1) return fail(KB_EINVAL, "graph cache must be 0 or 1");
+      h->cache = (int)value;
+      if (!value) clear_cache(h);
+      break;
+    case KB_OPT_MAX_NODES:
+      if (value < 1) return fail(KB_EINVAL, "max nodes must be >= 1");
+      h->max_nodes = value;
+      break;
+    default:
+      return fail(KB_EINVAL, "unknown option %d", option);
+  }
+  return KB_OK;
+}
+
+int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b) {
+  if (!h) return fail(KB_EINVAL, "null handle");
+  if (n_steps < 0 || batch_b < 0) return fail(KB_EINVAL, "n_steps and batch_b must be >= 0");
+  const int depth = iter_depth(h);
+  const int64_t n_iter = n_steps / depth;
+  const int64_t rem_steps = n_steps % depth;
+  kb_timing t{};
+  int status = KB_OK;
+  const bool pp = pingpong(h);
+
+  if (batch_b > 0 && (batch_b > h->max_nodes / h->K))
+    return fail(KB_EINVAL, "batch of %lld iterations x %d kernels exceeds %lld graph nodes", (long long)batch_b, h->K,
+                (long long)h->max_nodes);
+
+  int64_t nb = 0, peel = n_iter;
+  hipGraphExec_t execs[2] = {nullptr, nullptr};
+  if (batch_b > 0 && n_iter >= batch_b) {
+    nb = n_iter / batch_b;
+    peel = n_iter % batch_b;
+    // parities the replays start from
+    int need[2] = {h->cur, -1};
+    if (pp && (batch_b & 1) && nb > 1) need[1] = h->cur ^ 1;
+    const double t0 = now_s();
+    for (int q = 0; q < 2 && status == KB_OK; ++q) {
+      if (need[q] < 0) continue;
+      auto key = std::make_tuple(batch_b, depth, h->tile, pp ? need[q] : 0);
+      auto it = h->cache_map.find(key);
+      if (it != h->cache_map.end()) { execs[need[q]] = it->second; continue; }
+      hipGraphExec_t ex = nullptr;
+      int rc = build_graph(h, batch_b, depth, need[q], &ex);
+      if (rc != KB_OK) { status = KB_WFALLBACK; break; }
+      h->cache_map[key] = ex;
+      execs[need[q]] = ex;
+      t.n_graphs_built++;
+    }
+    if (t.n_graphs_built > 0) {
+      hipError_t e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) return fail(KB_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    t.t_create_s = now_s() - t0;
+    if (status == KB_WFALLBACK) { nb = 0; peel = n_iter; }
+  }
+
+  HIPCHK(hipEventRecord(h->ev0, h->stream));
+  for (int64_t j = 0; j < nb; ++j) {
+    hipGraphExec_t ex = execs[pp ? h->cur : 0];
+    HIPCHK(hipGraphLaunch(ex, h->stream));
+    if (pp && (batch_b & 1)) h->cur ^= 1;
+  }
+  for (int64_t j = 0; j < peel; ++j) {
+    int rc = launch_iter(h, depth, h->stream);
+    if (rc != KB_OK) return rc;
+  }
+  for (int64_t j = 0; j < rem_steps; ++j) {
+    int rc = launch_iter(h, 1, h->stream);
+    if (rc != KB_OK) return rc;
+  }
+  HIPCHK(hipEventRecord(h->ev1, h->stream));
+  t.n_graph_launches = nb;
+  t.n_nodes = nb > 0 ? batch_b * h->K : 0;
+  t.n_peeled = peel + rem_steps;
+  t.n_kernel_launches = (peel + rem_steps) * h->K;
+  h->last = t;
+  h->timed = true;
+  h->host_steps += n_steps;
+  if (!h->cache && !h->cache_map.empty()) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    clear_cache(h);
+  }
+  return status;
+}
+
+int kb_kernel_time(kb_problem *h, int64_t reps, double *out, int nout) {
+  if (!h || !out) return fail(KB_EINVAL, "null argument");
+  if (reps < 1 || reps > 256) return fail(KB_EINVAL, "reps must be 1..256");
+  if (nout < h->K) return fail(KB_EINVAL, "need room for %d kernels", h->K);
+  const int depth = iter_depth(h);
+  const size_t nev = (size_t)reps * h->K * 2;
+  while (h->kt_events.size() < nev) {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreate(&e));
+    h->kt_events.push_back(e);
+  }
+  Launch L[kMaxK];
+  size_t q = 0;
+  for (int64_t r = 0; r < reps; ++r) {
+    const int k = fill_iter(h, h->cur, depth, L);
+    if (k < 0) return fail(KB_EINVAL, "invalid kernel variant");
+    for (int j = 0; j < k; ++j, q += 2) {
+      HIPCHK(hipExtLaunchKernel(L[j].func, L[j].grid, L[j].block, L[j].params(), L[j].lds, h->stream,
+                                h->kt_events[q], h->kt_events[q + 1], 0));
+    }
+    if (pingpong(h)) h->cur ^= 1;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int j = 0; j < h->K; ++j) out[j] = 0.0;
+  q = 0;
+  for (int64_t r = 0; r < reps; ++r) {
+    for (int j = 0; j < h->K; ++j, q += 2) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, h->kt_events[q], h->kt_events[q + 1]));
+      out[j] += ms * 1e-3;
+    }
+  }
+  for (int j = 0; j < h->K; ++j) out[j] /= (double)reps;
+  h->host_steps += reps * depth;
+  return KB_OK;
+}
+
+int kb_last_timing(kb_problem *h, kb_timing *out) {
+  if (!h || !out) return fail(KB_EINVAL, "null argument");
+  if (!h->timed) return fail(KB_ESTATE, "no kb_run yet");
+  HIPCHK(hipEventSynchronize(h->ev1));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  *out = h->last;
+  out->t_exec_s = ms * 1e-3;
+  return KB_OK;
+}
+
+int kb_read(kb_problem *h, int field, void *dst, size_t bytes, int dst_on_device) {
+  if (!h || !dst) return fail(KB_EINVAL, "null argument");
+  float *dev = nullptr;
+  size_t need = 0;
+  bool hv = false;
+  if (!field_info(h, field, &dev, &need, &hv)) return fail(KB_EINVAL, "field %d not available", field);
+  if (bytes != need) return fail(KB_EINVAL, "field %d has %zu bytes, got %zu", field, need, bytes);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (hv) {
+    const std::vector<float> &v = field == KB_F_A ? h->a : h->b;
+    if (dst_on_device) HIPCHK(hipMemcpy(dst, v.data(), bytes, hipMemcpyHostToDevice));
+    else std::memcpy(dst, v.data(), bytes);
+    return KB_OK;
+  }
+  HIPCHK(hipMemcpy(dst, dev, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return KB_OK;
+}
+
+int kb_write(kb_problem *h, int field, const void *src, size_t bytes, int src_on_device) {
+  if (!h || !src) return fail(KB_EINVAL, "null argument");
+  float *dev = nullptr;
+  size_t need = 0;
+  bool hv = false;
+  if (!field_info(h, field, &dev, &need, &hv)) return fail(KB_EINVAL, "field %d not available", field);
+  if (bytes != need) return fail(KB_EINVAL, "field %d has %zu bytes, got %zu", field, need, bytes);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (hv) {
+    std::vector<float> &v = field == KB_F_A ? h->a : h->b;
+    if (src_on_device) HIPCHK(hipMemcpy(v.data(), src, bytes, hipMemcpyDeviceToHost));
+    else std::memcpy(v.data(), src, bytes);
+    clear_cache(h);   // a_k, b_k are baked into graph nodes
+    return KB_OK;
+  }
+  HIPCHK(hipMemcpy(dev, src, bytes, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+  return KB_OK;
+}
+
+int kb_reduce(kb_problem *h, double *out, int nout) {
+  if (!h || !out) return fail(KB_EINVAL, "null argument");
+  hipError_t e = hipSuccess;
+  int nres = 1;
+  if (pingpong(h)) {
+    const long long n = h->kind == KB_HEAT2D_MULTI ? h->total_cells : h->nz * h->ny * h->nx;
+    e = reduce_sum(h->Tbuf[h->cur], n, h->partials, h->red, h->stream);
+  } else if (h->kind == KB_SKELETON) {
+    e = reduce_sum(h->x, h->n, h->partials, h->red, h->stream);
+  } else {
+    const long long M = h->N + 1;
+    const float *E[3] = {h->F[0], h->F[1], h->F[2]};
+    const float *H[3] = {h->F[3], h->F[4], h->F[5]};
+    e = reduce_sumsq(E, 3, M * M * M, h->partials, h->red, h->stream);
+    if (e == hipSuccess) e = reduce_sumsq(H, 3, M * M * M, h->partials, h->red + 1, h->stream);
+    nres = 2;
+  }
+  if (e != hipSuccess) return fail(KB_EHIP, "reduction launch: %s", hipGetErrorString(e));
+  if (nout < nres) return fail(KB_EINVAL, "need room for %d results", nres);
+  double tmp[2];
+  HIPCHK(hipMemcpyAsync(tmp, h->red, nres * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int q = 0; q < nres; ++q) out[q] = tmp[q];
+  return KB_OK;
+}
+
+int kb_destroy(kb_problem *h) {
+  if (!h) return KB_OK;
+  int rc = KB_OK;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(KB_EHIP, "hipStreamSynchronize failed in destroy");
+  clear_cache(h);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+  for (hipEvent_t e : h->kt_events) (void)hipEventDestroy(e);
+  delete h;
+  return rc;
+}
+
+}  // extern "C"

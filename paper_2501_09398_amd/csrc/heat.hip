@@ -1,0 +1,252 @@
+// Thermal stencil kernels (2D 5-point, 3D 7-point, many-grid 2D) for gfx950.
+//
+// The update is the explicit thermal step of the Hotspot model that the
+// paper batches (Sec. III-C):
+//   T' = T + c*(P + (Tn+Ts-2T)/Ry + (Te+Tw-2T)/Rx [+ (Tu+Td-2T)/Rz] + (Tamb-T)/Rz)
+// with neighbour indices clamped to the grid.  Every kernel evaluates it
+// through heat_update*/ below in one fixed order of fused multiply-adds with
+// the coefficients c, c/Rx, c/Ry, c/Rz pre-rounded to float, so all kernel
+// variants (direct, LDS tile, temporal blocking, many-grid) produce the same
+// bits for the same step.  The library is built with -ffp-contract=off, so
+// only the explicit fmaf calls fuse.
+//
+// These kernels are bandwidth- or latency-bound (about 12 bytes and 13 flops
+// per cell-step), so they use plain vector ALU work, coalesced row access
+// (one wave64 covers 64 consecutive floats of a row) and LDS tiles, not MFMA.
+#include "kb_internal.h"
+
+namespace kb {
+
+__device__ __forceinline__ float heat_update(float t, float tn, float ts, float tw, float te, float p,
+                                             const HeatCoef &k) {
+  float dns = (tn + ts) - (t + t);
+  float dew = (te + tw) - (t + t);
+  float acc = k.cz * (k.Tamb - t);
+  acc = fmaf(k.cx, dew, acc);
+  acc = fmaf(k.cy, dns, acc);
+  acc = fmaf(k.cP, p, acc);
+  return t + acc;
+}
+
+__device__ __forceinline__ float heat3d_update(float t, float tn, float ts, float tw, float te, float tu,
+                                               float td, float p, bool has_p, const HeatCoef &k) {
+  float dns = (tn + ts) - (t + t);
+  float dew = (te + tw) - (t + t);
+  float dud = (tu + td) - (t + t);
+  float acc = k.cz * (k.Tamb - t);
+  acc = fmaf(k.cx, dew, acc);
+  acc = fmaf(k.cz, dud, acc);
+  acc = fmaf(k.cy, dns, acc);
+  if (has_p) acc = fmaf(k.cP, p, acc);
+  return t + acc;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Remap the hardware
+// block id so that XCD x receives one contiguous run of logical blocks
+// (a band of rows), which keeps the halo rows of neighbouring tiles in the
+// same XCD's L2.  The grid is padded to a multiple of 8; logical ids past
+// the end return.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_logical_block(int nblocks) {
+  int hw = blockIdx.x;
+  int per = (nblocks + kXcds - 1) / kXcds;
+  return (hw % kXcds) * per + hw / kXcds;
+}
+
+static inline int xcd_padded_grid(int nblocks) { return (nblocks + kXcds - 1) / kXcds * kXcds; }
+
+// ---------------------------------------------------------------------------
+// 2D direct kernel: one thread per cell, 64x4 threads per block.
+// ---------------------------------------------------------------------------
+constexpr int kDX = 64, kDY = 4;
+
+__global__ __launch_bounds__(256) void heat2d_direct_kernel(const Heat2DArgs a) {
+  const int tiles_x = (a.nx + kDX - 1) / kDX;
+  const int tiles_y = (a.ny + kDY - 1) / kDY;
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const int j = (lb % tiles_x) * kDX + threadIdx.x;
+  const int i = (lb / tiles_x) * kDY + threadIdx.y;
+  if (i >= a.ny || j >= a.nx) return;
+  const size_t nx = (size_t)a.nx;
+  const int in = i > 0 ? i - 1 : 0;
+  const int is = i < a.ny - 1 ? i + 1 : a.ny - 1;
+  const int jw = j > 0 ? j - 1 : 0;
+  const int je = j < a.nx - 1 ? j + 1 : a.nx - 1;
+  const float *row = a.T + (size_t)i * nx;
+  const float t = row[j];
+  const float v = heat_update(t, a.T[(size_t)in * nx + j], a.T[(size_t)is * nx + j], row[jw], row[je],
+                              a.P[(size_t)i * nx + j], a.k);
+  a.out[(size_t)i * nx + j] = v;
+}
+
+void make_heat2d_direct(Launch &L, const Heat2DArgs &a) {
+  int nb = ((a.nx + kDX - 1) / kDX) * ((a.ny + kDY - 1) / kDY);
+  L.set((const void *)heat2d_direct_kernel, dim3(xcd_padded_grid(nb)), dim3(kDX, kDY), 0, a);
+}
+
+// ---------------------------------------------------------------------------
+// 2D LDS tile kernel with temporal blocking.  A block owns a BX x BY tile of
+// outputs.  It loads the tile plus a halo of t cells (clipped to the grid)
+// into LDS, applies t steps there (ping-pong between two LDS buffers, P kept
+// in a third), and writes the tile.  At the grid's own edges the neighbour
+// index is clamped exactly as in a single step; at the halo's inner edges
+// the clamp is wrong, but that error moves inward one cell per step and
+// never reaches the tile after t steps.  Each step applies heat_update to
+// every cell, so the result equals t direct steps bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kMaxDepth = 16;
+
+template <int BX, int BY>
+__global__ __launch_bounds__(BX *BY) void heat2d_tile_kernel(const Heat2DArgs a) {
+  extern __shared__ float sm[];
+  const int t = a.tdepth;
+  const int tiles_x = (a.nx + BX - 1) / BX;
+  const int tiles_y = (a.ny + BY - 1) / BY;
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const int x0 = (lb % tiles_x) * BX;
+  const int y0 = (lb / tiles_x) * BY;
+  const int rx_lo = max(x0 - t, 0), rx_hi = min(x0 + BX + t, a.nx);
+  const int ry_lo = max(y0 - t, 0), ry_hi = min(y0 + BY + t, a.ny);
+  const int W = rx_hi - rx_lo, H = ry_hi - ry_lo;
+  const int cap = (BX + 2 * t) * (BY + 2 * t);
+  float *A = sm;
+  float *B = sm + cap;
+  float *Ps = sm + 2 * cap;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const size_t nx = (size_t)a.nx;
+
+  for (int yy = ty; yy < H; yy += BY) {
+    const size_t g = (size_t)(ry_lo + yy) * nx + rx_lo;
+    for (int xx = tx; xx < W; xx += BX) {
+      A[yy * W + xx] = a.T[g + xx];
+      Ps[yy * W + xx] = a.P[g + xx];
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < t; ++s) {
+    for (int yy = ty; yy < H; yy += BY) {
+      const int yn = yy > 0 ? yy - 1 : 0;
+      const int ys = yy < H - 1 ? yy + 1 : H - 1;
+      for (int xx = tx; xx < W; xx += BX) {
+        const int xw = xx > 0 ? xx - 1 : 0;
+        const int xe = xx < W - 1 ? xx + 1 : W - 1;
+        B[yy * W + xx] = heat_update(A[yy * W + xx], A[yn * W + xx], A[ys * W + xx], A[yy * W + xw],
+                                     A[yy * W + xe], Ps[yy * W + xx], a.k);
+      }
+    }
+    __syncthreads();
+    float *tmp = A; A = B; B = tmp;
+  }
+  const int gy = y0 + ty;
+  for (int yy = gy; yy < min(y0 + BY, a.ny); yy += BY) {
+    for (int xx = x0 + tx; xx < min(x0 + BX, a.nx); xx += BX) {
+      a.out[(size_t)yy * nx + xx] = A[(yy - ry_lo) * W + (xx - rx_lo)];
+    }
+  }
+}
+
+template <int BX, int BY>
+static void set_tile(Launch &L, const Heat2DArgs &a) {
+  int nb = ((a.nx + BX - 1) / BX) * ((a.ny + BY - 1) / BY);
+  unsigned shm = 3u * (BX + 2 * a.tdepth) * (BY + 2 * a.tdepth) * sizeof(float);
+  L.set((const void *)heat2d_tile_kernel<BX, BY>, dim3(xcd_padded_grid(nb)), dim3(BX, BY), shm, a);
+}
+
+int heat2d_tile_max_depth() { return kMaxDepth; }
+
+// variant: 2 = 64x4, 3 = 64x8, 4 = 64x16, 5 = 32x8, 6 = 16x16, 7 = 32x4
+bool make_heat2d_tile(Launch &L, const Heat2DArgs &a, int variant) {
+  if (a.tdepth < 1 || a.tdepth > kMaxDepth) return false;
+  switch (variant) {
+    case 2: set_tile<64, 4>(L, a); return true;
+    case 3: set_tile<64, 8>(L, a); return true;
+    case 4: set_tile<64, 16>(L, a); return true;
+    case 5: set_tile<32, 8>(L, a); return true;
+    case 6: set_tile<16, 16>(L, a); return true;
+    case 7: set_tile<32, 4>(L, a); return true;
+    default: return false;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3D kernel: one thread per (x, y) column, marching up the layers with the
+// column's three consecutive layers in registers.  P is the plane of layer 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void heat3d_kernel(const Heat3DArgs a) {
+  const int tiles_x = (a.nx + kDX - 1) / kDX;
+  const int tiles_y = (a.ny + kDY - 1) / kDY;
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const int j = (lb % tiles_x) * kDX + threadIdx.x;
+  const int i = (lb / tiles_x) * kDY + threadIdx.y;
+  if (i >= a.ny || j >= a.nx) return;
+  const size_t nx = (size_t)a.nx;
+  const size_t plane = (size_t)a.ny * nx;
+  const int in = i > 0 ? i - 1 : 0;
+  const int is = i < a.ny - 1 ? i + 1 : a.ny - 1;
+  const int jw = j > 0 ? j - 1 : 0;
+  const int je = j < a.nx - 1 ? j + 1 : a.nx - 1;
+  const size_t c = (size_t)i * nx + j;
+  const size_t on = (size_t)in * nx + j, os = (size_t)is * nx + j;
+  const size_t ow = (size_t)i * nx + jw, oe = (size_t)i * nx + je;
+  float td = a.T[c];
+  float tc = td;
+  for (int z = 0; z < a.nz; ++z) {
+    const size_t base = (size_t)z * plane;
+    const float tu = (z + 1 < a.nz) ? a.T[base + plane + c] : tc;
+    const float p = (z == 0) ? a.P[c] : 0.0f;
+    const float v = heat3d_update(tc, a.T[base + on], a.T[base + os], a.T[base + ow], a.T[base + oe], tu, td, p,
+                                  z == 0, a.k);
+    a.out[base + c] = v;
+    td = tc;
+    tc = tu;
+  }
+}
+
+void make_heat3d(Launch &L, const Heat3DArgs &a) {
+  int nb = ((a.nx + kDX - 1) / kDX) * ((a.ny + kDY - 1) / kDY);
+  L.set((const void *)heat3d_kernel, dim3(xcd_padded_grid(nb)), dim3(kDX, kDY), 0, a);
+}
+
+// ---------------------------------------------------------------------------
+// Many-grid kernel: one launch advances every grid by one step.  The grids'
+// 64x4 tiles are numbered consecutively; a block finds its grid by binary
+// search over the prefix sums of tiles per grid.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void heat2d_multi_kernel(const MultiArgs a) {
+  const int nb = a.block_start[a.G];
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  int lo = 0, hi = a.G - 1;
+  while (lo < hi) {            // largest g with block_start[g] <= lb
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.block_start[mid] <= lb) lo = mid; else hi = mid - 1;
+  }
+  const GridDesc gd = a.grids[lo];
+  const int local = lb - gd.block0;
+  const int j = (local % gd.tiles_x) * kMultiBX + threadIdx.x;
+  const int i = (local / gd.tiles_x) * kMultiBY + threadIdx.y;
+  if (i >= gd.ny || j >= gd.nx) return;
+  const size_t nx = (size_t)gd.nx;
+  const float *T = a.T + gd.off;
+  const int in = i > 0 ? i - 1 : 0;
+  const int is = i < gd.ny - 1 ? i + 1 : gd.ny - 1;
+  const int jw = j > 0 ? j - 1 : 0;
+  const int je = j < gd.nx - 1 ? j + 1 : gd.nx - 1;
+  const size_t c = (size_t)i * nx + j;
+  const float v = heat_update(T[c], T[(size_t)in * nx + j], T[(size_t)is * nx + j], T[(size_t)i * nx + jw],
+                              T[(size_t)i * nx + je], a.P[gd.off + c], a.k);
+  a.out[gd.off + c] = v;
+}
+
+void make_multi(Launch &L, const MultiArgs &a, int total_blocks) {
+  L.set((const void *)heat2d_multi_kernel, dim3(xcd_padded_grid(total_blocks)), dim3(kMultiBX, kMultiBY), 0, a);
+}
+
+}  // namespace kb

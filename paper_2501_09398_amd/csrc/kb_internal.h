@@ -1,0 +1,205 @@
+// Internal declarations of libkbatch (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kb.h"
+
+namespace kb {
+
+// ---------------------------------------------------------------------------
+// Counter-based SplitMix64 (Steele, Lea, Flood 2014), used for the seeded
+// initial state.  Draw idx of stream (seed, tag) is output idx+1 of a
+// SplitMix64 sequence whose state starts at seed ^ (tag << 48).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint64_t splitmix(uint64_t seed, uint64_t tag, uint64_t idx) {
+  uint64_t z = (seed ^ (tag << 48)) + (idx + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+enum Tag : uint64_t { kTagT0 = 1, kTagP = 2, kTagX0 = 3, kTagA = 4, kTagB = 5, kTagSrc = 6, kTagHot = 7 };
+
+// Host-side uniform draw, rounded once to float (matches the device draw).
+float host_uniform(uint64_t seed, uint64_t tag, uint64_t idx, double lo, double hi);
+// Integer on [0, m) from the top 24 bits.
+int64_t host_randint(uint64_t seed, uint64_t tag, uint64_t idx, int64_t m);
+
+// ---------------------------------------------------------------------------
+// One kernel launch: function, shape, and its single by-value argument
+// struct.  The per-launch driver and both graph builders consume the same
+// descriptors, so the two execution paths run identical kernels on
+// identical arguments.
+// ---------------------------------------------------------------------------
+struct Launch {
+  const void *func = nullptr;
+  dim3 grid{1, 1, 1};
+  dim3 block{1, 1, 1};
+  unsigned lds = 0;
+  alignas(16) unsigned char args[256];
+  size_t args_size = 0;
+  void *argv[1] = {nullptr};
+
+  template <class A> void set(const void *f, dim3 g, dim3 b, unsigned shm, const A &a) {
+    static_assert(sizeof(A) <= sizeof(args), "kernel argument struct too large");
+    func = f; grid = g; block = b; lds = shm;
+    std::memcpy(args, &a, sizeof(A));
+    args_size = sizeof(A);
+    argv[0] = args;
+  }
+  // argv points into this object; refresh after copies.
+  void **params() { argv[0] = args; return argv; }
+};
+
+// ---------------------------------------------------------------------------
+// Kernel argument structs (passed by value).
+// ---------------------------------------------------------------------------
+struct HeatCoef {
+  float cP, cx, cy, cz, Tamb;   // c, c/Rx, c/Ry, c/Rz, Tamb rounded to float
+};
+
+struct Heat2DArgs {
+  const float *T; float *out; const float *P;
+  int ny, nx;
+  HeatCoef k;
+  int tdepth;                  // steps per launch (tile kernels)
+};
+
+struct Heat3DArgs {
+  const float *T; float *out; const float *P;   // P: plane of layer 0
+  int nz, ny, nx;
+  HeatCoef k;
+};
+
+struct GridDesc {               // one grid of the many-grid problem
+  long long off;                // first cell in the concatenated arrays
+  int ny, nx;
+  int tiles_x;                  // tiles along x
+  int block0;                   // first block of this grid
+};
+
+struct MultiArgs {
+  const float *T; float *out; const float *P;
+  const GridDesc *grids;
+  const int *block_start;       // G+1 prefix sums of blocks per grid
+  int G;
+  HeatCoef k;
+};
+
+struct SkelArgs {
+  float *x; long long n; float a, b;
+};
+
+struct FdtdArgs {
+  float *Ex, *Ey, *Ez, *Hx, *Hy, *Hz;
+  int N; float dt;
+};
+
+struct SrcArgs {
+  float *Ez; long long src;     // flat index of the source node
+  const float *g; int glen;     // amplitude per absolute step
+  float *probe; int pcap;
+  long long *step;
+};
+
+struct InitArgs {
+  float *out; long long n; unsigned long long seed, tag, offset;
+  double lo, span;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers / descriptor builders, defined in the .hip files.
+// ---------------------------------------------------------------------------
+void make_init(Launch &L, const InitArgs &a);
+void make_heat2d_direct(Launch &L, const Heat2DArgs &a);
+bool make_heat2d_tile(Launch &L, const Heat2DArgs &a, int variant);   // false: bad variant
+int heat2d_tile_max_depth();
+void make_heat3d(Launch &L, const Heat3DArgs &a);
+constexpr int kMultiBX = 64, kMultiBY = 4;   // tile of the many-grid kernel
+void make_multi(Launch &L, const MultiArgs &a, int total_blocks);
+void make_skeleton(Launch &L, const SkelArgs &a, int variant);
+void make_fdtd_h(Launch &L, const FdtdArgs &a);
+void make_fdtd_e(Launch &L, const FdtdArgs &a);
+void make_fdtd_src(Launch &L, const SrcArgs &a);
+
+// Deterministic reductions (enqueued on s; partials has >= reduce_max_blocks doubles).
+int reduce_max_blocks();
+hipError_t reduce_sum(const float *x, long long n, double *partials, double *result, hipStream_t s);
+hipError_t reduce_sumsq(const float *const *fields, int nf, long long n, double *partials, double *result,
+                        hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Problem state.
+// ---------------------------------------------------------------------------
+struct FieldRef {
+  float *ptr = nullptr;         // device
+  size_t bytes = 0;
+  bool host_only = false;       // lives in host memory of the handle
+  float *host = nullptr;
+};
+
+}  // namespace kb
+
+struct kb_problem {
+  int kind = 0;
+  int K = 1;                    // kernels per iteration
+  hipStream_t stream = nullptr;
+  hipStream_t capture_stream = nullptr;
+  int device = 0;
+  unsigned char *ws = nullptr;
+  size_t ws_bytes = 0;
+
+  // options
+  int builder = 0;              // 0 explicit nodes, 1 stream capture
+  int tile = 0;                 // kernel variant (0 = default)
+  int tdepth = 1;
+  int cache = 1;
+  int64_t max_nodes = 65536;
+
+  // heat
+  float *Tbuf[2] = {nullptr, nullptr};
+  float *P = nullptr;
+  int cur = 0;                  // index of the buffer holding the current T
+  int64_t nz = 1, ny = 0, nx = 0;
+  kb::HeatCoef hk{};
+  // multi
+  int G = 0;
+  kb::GridDesc *grids_d = nullptr;
+  int *block_start_d = nullptr;
+  int total_blocks = 0;
+  int64_t total_cells = 0;
+  std::vector<int64_t> grid_shape;
+  // skeleton
+  float *x = nullptr;
+  int64_t n = 0;
+  std::vector<float> a, b;
+  // fdtd
+  int N = 0;
+  float dt = 0.5f;
+  float *F[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  float *g = nullptr; int glen = 0;
+  float *probe = nullptr; int pcap = 0;
+  long long *step = nullptr;
+  long long src = 0;
+  int src_ijk[3] = {0, 0, 0};
+  // reductions
+  double *partials = nullptr;
+  double *red = nullptr;
+
+  // graphs: key (b, tdepth, tile, cur) -> exec graph
+  std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> cache_map;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> kt_events;   // kb_kernel_time start/stop pairs
+  kb_timing last{};
+  bool timed = false;
+  int64_t host_steps = 0;
+};

@@ -1,0 +1,213 @@
+// Seeded initial state, the skeleton chain, the Yee FDTD kernels and the
+// deterministic reductions.
+#include "kb_internal.h"
+
+namespace kb {
+
+// ---------------------------------------------------------------------------
+// Initial state: out[i] = float(lo + span * u), u = (z >> 40) * 2^-24 with
+// z = splitmix(seed, tag, offset + i).  The double multiply and add are
+// explicitly unfused so the host generator gives identical bits.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void init_uniform_kernel(const InitArgs a) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  const uint64_t z = splitmix(a.seed, a.tag, a.offset + (uint64_t)i);
+  const double u = (double)(z >> 40) * 0x1.0p-24;
+  a.out[i] = (float)__dadd_rn(a.lo, __dmul_rn(a.span, u));
+}
+
+void make_init(Launch &L, const InitArgs &a) {
+  L.set((const void *)init_uniform_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, a);
+}
+
+float host_uniform(uint64_t seed, uint64_t tag, uint64_t idx, double lo, double hi) {
+  const uint64_t z = splitmix(seed, tag, idx);
+  const double u = (double)(z >> 40) * 0x1.0p-24;
+  return (float)(lo + (hi - lo) * u);   // built with -ffp-contract=off: no fusion
+}
+
+int64_t host_randint(uint64_t seed, uint64_t tag, uint64_t idx, int64_t m) {
+  const uint64_t top = splitmix(seed, tag, idx) >> 40;
+  return (int64_t)((top * (uint64_t)m) >> 24);
+}
+
+// ---------------------------------------------------------------------------
+// Skeleton kernel: x <- fma(a, x, b) on every element (the skeleton
+// application's small element-wise kernel, Sec. III-C).  Memory-bound at
+// 8 bytes per element; variant picks elements per thread.
+// ---------------------------------------------------------------------------
+template <int VEC>
+__global__ __launch_bounds__(256) void skeleton_kernel(const SkelArgs s) {
+  const long long base = ((long long)blockIdx.x * 256 + threadIdx.x) * VEC;
+  if (base + VEC <= s.n) {
+    if constexpr (VEC == 4) {
+      float4 v = *reinterpret_cast<const float4 *>(s.x + base);
+      v.x = fmaf(s.a, v.x, s.b);
+      v.y = fmaf(s.a, v.y, s.b);
+      v.z = fmaf(s.a, v.z, s.b);
+      v.w = fmaf(s.a, v.w, s.b);
+      *reinterpret_cast<float4 *>(s.x + base) = v;
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) s.x[base + e] = fmaf(s.a, s.x[base + e], s.b);
+    }
+  } else {
+    for (long long e = base; e < s.n; ++e) s.x[e] = fmaf(s.a, s.x[e], s.b);
+  }
+}
+
+// variant: 1 = 4 elements per thread (16-byte access), 2 = 1 element, 3 = 8
+void make_skeleton(Launch &L, const SkelArgs &a, int variant) {
+  int vec = variant == 2 ? 1 : (variant == 3 ? 8 : 4);
+  long long threads = (a.n + vec - 1) / vec;
+  dim3 grid((unsigned)((threads + 255) / 256));
+  if (vec == 1) L.set((const void *)skeleton_kernel<1>, grid, dim3(256), 0, a);
+  else if (vec == 8) L.set((const void *)skeleton_kernel<8>, grid, dim3(256), 0, a);
+  else L.set((const void *)skeleton_kernel<4>, grid, dim3(256), 0, a);
+}
+
+// ---------------------------------------------------------------------------
+// Yee FDTD kernels (the FDTD Maxwell cavity solver of Sec. III-C, two field
+// kernels per step).  dx = 1, eps = mu = 1; every field on a padded (N+1)^3
+// grid, index (k*(N+1)+j)*(N+1)+i.  Positions: Ex(i+1/2,j,k) Ey(i,j+1/2,k)
+// Ez(i,j,k+1/2) Hx(i,j+1/2,k+1/2) Hy(i+1/2,j,k+1/2) Hz(i+1/2,j+1/2,k).
+// One thread per node (i fastest across a wave64), all three components.
+// H -= dt * curl E on every H node; E += dt * curl H on interior E nodes
+// (tangential E on the PEC walls is never written).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fdtd_h_kernel(const FdtdArgs f) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  const int N = f.N;
+  if (i > N || j > N) return;
+  const long long M = N + 1;
+  const long long c = ((long long)k * M + j) * M + i;
+  const long long sj = M, sk = M * M;
+  const float dt = f.dt;
+  if (j < N && k < N)
+    f.Hx[c] = f.Hx[c] - dt * ((f.Ez[c + sj] - f.Ez[c]) - (f.Ey[c + sk] - f.Ey[c]));
+  if (i < N && k < N)
+    f.Hy[c] = f.Hy[c] - dt * ((f.Ex[c + sk] - f.Ex[c]) - (f.Ez[c + 1] - f.Ez[c]));
+  if (i < N && j < N)
+    f.Hz[c] = f.Hz[c] - dt * ((f.Ey[c + 1] - f.Ey[c]) - (f.Ex[c + sj] - f.Ex[c]));
+}
+
+__global__ __launch_bounds__(256) void fdtd_e_kernel(const FdtdArgs f) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  const int N = f.N;
+  if (i > N || j > N) return;
+  const long long M = N + 1;
+  const long long c = ((long long)k * M + j) * M + i;
+  const long long sj = M, sk = M * M;
+  const float dt = f.dt;
+  const bool ii = i >= 1 && i <= N - 1;
+  const bool jj = j >= 1 && j <= N - 1;
+  const bool kk = k >= 1 && k <= N - 1;
+  if (i < N && jj && kk)
+    f.Ex[c] = f.Ex[c] + dt * ((f.Hz[c] - f.Hz[c - sj]) - (f.Hy[c] - f.Hy[c - sk]));
+  if (j < N && ii && kk)
+    f.Ey[c] = f.Ey[c] + dt * ((f.Hx[c] - f.Hx[c - sk]) - (f.Hz[c] - f.Hz[c - 1]));
+  if (k < N && ii && jj)
+    f.Ez[c] = f.Ez[c] + dt * ((f.Hy[c] - f.Hy[c - 1]) - (f.Hx[c] - f.Hx[c - sj]));
+}
+
+static dim3 fdtd_grid(int N) { return dim3((unsigned)((N + 1 + 63) / 64), (unsigned)((N + 1 + 3) / 4), (unsigned)(N + 1)); }
+
+void make_fdtd_h(Launch &L, const FdtdArgs &a) { L.set((const void *)fdtd_h_kernel, fdtd_grid(a.N), dim3(64, 4), 0, a); }
+void make_fdtd_e(Launch &L, const FdtdArgs &a) { L.set((const void *)fdtd_e_kernel, fdtd_grid(a.N), dim3(64, 4), 0, a); }
+
+// Soft source (the third kernel of a step): reads the device step counter n,
+// adds g[n] to Ez at the source node, records the probe, increments n.  The
+// counter lives on the device so a replayed graph sees the absolute step.
+__global__ void fdtd_src_kernel(const SrcArgs s) {
+  if (threadIdx.x != 0) return;
+  const long long n = *s.step;
+  float v = s.Ez[s.src];
+  if (n >= 0 && n < s.glen) {
+    v = v + s.g[n];
+    s.Ez[s.src] = v;
+  }
+  if (n >= 0 && n < s.pcap) s.probe[n] = v;
+  *s.step = n + 1;
+}
+
+void make_fdtd_src(Launch &L, const SrcArgs &a) { L.set((const void *)fdtd_src_kernel, dim3(1), dim3(64), 0, a); }
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions.  Pass 1: block b sums a fixed contiguous chunk
+// (each thread a fixed strided subset, in double), then a fixed wave64
+// butterfly and a fixed cross-wave order; pass 2: one block sums the
+// partials the same way.  The result depends only on n, never on timing.
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 1024;
+int reduce_max_blocks() { return kRedBlocks; }
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double wsum[4];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) wsum[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+  return r;
+}
+
+struct RedArgs {
+  const float *f[6]; int nf; int square; long long n; long long chunk; double *partials;
+};
+
+__global__ __launch_bounds__(256) void reduce_pass1(const RedArgs a) {
+  const long long lo = (long long)blockIdx.x * a.chunk;
+  const long long hi = min(lo + a.chunk, a.n);
+  double acc = 0.0;
+  for (int q = 0; q < a.nf; ++q) {
+    const float *x = a.f[q];
+    for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+      const double v = (double)x[i];
+      acc += a.square ? v * v : v;
+    }
+  }
+  const double r = block_sum(acc);
+  if (threadIdx.x == 0) a.partials[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void reduce_pass2(const double *partials, int nb, double *out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) acc += partials[i];
+  const double r = block_sum(acc);
+  if (threadIdx.x == 0) *out = r;
+}
+
+static hipError_t reduce_impl(const float *const *f, int nf, int square, long long n, double *partials,
+                              double *result, hipStream_t s) {
+  long long chunk = (n + kRedBlocks - 1) / kRedBlocks;
+  chunk = ((chunk + 1023) / 1024) * 1024;
+  if (chunk < 1024) chunk = 1024;
+  const int nb = n > 0 ? (int)((n + chunk - 1) / chunk) : 1;
+  RedArgs a{};
+  for (int q = 0; q < nf && q < 6; ++q) a.f[q] = f[q];
+  a.nf = nf; a.square = square; a.n = n; a.chunk = chunk; a.partials = partials;
+  hipLaunchKernelGGL(reduce_pass1, dim3(nb), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(256), 0, s, (const double *)partials, nb, result);
+  return hipGetLastError();
+}
+
+hipError_t reduce_sum(const float *x, long long n, double *partials, double *result, hipStream_t s) {
+  const float *f[1] = {x};
+  return reduce_impl(f, 1, 0, n, partials, result, s);
+}
+
+hipError_t reduce_sumsq(const float *const *fields, int nf, long long n, double *partials, double *result,
+                        hipStream_t s) {
+  return reduce_impl(fields, nf, 1, n, partials, result, s);
+}
+
+}  // namespace kb

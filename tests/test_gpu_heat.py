@@ -1,0 +1,257 @@
+"""GPU parity of the thermal stencils through the C ABI.
+
+Bars: the seeded initial state is bit-identical to the generator; the float32
+GPU result is within 1e-5 relative max-norm of the float32 oracle; every
+graph-batched run (any b, either builder, with peeling) and every kernel
+variant (direct, LDS tile, temporal depth t) is bit-identical to the direct
+per-launch run; the error against the float64 oracle is reported.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, need_gpu, rel_maxnorm
+
+pytestmark = pytest.mark.gpu
+
+HEAT = dict(c=1e-3, Rx=1.0, Ry=1.0, Rz=10.0, Tamb=300.0)
+HEAT_ANISO = dict(c=1e-3, Rx=1.0, Ry=2.0, Rz=10.0, Tamb=300.0)
+
+
+def coeffs(d):
+    return (d["c"], d["Rx"], d["Ry"], d["Rz"], d["Tamb"])
+
+
+@pytest.fixture(scope="module")
+def kb():
+    need_gpu()
+    import paper_2501_09398_amd as kb
+    kb.lib()
+    return kb
+
+
+def run_heat2d(kb, shape, steps, b=0, seed=0, c=HEAT, tile=0, tdepth=1, builder=0):
+    with kb.Problem(kb.HEAT2D, shape, coeffs(c), seed) as p:
+        if tile:
+            p.set_option(kb.OPT_TILE, tile)
+            p.set_option(kb.OPT_TDEPTH, tdepth)
+        p.set_option(kb.OPT_BUILDER, builder)
+        rc = p.run(steps, b)
+        assert rc == 0
+        return p.read(kb.F_T)
+
+
+def test_heat2d_initial_state_matches_generator(kb):
+    announce("heat2d init 37x70 seed 3")
+    with kb.Problem(kb.HEAT2D, (37, 70), coeffs(HEAT), 3) as p:
+        T0, P = synth.heat2d_init(3, 37, 70)
+        assert np.array_equal(p.read(kb.F_T), T0)
+        assert np.array_equal(p.read(kb.F_P), P)
+
+
+@pytest.mark.parametrize("shape,steps,c", [((64, 80), 50, HEAT), ((37, 130), 33, HEAT_ANISO),
+                                           ((256, 256), 200, HEAT), ((1, 5), 20, HEAT), ((7, 1), 20, HEAT)])
+def test_heat2d_vs_oracle(kb, shape, steps, c):
+    announce(f"heat2d oracle {shape} steps {steps}")
+    T0, P = synth.heat2d_init(1, *shape)
+    got = run_heat2d(kb, shape, steps, seed=1, c=c)
+    ref32 = oracle.heat2d(T0, P, steps, dtype=np.float32, **c)
+    ref64 = oracle.heat2d(T0, P, steps, **c)
+    assert rel_maxnorm(got, ref32) < 1e-5
+    err64 = rel_maxnorm(got, ref64)
+    print(f"heat2d {shape} x{steps}: rel err vs float64 oracle {err64:.3e}, vs float32 {rel_maxnorm(got, ref32):.3e}")
+
+
+def test_heat2d_full_size_workload(kb):
+    # 256x256, 1000 steps, graph batches of 100 (the configuration the
+    # benchmark times) against the float32 and float64 oracles.
+    announce("heat2d 256x256 1000 steps b=100")
+    T0, P = synth.heat2d_init(20250116, 256, 256)
+    got = run_heat2d(kb, (256, 256), 1000, b=100, seed=20250116)
+    ref32 = oracle.heat2d(T0, P, 1000, dtype=np.float32)
+    ref64 = oracle.heat2d(T0, P, 1000)
+    assert rel_maxnorm(got, ref32) < 1e-5
+    print(f"heat2d 256^2 x1000: vs f32 {rel_maxnorm(got, ref32):.3e} vs f64 {rel_maxnorm(got, ref64):.3e}")
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 7, 10, 100])
+@pytest.mark.parametrize("builder", [0, 1])
+def test_heat2d_graph_bitwise_equals_per_launch(kb, b, builder):
+    announce(f"heat2d graph b={b} builder={builder}")
+    shape, steps = (61, 150), 101
+    base = run_heat2d(kb, shape, steps, b=0, seed=2)
+    got = run_heat2d(kb, shape, steps, b=b, seed=2, builder=builder)
+    assert np.array_equal(base, got)
+
+
+def test_heat2d_split_runs_and_cache(kb):
+    announce("heat2d split runs")
+    shape = (50, 70)
+    whole = run_heat2d(kb, shape, 90, b=0, seed=4)
+    with kb.Problem(kb.HEAT2D, shape, coeffs(HEAT), 4) as p:
+        for n, b in [(13, 5), (30, 5), (7, 0), (40, 3)]:
+            p.run(n, b)
+        t = p.last_timing()
+        assert t["n_graphs_built"] == 0 or t["n_graphs_built"] <= 2
+        assert np.array_equal(p.read(kb.F_T), whole)
+
+
+def test_heat2d_write_resume(kb):
+    announce("heat2d write/resume")
+    shape = (40, 40)
+    whole = run_heat2d(kb, shape, 60, b=6, seed=5)
+    with kb.Problem(kb.HEAT2D, shape, coeffs(HEAT), 5) as p:
+        p.run(25, 5)
+        state = p.read(kb.F_T)
+    with kb.Problem(kb.HEAT2D, shape, coeffs(HEAT), 999) as q:
+        q.write(kb.F_T, state)
+        q.write(kb.F_P, synth.heat2d_init(5, *shape)[1])
+        q.run(35, 7)
+        assert np.array_equal(q.read(kb.F_T), whole)
+
+
+@pytest.mark.parametrize("tile", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tdepth", [1, 2, 5, 16])
+def test_heat2d_tile_variants_bitwise(kb, tile, tdepth):
+    announce(f"heat2d tile {tile} t={tdepth}")
+    shape, steps = (70, 133), 37
+    base = run_heat2d(kb, shape, steps, seed=6)
+    got = run_heat2d(kb, shape, steps, seed=6, tile=tile, tdepth=tdepth)
+    assert np.array_equal(base, got)
+    got_g = run_heat2d(kb, shape, steps, b=2, seed=6, tile=tile, tdepth=tdepth)
+    assert np.array_equal(base, got_g)
+
+
+def test_heat2d_tiny_grids_temporal(kb):
+    for shape in [(1, 1), (2, 3), (5, 1), (3, 200)]:
+        announce(f"heat2d tiny {shape}")
+        base = run_heat2d(kb, shape, 20, seed=7)
+        got = run_heat2d(kb, shape, 20, seed=7, tile=3, tdepth=8)
+        assert np.array_equal(base, got)
+        T0, P = synth.heat2d_init(7, *shape)
+        assert rel_maxnorm(got, oracle.heat2d(T0, P, 20, dtype=np.float32)) < 1e-5
+
+
+def test_heat2d_zero_steps_and_errors(kb):
+    with kb.Problem(kb.HEAT2D, (16, 16), coeffs(HEAT), 8) as p:
+        T0 = p.read(kb.F_T)
+        p.run(0, 0)
+        p.run(0, 5)
+        assert np.array_equal(p.read(kb.F_T), T0)
+        with pytest.raises(kb.KBError):
+            p.run(-1, 0)
+        with pytest.raises(kb.KBError):
+            p.run(10, -2)
+        p.set_option(kb.OPT_MAX_NODES, 10)
+        with pytest.raises(kb.KBError):
+            p.run(100, 11)
+        with pytest.raises(kb.KBError):
+            p.set_option(kb.OPT_TDEPTH, 17)
+        with pytest.raises(kb.KBError):
+            p.set_option(kb.OPT_TILE, 9)
+    with pytest.raises(kb.KBError):
+        kb.Problem(kb.HEAT2D, (16, 16), (0.3, 1.0, 1.0, 10.0, 300.0), 0)   # c*(2+2+0.1) >= 1
+
+
+def test_heat2d_reduce_mean(kb):
+    announce("heat2d reduce")
+    with kb.Problem(kb.HEAT2D, (300, 200), coeffs(HEAT), 9) as p:
+        p.run(100, 10)
+        T = p.read(kb.F_T).astype(np.float64)
+        s1 = p.reduce()[0]
+        s2 = p.reduce()[0]
+        assert s1 == s2
+        exact = float(np.sum(T))
+        assert abs(s1 - exact) <= T.size * 2.0 ** -50 * np.sum(np.abs(T))
+
+
+# ---- 3D ----------------------------------------------------------------------
+
+def run_heat3d(kb, shape, steps, b=0, seed=0, builder=0):
+    with kb.Problem(kb.HEAT3D, shape, coeffs(HEAT), seed) as p:
+        p.set_option(kb.OPT_BUILDER, builder)
+        p.run(steps, b)
+        return p.read(kb.F_T)
+
+
+def test_heat3d_initial_state(kb):
+    with kb.Problem(kb.HEAT3D, (3, 20, 70), coeffs(HEAT), 11) as p:
+        T0, P = synth.heat3d_init(11, 3, 20, 70)
+        assert np.array_equal(p.read(kb.F_T), T0)
+        assert np.array_equal(p.read(kb.F_P), P)
+
+
+@pytest.mark.parametrize("shape,steps", [((3, 20, 70), 40), ((8, 64, 64), 100), ((1, 9, 9), 10), ((2, 1, 1), 5)])
+def test_heat3d_vs_oracle(kb, shape, steps):
+    announce(f"heat3d oracle {shape} x{steps}")
+    T0, P = synth.heat3d_init(12, *shape)
+    got = run_heat3d(kb, shape, steps, seed=12)
+    ref32 = oracle.heat3d(T0, P, steps, dtype=np.float32)
+    ref64 = oracle.heat3d(T0, P, steps)
+    assert rel_maxnorm(got, ref32) < 1e-5
+    print(f"heat3d {shape}: vs f64 {rel_maxnorm(got, ref64):.3e}")
+
+
+@pytest.mark.parametrize("b", [1, 4, 9])
+def test_heat3d_graph_bitwise(kb, b):
+    announce(f"heat3d graph b={b}")
+    base = run_heat3d(kb, (4, 33, 90), 50, seed=13)
+    for builder in (0, 1):
+        assert np.array_equal(base, run_heat3d(kb, (4, 33, 90), 50, b=b, seed=13, builder=builder))
+
+
+def test_heat3d_full_size_sampled(kb):
+    # 512x512x8 at the benchmark's launch configuration: 200 steps against
+    # the float32 oracle on the whole field, then the mean closed form after
+    # 2000 steps (the clamped Laplacian sums to zero).
+    announce("heat3d 8x512x512")
+    shape = (8, 512, 512)
+    T0, P = synth.heat3d_init(20250116, *shape)
+    got = run_heat3d(kb, shape, 200, b=100, seed=20250116)
+    ref32 = oracle.heat3d(T0, P, 200, dtype=np.float32)
+    assert rel_maxnorm(got, ref32) < 1e-5
+    with kb.Problem(kb.HEAT3D, shape, coeffs(HEAT), 20250116) as p:
+        p.run(2000, 100)
+        mean = p.reduce()[0] / T0.size
+    m0 = np.mean(T0.astype(np.float64))
+    pbar = np.sum(P.astype(np.float64)) / T0.size
+    ref = 300 + pbar * 10 + (m0 - 300 - pbar * 10) * (1 - 1e-4) ** 2000
+    assert abs(mean - ref) / ref < 1e-5
+
+
+# ---- many grids ------------------------------------------------------------
+
+def test_multigrid_matches_single_grids(kb):
+    announce("multigrid 6 grids")
+    sides = [(17, 70), (64, 64), (5, 130), (100, 33), (1, 1), (40, 250)]
+    shape = [len(sides)] + [v for s in sides for v in s]
+    with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 14) as p:
+        p.run(30, 7)
+        allT = p.read(kb.F_T)
+    T0 = synth.uniform_f32(14, synth.TAG_T0, allT.size, *synth.T0_RANGE)
+    P = synth.uniform_f32(14, synth.TAG_P, allT.size, *synth.P_RANGE)
+    off = 0
+    for ny, nx in sides:
+        n = ny * nx
+        ref = oracle.heat2d(T0[off:off + n].reshape(ny, nx), P[off:off + n].reshape(ny, nx), 30, dtype=np.float32)
+        got = allT[off:off + n].reshape(ny, nx)
+        assert rel_maxnorm(got, ref) < 1e-5
+        # bit-identical to a single-grid run of the same data
+        with kb.Problem(kb.HEAT2D, (ny, nx), coeffs(HEAT), 0) as q:
+            q.write(kb.F_T, T0[off:off + n])
+            q.write(kb.F_P, P[off:off + n])
+            q.run(30, 0)
+            assert np.array_equal(q.read(kb.F_T), got)
+        off += n
+
+
+def test_multigrid_graph_bitwise(kb):
+    sides = synth.multigrid_sides(3, 8, 16, 200)
+    shape = [len(sides)] + [v for s in sides for v in (s, s)]
+    outs = []
+    for b in (0, 1, 5):
+        with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 15) as p:
+            p.run(23, b)
+            outs.append(p.read(kb.F_T))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])

@@ -1,0 +1,201 @@
+"""GPU parity of the skeleton chain and the Yee FDTD solver through the C ABI.
+
+Both are bit-identical to the float32 oracle: the skeleton update is one
+fused multiply-add per kernel on both sides, and every FDTD coefficient is
+0.5, so product and difference round the same way with or without fusion.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, need_gpu, rel_maxnorm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kb():
+    need_gpu()
+    import paper_2501_09398_amd as kb
+    kb.lib()
+    return kb
+
+
+# ---- skeleton -------------------------------------------------------------
+
+def test_skeleton_initial_state(kb):
+    with kb.Problem(kb.SKELETON, (1000,), (4,), 21) as p:
+        x0, a, b = synth.skeleton_init(21, 1000, 4)
+        assert np.array_equal(p.read(kb.F_X), x0)
+        assert np.array_equal(p.read(kb.F_A), a)
+        assert np.array_equal(p.read(kb.F_B), b)
+
+
+@pytest.mark.parametrize("n", [1, 3, 1000, 4099, 1 << 16])
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_skeleton_bitwise_vs_oracle(kb, n, variant):
+    announce(f"skeleton n={n} variant={variant}")
+    iters = 300
+    x0, a, b = synth.skeleton_init(22, n, 4)
+    with kb.Problem(kb.SKELETON, (n,), (4,), 22) as p:
+        p.set_option(kb.OPT_TILE, variant)
+        p.run(iters, 0)
+        got = p.read(kb.F_X)
+    ref = oracle.skeleton(x0, a, b, iters, dtype=np.float32)
+    assert np.array_equal(got, ref)
+    print(f"skeleton n={n}: vs f64 {rel_maxnorm(got, oracle.skeleton(x0, a, b, iters)):.3e}")
+
+
+@pytest.mark.parametrize("b", [1, 3, 50, 2000])
+@pytest.mark.parametrize("builder", [0, 1])
+def test_skeleton_graph_bitwise(kb, b, builder):
+    announce(f"skeleton graph b={b} builder={builder}")
+    n, iters = 4096, 2503
+    outs = []
+    for bb in (0, b):
+        with kb.Problem(kb.SKELETON, (n,), (4,), 23) as p:
+            p.set_option(kb.OPT_BUILDER, builder)
+            p.run(iters, bb)
+            outs.append(p.read(kb.F_X))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_skeleton_full_size_workload(kb):
+    # 2^16 elements, K = 4, 10,000 iterations, graph batches of 100.
+    announce("skeleton 2^16 x 10000 b=100")
+    n, iters = 1 << 16, 10000
+    x0, a, b = synth.skeleton_init(20250116, n, 4)
+    with kb.Problem(kb.SKELETON, (n,), (4,), 20250116) as p:
+        p.run(iters, 100)
+        got = p.read(kb.F_X)
+        t = p.last_timing()
+        assert t["n_graph_launches"] == 100 and t["n_nodes"] == 400
+    assert np.array_equal(got, oracle.skeleton(x0, a, b, iters, dtype=np.float32))
+
+
+def test_skeleton_explicit_coefficients_and_write(kb):
+    with kb.Problem(kb.SKELETON, (64,), (2, 0.5, 0.5, 0.0, 0.0), 24) as p:
+        x0 = p.read(kb.F_X)
+        p.run(3, 2)
+        assert np.array_equal(p.read(kb.F_X), x0 * np.float32(2.0 ** -6))
+        p.write(kb.F_A, np.array([1.0, 1.0], np.float32))
+        p.write(kb.F_B, np.array([0.25, -0.25], np.float32))
+        before = p.read(kb.F_X)
+        p.run(10, 4)           # graph cache was invalidated by the write
+        ref = oracle.skeleton(before, np.array([1, 1], np.float32), np.array([0.25, -0.25], np.float32), 10,
+                              dtype=np.float32)
+        assert np.array_equal(p.read(kb.F_X), ref)
+
+
+def test_skeleton_reduce(kb):
+    with kb.Problem(kb.SKELETON, (100003,), (4,), 25) as p:
+        p.run(10, 5)
+        x = p.read(kb.F_X).astype(np.float64)
+        s = p.reduce()[0]
+        assert abs(s - np.sum(x)) <= x.size * 2.0 ** -50 * np.sum(np.abs(x))
+
+
+# ---- FDTD -----------------------------------------------------------------
+
+def gpu_fields(kb, p):
+    return {k: p.read(f) for k, f in kb.FDTD_FIELDS.items()}
+
+
+def test_fdtd_source_cell_from_seed(kb):
+    for N in (8, 33):
+        src = synth.fdtd_source_cell(31, N)
+        with kb.Problem(kb.FDTD3D, (N, 64), kb.FDTD_COEFFS, 31) as p:
+            p.run(1, 0)
+            ez = p.read(kb.F_EZ)
+            _, g32 = oracle.fdtd_pulse(1)
+            i, j, k = src
+            assert ez[k, j, i] == g32[0]
+            assert np.count_nonzero(ez) == 1
+
+
+@pytest.mark.parametrize("N,steps", [(8, 150), (17, 120), (32, 300)])
+def test_fdtd_bitwise_vs_oracle(kb, N, steps):
+    announce(f"fdtd N={N} steps={steps}")
+    seed = 32
+    src = synth.fdtd_source_cell(seed, N)
+    _, g32 = oracle.fdtd_pulse(steps + 1)
+    ref, probe_ref = oracle.fdtd(oracle.fdtd_zero_fields(N, np.float32), N, steps, src=src, g=g32,
+                                 dtype=np.float32)
+    with kb.Problem(kb.FDTD3D, (N, 512), kb.FDTD_COEFFS, seed) as p:
+        p.run(steps, 0)
+        got = gpu_fields(kb, p)
+        probe = p.read(kb.F_PROBE)
+        assert p.read(kb.F_STEP)[0] == steps
+    for k in oracle.FDTD_FIELDS:
+        assert np.array_equal(got[k], ref[k]), k
+    assert np.array_equal(probe[:steps], probe_ref)
+    assert np.all(probe[steps:] == 0)
+
+
+@pytest.mark.parametrize("b", [1, 7, 40])
+@pytest.mark.parametrize("builder", [0, 1])
+def test_fdtd_graph_bitwise(kb, b, builder):
+    announce(f"fdtd graph b={b} builder={builder}")
+    N, steps = 20, 203
+    outs = []
+    for bb in (0, b):
+        with kb.Problem(kb.FDTD3D, (N, 256), kb.FDTD_COEFFS, 33) as p:
+            p.set_option(kb.OPT_BUILDER, builder)
+            p.run(steps, bb)
+            outs.append((gpu_fields(kb, p), p.read(kb.F_PROBE), p.read(kb.F_STEP)))
+    for k in oracle.FDTD_FIELDS:
+        assert np.array_equal(outs[0][0][k], outs[1][0][k])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2][0] == outs[1][2][0] == steps
+
+
+def test_fdtd_explicit_source_and_cavity_mode(kb):
+    # No source (width 0); Ez initialised to the lowest TM mode with H = 0:
+    # the amplitude obeys e_{n+1} + e_{n-1} = (2 - dt^2 lam) e_n.
+    announce("fdtd cavity mode N=24")
+    N, dt = 24, 0.5
+    M = N + 1
+    i = np.arange(M)
+    phi = np.sin(np.pi * i[None, :] / N) * np.sin(np.pi * i[:, None] / N)
+    ez = np.zeros((M, M, M), np.float32)
+    ez[:N] = phi[None]
+    with kb.Problem(kb.FDTD3D, (N, 16), (0.5, 0.0, 80.0), 0) as p:
+        p.write(kb.F_EZ, ez)
+        amps = [1.0]
+        for _ in range(60):
+            p.run(1, 0)
+            e = p.read(kb.F_EZ)
+            amps.append(float(e[N // 2, N // 2, N // 2] / phi[N // 2, N // 2]))
+    e = np.array(amps)
+    lam = 8 * np.sin(np.pi / (2 * N)) ** 2
+    assert np.max(np.abs(e[2:] + e[:-2] - (2 - dt * dt * lam) * e[1:-1])) < 1e-5
+
+
+def test_fdtd_energy_reduce(kb):
+    N = 16
+    with kb.Problem(kb.FDTD3D, (N, 64), kb.FDTD_COEFFS, 34) as p:
+        p.run(120, 10)
+        f = gpu_fields(kb, p)
+        e2, h2 = p.reduce()
+    ref_e = sum(np.sum(f[k].astype(np.float64) ** 2) for k in ("Ex", "Ey", "Ez"))
+    ref_h = sum(np.sum(f[k].astype(np.float64) ** 2) for k in ("Hx", "Hy", "Hz"))
+    assert abs(e2 - ref_e) <= 1e-12 * ref_e and abs(h2 - ref_h) <= 1e-12 * ref_h
+
+
+def test_fdtd_full_size_sampled(kb):
+    # 128^3 at the benchmark's launch configuration: 100 steps (source on)
+    # against the float32 oracle, bit for bit.
+    announce("fdtd 128^3 100 steps b=50")
+    N, steps, seed = 128, 100, 20250116
+    src = synth.fdtd_source_cell(seed, N)
+    _, g32 = oracle.fdtd_pulse(steps + 1)
+    ref, probe_ref = oracle.fdtd(oracle.fdtd_zero_fields(N, np.float32), N, steps, src=src, g=g32,
+                                 dtype=np.float32)
+    with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, seed) as p:
+        p.run(steps, 50)
+        got = gpu_fields(kb, p)
+        probe = p.read(kb.F_PROBE)
+    for k in oracle.FDTD_FIELDS:
+        assert np.array_equal(got[k], ref[k]), k
+    assert np.array_equal(probe[:steps], probe_ref)
