@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark: iteration-batched hipGraph replay vs one launch per kernel.
+
+Workload: the skeleton iterative application -- each iteration runs a chain
+of K = 4 small element-wise kernels x <- a_k x + b_k on a 2^16-element
+float32 vector -- for 10,000 iterations (40,000 kernel executions), the
+configuration on which the paper characterises its method (Sec. III-C,
+IV-A/B).  Inputs are synthetic and seeded (x0 ~ U[-1,1), a_k ~ U[0.9,1),
+b_k ~ U[-0.01,0.01)) and are resident on the device before timing starts.
+
+Procedure (Sec. III-C):
+  1. sweep the iteration batch b over the divisors of 10,000 up to 2,000,
+     measuring graph creation T_C (build + instantiate + upload) and
+     execution T_E; fit Eq. 2 and Eq. 6 and take the b minimising Eq. 1;
+  2. warm up, then time `--steps` whole jobs at that b, each job paying its
+     own graph creation (T = T_C + T_E, Eq. 1);
+  3. time the same jobs launching every kernel separately (the baseline);
+  4. time the dominant kernel's device duration with per-dispatch events;
+  5. time the CPU oracle on a bounded sample of the same job.
+One JSON line is printed.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_ELEM = 1 << 16
+K = 4
+ITERS = 10000
+SEED = 20250116
+HBM_PEAK_GBS = 8000.0
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "skeleton_2p16_hbm_counters.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "kernels_misc.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed jobs (each 10,000 iterations)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--b", type=int, default=0, help="fix the batch size instead of fitting it")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the b sweep (requires --b)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--sweep-reps", type=int, default=3, help="repeats per b in the model sweep (median)")
+    ap.add_argument("--arm", choices=("both", "graph", "per_launch"), default="both",
+                    help="'graph' skips the per-launch baseline; 'per_launch' times only the baseline "
+                         "(both for profiling one arm alone)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy of known size (2^26 floats read and written by the "
+                         "element-wise kernel with a=1, b=0), to scale hardware byte counters")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    """Three launches of the element-wise kernel as a plain copy: 256 MiB
+    read and 256 MiB written per launch."""
+    import torch
+    import paper_2501_09398_amd as kb
+    n = 1 << 26
+    with kb.Problem(kb.SKELETON, (n,), (1, 1.0, 0.0), 0, device=0) as p:
+        p.run(3, 0)
+        p.last_timing()
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"elements": n, "bytes_read": 4 * n, "bytes_written": 4 * n,
+                                           "launches": 3}}), flush=True)
+
+
+def skeleton_kernel_hash():
+    """Hash of the skeleton kernel's source text, to tell whether stored
+    hardware counters still describe the current kernel."""
+    import hashlib
+    src = open(KERNEL_SOURCE).read()
+    a = src.index("template <int VEC>")
+    b = src.index("void make_skeleton")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def stored_traffic():
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    try:
+        d = json.load(open(COUNTERS_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != skeleton_kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU decomposition is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_2501_09398_amd as kb
+    from paper_2501_09398_amd import perfmodel as pm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    kb.lib()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    prob = kb.Problem(kb.SKELETON, (N_ELEM,), (K,), SEED, device=0)
+    prob.set_option(kb.OPT_GRAPH_CACHE, 0)       # every job pays its own T_C
+    elem_updates = N_ELEM * K * ITERS
+
+    def job(b):
+        prob.run(ITERS, b)
+        t = prob.last_timing()       # synchronises
+        return t
+
+    # 1. sweep b, fit Eqs. 2 and 6 -----------------------------------------
+    cands = pm.divisors(ITERS, 1, 2000)
+    sweep = []
+    model = None
+    if not args.no_sweep and args.arm != "per_launch":
+        job(100)
+        for b in cands:
+            reps = [job(b) for _ in range(args.sweep_reps)]
+            sweep.append((b, float(np.median([t["t_create_s"] for t in reps])),
+                          float(np.median([t["t_exec_s"] for t in reps]))))
+        S = np.array([s[0] for s in sweep], float)
+        model = pm.Model(pm.fit_creation(K * S, [s[1] for s in sweep]),
+                         pm.fit_execution(S, [s[2] for s in sweep]), K=K)
+        b_model, _ = model.best(cands)
+        measured_total = {s[0]: s[1] + s[2] for s in sweep}
+        b_measured = min(measured_total, key=measured_total.get)
+    b_star = args.b if args.b > 0 else (b_model if model else 100)
+    if args.arm == "per_launch":
+        b_star = 0
+
+    # 2. warm-up and timed graph jobs --------------------------------------
+    for _ in range(args.warmup):
+        job(b_star)
+    torch.cuda.synchronize()
+    graph_T, graph_TC, graph_TE = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        t = job(b_star)
+        graph_T.append(time.perf_counter() - s0)
+        graph_TC.append(t["t_create_s"])
+        graph_TE.append(t["t_exec_s"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = elem_updates * args.steps / wall / 1e9
+
+    # 3. baseline: one launch per kernel ------------------------------------
+    base_T, base_TE = [], []
+    if args.arm == "both":
+        for _ in range(max(1, args.warmup)):
+            job(0)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            s0 = time.perf_counter()
+            t = job(0)
+            base_T.append(time.perf_counter() - s0)
+            base_TE.append(t["t_exec_s"])
+        torch.cuda.synchronize()
+        sp, sp_err = pm.speedup(base_T, graph_T)
+    else:
+        sp = sp_err = None
+
+    # 4. dominant kernel: mean duration per launch over the timed replays,
+    # from the HIP events that bracket each job's launches on its stream.
+    n_launch = K * ITERS
+    kern_s = float(np.mean(graph_TE)) / n_launch
+    bytes_per_launch = N_ELEM * 8                  # read x, write x
+    achieved = bytes_per_launch / kern_s / 1e9
+    prob.destroy()
+
+    # 5. CPU oracle on a bounded sample --------------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        import synth
+        x0, a, b = synth.skeleton_init(SEED, N_ELEM, K)
+        s0 = time.perf_counter()
+        oracle.skeleton(x0, a, b, 20, dtype=np.float32)
+        probe = max(time.perf_counter() - s0, 1e-6) / 20
+        iters = int(min(ITERS, max(20, args.cpu_seconds / probe)))
+        s0 = time.perf_counter()
+        oracle.skeleton(x0, a, b, iters, dtype=np.float32)
+        dt = time.perf_counter() - s0
+        cpu = {"value": N_ELEM * K * iters / dt / 1e9, "unit": "Gcell-upd/s", "cores": 1, "kind": "oracle",
+               "sample": f"{iters} of the {ITERS} iterations of the same 2^16-element K=4 chain "
+                         f"(float32, single thread, {dt:.1f} s, {platform.processor() or platform.machine()})"}
+
+    us_iter_graph = float(np.mean(graph_T)) / ITERS * 1e6
+    per_launch = None
+    if base_T:
+        per_launch = {"us_per_iter": float(np.mean(base_T)) / ITERS * 1e6,
+                      "us_per_iter_device": float(np.mean(base_TE)) / ITERS * 1e6,
+                      "gcell_upd_s": elem_updates / float(np.mean(base_T)) / 1e9}
+    line = {
+        "metric": "µs/iter & Gcell-upd/s: hipGraph batch-b vs per-launch; % HBM peak",
+        "value": value,
+        "unit": "Gcell-upd/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded SplitMix64: x0~U[-1,1), a_k~U[0.9,1), b_k~U[-0.01,0.01))",
+        "config": {"workload": "skeleton chain: K=4 element-wise kernels x<-a_k*x+b_k on 2^16 float32, "
+                               "10000 iterations per job, graph batch b with loop peeling",
+                   "b": b_star, "elements": N_ELEM, "kernels_per_iter": K, "iterations": ITERS,
+                   "parallelism": "single GPU"},
+        "arms": {
+            "graph": {"b": b_star, "us_per_iter": us_iter_graph,
+                      "us_per_iter_warm": float(np.mean(graph_TE)) / ITERS * 1e6,
+                      "t_create_ms": float(np.mean(graph_TC)) * 1e3,
+                      "gcell_upd_s": elem_updates / float(np.mean(graph_T)) / 1e9},
+            "per_launch": per_launch,
+            "speedup": sp, "speedup_err": sp_err,
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
+                     "kernel": "skeleton_kernel<4>", "kernel_us": kern_s * 1e6,
+                     "bytes_per_launch": bytes_per_launch},
+        "cpu_baseline": cpu,
+    }
+    if model is not None:
+        line["model"] = {"k_c_s_per_node": model.creation.k_c, "b_c_s": model.creation.b_c,
+                         "mae_c_s": model.creation.mae, "a_s": model.execution.a, "b_s": model.execution.b,
+                         "mae_e_s": model.execution.mae, "b_model": b_model,
+                         "b_closed_form": model.s_closed_form(), "b_measured_best": b_measured,
+                         # a = (number of iterations) * (T_a - T_i): the extra
+                         # gap of a graph launch over a node-to-node gap
+                         "T_a_minus_T_i_us": model.execution.a / ITERS * 1e6}
+        line["sweep"] = [[s[0], round(s[1] * 1e3, 4), round(s[2] * 1e3, 4)] for s in sweep]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -209,14 +209,6 @@ int kb_reduce(kb_problem *h, double *out, int nout);
 /* Timing of the last kb_run() (synchronises the stream).                   */
 int kb_last_timing(kb_problem *h, kb_timing *out);
 
-/* Device duration of each of the K kernels of one iteration: runs `reps`
- * iterations per launch (1 <= reps <= 256), each kernel with start/stop
- * events bound to its own dispatch (hipExtLaunchKernel), and writes the
- * mean seconds of kernel k to out[k] (nout >= K).  Advances the state by
- * reps iterations exactly like kb_run(h, reps*t, 0).  Synchronous.
- * Errors: KB_EINVAL, KB_EHIP.                                              */
-int kb_kernel_time(kb_problem *h, int64_t reps, double *out, int nout);
-
 /* Number of kernels per iteration (K) of the problem, or < 0 on error.    */
 int kb_kernels_per_iter(const kb_problem *h);
 

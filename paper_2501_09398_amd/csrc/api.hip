@@ -594,43 +594,6 @@ int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b) {
   return status;
 }
 
-int kb_kernel_time(kb_problem *h, int64_t reps, double *out, int nout) {
-  if (!h || !out) return fail(KB_EINVAL, "null argument");
-  if (reps < 1 || reps > 256) return fail(KB_EINVAL, "reps must be 1..256");
-  if (nout < h->K) return fail(KB_EINVAL, "need room for %d kernels", h->K);
-  const int depth = iter_depth(h);
-  const size_t nev = (size_t)reps * h->K * 2;
-  while (h->kt_events.size() < nev) {
-    hipEvent_t e = nullptr;
-    HIPCHK(hipEventCreate(&e));
-    h->kt_events.push_back(e);
-  }
-  Launch L[kMaxK];
-  size_t q = 0;
-  for (int64_t r = 0; r < reps; ++r) {
-    const int k = fill_iter(h, h->cur, depth, L);
-    if (k < 0) return fail(KB_EINVAL, "invalid kernel variant");
-    for (int j = 0; j < k; ++j, q += 2) {
-      HIPCHK(hipExtLaunchKernel(L[j].func, L[j].grid, L[j].block, L[j].params(), L[j].lds, h->stream,
-                                h->kt_events[q], h->kt_events[q + 1], 0));
-    }
-    if (pingpong(h)) h->cur ^= 1;
-  }
-  HIPCHK(hipStreamSynchronize(h->stream));
-  for (int j = 0; j < h->K; ++j) out[j] = 0.0;
-  q = 0;
-  for (int64_t r = 0; r < reps; ++r) {
-    for (int j = 0; j < h->K; ++j, q += 2) {
-      float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, h->kt_events[q], h->kt_events[q + 1]));
-      out[j] += ms * 1e-3;
-    }
-  }
-  for (int j = 0; j < h->K; ++j) out[j] /= (double)reps;
-  h->host_steps += reps * depth;
-  return KB_OK;
-}
-
 int kb_last_timing(kb_problem *h, kb_timing *out) {
   if (!h || !out) return fail(KB_EINVAL, "null argument");
   if (!h->timed) return fail(KB_ESTATE, "no kb_run yet");
@@ -713,7 +676,6 @@ int kb_destroy(kb_problem *h) {
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
-  for (hipEvent_t e : h->kt_events) (void)hipEventDestroy(e);
   delete h;
   return rc;
 }

@@ -198,7 +198,6 @@ struct kb_problem {
   // graphs: key (b, tdepth, tile, cur) -> exec graph
   std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> cache_map;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  std::vector<hipEvent_t> kt_events;   // kb_kernel_time start/stop pairs
   kb_timing last{};
   bool timed = false;
   int64_t host_steps = 0;
