@@ -120,9 +120,19 @@ extern "C" {
  *   0 = explicit kernel nodes (hipGraphAddKernelNode chain, Listing 3)
  *   1 = stream capture of the per-launch loop (Sec. II)                   */
 #define KB_OPT_BUILDER   1
-/* KB_OPT_TILE: kernel variant of the stencil problems (0 = library default).
- *   KB_HEAT2D/KB_HEAT2D_MULTI: 1 = direct (one thread per cell, 64x4
- *   blocks), 2 = LDS halo tile.                                          */
+/* KB_OPT_TILE: kernel variant (0 = default for the shape).  Every variant
+ * of a problem produces the same bits.
+ *   KB_HEAT2D: 1 = one thread per cell (64x4 blocks);
+ *              2..7 = LDS halo tile with temporal blocking (KB_OPT_TDEPTH),
+ *                     tiles 64x4, 64x8, 64x16, 32x8, 16x16, 32x4;
+ *              8..12 = float4 rows, a wave walking 1, 2, 4, 8, 16 rows;
+ *              13, 14 = 1 and 2 rows with streaming (non-temporal) stores
+ *                     (8..14 need nx % 4 == 0).
+ *              Default: 13 if nx % 4 == 0, else 1.
+ *   KB_HEAT3D: 1 = one thread per column; float4 rows (nx % 4 == 0):
+ *              2 = plain, 3 = next layer prefetched, 4 = prefetched with
+ *              streaming stores.  Default: 4 if nx % 4 == 0, else 1.
+ *   KB_SKELETON: 1 = 4 elements per thread (default), 2 = 1, 3 = 8.     */
 #define KB_OPT_TILE      2
 /* KB_OPT_TDEPTH: temporal-blocking depth t >= 1 for KB_HEAT2D: one launch
  *   of the LDS tile kernel advances t steps (1 <= t <= 16).                */

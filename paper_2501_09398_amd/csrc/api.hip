@@ -130,11 +130,21 @@ bool pingpong(const kb_problem *h) {
   return h->kind == KB_HEAT2D || h->kind == KB_HEAT3D || h->kind == KB_HEAT2D_MULTI;
 }
 
-int heat2d_variant(const kb_problem *h) { return h->tile == 0 ? 1 : h->tile; }
+// Kernel variant in use: the option, or the default for the shape (vector
+// rows when every row is 16-byte aligned, else one thread per cell).
+int heat2d_variant(const kb_problem *h) {
+  if (h->tile != 0) return h->tile;
+  return h->nx % 4 == 0 ? 13 : 1;
+}
+int heat3d_variant(const kb_problem *h) {
+  if (h->tile != 0) return h->tile;
+  return h->nx % 4 == 0 ? 4 : 1;
+}
+bool heat2d_is_tile(int v) { return v >= 2 && v <= 7; }
 
 // Temporal depth of one iteration.
 int iter_depth(const kb_problem *h) {
-  return (h->kind == KB_HEAT2D && heat2d_variant(h) >= 2) ? h->tdepth : 1;
+  return (h->kind == KB_HEAT2D && heat2d_is_tile(heat2d_variant(h))) ? h->tdepth : 1;
 }
 
 // Fill the K launch descriptors of one iteration that starts from buffer
@@ -144,17 +154,16 @@ int fill_iter(const kb_problem *h, int cur, int depth, Launch *L) {
     case KB_HEAT2D: {
       Heat2DArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, (int)h->ny, (int)h->nx, h->hk, depth};
       const int v = heat2d_variant(h);
-      if (v == 1 || (depth == 1 && h->tile == 0)) {
+      if (v == 1) {
         make_heat2d_direct(L[0], a);
         return 1;
       }
-      if (!make_heat2d_tile(L[0], a, v)) return -1;
-      return 1;
+      if (heat2d_is_tile(v)) return make_heat2d_tile(L[0], a, v) ? 1 : -1;
+      return make_heat2d_vec(L[0], a, v) ? 1 : -1;
     }
     case KB_HEAT3D: {
       Heat3DArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, (int)h->nz, (int)h->ny, (int)h->nx, h->hk};
-      make_heat3d(L[0], a);
-      return 1;
+      return make_heat3d(L[0], a, heat3d_variant(h)) ? 1 : -1;
     }
     case KB_HEAT2D_MULTI: {
       MultiArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids_d, h->block_start_d, h->G, h->hk};
@@ -493,7 +502,8 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       break;
     case KB_OPT_TILE: {
       bool ok = false;
-      if (h->kind == KB_HEAT2D) ok = value >= 0 && value <= 7;
+      if (h->kind == KB_HEAT2D) ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0);
+      else if (h->kind == KB_HEAT3D) ok = value == 0 || value == 1 || (value >= 2 && value <= 4 && h->nx % 4 == 0);
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
       else ok = value == 0;
       if (!ok) return fail(KB_EINVAL, "kernel variant %lld not available for this problem", (long long)value);

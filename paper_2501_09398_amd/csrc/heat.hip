@@ -174,6 +174,169 @@ bool make_heat2d_tile(Launch &L, const Heat2DArgs &a, int variant) {
 }
 
 // ---------------------------------------------------------------------------
+// Vector row kernels (rows of nx % 4 == 0 floats, so every row starts on a
+// 16-byte boundary).  A wave64 covers 256 consecutive columns, four per lane
+// as one float4; east/west neighbours come from the adjacent lanes through
+// wave shuffles, and lanes 0 and 63 load the single cell beyond their wave
+// (clamped at the grid edge).  Each wave walks R rows downwards keeping the
+// rows above, at and below the current one in registers, so a row of T is
+// read from memory once per strip plus one halo row at each end.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 load_row4(const float *base, size_t row, size_t nx, int x, bool xin) {
+  return xin ? *reinterpret_cast<const float4 *>(base + row * nx + x) : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// West and east neighbours of a lane's four cells in one row.
+__device__ __forceinline__ void row_neighbours(const float *row, const float4 &c, int x, int nx, int lane,
+                                               float &wv, float &ev) {
+  wv = __shfl_up(c.w, 1, 64);
+  ev = __shfl_down(c.x, 1, 64);
+  if (lane == 0) wv = x > 0 ? row[x - 1] : c.x;
+  if (x + 4 >= nx) ev = c.w;
+  else if (lane == 63) ev = row[x + 4];
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Store a float4 row segment; NT = non-temporal (streaming) store that does
+// not keep the line in cache.
+template <bool NT>
+__device__ __forceinline__ void store_row4(float *__restrict__ dst, const float4 &o) {
+  if constexpr (NT) {
+    f4v v = {o.x, o.y, o.z, o.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(dst));
+  } else {
+    *reinterpret_cast<float4 *>(dst) = o;
+  }
+}
+
+template <int R, bool NT>
+__global__ __launch_bounds__(256) void heat2d_vec_kernel(const Heat2DArgs a) {
+  const int tiles_x = (a.nx + 255) / 256;
+  const int tiles_y = (a.ny + 4 * R - 1) / (4 * R);
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const int lane = threadIdx.x;
+  const int y0 = (lb / tiles_x) * (4 * R) + threadIdx.y * R;
+  if (y0 >= a.ny) return;                       // whole wave
+  const int x = (lb % tiles_x) * 256 + lane * 4;
+  const bool xin = x < a.nx;
+  const size_t nx = (size_t)a.nx;
+  const float *__restrict__ T = a.T;            // T, P and out never alias
+  const float *__restrict__ P = a.P;
+  float *__restrict__ out = a.out;
+  float4 up = load_row4(T, y0 > 0 ? y0 - 1 : 0, nx, x, xin);
+  float4 cur = load_row4(T, y0, nx, x, xin);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int y = y0 + r;
+    if (y >= a.ny) break;
+    const float4 dn = load_row4(T, y + 1 < a.ny ? y + 1 : a.ny - 1, nx, x, xin);
+    const float4 p = load_row4(P, y, nx, x, xin);
+    float wv, ev;
+    row_neighbours(T + (size_t)y * nx, cur, x, a.nx, lane, wv, ev);
+    float4 o;
+    o.x = heat_update(cur.x, up.x, dn.x, wv, cur.y, p.x, a.k);
+    o.y = heat_update(cur.y, up.y, dn.y, cur.x, cur.z, p.y, a.k);
+    o.z = heat_update(cur.z, up.z, dn.z, cur.y, cur.w, p.z, a.k);
+    o.w = heat_update(cur.w, up.w, dn.w, cur.z, ev, p.w, a.k);
+    if (xin) store_row4<NT>(out + (size_t)y * nx + x, o);
+    up = cur;
+    cur = dn;
+  }
+}
+
+template <int R, bool NT>
+static void set_vec(Launch &L, const Heat2DArgs &a) {
+  int nb = ((a.nx + 255) / 256) * ((a.ny + 4 * R - 1) / (4 * R));
+  L.set((const void *)heat2d_vec_kernel<R, NT>, dim3(xcd_padded_grid(nb)), dim3(64, 4), 0, a);
+}
+
+// variant: 8 = 1 row per wave, 9 = 2, 10 = 4, 11 = 8, 12 = 16;
+//          13 = 1 row per wave with non-temporal stores, 14 = 2 rows, ditto
+bool make_heat2d_vec(Launch &L, const Heat2DArgs &a, int variant) {
+  if (a.nx % 4 != 0) return false;
+  switch (variant) {
+    case 8: set_vec<1, false>(L, a); return true;
+    case 9: set_vec<2, false>(L, a); return true;
+    case 10: set_vec<4, false>(L, a); return true;
+    case 11: set_vec<8, false>(L, a); return true;
+    case 12: set_vec<16, false>(L, a); return true;
+    case 13: set_vec<1, true>(L, a); return true;
+    case 14: set_vec<2, true>(L, a); return true;
+    default: return false;
+  }
+}
+
+// 3D vector kernel: a wave covers 256 columns of one row and marches up the
+// layers with the layers below, at and above in registers; the rows y-1 and
+// y+1 of the current layer are read (they are the rows of the neighbouring
+// waves, so they come from cache).  PF: the loads of layer z+1 are issued
+// before layer z is computed and stored (software pipelining), so every
+// wave keeps the next layer's three rows in flight.  NT: streaming stores.
+template <bool PF, bool NT>
+__global__ __launch_bounds__(256) void heat3d_vec_kernel(const Heat3DArgs a) {
+  const int tiles_x = (a.nx + 255) / 256;
+  const int tiles_y = (a.ny + 3) / 4;
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const int lane = threadIdx.x;
+  const int y = (lb / tiles_x) * 4 + threadIdx.y;
+  if (y >= a.ny) return;
+  const int x = (lb % tiles_x) * 256 + lane * 4;
+  const bool xin = x < a.nx;
+  const size_t nx = (size_t)a.nx;
+  const size_t ny = (size_t)a.ny;
+  const size_t yn = y > 0 ? y - 1 : 0, ys = y + 1 < a.ny ? y + 1 : a.ny - 1;
+  const float *__restrict__ T = a.T;            // T, P and out never alias
+  const float *__restrict__ P = a.P;
+  float *__restrict__ out = a.out;
+  float4 td = load_row4(T, y, nx, x, xin);
+  float4 tc = td;
+  // rows of layer 0 (and layer 1 above it) for the first iteration
+  float4 tu = a.nz > 1 ? load_row4(T, ny + y, nx, x, xin) : tc;
+  float4 tn = load_row4(T, yn, nx, x, xin);
+  float4 ts = load_row4(T, ys, nx, x, xin);
+  for (int z = 0; z < a.nz; ++z) {
+    const size_t zr = (size_t)z * ny;            // first row of layer z
+    if constexpr (!PF) {
+      if (z > 0) {
+        tu = z + 1 < a.nz ? load_row4(T, zr + ny + y, nx, x, xin) : tc;
+        tn = load_row4(T, zr + yn, nx, x, xin);
+        ts = load_row4(T, zr + ys, nx, x, xin);
+      }
+    }
+    float4 tu2 = tu, tn2 = tn, ts2 = ts;         // rows for layer z+1
+    if constexpr (PF) {
+      if (z + 1 < a.nz) {
+        tu2 = z + 2 < a.nz ? load_row4(T, zr + 2 * ny + y, nx, x, xin) : tu;
+        tn2 = load_row4(T, zr + ny + yn, nx, x, xin);
+        ts2 = load_row4(T, zr + ny + ys, nx, x, xin);
+      }
+    }
+    const bool hp = z == 0;
+    const float4 p = hp ? load_row4(P, y, nx, x, xin) : make_float4(0.f, 0.f, 0.f, 0.f);
+    float wv, ev;
+    row_neighbours(T + (zr + y) * nx, tc, x, a.nx, lane, wv, ev);
+    float4 o;
+    o.x = heat3d_update(tc.x, tn.x, ts.x, wv, tc.y, tu.x, td.x, p.x, hp, a.k);
+    o.y = heat3d_update(tc.y, tn.y, ts.y, tc.x, tc.z, tu.y, td.y, p.y, hp, a.k);
+    o.z = heat3d_update(tc.z, tn.z, ts.z, tc.y, tc.w, tu.z, td.z, p.z, hp, a.k);
+    o.w = heat3d_update(tc.w, tn.w, ts.w, tc.z, ev, tu.w, td.w, p.w, hp, a.k);
+    if (xin) store_row4<NT>(out + (zr + y) * nx + x, o);
+    td = tc;
+    tc = tu;
+    if constexpr (PF) {
+      tu = tu2;
+      tn = tn2;
+      ts = ts2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 3D kernel: one thread per (x, y) column, marching up the layers with the
 // column's three consecutive layers in registers.  P is the plane of layer 0.
 // ---------------------------------------------------------------------------
@@ -209,9 +372,22 @@ __global__ __launch_bounds__(256) void heat3d_kernel(const Heat3DArgs a) {
   }
 }
 
-void make_heat3d(Launch &L, const Heat3DArgs &a) {
+// variant: 1 = scalar columns; vector rows (nx % 4 == 0): 2 = plain,
+// 3 = next layer prefetched, 4 = prefetched with streaming stores
+bool make_heat3d(Launch &L, const Heat3DArgs &a, int variant) {
+  if (variant >= 2 && variant <= 4) {
+    if (a.nx % 4 != 0) return false;
+    int nb = ((a.nx + 255) / 256) * ((a.ny + 3) / 4);
+    const void *f = variant == 2 ? (const void *)heat3d_vec_kernel<false, false>
+                  : variant == 3 ? (const void *)heat3d_vec_kernel<true, false>
+                                 : (const void *)heat3d_vec_kernel<true, true>;
+    L.set(f, dim3(xcd_padded_grid(nb)), dim3(64, 4), 0, a);
+    return true;
+  }
+  if (variant != 1) return false;
   int nb = ((a.nx + kDX - 1) / kDX) * ((a.ny + kDY - 1) / kDY);
   L.set((const void *)heat3d_kernel, dim3(xcd_padded_grid(nb)), dim3(kDX, kDY), 0, a);
+  return true;
 }
 
 // ---------------------------------------------------------------------------

@@ -123,7 +123,8 @@ void make_init(Launch &L, const InitArgs &a);
 void make_heat2d_direct(Launch &L, const Heat2DArgs &a);
 bool make_heat2d_tile(Launch &L, const Heat2DArgs &a, int variant);   // false: bad variant
 int heat2d_tile_max_depth();
-void make_heat3d(Launch &L, const Heat3DArgs &a);
+bool make_heat3d(Launch &L, const Heat3DArgs &a, int variant);   // false: bad variant
+bool make_heat2d_vec(Launch &L, const Heat2DArgs &a, int variant);  // false: bad variant / nx % 4
 constexpr int kMultiBX = 64, kMultiBY = 4;   // tile of the many-grid kernel
 void make_multi(Launch &L, const MultiArgs &a, int total_blocks);
 void make_skeleton(Launch &L, const SkelArgs &a, int variant);

@@ -123,6 +123,24 @@ def test_heat2d_tile_variants_bitwise(kb, tile, tdepth):
     assert np.array_equal(base, got_g)
 
 
+@pytest.mark.parametrize("shape", [(70, 132), (33, 260), (5, 4), (1, 4), (4, 8), (130, 1024), (9, 516)])
+@pytest.mark.parametrize("tile", [8, 9, 10, 11, 12, 13, 14])
+def test_heat2d_vector_variants_bitwise(kb, shape, tile):
+    announce(f"heat2d vec tile {tile} {shape}")
+    steps = 23
+    base = run_heat2d(kb, shape, steps, seed=16, tile=1)
+    assert np.array_equal(base, run_heat2d(kb, shape, steps, seed=16, tile=tile))
+    assert np.array_equal(base, run_heat2d(kb, shape, steps, b=5, seed=16, tile=tile))
+    T0, P = synth.heat2d_init(16, *shape)
+    assert rel_maxnorm(base, oracle.heat2d(T0, P, steps, dtype=np.float32)) < 1e-5
+
+
+def test_heat2d_vector_variant_needs_aligned_rows(kb):
+    with kb.Problem(kb.HEAT2D, (8, 10), coeffs(HEAT), 0) as p:
+        with pytest.raises(kb.KBError):
+            p.set_option(kb.OPT_TILE, 11)
+
+
 def test_heat2d_tiny_grids_temporal(kb):
     for shape in [(1, 1), (2, 3), (5, 1), (3, 200)]:
         announce(f"heat2d tiny {shape}")
@@ -149,7 +167,7 @@ def test_heat2d_zero_steps_and_errors(kb):
         with pytest.raises(kb.KBError):
             p.set_option(kb.OPT_TDEPTH, 17)
         with pytest.raises(kb.KBError):
-            p.set_option(kb.OPT_TILE, 9)
+            p.set_option(kb.OPT_TILE, 99)
     with pytest.raises(kb.KBError):
         kb.Problem(kb.HEAT2D, (16, 16), (0.3, 1.0, 1.0, 10.0, 300.0), 0)   # c*(2+2+0.1) >= 1
 
@@ -168,9 +186,10 @@ def test_heat2d_reduce_mean(kb):
 
 # ---- 3D ----------------------------------------------------------------------
 
-def run_heat3d(kb, shape, steps, b=0, seed=0, builder=0):
+def run_heat3d(kb, shape, steps, b=0, seed=0, builder=0, tile=0):
     with kb.Problem(kb.HEAT3D, shape, coeffs(HEAT), seed) as p:
         p.set_option(kb.OPT_BUILDER, builder)
+        p.set_option(kb.OPT_TILE, tile)
         p.run(steps, b)
         return p.read(kb.F_T)
 
@@ -191,6 +210,17 @@ def test_heat3d_vs_oracle(kb, shape, steps):
     ref64 = oracle.heat3d(T0, P, steps)
     assert rel_maxnorm(got, ref32) < 1e-5
     print(f"heat3d {shape}: vs f64 {rel_maxnorm(got, ref64):.3e}")
+
+
+@pytest.mark.parametrize("shape", [(3, 20, 72), (8, 64, 64), (2, 5, 4), (1, 3, 260), (5, 33, 516)])
+@pytest.mark.parametrize("tile", [2, 3, 4])
+def test_heat3d_vector_variant_bitwise(kb, shape, tile):
+    announce(f"heat3d vec {tile} {shape}")
+    base = run_heat3d(kb, shape, 17, seed=17, tile=1)
+    assert np.array_equal(base, run_heat3d(kb, shape, 17, seed=17, tile=tile))
+    assert np.array_equal(base, run_heat3d(kb, shape, 17, b=4, seed=17, tile=tile))
+    T0, P = synth.heat3d_init(17, *shape)
+    assert rel_maxnorm(base, oracle.heat3d(T0, P, 17, dtype=np.float32)) < 1e-5
 
 
 @pytest.mark.parametrize("b", [1, 4, 9])
