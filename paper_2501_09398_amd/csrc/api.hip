@@ -65,6 +65,9 @@ struct Layout {
 
 bool heat_shape_ok(int64_t v) { return v >= 1 && v <= (int64_t)1 << 20; }
 
+// FDTD row pitch: N+1 nodes rounded up to a multiple of 4 floats (16 bytes).
+int64_t fdtd_pitch(int64_t N) { return (N + 1 + 3) / 4 * 4; }
+
 // Workspace offsets of every buffer of a problem.  Returns false on a bad
 // shape.  Offsets are written to off[] in the order documented per problem.
 bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off) {
@@ -99,7 +102,7 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
       const int64_t pcap = ndim == 2 ? shape[1] : kDefaultProbe;
       if (pcap < 0 || pcap > ((int64_t)1 << 28)) return false;
       const int64_t M = shape[0] + 1;
-      for (int f = 0; f < 6; ++f) off[5 + f] = L.add(M * M * M * 4);
+      for (int f = 0; f < 6; ++f) off[5 + f] = L.add(M * M * fdtd_pitch(shape[0]) * 4);
       off[11] = L.add(kGCap * 4);
       off[12] = L.add((pcap > 0 ? pcap : 1) * 4);
       off[13] = L.add(8);
@@ -178,9 +181,9 @@ int fill_iter(const kb_problem *h, int cur, int depth, Launch *L) {
       return h->K;
     }
     case KB_FDTD3D: {
-      FdtdArgs f{h->F[0], h->F[1], h->F[2], h->F[3], h->F[4], h->F[5], h->N, h->dt};
-      make_fdtd_h(L[0], f);
-      make_fdtd_e(L[1], f);
+      FdtdArgs f{h->F[0], h->F[1], h->F[2], h->F[3], h->F[4], h->F[5], h->N, h->pitch, h->dt};
+      const int v = h->tile == 0 ? 2 : h->tile;
+      if (!make_fdtd_h(L[0], f, v) || !make_fdtd_e(L[1], f, v)) return -1;
       SrcArgs s{h->F[2], h->src, h->g, h->glen, h->probe, h->pcap, h->step};
       make_fdtd_src(L[2], s);
       return 3;
@@ -273,8 +276,15 @@ int enqueue_init(kb_problem *h, float *dst, long long n, uint64_t seed, uint64_t
   return KB_OK;
 }
 
-bool field_info(const kb_problem *h, int field, float **dev, size_t *bytes, bool *host_vec) {
+// Device location and user-visible size of a field.  *host_vec: the field
+// lives in host memory of the handle.  *rows/*pitch: > 0 for the FDTD fields,
+// whose rows of N+1 floats are stored with a pitch of h->P floats on the
+// device (the caller sees them dense).
+bool field_info(const kb_problem *h, int field, float **dev, size_t *bytes, bool *host_vec, size_t *rows,
+                size_t *pitch) {
   *host_vec = false;
+  *rows = 0;
+  *pitch = 0;
   switch (field) {
     case KB_F_T:
       if (!pingpong(h)) return false;
@@ -295,7 +305,10 @@ bool field_info(const kb_problem *h, int field, float **dev, size_t *bytes, bool
     case KB_F_EX: case KB_F_EY: case KB_F_EZ: case KB_F_HX: case KB_F_HY: case KB_F_HZ: {
       if (h->kind != KB_FDTD3D) return false;
       const int64_t M = h->N + 1;
-      *dev = h->F[field - KB_F_EX]; *bytes = M * M * M * 4; return true;
+      *dev = h->F[field - KB_F_EX]; *bytes = M * M * M * 4;
+      *rows = M * M;
+      *pitch = h->pitch;
+      return true;
     }
     case KB_F_PROBE:
       if (h->kind != KB_FDTD3D) return false;
@@ -443,6 +456,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       if (!(courant > 0) || !(courant < 1.0 / std::sqrt(3.0)))
         return bail(fail(KB_EINVAL, "courant number %g outside (0, 1/sqrt(3))", courant));
       h->N = N;
+      h->pitch = (int)fdtd_pitch(N);
       h->dt = (float)courant;
       h->K = 3;
       for (int f = 0; f < 6; ++f) h->F[f] = P(off[5 + f]);
@@ -462,7 +476,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       }
       h->src_ijk[0] = si; h->src_ijk[1] = sj; h->src_ijk[2] = sk;
       const long long M = N + 1;
-      h->src = ((long long)sk * M + sj) * M + si;
+      h->src = ((long long)sk * M + sj) * h->pitch + si;
       // amplitude table: g(n) = exp(-((n - delay)/width)^2) rounded to float,
       // up to the first step after which every value rounds to zero.
       std::vector<float> gt;
@@ -478,7 +492,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       }
       h->glen = (int)gt.size();
       for (int f = 0; f < 6; ++f)
-        if (hipMemsetAsync(h->F[f], 0, M * M * M * 4, h->stream) != hipSuccess)
+        if (hipMemsetAsync(h->F[f], 0, M * M * h->pitch * 4, h->stream) != hipSuccess)
           return bail(fail(KB_EHIP, "hipMemsetAsync failed"));
       if (hipMemsetAsync(h->probe, 0, (size_t)(h->pcap > 0 ? h->pcap : 1) * 4, h->stream) != hipSuccess ||
           hipMemsetAsync(h->step, 0, 8, h->stream) != hipSuccess)
@@ -505,6 +519,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       if (h->kind == KB_HEAT2D) ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0);
       else if (h->kind == KB_HEAT3D) ok = value == 0 || value == 1 || (value >= 2 && value <= 4 && h->nx % 4 == 0);
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
+      else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 2;
       else ok = value == 0;
       if (!ok) return fail(KB_EINVAL, "kernel variant %lld not available for this problem", (long long)value);
       if (h->tile != value) clear_cache(h);
@@ -618,9 +633,10 @@ int kb_last_timing(kb_problem *h, kb_timing *out) {
 int kb_read(kb_problem *h, int field, void *dst, size_t bytes, int dst_on_device) {
   if (!h || !dst) return fail(KB_EINVAL, "null argument");
   float *dev = nullptr;
-  size_t need = 0;
+  size_t need = 0, rows = 0, pitch = 0;
   bool hv = false;
-  if (!field_info(h, field, &dev, &need, &hv)) return fail(KB_EINVAL, "field %d not available", field);
+  if (!field_info(h, field, &dev, &need, &hv, &rows, &pitch))
+    return fail(KB_EINVAL, "field %d not available", field);
   if (bytes != need) return fail(KB_EINVAL, "field %d has %zu bytes, got %zu", field, need, bytes);
   HIPCHK(hipStreamSynchronize(h->stream));
   if (hv) {
@@ -629,16 +645,23 @@ int kb_read(kb_problem *h, int field, void *dst, size_t bytes, int dst_on_device
     else std::memcpy(dst, v.data(), bytes);
     return KB_OK;
   }
-  HIPCHK(hipMemcpy(dst, dev, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (rows) {
+    const size_t w = bytes / rows;   // dense row bytes
+    HIPCHK(hipMemcpy2D(dst, w, dev, pitch * sizeof(float), w, rows, kind));
+  } else {
+    HIPCHK(hipMemcpy(dst, dev, bytes, kind));
+  }
   return KB_OK;
 }
 
 int kb_write(kb_problem *h, int field, const void *src, size_t bytes, int src_on_device) {
   if (!h || !src) return fail(KB_EINVAL, "null argument");
   float *dev = nullptr;
-  size_t need = 0;
+  size_t need = 0, rows = 0, pitch = 0;
   bool hv = false;
-  if (!field_info(h, field, &dev, &need, &hv)) return fail(KB_EINVAL, "field %d not available", field);
+  if (!field_info(h, field, &dev, &need, &hv, &rows, &pitch))
+    return fail(KB_EINVAL, "field %d not available", field);
   if (bytes != need) return fail(KB_EINVAL, "field %d has %zu bytes, got %zu", field, need, bytes);
   HIPCHK(hipStreamSynchronize(h->stream));
   if (hv) {
@@ -648,7 +671,13 @@ int kb_write(kb_problem *h, int field, const void *src, size_t bytes, int src_on
     clear_cache(h);   // a_k, b_k are baked into graph nodes
     return KB_OK;
   }
-  HIPCHK(hipMemcpy(dev, src, bytes, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+  const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (rows) {
+    const size_t w = bytes / rows;   // dense row bytes; the padding columns stay zero
+    HIPCHK(hipMemcpy2D(dev, pitch * sizeof(float), src, w, w, rows, kind));
+  } else {
+    HIPCHK(hipMemcpy(dev, src, bytes, kind));
+  }
   return KB_OK;
 }
 
@@ -662,11 +691,12 @@ int kb_reduce(kb_problem *h, double *out, int nout) {
   } else if (h->kind == KB_SKELETON) {
     e = reduce_sum(h->x, h->n, h->partials, h->red, h->stream);
   } else {
-    const long long M = h->N + 1;
+    // padded arrays: the padding columns hold zeros and add nothing
+    const long long n = (long long)(h->N + 1) * (h->N + 1) * h->pitch;
     const float *E[3] = {h->F[0], h->F[1], h->F[2]};
     const float *H[3] = {h->F[3], h->F[4], h->F[5]};
-    e = reduce_sumsq(E, 3, M * M * M, h->partials, h->red, h->stream);
-    if (e == hipSuccess) e = reduce_sumsq(H, 3, M * M * M, h->partials, h->red + 1, h->stream);
+    e = reduce_sumsq(E, 3, n, h->partials, h->red, h->stream);
+    if (e == hipSuccess) e = reduce_sumsq(H, 3, n, h->partials, h->red + 1, h->stream);
     nres = 2;
   }
   if (e != hipSuccess) return fail(KB_EHIP, "reduction launch: %s", hipGetErrorString(e));

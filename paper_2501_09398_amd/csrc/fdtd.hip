@@ -1,0 +1,254 @@
+// Yee FDTD kernels for the PEC cavity (the FDTD Maxwell solver of Sec. III-C:
+// an H kernel and an E kernel per step, plus the soft-source kernel).
+//
+// dx = 1, eps = mu = 1.  Each field lives on (N+1)^3 nodes stored with a row
+// pitch P (a multiple of 4 floats >= N+1, so every row starts on a 16-byte
+// boundary): node (i, j, k) is at (k*(N+1) + j)*P + i; the columns i > N are
+// padding and stay zero.  Component positions:
+//   Ex(i+1/2, j, k)  Ey(i, j+1/2, k)  Ez(i, j, k+1/2)
+//   Hx(i, j+1/2, k+1/2)  Hy(i+1/2, j, k+1/2)  Hz(i+1/2, j+1/2, k)
+// H -= dt * curl E on every H node (Hx for i <= N, j, k < N; Hy for i, k < N;
+// Hz for i, j < N); E += dt * curl H on the interior E nodes only, so the
+// tangential E on the walls is never written (PEC).  Each update is
+// new = old -/+ dt*((a - b) - (c - d)) with that exact grouping; dt = 0.5
+// makes the product exact, so fused and unfused evaluation agree.
+//
+// Both kernels are HBM-bound: 36 algorithmic bytes per node (three fields
+// read, three read and written).
+#include "kb_internal.h"
+
+namespace kb {
+
+// ---------------------------------------------------------------------------
+// Scalar kernels: one thread per node, 64x4 threads over (i, j), grid z = k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fdtd_h_kernel(const FdtdArgs f) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  const int N = f.N;
+  if (i > N || j > N) return;
+  const long long M = N + 1;
+  const long long sj = f.P, sk = M * f.P;
+  const long long c = (long long)k * sk + (long long)j * sj + i;
+  const float dt = f.dt;
+  if (j < N && k < N)
+    f.Hx[c] = f.Hx[c] - dt * ((f.Ez[c + sj] - f.Ez[c]) - (f.Ey[c + sk] - f.Ey[c]));
+  if (i < N && k < N)
+    f.Hy[c] = f.Hy[c] - dt * ((f.Ex[c + sk] - f.Ex[c]) - (f.Ez[c + 1] - f.Ez[c]));
+  if (i < N && j < N)
+    f.Hz[c] = f.Hz[c] - dt * ((f.Ey[c + 1] - f.Ey[c]) - (f.Ex[c + sj] - f.Ex[c]));
+}
+
+__global__ __launch_bounds__(256) void fdtd_e_kernel(const FdtdArgs f) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  const int N = f.N;
+  if (i > N || j > N) return;
+  const long long M = N + 1;
+  const long long sj = f.P, sk = M * f.P;
+  const long long c = (long long)k * sk + (long long)j * sj + i;
+  const float dt = f.dt;
+  const bool ii = i >= 1 && i <= N - 1;
+  const bool jj = j >= 1 && j <= N - 1;
+  const bool kk = k >= 1 && k <= N - 1;
+  if (i < N && jj && kk)
+    f.Ex[c] = f.Ex[c] + dt * ((f.Hz[c] - f.Hz[c - sj]) - (f.Hy[c] - f.Hy[c - sk]));
+  if (j < N && ii && kk)
+    f.Ey[c] = f.Ey[c] + dt * ((f.Hx[c] - f.Hx[c - sk]) - (f.Hz[c] - f.Hz[c - 1]));
+  if (k < N && ii && jj)
+    f.Ez[c] = f.Ez[c] + dt * ((f.Hy[c] - f.Hy[c - 1]) - (f.Hx[c] - f.Hx[c - sj]));
+}
+
+static dim3 scalar_grid(int N) {
+  return dim3((unsigned)((N + 1 + 63) / 64), (unsigned)((N + 1 + 3) / 4), (unsigned)(N + 1));
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels: one thread per float4 of four consecutive nodes in i.  A
+// plane's float4 slots are numbered q = j*(P/4) + i/4 and split into blocks
+// of 256; blocks are numbered plane by plane and remapped so that each XCD
+// runs one contiguous band of planes, keeping the k+1 (H) or k-1 (E) plane a
+// block reads in the same L2 as the block that owns it.  Neighbours along i
+// come from the adjacent lane (wave shuffle) or, at a wave edge, from
+// memory; along j and k from memory (cache).  Components whose node is not
+// updated keep their old value, so the float4 store rewrites them unchanged.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st4(float *p, const float4 &v) { *reinterpret_cast<float4 *>(p) = v; }
+__device__ __forceinline__ float comp(const float4 &v, int e) {
+  return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
+
+struct VecPos {
+  int k, j, i0, lane;
+  bool qin;
+  size_t c;        // offset of node (i0, j, k)
+};
+
+__device__ __forceinline__ bool vec_pos(const FdtdArgs &f, VecPos &p) {
+  const int M = f.N + 1, P4 = f.P / 4;
+  const int Q = M * P4;                       // float4 slots per plane
+  const int bpp = (Q + 255) / 256;            // blocks per plane
+  const int nb = bpp * M;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return false;
+  p.k = lb / bpp;
+  const int q = (lb - p.k * bpp) * 256 + (int)threadIdx.x;
+  p.qin = q < Q;
+  const int qq = p.qin ? q : Q - 1;
+  p.j = qq / P4;
+  p.i0 = (qq - p.j * P4) * 4;
+  p.lane = threadIdx.x & 63;
+  p.c = ((size_t)p.k * M + p.j) * f.P + p.i0;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void fdtd_h_vec_kernel(const FdtdArgs f) {
+  VecPos p;
+  if (!vec_pos(f, p)) return;
+  const int N = f.N;
+  const size_t sj = f.P, sk = (size_t)(N + 1) * f.P;
+  const float *__restrict__ Ex = f.Ex;
+  const float *__restrict__ Ey = f.Ey;
+  const float *__restrict__ Ez = f.Ez;
+  float *__restrict__ Hx = f.Hx;
+  float *__restrict__ Hy = f.Hy;
+  float *__restrict__ Hz = f.Hz;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const size_t c = p.c;
+  const bool in = p.qin;
+  const float4 ex = in ? ld4(Ex + c) : z4;
+  const float4 ey = in ? ld4(Ey + c) : z4;
+  const float4 ez = in ? ld4(Ez + c) : z4;
+  const float4 hx = in ? ld4(Hx + c) : z4;
+  const float4 hy = in ? ld4(Hy + c) : z4;
+  const float4 hz = in ? ld4(Hz + c) : z4;
+  const bool kup = in && p.k < N, jup = in && p.j < N;
+  const float4 ex_k = kup ? ld4(Ex + c + sk) : z4;     // k+1
+  const float4 ey_k = kup ? ld4(Ey + c + sk) : z4;
+  const float4 ez_j = jup ? ld4(Ez + c + sj) : z4;     // j+1
+  const float4 ex_j = jup ? ld4(Ex + c + sj) : z4;
+  // i+4 (east of the last component): the next lane's first component when
+  // it is in the same row, else memory; past the row it is never used.
+  float ey_e = __shfl_down(ey.x, 1, 64);
+  float ez_e = __shfl_down(ez.x, 1, 64);
+  if (p.lane == 63 && in && p.i0 + 4 < f.P) {
+    ey_e = Ey[c + 4];
+    ez_e = Ez[c + 4];
+  }
+  const float dt = f.dt;
+  float ox[4], oy[4], oz[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = p.i0 + e;
+    const float eyc = comp(ey, e), ezc = comp(ez, e), exc = comp(ex, e);
+    const float eye = e < 3 ? comp(ey, e + 1) : ey_e;
+    const float eze = e < 3 ? comp(ez, e + 1) : ez_e;
+    ox[e] = (i <= N && p.j < N && p.k < N)
+                ? comp(hx, e) - dt * ((comp(ez_j, e) - ezc) - (comp(ey_k, e) - eyc)) : comp(hx, e);
+    oy[e] = (i < N && p.k < N) ? comp(hy, e) - dt * ((comp(ex_k, e) - exc) - (eze - ezc)) : comp(hy, e);
+    oz[e] = (i < N && p.j < N) ? comp(hz, e) - dt * ((eye - eyc) - (comp(ex_j, e) - exc)) : comp(hz, e);
+  }
+  if (in) {
+    st4(Hx + c, make_float4(ox[0], ox[1], ox[2], ox[3]));
+    st4(Hy + c, make_float4(oy[0], oy[1], oy[2], oy[3]));
+    st4(Hz + c, make_float4(oz[0], oz[1], oz[2], oz[3]));
+  }
+}
+
+__global__ __launch_bounds__(256) void fdtd_e_vec_kernel(const FdtdArgs f) {
+  VecPos p;
+  if (!vec_pos(f, p)) return;
+  const int N = f.N;
+  const size_t sj = f.P, sk = (size_t)(N + 1) * f.P;
+  float *__restrict__ Ex = f.Ex;
+  float *__restrict__ Ey = f.Ey;
+  float *__restrict__ Ez = f.Ez;
+  const float *__restrict__ Hx = f.Hx;
+  const float *__restrict__ Hy = f.Hy;
+  const float *__restrict__ Hz = f.Hz;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const size_t c = p.c;
+  const bool in = p.qin;
+  const float4 ex = in ? ld4(Ex + c) : z4;
+  const float4 ey = in ? ld4(Ey + c) : z4;
+  const float4 ez = in ? ld4(Ez + c) : z4;
+  const float4 hx = in ? ld4(Hx + c) : z4;
+  const float4 hy = in ? ld4(Hy + c) : z4;
+  const float4 hz = in ? ld4(Hz + c) : z4;
+  const bool kdn = in && p.k > 0, jdn = in && p.j > 0;
+  const float4 hy_k = kdn ? ld4(Hy + c - sk) : z4;     // k-1
+  const float4 hx_k = kdn ? ld4(Hx + c - sk) : z4;
+  const float4 hz_j = jdn ? ld4(Hz + c - sj) : z4;     // j-1
+  const float4 hx_j = jdn ? ld4(Hx + c - sj) : z4;
+  // i-1 (west of the first component): the previous lane's last component
+  // when it is in the same row, else memory; at i = 0 it is never used.
+  float hz_w = __shfl_up(hz.w, 1, 64);
+  float hy_w = __shfl_up(hy.w, 1, 64);
+  if (p.lane == 0 && in && p.i0 > 0) {
+    hz_w = Hz[c - 1];
+    hy_w = Hy[c - 1];
+  }
+  const float dt = f.dt;
+  const bool jj = p.j >= 1 && p.j <= N - 1;
+  const bool kk = p.k >= 1 && p.k <= N - 1;
+  float ox[4], oy[4], oz[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = p.i0 + e;
+    const bool ii = i >= 1 && i <= N - 1;
+    const float hzc = comp(hz, e), hyc = comp(hy, e), hxc = comp(hx, e);
+    const float hzw = e > 0 ? comp(hz, e - 1) : hz_w;
+    const float hyw = e > 0 ? comp(hy, e - 1) : hy_w;
+    ox[e] = (i < N && jj && kk) ? comp(ex, e) + dt * ((hzc - comp(hz_j, e)) - (hyc - comp(hy_k, e))) : comp(ex, e);
+    oy[e] = (p.j < N && ii && kk) ? comp(ey, e) + dt * ((hxc - comp(hx_k, e)) - (hzc - hzw)) : comp(ey, e);
+    oz[e] = (p.k < N && ii && jj) ? comp(ez, e) + dt * ((hyc - hyw) - (hxc - comp(hx_j, e))) : comp(ez, e);
+  }
+  if (in) {
+    st4(Ex + c, make_float4(ox[0], ox[1], ox[2], ox[3]));
+    st4(Ey + c, make_float4(oy[0], oy[1], oy[2], oy[3]));
+    st4(Ez + c, make_float4(oz[0], oz[1], oz[2], oz[3]));
+  }
+}
+
+static dim3 vec_grid(const FdtdArgs &a) {
+  const int M = a.N + 1, P4 = a.P / 4;
+  const int bpp = (M * P4 + 255) / 256;
+  return dim3((unsigned)xcd_padded_grid(bpp * M));
+}
+
+// variant: 1 = scalar, 2 = vector (default)
+bool make_fdtd_h(Launch &L, const FdtdArgs &a, int variant) {
+  if (variant == 1) L.set((const void *)fdtd_h_kernel, scalar_grid(a.N), dim3(64, 4), 0, a);
+  else if (variant == 2) L.set((const void *)fdtd_h_vec_kernel, vec_grid(a), dim3(256), 0, a);
+  else return false;
+  return true;
+}
+
+bool make_fdtd_e(Launch &L, const FdtdArgs &a, int variant) {
+  if (variant == 1) L.set((const void *)fdtd_e_kernel, scalar_grid(a.N), dim3(64, 4), 0, a);
+  else if (variant == 2) L.set((const void *)fdtd_e_vec_kernel, vec_grid(a), dim3(256), 0, a);
+  else return false;
+  return true;
+}
+
+// Soft source (the third kernel of a step): reads the device step counter n,
+// adds g[n] to Ez at the source node, records the probe, increments n.  The
+// counter lives on the device so a replayed graph sees the absolute step.
+__global__ void fdtd_src_kernel(const SrcArgs s) {
+  if (threadIdx.x != 0) return;
+  const long long n = *s.step;
+  float v = s.Ez[s.src];
+  if (n >= 0 && n < s.glen) {
+    v = v + s.g[n];
+    s.Ez[s.src] = v;
+  }
+  if (n >= 0 && n < s.pcap) s.probe[n] = v;
+  *s.step = n + 1;
+}
+
+void make_fdtd_src(Launch &L, const SrcArgs &a) { L.set((const void *)fdtd_src_kernel, dim3(1), dim3(64), 0, a); }
+
+}  // namespace kb

@@ -41,21 +41,6 @@ __device__ __forceinline__ float heat3d_update(float t, float tn, float ts, floa
   return t + acc;
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs.  Remap the hardware
-// block id so that XCD x receives one contiguous run of logical blocks
-// (a band of rows), which keeps the halo rows of neighbouring tiles in the
-// same XCD's L2.  The grid is padded to a multiple of 8; logical ids past
-// the end return.
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ int xcd_logical_block(int nblocks) {
-  int hw = blockIdx.x;
-  int per = (nblocks + kXcds - 1) / kXcds;
-  return (hw % kXcds) * per + hw / kXcds;
-}
-
-static inline int xcd_padded_grid(int nblocks) { return (nblocks + kXcds - 1) / kXcds * kXcds; }
-
 // ---------------------------------------------------------------------------
 // 2D direct kernel: one thread per cell, 64x4 threads per block.
 // ---------------------------------------------------------------------------

@@ -61,6 +61,23 @@ struct Launch {
 };
 
 // ---------------------------------------------------------------------------
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Kernels remap the hardware block id so that XCD x receives one contiguous
+// run of logical blocks (a band of rows or planes), which keeps the halo
+// rows/planes of neighbouring tiles in the same L2.  The grid is padded to a
+// multiple of 8; logical ids past the end return.
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_logical_block(int nblocks) {
+  const int hw = blockIdx.x;
+  const int per = (nblocks + kXcds - 1) / kXcds;
+  return (hw % kXcds) * per + hw / kXcds;
+}
+
+inline int xcd_padded_grid(int nblocks) { return (nblocks + kXcds - 1) / kXcds * kXcds; }
+
+// ---------------------------------------------------------------------------
 // Kernel argument structs (passed by value).
 // ---------------------------------------------------------------------------
 struct HeatCoef {
@@ -101,7 +118,9 @@ struct SkelArgs {
 
 struct FdtdArgs {
   float *Ex, *Ey, *Ez, *Hx, *Hy, *Hz;
-  int N; float dt;
+  int N;        // cells per edge; nodes 0..N in each direction
+  int P;        // row pitch in floats (multiple of 4, >= N+1)
+  float dt;
 };
 
 struct SrcArgs {
@@ -128,8 +147,8 @@ bool make_heat2d_vec(Launch &L, const Heat2DArgs &a, int variant);  // false: ba
 constexpr int kMultiBX = 64, kMultiBY = 4;   // tile of the many-grid kernel
 void make_multi(Launch &L, const MultiArgs &a, int total_blocks);
 void make_skeleton(Launch &L, const SkelArgs &a, int variant);
-void make_fdtd_h(Launch &L, const FdtdArgs &a);
-void make_fdtd_e(Launch &L, const FdtdArgs &a);
+bool make_fdtd_h(Launch &L, const FdtdArgs &a, int variant);   // false: bad variant
+bool make_fdtd_e(Launch &L, const FdtdArgs &a, int variant);
 void make_fdtd_src(Launch &L, const SrcArgs &a);
 
 // Deterministic reductions (enqueued on s; partials has >= reduce_max_blocks doubles).
@@ -185,6 +204,7 @@ struct kb_problem {
   std::vector<float> a, b;
   // fdtd
   int N = 0;
+  int pitch = 0;                // FDTD row pitch in floats (multiple of 4)
   float dt = 0.5f;
   float *F[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   float *g = nullptr; int glen = 0;

@@ -1,5 +1,4 @@
-// Seeded initial state, the skeleton chain, the Yee FDTD kernels and the
-// deterministic reductions.
+// Seeded initial state, the skeleton chain and the deterministic reductions.
 #include "kb_internal.h"
 
 namespace kb {
@@ -66,76 +65,6 @@ void make_skeleton(Launch &L, const SkelArgs &a, int variant) {
   else if (vec == 8) L.set((const void *)skeleton_kernel<8>, grid, dim3(256), 0, a);
   else L.set((const void *)skeleton_kernel<4>, grid, dim3(256), 0, a);
 }
-
-// ---------------------------------------------------------------------------
-// Yee FDTD kernels (the FDTD Maxwell cavity solver of Sec. III-C, two field
-// kernels per step).  dx = 1, eps = mu = 1; every field on a padded (N+1)^3
-// grid, index (k*(N+1)+j)*(N+1)+i.  Positions: Ex(i+1/2,j,k) Ey(i,j+1/2,k)
-// Ez(i,j,k+1/2) Hx(i,j+1/2,k+1/2) Hy(i+1/2,j,k+1/2) Hz(i+1/2,j+1/2,k).
-// One thread per node (i fastest across a wave64), all three components.
-// H -= dt * curl E on every H node; E += dt * curl H on interior E nodes
-// (tangential E on the PEC walls is never written).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void fdtd_h_kernel(const FdtdArgs f) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k = blockIdx.z;
-  const int N = f.N;
-  if (i > N || j > N) return;
-  const long long M = N + 1;
-  const long long c = ((long long)k * M + j) * M + i;
-  const long long sj = M, sk = M * M;
-  const float dt = f.dt;
-  if (j < N && k < N)
-    f.Hx[c] = f.Hx[c] - dt * ((f.Ez[c + sj] - f.Ez[c]) - (f.Ey[c + sk] - f.Ey[c]));
-  if (i < N && k < N)
-    f.Hy[c] = f.Hy[c] - dt * ((f.Ex[c + sk] - f.Ex[c]) - (f.Ez[c + 1] - f.Ez[c]));
-  if (i < N && j < N)
-    f.Hz[c] = f.Hz[c] - dt * ((f.Ey[c + 1] - f.Ey[c]) - (f.Ex[c + sj] - f.Ex[c]));
-}
-
-__global__ __launch_bounds__(256) void fdtd_e_kernel(const FdtdArgs f) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k = blockIdx.z;
-  const int N = f.N;
-  if (i > N || j > N) return;
-  const long long M = N + 1;
-  const long long c = ((long long)k * M + j) * M + i;
-  const long long sj = M, sk = M * M;
-  const float dt = f.dt;
-  const bool ii = i >= 1 && i <= N - 1;
-  const bool jj = j >= 1 && j <= N - 1;
-  const bool kk = k >= 1 && k <= N - 1;
-  if (i < N && jj && kk)
-    f.Ex[c] = f.Ex[c] + dt * ((f.Hz[c] - f.Hz[c - sj]) - (f.Hy[c] - f.Hy[c - sk]));
-  if (j < N && ii && kk)
-    f.Ey[c] = f.Ey[c] + dt * ((f.Hx[c] - f.Hx[c - sk]) - (f.Hz[c] - f.Hz[c - 1]));
-  if (k < N && ii && jj)
-    f.Ez[c] = f.Ez[c] + dt * ((f.Hy[c] - f.Hy[c - 1]) - (f.Hx[c] - f.Hx[c - sj]));
-}
-
-static dim3 fdtd_grid(int N) { return dim3((unsigned)((N + 1 + 63) / 64), (unsigned)((N + 1 + 3) / 4), (unsigned)(N + 1)); }
-
-void make_fdtd_h(Launch &L, const FdtdArgs &a) { L.set((const void *)fdtd_h_kernel, fdtd_grid(a.N), dim3(64, 4), 0, a); }
-void make_fdtd_e(Launch &L, const FdtdArgs &a) { L.set((const void *)fdtd_e_kernel, fdtd_grid(a.N), dim3(64, 4), 0, a); }
-
-// Soft source (the third kernel of a step): reads the device step counter n,
-// adds g[n] to Ez at the source node, records the probe, increments n.  The
-// counter lives on the device so a replayed graph sees the absolute step.
-__global__ void fdtd_src_kernel(const SrcArgs s) {
-  if (threadIdx.x != 0) return;
-  const long long n = *s.step;
-  float v = s.Ez[s.src];
-  if (n >= 0 && n < s.glen) {
-    v = v + s.g[n];
-    s.Ez[s.src] = v;
-  }
-  if (n >= 0 && n < s.pcap) s.probe[n] = v;
-  *s.step = n + 1;
-}
-
-void make_fdtd_src(Launch &L, const SrcArgs &a) { L.set((const void *)fdtd_src_kernel, dim3(1), dim3(64), 0, a); }
 
 // ---------------------------------------------------------------------------
 // Deterministic reductions.  Pass 1: block b sums a fixed contiguous chunk

@@ -114,15 +114,17 @@ def test_fdtd_source_cell_from_seed(kb):
             assert np.count_nonzero(ez) == 1
 
 
-@pytest.mark.parametrize("N,steps", [(8, 150), (17, 120), (32, 300)])
-def test_fdtd_bitwise_vs_oracle(kb, N, steps):
-    announce(f"fdtd N={N} steps={steps}")
+@pytest.mark.parametrize("N,steps", [(8, 150), (17, 120), (32, 300), (5, 60), (6, 60)])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_fdtd_bitwise_vs_oracle(kb, N, steps, variant):
+    announce(f"fdtd N={N} steps={steps} variant={variant}")
     seed = 32
     src = synth.fdtd_source_cell(seed, N)
     _, g32 = oracle.fdtd_pulse(steps + 1)
     ref, probe_ref = oracle.fdtd(oracle.fdtd_zero_fields(N, np.float32), N, steps, src=src, g=g32,
                                  dtype=np.float32)
     with kb.Problem(kb.FDTD3D, (N, 512), kb.FDTD_COEFFS, seed) as p:
+        p.set_option(kb.OPT_TILE, variant)
         p.run(steps, 0)
         got = gpu_fields(kb, p)
         probe = p.read(kb.F_PROBE)
@@ -199,3 +201,23 @@ def test_fdtd_full_size_sampled(kb):
     for k in oracle.FDTD_FIELDS:
         assert np.array_equal(got[k], ref[k]), k
     assert np.array_equal(probe[:steps], probe_ref)
+
+
+@pytest.mark.parametrize("N", [7, 12, 33])
+def test_fdtd_random_fields_both_variants(kb, N):
+    # Arbitrary (non-PEC) fields written through kb_write: both kernel
+    # variants match the float32 oracle bit for bit, including nodes that
+    # the update leaves alone.
+    announce(f"fdtd random fields N={N}")
+    rng = np.random.default_rng(N)
+    M = N + 1
+    f0 = {k: rng.standard_normal((M, M, M)).astype(np.float32) for k in oracle.FDTD_FIELDS}
+    ref, _ = oracle.fdtd(f0, N, 9, dtype=np.float32)
+    for variant in (1, 2):
+        with kb.Problem(kb.FDTD3D, (N, 16), (0.5, 0.0, 80.0), 0) as p:
+            p.set_option(kb.OPT_TILE, variant)
+            for k, fid in kb.FDTD_FIELDS.items():
+                p.write(fid, f0[k])
+            p.run(9, 4)
+            for k, fid in kb.FDTD_FIELDS.items():
+                assert np.array_equal(p.read(fid), ref[k]), (variant, k)
