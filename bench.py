@@ -15,8 +15,12 @@ Procedure (Sec. III-C):
   2. warm up, then time `--steps` whole jobs at that b, each job paying its
      own graph creation (T = T_C + T_E, Eq. 1);
   3. time the same jobs launching every kernel separately (the baseline);
-  4. time the dominant kernel's device duration with per-dispatch events;
-  5. time the CPU oracle on a bounded sample of the same job.
+  4. take the dominant kernel's mean duration per launch from the HIP
+     events around the timed replays (roofline);
+  5. time the other workloads per launch vs graph batches (2D stencil with
+     the autotuned kernel, depth and b; 3D stencil; 64 uneven grids; FDTD
+     128^3 and 256^3) and the large grids against the HBM roofline;
+  6. time the CPU oracle on a bounded sample of the same job.
 One JSON line is printed.
 """
 from __future__ import annotations
@@ -54,10 +58,38 @@ def parse():
     ap.add_argument("--arm", choices=("both", "graph", "per_launch"), default="both",
                     help="'graph' skips the per-launch baseline; 'per_launch' times only the baseline "
                          "(both for profiling one arm alone)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other workloads (2D/3D stencils, many grids, FDTD, large grids)")
+    ap.add_argument("--kernel-only", choices=sorted(KERNEL_RUNS),
+                    help="run only one workload's kernels per launch for a few steps (counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (2^26 floats read and written by the "
                          "element-wise kernel with a=1, b=0), to scale hardware byte counters")
     return ap.parse_args()
+
+
+KERNEL_RUNS = {
+    # name: (problem, shape, coeffs-attr, variant, steps per launch loop)
+    "skeleton_2p16": ("SKELETON", (N_ELEM,), None, 1, 100),
+    "heat2d_16384": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 13, 5),
+    "heat3d_8x4096": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 4, 5),
+    "fdtd_256": ("FDTD3D", (256, 64), "FDTD_COEFFS", 2, 5),
+}
+
+
+def kernel_only(name):
+    """Run one workload's kernels per launch for a few steps and nothing else
+    (for hardware-counter runs, which serialise every dispatch)."""
+    import torch
+    import paper_2501_09398_amd as kb
+    prob, shape, co, var, steps = KERNEL_RUNS[name]
+    coeffs = (K,) if co is None else getattr(kb, co)
+    with kb.Problem(getattr(kb, prob), shape, coeffs, SEED, device=0) as p:
+        p.set_option(kb.OPT_TILE, var)
+        p.run(steps, 0)
+        p.last_timing()
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_only": name, "steps": steps}), flush=True)
 
 
 def copy_calibration():
@@ -96,6 +128,101 @@ def stored_traffic():
     return d.get("hbm_bytes_per_launch")
 
 
+def workloads(kb, pm, autotune, np):
+    """The other workloads of the study, each per launch vs graph batches,
+    plus the large grids against the HBM roofline.  Seeded synthetic inputs
+    of each workload's shape; every run starts from the device-resident state."""
+    out = {}
+
+    def arm(p, n, b, reps=3):
+        p.run(n, b)
+        p.last_timing()                      # warm-up (builds the graph if any)
+        te = []
+        for _ in range(reps):
+            p.run(n, b)
+            te.append(p.last_timing()["t_exec_s"])
+        return float(np.median(te))
+
+    def cold(p, n, b):
+        p.set_option(kb.OPT_GRAPH_CACHE, 0)
+        p.run(n, b)
+        t = p.last_timing()
+        p.set_option(kb.OPT_GRAPH_CACHE, 1)
+        return t["t_create_s"] + t["t_exec_s"]
+
+    # 2D thermal stencil, 256x256, 1000 steps (launch-bound)
+    n = 1000
+    d = {"steps": n, "cells": 256 * 256}
+    with kb.Problem(kb.HEAT2D, (256, 256), kb.HEAT_COEFFS, SEED) as p:
+        p.set_option(kb.OPT_TILE, 1)
+        d["per_launch_us_step"] = arm(p, n, 0) / n * 1e6
+        for b in (1, 10, 100, 1000):
+            d[f"graph_b{b}_us_step"] = arm(p, n, b) / n * 1e6
+            d[f"graph_b{b}_cold_us_step"] = cold(p, n, b) / n * 1e6
+    tr = autotune.tune(kb, kb.HEAT2D, (256, 256), kb.HEAT_COEFFS, n, seed=SEED, reps=2)
+    d["autotuned"] = {"variant": tr.variant, "depth": tr.depth, "b": tr.b,
+                      "us_step": tr.us_per_step_warm, "cold_us_step": tr.us_per_step_cold,
+                      "t_create_ms": tr.t_create_s * 1e3, "b_measured_best": tr.b_measured}
+    d["speedup_graph_b100_vs_per_launch"] = d["per_launch_us_step"] / d["graph_b100_us_step"]
+    d["speedup_autotuned_vs_per_launch"] = d["per_launch_us_step"] / tr.us_per_step_warm
+    d["gcell_upd_s_autotuned"] = 256 * 256 / tr.us_per_step_warm / 1e3
+    out["heat2d_256x256_1000"] = d
+
+    # 3D stencil 8x512x512, 2000 steps
+    n = 2000
+    d = {"steps": n, "cells": 8 * 512 * 512}
+    with kb.Problem(kb.HEAT3D, (8, 512, 512), kb.HEAT_COEFFS, SEED) as p:
+        for v in (1, 4):
+            p.set_option(kb.OPT_TILE, v)
+            d[f"v{v}_per_launch_us_step"] = arm(p, n, 0, 2) / n * 1e6
+            d[f"v{v}_graph_b100_us_step"] = arm(p, n, 100, 2) / n * 1e6
+    best = min(d[k] for k in d if k.endswith("graph_b100_us_step"))
+    d["gcell_upd_s"] = 8 * 512 * 512 / best / 1e3
+    out["heat3d_8x512x512_2000"] = d
+
+    # many uneven grids, one kernel per step over all of them
+    import synth
+    sides = synth.multigrid_sides(SEED, 64)
+    shape = [64] + [v for s in sides for v in (s, s)]
+    n = 2000
+    cells = sum(s * s for s in sides)
+    d = {"steps": n, "grids": 64, "cells": cells}
+    with kb.Problem(kb.HEAT2D_MULTI, shape, kb.HEAT_COEFFS, SEED) as p:
+        d["per_launch_us_step"] = arm(p, n, 0, 2) / n * 1e6
+        d["graph_b100_us_step"] = arm(p, n, 100, 2) / n * 1e6
+    d["gcell_upd_s"] = cells / d["graph_b100_us_step"] / 1e3
+    d["hbm_frac"] = 12.0 * cells / (d["graph_b100_us_step"] * 1e-6) / (HBM_PEAK_GBS * 1e9)
+    out["multigrid_64_2000"] = d
+
+    # FDTD cavities
+    for N, n in ((128, 10000), (256, 2000)):
+        d = {"steps": n, "cells": N ** 3}
+        with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, SEED) as p:
+            d["per_launch_us_step"] = arm(p, n, 0, 1) / n * 1e6
+            d["graph_b100_us_step"] = arm(p, n, 100, 1) / n * 1e6
+        d["gcell_upd_s"] = N ** 3 / d["graph_b100_us_step"] / 1e3
+        d["hbm_frac"] = 72.0 * (N + 1) ** 3 / (d["graph_b100_us_step"] * 1e-6) / (HBM_PEAK_GBS * 1e9)
+        out[f"fdtd_{N}^3_{n}"] = d
+
+    # large grids against the HBM roofline (working sets >> 256 MB cache)
+    big = {}
+    for name, prob, shp, var, bytes_per_cell in (
+            ("heat2d_16384^2", kb.HEAT2D, (16384, 16384), 13, 12.0),
+            ("heat2d_8192^2", kb.HEAT2D, (8192, 8192), 13, 12.0),
+            ("heat3d_8x4096^2", kb.HEAT3D, (8, 4096, 4096), 4, 8.5)):
+        with kb.Problem(prob, shp, kb.HEAT_COEFFS, SEED) as p:
+            p.set_option(kb.OPT_TILE, var)
+            t = arm(p, 20, 0, 2) / 20
+        cells = int(np.prod(shp))
+        gbs = bytes_per_cell * cells / t / 1e9
+        big[name] = {"us_step": t * 1e6, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS, "gcell_upd_s": cells / t / 1e9}
+    d = out["fdtd_256^3_2000"]
+    big["fdtd_256^3"] = {"us_step": d["graph_b100_us_step"], "frac": d["hbm_frac"],
+                         "GB_s": d["hbm_frac"] * HBM_PEAK_GBS, "gcell_upd_s": d["gcell_upd_s"]}
+    out["large_grids_hbm"] = big
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -104,6 +231,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.kernel_only:
+        kernel_only(args.kernel_only)
         return
 
     import numpy as np
@@ -186,6 +316,11 @@ def main():
     achieved = bytes_per_launch / kern_s / 1e9
     prob.destroy()
 
+    wl = None
+    if not args.no_workloads and args.arm == "both":
+        from paper_2501_09398_amd import autotune
+        wl = workloads(kb, pm, autotune, np)
+
     # 5. CPU oracle on a bounded sample --------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -239,6 +374,7 @@ def main():
                      "kernel": "skeleton_kernel<4>", "kernel_us": kern_s * 1e6,
                      "bytes_per_launch": bytes_per_launch},
         "cpu_baseline": cpu,
+        "workloads": wl,
     }
     if model is not None:
         line["model"] = {"k_c_s_per_node": model.creation.k_c, "b_c_s": model.creation.b_c,

@@ -128,10 +128,11 @@ extern "C" {
  *              8..12 = float4 rows, a wave walking 1, 2, 4, 8, 16 rows;
  *              13, 14 = 1 and 2 rows with streaming (non-temporal) stores
  *                     (8..14 need nx % 4 == 0).
- *              Default: 13 if nx % 4 == 0, else 1.
+ *              Default: 13 if nx % 4 == 0 and ny*nx >= 2^20, else 1.
  *   KB_HEAT3D: 1 = one thread per column; float4 rows (nx % 4 == 0):
  *              2 = plain, 3 = next layer prefetched, 4 = prefetched with
- *              streaming stores.  Default: 4 if nx % 4 == 0, else 1.
+ *              streaming stores.  Default: 4 if nx % 4 == 0 and
+ *              ny*nx >= 2^20, else 1.
  *   KB_SKELETON: 1 = 4 elements per thread (default), 2 = 1, 3 = 8.     */
 #define KB_OPT_TILE      2
 /* KB_OPT_TDEPTH: temporal-blocking depth t >= 1 for KB_HEAT2D: one launch

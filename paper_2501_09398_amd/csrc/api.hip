@@ -135,13 +135,16 @@ bool pingpong(const kb_problem *h) {
 
 // Kernel variant in use: the option, or the default for the shape (vector
 // rows when every row is 16-byte aligned, else one thread per cell).
+// Measured on MI355X: the vector kernels win once a plane has about a
+// million cells; below that the one-thread-per-cell kernels have more waves
+// in flight and are faster.
 int heat2d_variant(const kb_problem *h) {
   if (h->tile != 0) return h->tile;
-  return h->nx % 4 == 0 ? 13 : 1;
+  return (h->nx % 4 == 0 && h->ny * h->nx >= (1 << 20)) ? 13 : 1;
 }
 int heat3d_variant(const kb_problem *h) {
   if (h->tile != 0) return h->tile;
-  return h->nx % 4 == 0 ? 4 : 1;
+  return (h->nx % 4 == 0 && h->ny * h->nx >= (1 << 20)) ? 4 : 1;
 }
 bool heat2d_is_tile(int v) { return v >= 2 && v <= 7; }
 

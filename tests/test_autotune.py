@@ -1,0 +1,105 @@
+"""Autotuner logic against a synthetic timing model (no GPU), and on the GPU
+against the real library."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2501_09398_amd import autotune, perfmodel as pm
+
+
+class FakeKB:
+    """Stands in for the binding: timings follow Eqs. 2 and 3 exactly."""
+    HEAT2D, HEAT3D, SKELETON, FDTD3D, HEAT2D_MULTI = 1, 2, 3, 4, 5
+    OPT_BUILDER, OPT_TILE, OPT_TDEPTH, OPT_GRAPH_CACHE, OPT_MAX_NODES = 1, 2, 3, 4, 5
+    # per-launch kernel time (s) per variant; variant 6 with depth 8 is best
+    T_K = {1: 3e-6, 2: 4e-6, 3: 3.5e-6, 4: 3.6e-6, 5: 3.4e-6, 6: 3.2e-6, 7: 3.9e-6,
+           8: 2.9e-6, 9: 2.95e-6, 10: 3.1e-6, 11: 3.3e-6, 12: 3.5e-6, 13: 2.8e-6, 14: 2.85e-6}
+    T_I, T_A, K_C, B_C = 0.5e-6, 8e-6, 3e-6, 2e-4
+
+    class Problem:
+        def __init__(self, kbm, problem, shape, coeffs, seed):
+            self.kbm, self.v, self.t, self.last = kbm, 1, 1, None
+
+        def __enter__(self):
+            return self
+
+        def __exit__(self, *a):
+            pass
+
+        def kernels_per_iter(self):
+            return 1
+
+        def set_option(self, opt, val):
+            if opt == FakeKB.OPT_TILE:
+                self.v = val
+            elif opt == FakeKB.OPT_TDEPTH:
+                self.t = val
+
+        def run(self, n, b):
+            t = self.t if 2 <= self.v <= 7 else 1
+            iters = n // t
+            tk = FakeKB.T_K[self.v] * (1 + 0.1 * t) / t * t    # deeper steps cost a little more each
+            nb = iters // b
+            te = iters * (tk + FakeKB.T_I) + nb * (FakeKB.T_A - FakeKB.T_I)
+            self.last = {"t_create_s": FakeKB.K_C * b + FakeKB.B_C, "t_exec_s": te}
+
+        def last_timing(self):
+            return self.last
+
+
+def fake_kb():
+    kb = FakeKB()
+    kb.Problem = lambda *a: FakeKB.Problem(kb, *a)
+    return kb
+
+
+def test_tuner_picks_fastest_kernel_and_model_batch():
+    kb = fake_kb()
+    res = autotune.tune(kb, kb.HEAT2D, (256, 256), (), 1000, reps=1)
+    # per step: variant v with depth t costs T_K[v]*(1+0.1t) + T_I/t + ...;
+    # the cheapest per step is the one with the largest depth
+    per_step = {(v, t): (FakeKB.T_K[v] * (1 + 0.1 * t) + FakeKB.T_I) / t
+                for v, t in autotune.kernel_candidates(kb, kb.HEAT2D, (256, 256))}
+    assert (res.variant, res.depth) == min(per_step, key=per_step.get)
+    n_iter = 1000 // res.depth
+    assert n_iter % res.b == 0
+    # exact data: the fitted model recovers a = n_iter (T_a - T_i) and k_c,
+    # and b is the admissible minimiser of k_c b + a / b
+    a = n_iter * (FakeKB.T_A - FakeKB.T_I)
+    assert math.isclose(res.model["execution"]["a"], a, rel_tol=1e-9)
+    assert math.isclose(res.model["creation"]["k_c"], FakeKB.K_C, rel_tol=1e-9)
+    cands = [d for d in pm.divisors(n_iter) if d <= 4096]
+    expect = min(cands, key=lambda b: FakeKB.K_C * b + a / b)
+    assert res.b == expect
+
+
+def test_kernel_candidates_respect_alignment():
+    kb = FakeKB()
+    c_aligned = autotune.kernel_candidates(kb, kb.HEAT2D, (64, 256))
+    c_ragged = autotune.kernel_candidates(kb, kb.HEAT2D, (64, 250))
+    assert any(v >= 8 for v, _ in c_aligned)
+    assert not any(v >= 8 for v, _ in c_ragged)
+    assert autotune.kernel_candidates(kb, kb.HEAT3D, (8, 64, 66)) == [(1, 1)]
+
+
+@pytest.mark.gpu
+def test_autotuned_heat2d_is_bitwise_and_not_slower():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_09398_amd as kb
+    kb.lib()
+    shape, n = (256, 256), 1000
+    res = autotune.tune(kb, kb.HEAT2D, shape, kb.HEAT_COEFFS, n, seed=3, reps=2)
+    print("tuned:", res.variant, res.depth, res.b, res.us_per_step_warm)
+    with kb.Problem(kb.HEAT2D, shape, kb.HEAT_COEFFS, 3) as p:
+        p.run(n, 0)
+        base = p.read(kb.F_T)
+        per_launch = p.last_timing()["t_exec_s"] / n * 1e6
+    with kb.Problem(kb.HEAT2D, shape, kb.HEAT_COEFFS, 3) as p:
+        p.set_option(kb.OPT_TILE, res.variant)
+        p.set_option(kb.OPT_TDEPTH, res.depth)
+        p.run(n, res.b)
+        assert np.array_equal(p.read(kb.F_T), base)
+    assert res.us_per_step_warm <= per_launch
