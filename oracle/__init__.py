@@ -147,3 +147,99 @@ def fdtd(fields, N, nsteps, dt=0.5, src=None, g=None, n_start=0, dtype=np.float6
                                      _ptr(src_arr), gp, int(n_start), int(nsteps),
                                      _ptr(probe) if src is not None else None)
     return f, probe[:nsteps]
+
+
+# ---------------------------------------------------------------------------
+# Learned k-step surrogate (surrogate.c): forward, loss gradient, Adam.
+# ---------------------------------------------------------------------------
+SG_NW = 19393
+
+
+def _setup_sg(L):
+    L.or_sg_nweights.restype = C.c_int
+    L.or_bf16_round.argtypes = [C.c_double]
+    L.or_bf16_round.restype = C.c_double
+    L.or_sg_conv3x3.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_long, C.c_long,
+                                C.c_void_p]
+    L.or_sg_conv3x3.restype = None
+    L.or_sg_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_long, C.c_long, C.c_int, C.c_void_p]
+    L.or_sg_forward.restype = C.c_int
+    L.or_sg_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_long, C.c_long,
+                                  C.c_double, C.c_int, C.c_void_p, C.c_void_p]
+    L.or_sg_loss_grad.restype = C.c_int
+    L.or_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_long, C.c_long, C.c_double,
+                          C.c_double, C.c_double, C.c_double]
+    L.or_adam.restype = None
+
+
+_sg_ready = False
+
+
+def _sg():
+    global _sg_ready
+    L = lib()
+    if not _sg_ready:
+        _setup_sg(L)
+        _sg_ready = True
+    return L
+
+
+def bf16_round(v):
+    """Round each value to the nearest bf16 (ties to even), in float64."""
+    L = _sg()
+    a = np.asarray(v, dtype=np.float64)
+    return np.vectorize(L.or_bf16_round, otypes=[np.float64])(a) if a.ndim else L.or_bf16_round(float(a))
+
+
+def sg_conv3x3(W, b, x):
+    """One 3x3 convolution with replicate padding: W[co][ci][3][3], b[co]
+    (or None), x[ci][H][W] -> [co][H][W], float64."""
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    co, ci = W.shape[:2]
+    _, H, Wd = x.shape
+    out = np.empty((co, H, Wd), np.float64)
+    bp = None
+    if b is not None:
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        bp = _ptr(b)
+    _sg().or_sg_conv3x3(_ptr(W), bp, _ptr(x), ci, co, H, Wd, _ptr(out))
+    return out
+
+
+def sg_forward(w, T0, P, round_bf16=True):
+    """Network output y (normalised increment) for one field, float64."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    assert w.size == SG_NW
+    T0 = np.ascontiguousarray(T0, dtype=np.float32)
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    H, Wd = T0.shape
+    y = np.empty((H, Wd), np.float64)
+    if _sg().or_sg_forward(_ptr(w), _ptr(T0), _ptr(P), H, Wd, int(round_bf16), _ptr(y)):
+        raise MemoryError("oracle sg_forward")
+    return y
+
+
+def sg_loss_grad(w, T0, P, target, norm=None, round_bf16=True):
+    """(loss, grad) of sum (y - target)^2 / norm for one field (norm
+    defaults to its pixel count)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    T0 = np.ascontiguousarray(T0, dtype=np.float32)
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    target = np.ascontiguousarray(target, dtype=np.float64)
+    H, Wd = T0.shape
+    norm = float(H * Wd if norm is None else norm)
+    g = np.zeros(SG_NW, np.float64)
+    loss = np.zeros(1, np.float64)
+    if _sg().or_sg_loss_grad(_ptr(w), _ptr(T0), _ptr(P), _ptr(target), H, Wd, norm, int(round_bf16), _ptr(g),
+                             _ptr(loss)):
+        raise MemoryError("oracle sg_loss_grad")
+    return float(loss[0]), g
+
+
+def adam(w, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays w, m, v."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    _sg().or_adam(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.size, int(step), lr, b1, b2, eps)

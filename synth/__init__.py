@@ -142,3 +142,40 @@ def multigrid_init(seed: int, sides):
         Ps.append(uniform_f32(seed, TAG_P, n, *P_RANGE, offset=off).reshape(s, s))
         off += n
     return T0s, Ps
+
+
+def hot_spot_power(seed: int, ny: int, nx: int, offset: int = 0):
+    """Power map P ~ U[0,1) plus 1-4 Gaussian hot spots of amplitude
+    U[1,4) and width sigma U[4,32) cells at uniform centres (tag 7 draws:
+    count, then per spot centre y, centre x, amplitude, sigma).  The
+    Gaussians are evaluated in float64 and the sum rounded once to float32."""
+    base = uniform01(seed, TAG_P, np.arange(offset, offset + ny * nx, dtype=np.uint64)).reshape(ny, nx)
+    P = base.copy()
+    k0 = offset * 8
+    count = 1 + int(randint(seed, TAG_HOT, k0, 4))
+    yy = np.arange(ny)[:, None]
+    xx = np.arange(nx)[None, :]
+    for h in range(count):
+        u = uniform01(seed, TAG_HOT, np.arange(k0 + 1 + 4 * h, k0 + 5 + 4 * h, dtype=np.uint64))
+        cy, cx, amp, sig = u[0] * ny, u[1] * nx, 1.0 + 3.0 * u[2], 4.0 + 28.0 * u[3]
+        P += amp * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2.0 * sig * sig))
+    return P.astype(np.float32)
+
+
+def surrogate_init(seed: int):
+    """Initial weights of the 4-layer surrogate (19393 float32, canonical
+    order W1, b1, W2, b2, W3, b3, W4, b4): weights and biases of layer l
+    uniform on [-1/sqrt(fan_in), 1/sqrt(fan_in)) with fan_in = 9*cin, except
+    the last layer, which starts at zero (the untrained network predicts no
+    change)."""
+    cin, cout = (2, 32, 32, 32), (32, 32, 32, 1)
+    parts, off = [], 0
+    for l in range(4):
+        nw, nb = cout[l] * cin[l] * 9, cout[l]
+        bound = 1.0 / np.sqrt(9.0 * cin[l])
+        if l == 3:
+            parts.append(np.zeros(nw + nb, np.float32))
+        else:
+            parts.append(uniform_f32(seed, 9, nw + nb, -bound, bound, offset=off))
+        off += nw + nb
+    return np.concatenate(parts)
