@@ -94,11 +94,36 @@ extern "C" {
  *   initial: grid g draws its cells at flat offset sum_{h<g} ny_h*nx_h of the
  *            same streams as KB_HEAT2D.
  */
+/*
+ * KB_HEAT2D_SURROGATE  (the 2D thermal problem advanced k steps at a time by
+ *   a learned surrogate, with the plain stencil as checked fallback)
+ *   shape  = {ny, nx} or {ny, nx, train_pixels}: the field (ny, nx >= 32)
+ *            and the pixel capacity of one training batch (crops x C x C).
+ *   coeffs = {c, Rx, Ry, Rz, Tamb} or {c, Rx, Ry, Rz, Tamb, s, threshold, k}
+ *            (defaults s = 0.8, threshold = 1e-3, k = 16; 1 <= k <= 16).
+ *            One iteration is one block of k steps:
+ *              y = NN((T-333)/10, (P-0.5)/0.29)  (4 layers of 3x3 conv, 32
+ *                  channels, GELU, replicate padding; bf16 operands on the
+ *                  matrix cores, float32 accumulation);
+ *              T_k = T + s*y  (float32);
+ *              residual r = max(r_mean, r_tile) (the mean of T against its
+ *                  exact k-step recurrence; four seeded 32x32 tiles against
+ *                  the plain stencil), both relative to max|T_k|;
+ *              if r > threshold the block is redone with k plain steps
+ *                  from T (one predicated launch; the graph stays static).
+ *            n_steps mod k steps run as plain steps.
+ *   fields : KB_F_T, KB_F_P as KB_HEAT2D; KB_F_W (19393 float weights:
+ *            W1[32][2][3][3], b1[32], W2[32][32][3][3], b2[32],
+ *            W3[32][32][3][3], b3[32], W4[1][32][3][3], b4[1]; zero at
+ *            creation = no change); KB_F_SGSTATS (int64[2]: blocks checked,
+ *            fallbacks); KB_F_RESID (double[4096]: r of each checked block).
+ */
 #define KB_HEAT2D        1
 #define KB_HEAT3D        2
 #define KB_SKELETON      3
 #define KB_FDTD3D        4
 #define KB_HEAT2D_MULTI  5
+#define KB_HEAT2D_SURROGATE 6
 
 /* ---- fields (kb_read / kb_write) --------------------------------------- */
 #define KB_F_T      1
@@ -114,6 +139,9 @@ extern "C" {
 #define KB_F_HZ    15
 #define KB_F_PROBE 16
 #define KB_F_STEP  17   /* int64 count of steps advanced on the device */
+#define KB_F_W     20   /* surrogate weights (float32[19393])           */
+#define KB_F_SGSTATS 21 /* surrogate blocks checked, fallbacks (int64[2]) */
+#define KB_F_RESID 22   /* surrogate residual per checked block (double[4096]) */
 
 /* ---- options (kb_set_option) ------------------------------------------- */
 /* KB_OPT_BUILDER: how a batch graph is built.
@@ -219,6 +247,30 @@ int kb_reduce(kb_problem *h, double *out, int nout);
 
 /* Timing of the last kb_run() (synchronises the stream).                   */
 int kb_last_timing(kb_problem *h, kb_timing *out);
+
+/* Surrogate training (KB_HEAT2D_SURROGATE created with train_pixels > 0).
+ * The batch is ncrop crops of crop x crop pixels (crop a multiple of 64,
+ * ncrop*crop^2 <= train_pixels, ncrop <= 1024) cut from stored fields:
+ *   T0, P, T16 : device float32 [nfield][Hf][Wf]: start state, power map,
+ *                and the state after k plain steps (the target is
+ *                (T16 - T0)/s);
+ *   crops      : host int32 [ncrop][3] = {field, y0, x0}.
+ * The loss is the mean over the batch's pixels of (y - target)^2; the
+ * gradient covers all 19393 weights (float32 accumulation of bf16
+ * products; per-block partial sums in a fixed order, so it is
+ * deterministic).  Synchronous.
+ * kb_sg_loss_grad  : loss (host, may be NULL) and gradient (host float
+ *                    [19393], may be NULL); the weights are unchanged.
+ * kb_sg_train_step : one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ *                    bias-corrected with the handle's step count) at
+ *                    learning rate lr; loss (may be NULL) is the batch loss
+ *                    before the step.
+ * Errors: KB_EINVAL (not a surrogate, crop outside its field, batch too
+ *         large), KB_EHIP.                                                 */
+int kb_sg_loss_grad(kb_problem *h, const float *T0, const float *P, const float *T16, int nfield, int Hf,
+                    int Wf, const int *crops, int ncrop, int crop, double *loss, float *grad);
+int kb_sg_train_step(kb_problem *h, const float *T0, const float *P, const float *T16, int nfield, int Hf,
+                     int Wf, const int *crops, int ncrop, int crop, double lr, double *loss);
 
 /* Number of kernels per iteration (K) of the problem, or < 0 on error.    */
 int kb_kernels_per_iter(const kb_problem *h);

@@ -22,10 +22,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkbatch.so")
 
 # problems
-HEAT2D, HEAT3D, SKELETON, FDTD3D, HEAT2D_MULTI = 1, 2, 3, 4, 5
+HEAT2D, HEAT3D, SKELETON, FDTD3D, HEAT2D_MULTI, HEAT2D_SURROGATE = 1, 2, 3, 4, 5, 6
 # fields
 F_T, F_P, F_X, F_A, F_B = 1, 2, 3, 4, 5
 F_EX, F_EY, F_EZ, F_HX, F_HY, F_HZ, F_PROBE, F_STEP = 10, 11, 12, 13, 14, 15, 16, 17
+F_W, F_SGSTATS, F_RESID = 20, 21, 22
+SG_NW = 19393
 FDTD_FIELDS = {"Ex": F_EX, "Ey": F_EY, "Ez": F_EZ, "Hx": F_HX, "Hy": F_HY, "Hz": F_HZ}
 # options
 OPT_BUILDER, OPT_TILE, OPT_TDEPTH, OPT_GRAPH_CACHE, OPT_MAX_NODES = 1, 2, 3, 4, 5
@@ -77,6 +79,13 @@ def lib():
         L.kb_reduce.restype = C.c_int
         L.kb_last_timing.argtypes = [vp, C.POINTER(Timing)]
         L.kb_last_timing.restype = C.c_int
+        fp = C.POINTER(C.c_float)
+        L.kb_sg_loss_grad.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, C.c_int,
+                                      C.POINTER(C.c_double), fp]
+        L.kb_sg_loss_grad.restype = C.c_int
+        L.kb_sg_train_step.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, C.c_int,
+                                       C.c_double, C.POINTER(C.c_double)]
+        L.kb_sg_train_step.restype = C.c_int
         L.kb_kernels_per_iter.argtypes = [vp]
         L.kb_kernels_per_iter.restype = C.c_int
         L.kb_destroy.argtypes = [vp]
@@ -164,11 +173,17 @@ class Problem:
             return ((s[1] if len(s) > 1 else 16384),), np.float32
         if field == F_STEP:
             return (1,), np.int64
+        if field == F_W:
+            return (SG_NW,), np.float32
+        if field == F_SGSTATS:
+            return (2,), np.int64
+        if field == F_RESID:
+            return (4096,), np.float64
         if field in (F_A, F_B):
             return (self.kernels_per_iter(),), np.float32
         if field == F_X:
             return (s[0],), np.float32
-        if p == HEAT2D:
+        if p in (HEAT2D, HEAT2D_SURROGATE):
             return (s[0], s[1]), np.float32
         if p == HEAT3D:
             return ((s[0], s[1], s[2]) if field == F_T else (s[1], s[2])), np.float32
@@ -195,6 +210,37 @@ class Problem:
         if arr.size != int(np.prod(shp)):
             raise KBError(EINVAL, f"field {field} needs {np.prod(shp)} values, got {arr.size}")
         _check(lib().kb_write(self._h, field, arr.ctypes.data_as(C.c_void_p), arr.nbytes, 0))
+
+    # -- surrogate training (KB_HEAT2D_SURROGATE) ------------------------------
+    @staticmethod
+    def _fields(T0, P, T16):
+        for t in (T0, P, T16):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.dim() == 3
+        assert T0.shape == P.shape == T16.shape
+        return T0.shape
+
+    def sg_loss_grad(self, T0, P, T16, crops, crop):
+        """(loss, gradient[19393]) on the crops (int array [n][3]: field,
+        y0, x0) of device fields T0, P, T16 ([nfield][H][W] float32)."""
+        nf, H, W = self._fields(T0, P, T16)
+        cr = np.ascontiguousarray(crops, dtype=np.int32)
+        loss = C.c_double()
+        grad = np.empty(SG_NW, np.float32)
+        _check(lib().kb_sg_loss_grad(self._h, C.c_void_p(T0.data_ptr()), C.c_void_p(P.data_ptr()),
+                                     C.c_void_p(T16.data_ptr()), nf, H, W, cr.ctypes.data_as(C.c_void_p),
+                                     cr.shape[0], int(crop), C.byref(loss),
+                                     grad.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, grad
+
+    def sg_train_step(self, T0, P, T16, crops, crop, lr):
+        """One Adam step on the crops; returns the batch loss before it."""
+        nf, H, W = self._fields(T0, P, T16)
+        cr = np.ascontiguousarray(crops, dtype=np.int32)
+        loss = C.c_double()
+        _check(lib().kb_sg_train_step(self._h, C.c_void_p(T0.data_ptr()), C.c_void_p(P.data_ptr()),
+                                      C.c_void_p(T16.data_ptr()), nf, H, W, cr.ctypes.data_as(C.c_void_p),
+                                      cr.shape[0], int(crop), float(lr), C.byref(loss)))
+        return loss.value
 
     def destroy(self):
         if self._h:

@@ -21,7 +21,7 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkbatch.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "heat.hip", "fdtd.hip", "kernels_misc.hip"]
+SOURCES = ["api.hip", "heat.hip", "fdtd.hip", "kernels_misc.hip", "surrogate.hip", "sg_api.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -32,6 +32,15 @@ namespace {
 
 thread_local std::string g_err;
 
+}  // namespace
+
+int kb::kb_set_error(int code, const char *msg) {
+  g_err = msg;
+  return code;
+}
+
+namespace {
+
 int fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -124,13 +133,21 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
       off[3] = L.add(red); off[4] = L.add(64);
       return true;
     }
+    case KB_HEAT2D_SURROGATE: {
+      const size_t sg = sg_workspace_bytes(shape, ndim);
+      if (!sg) return false;
+      L.total = sg;
+      off[3] = L.add(red); off[4] = L.add(64);
+      return true;
+    }
     default:
       return false;
   }
 }
 
 bool pingpong(const kb_problem *h) {
-  return h->kind == KB_HEAT2D || h->kind == KB_HEAT3D || h->kind == KB_HEAT2D_MULTI;
+  return h->kind == KB_HEAT2D || h->kind == KB_HEAT3D || h->kind == KB_HEAT2D_MULTI ||
+         h->kind == KB_HEAT2D_SURROGATE;
 }
 
 // Kernel variant in use: the option, or the default for the shape (vector
@@ -150,6 +167,7 @@ bool heat2d_is_tile(int v) { return v >= 2 && v <= 7; }
 
 // Temporal depth of one iteration.
 int iter_depth(const kb_problem *h) {
+  if (h->kind == KB_HEAT2D_SURROGATE) return sg_iter_depth(h);
   return (h->kind == KB_HEAT2D && heat2d_is_tile(heat2d_variant(h))) ? h->tdepth : 1;
 }
 
@@ -170,6 +188,13 @@ int fill_iter(const kb_problem *h, int cur, int depth, Launch *L) {
     case KB_HEAT3D: {
       Heat3DArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, (int)h->nz, (int)h->ny, (int)h->nx, h->hk};
       return make_heat3d(L[0], a, heat3d_variant(h)) ? 1 : -1;
+    }
+    case KB_HEAT2D_SURROGATE: {
+      if (depth == sg_iter_depth(h)) return sg_fill_iter(h, cur, L);
+      // leftover steps: plain single steps
+      Heat2DArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, (int)h->ny, (int)h->nx, h->hk, 1};
+      make_heat2d_direct(L[0], a);
+      return 1;
     }
     case KB_HEAT2D_MULTI: {
       MultiArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids_d, h->block_start_d, h->G, h->hk};
@@ -319,6 +344,9 @@ bool field_info(const kb_problem *h, int field, float **dev, size_t *bytes, bool
     case KB_F_STEP:
       if (h->kind != KB_FDTD3D) return false;
       *dev = reinterpret_cast<float *>(h->step); *bytes = 8; return true;
+    case KB_F_W: case KB_F_SGSTATS: case KB_F_RESID:
+      if (h->kind != KB_HEAT2D_SURROGATE) return false;
+      return sg_field(h, field, dev, bytes);
   }
   return false;
 }
@@ -401,6 +429,20 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       if ((rc = enqueue_init(h, h->Tbuf[0], h->nz * h->ny * h->nx, seed, kTagT0, 0, 323.0, 343.0)) ||
           (rc = enqueue_init(h, h->P, h->ny * h->nx, seed, kTagP, 0, 0.0, 1.0)))
         return bail(rc);
+      break;
+    }
+    case KB_HEAT2D_SURROGATE: {
+      if (ncoeffs != 0 && ncoeffs != 5 && ncoeffs != 8)
+        return bail(fail(KB_EINVAL, "surrogate coeffs: {c, Rx, Ry, Rz, Tamb[, s, threshold, k]}"));
+      if ((rc = check_heat_coeffs(coeffs, ncoeffs == 8 ? 5 : ncoeffs, 0, &h->hk)) != KB_OK) return bail(rc);
+      std::string err;
+      if ((rc = sg_create(h, shape, ndim, coeffs, ncoeffs, seed, err)) != KB_OK)
+        return bail(fail(rc, "%s", err.c_str()));
+      if ((rc = enqueue_init(h, h->Tbuf[0], h->ny * h->nx, seed, kTagT0, 0, 323.0, 343.0)) ||
+          (rc = enqueue_init(h, h->P, h->ny * h->nx, seed, kTagP, 0, 0.0, 1.0)))
+        return bail(rc);
+      if (sg_power_changed(h) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+        return bail(fail(KB_EHIP, "surrogate set-up failed"));
       break;
     }
     case KB_HEAT2D_MULTI: {
@@ -681,6 +723,11 @@ int kb_write(kb_problem *h, int field, const void *src, size_t bytes, int src_on
   } else {
     HIPCHK(hipMemcpy(dev, src, bytes, kind));
   }
+  if (h->kind == KB_HEAT2D_SURROGATE && (field == KB_F_W || field == KB_F_P)) {
+    // derived device data: the packed bf16 weights, the power sum
+    HIPCHK(field == KB_F_W ? sg_repack(h) : sg_power_changed(h));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
   return KB_OK;
 }
 
@@ -719,6 +766,7 @@ int kb_destroy(kb_problem *h) {
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+  if (h->sg) sg_destroy(h);
   delete h;
   return rc;
 }

@@ -13,33 +13,10 @@
 // These kernels are bandwidth- or latency-bound (about 12 bytes and 13 flops
 // per cell-step), so they use plain vector ALU work, coalesced row access
 // (one wave64 covers 64 consecutive floats of a row) and LDS tiles, not MFMA.
+#include "heat_update.h"
 #include "kb_internal.h"
 
 namespace kb {
-
-__device__ __forceinline__ float heat_update(float t, float tn, float ts, float tw, float te, float p,
-                                             const HeatCoef &k) {
-  float dns = (tn + ts) - (t + t);
-  float dew = (te + tw) - (t + t);
-  float acc = k.cz * (k.Tamb - t);
-  acc = fmaf(k.cx, dew, acc);
-  acc = fmaf(k.cy, dns, acc);
-  acc = fmaf(k.cP, p, acc);
-  return t + acc;
-}
-
-__device__ __forceinline__ float heat3d_update(float t, float tn, float ts, float tw, float te, float tu,
-                                               float td, float p, bool has_p, const HeatCoef &k) {
-  float dns = (tn + ts) - (t + t);
-  float dew = (te + tw) - (t + t);
-  float dud = (tu + td) - (t + t);
-  float acc = k.cz * (k.Tamb - t);
-  acc = fmaf(k.cx, dew, acc);
-  acc = fmaf(k.cz, dud, acc);
-  acc = fmaf(k.cy, dns, acc);
-  if (has_p) acc = fmaf(k.cP, p, acc);
-  return t + acc;
-}
 
 // ---------------------------------------------------------------------------
 // 2D direct kernel: one thread per cell, 64x4 threads per block.
@@ -87,6 +64,7 @@ constexpr int kMaxDepth = 16;
 template <int BX, int BY>
 __global__ __launch_bounds__(BX *BY) void heat2d_tile_kernel(const Heat2DArgs a) {
   extern __shared__ float sm[];
+  if (a.flag && *a.flag == 0) return;           // predicated launch (whole grid)
   const int t = a.tdepth;
   const int tiles_x = (a.nx + BX - 1) / BX;
   const int tiles_y = (a.ny + BY - 1) / BY;

@@ -89,6 +89,7 @@ struct Heat2DArgs {
   int ny, nx;
   HeatCoef k;
   int tdepth;                  // steps per launch (tile kernels)
+  const int *flag;             // tile kernels: run only if *flag != 0 (null: always)
 };
 
 struct Heat3DArgs {
@@ -151,6 +152,21 @@ bool make_fdtd_h(Launch &L, const FdtdArgs &a, int variant);   // false: bad var
 bool make_fdtd_e(Launch &L, const FdtdArgs &a, int variant);
 void make_fdtd_src(Launch &L, const SrcArgs &a);
 
+// Surrogate problem (sg_api.hip).
+struct SgState;
+size_t sg_workspace_bytes(const int64_t *shape, int ndim);
+int sg_create(kb_problem *h, const int64_t *shape, int ndim, const double *c, int nc, uint64_t seed,
+              std::string &err);
+void sg_destroy(kb_problem *h);
+int sg_iter_depth(const kb_problem *h);
+int sg_fill_iter(const kb_problem *h, int cur, Launch *L);
+bool sg_field(const kb_problem *h, int field, float **dev, size_t *bytes);
+hipError_t sg_repack(kb_problem *h);
+hipError_t sg_power_changed(kb_problem *h);
+
+// Record an error message for kb_last_error(); returns code.
+int kb_set_error(int code, const char *msg);
+
 // Deterministic reductions (enqueued on s; partials has >= reduce_max_blocks doubles).
 int reduce_max_blocks();
 hipError_t reduce_sum(const float *x, long long n, double *partials, double *result, hipStream_t s);
@@ -212,6 +228,8 @@ struct kb_problem {
   long long *step = nullptr;
   long long src = 0;
   int src_ijk[3] = {0, 0, 0};
+  // learned surrogate (KB_HEAT2D_SURROGATE)
+  kb::SgState *sg = nullptr;
   // reductions
   double *partials = nullptr;
   double *red = nullptr;
