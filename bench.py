@@ -74,6 +74,8 @@ KERNEL_RUNS = {
     "heat2d_16384": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 13, 5),
     "heat3d_8x4096": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 4, 5),
     "fdtd_256": ("FDTD3D", (256, 64), "FDTD_COEFFS", 2, 5),
+    "surrogate_512": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 1, 160),
+    "surrogate_512_layered": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 2, 160),
 }
 
 
@@ -84,8 +86,16 @@ def kernel_only(name):
     import paper_2501_09398_amd as kb
     prob, shape, co, var, steps = KERNEL_RUNS[name]
     coeffs = (K,) if co is None else getattr(kb, co)
+    if prob == "HEAT2D_SURROGATE":
+        import numpy as np
+        import synth
+        coeffs = tuple(coeffs) + (0.8, 1e30, 16)          # check never falls back
     with kb.Problem(getattr(kb, prob), shape, coeffs, SEED, device=0) as p:
         p.set_option(kb.OPT_TILE, var)
+        if prob == "HEAT2D_SURROGATE":                    # a network with every layer active
+            w = synth.surrogate_init(SEED)
+            w[19104:19393] = synth.uniform_f32(SEED, 9, 289, -0.06, 0.06)
+            p.write(kb.F_W, w.astype(np.float32))
         p.run(steps, 0)
         p.last_timing()
     torch.cuda.synchronize()
@@ -204,6 +214,41 @@ def workloads(kb, pm, autotune, np):
         d["hbm_frac"] = 72.0 * (N + 1) ** 3 / (d["graph_b100_us_step"] * 1e-6) / (HBM_PEAK_GBS * 1e9)
         out[f"fdtd_{N}^3_{n}"] = d
 
+    # learned 16-step surrogate at 512^2 (network, residual check and the
+    # predicated fallback in every block) vs the plain stencil
+    from paper_2501_09398_amd import sg_train
+    if os.path.exists(sg_train.WEIGHTS_FILE):
+        w = sg_train.load_weights()
+        N, k, n = 512, 16, 160
+        T0, _ = synth.heat2d_init(SEED, N, N)
+        P = synth.hot_spot_power(SEED, N, N)
+        d = {"steps": n, "cells": N * N, "k": k, "blocks": n // k}
+        for var, name in ((1, "fused"), (2, "per_layer")):
+            with kb.Problem(kb.HEAT2D_SURROGATE, (N, N), kb.HEAT_COEFFS + (0.8, 1e-3, k), SEED) as p:
+                p.set_option(kb.OPT_TILE, var)
+                p.write(kb.F_T, T0)
+                p.write(kb.F_P, P)
+                p.write(kb.F_W, w)
+                d[f"{name}_per_launch_us_block"] = arm(p, n, 0, 2) / (n // k) * 1e6
+                d[f"{name}_graph_b10_us_block"] = arm(p, n, 10, 2) / (n // k) * 1e6
+                st = p.read(kb.F_SGSTATS)
+                d[f"{name}_fallback_rate"] = float(st[1]) / max(1.0, float(st[0]))
+        tr = autotune.tune(kb, kb.HEAT2D, (N, N), kb.HEAT_COEFFS, n, seed=SEED, reps=2)
+        d["plain_autotuned"] = {"variant": tr.variant, "depth": tr.depth, "b": tr.b,
+                                "us_block": tr.us_per_step_warm * k}
+        d["speed_vs_plain"] = tr.us_per_step_warm * k / d["fused_graph_b10_us_block"]
+        # algorithmic MFMA work: 2 * (9*2*32 + 2 * 9*32*32 + 9*32) = 38,592 FLOP
+        # per pixel and application (10.12 GFLOP at 512^2), against the
+        # 2.5 PFLOP/s dense bf16 peak; the block time includes the check and
+        # the (predicated) fallback node
+        gflop = 38592.0 * N * N / 1e9
+        d["network_gflop"] = gflop
+        d["fused_block_tflops"] = gflop / (d["fused_graph_b10_us_block"] * 1e-6) / 1e3
+        d["fused_block_mfma_frac"] = d["fused_block_tflops"] / 2500.0
+        ev = sg_train.evaluate(w, [SEED + 1, SEED + 2])
+        d["accuracy_vs_plain_gpu"] = {key: max(r[key] for r in ev) for key in ev[0] if key != "seed"}
+        out["surrogate_512_k16"] = d
+
     # large grids against the HBM roofline (working sets >> 256 MB cache)
     big = {}
     for name, prob, shp, var, bytes_per_cell in (
@@ -262,10 +307,12 @@ def main():
     model = None
     if not args.no_sweep and args.arm != "per_launch":
         job(100)
+        graph_mem = []                          # (nodes, bytes) of each built graph
         for b in cands:
             reps = [job(b) for _ in range(args.sweep_reps)]
             sweep.append((b, float(np.median([t["t_create_s"] for t in reps])),
                           float(np.median([t["t_exec_s"] for t in reps]))))
+            graph_mem.append((K * b, float(np.median([t["graph_mem_bytes"] for t in reps]))))
         S = np.array([s[0] for s in sweep], float)
         model = pm.Model(pm.fit_creation(K * S, [s[1] for s in sweep]),
                          pm.fit_execution(S, [s[2] for s in sweep]), K=K)
@@ -385,6 +432,14 @@ def main():
                          # gap of a graph launch over a node-to-node gap
                          "T_a_minus_T_i_us": model.execution.a / ITERS * 1e6}
         line["sweep"] = [[s[0], round(s[1] * 1e3, 4), round(s[2] * 1e3, 4)] for s in sweep]
+        # graph memory footprint vs node count (Fig. 2's bars): least-squares
+        # bytes = m_node * nodes + m_0 over the sweep's graphs
+        gx = np.array([g[0] for g in graph_mem], float)
+        gy = np.array([g[1] for g in graph_mem], float)
+        if len(gx) >= 2 and np.ptp(gx) > 0:
+            m_node, m_0 = np.polyfit(gx, gy, 1)
+            line["graph_memory"] = {"bytes_per_node": float(m_node), "bytes_fixed": float(m_0),
+                                    "points": [[int(a), int(b)] for a, b in graph_mem]}
     print(json.dumps(line), flush=True)
 
 

@@ -108,7 +108,10 @@ extern "C" {
  *              T_k = T + s*y  (float32);
  *              residual r = max(r_mean, r_tile) (the mean of T against its
  *                  exact k-step recurrence; four seeded 32x32 tiles against
- *                  the plain stencil), both relative to max|T_k|;
+ *                  the plain stencil), both relative to max|T_k|; tile t
+ *                  has its origin at row floor(u*(ny-31)), column
+ *                  floor(u'*(nx-31)), u and u' the generator's draws 2t and
+ *                  2t+1 of stream 10 of the seed;
  *              if r > threshold the block is redone with k plain steps
  *                  from T (one predicated launch; the graph stays static).
  *            n_steps mod k steps run as plain steps.
@@ -142,6 +145,10 @@ extern "C" {
 #define KB_F_W     20   /* surrogate weights (float32[19393])           */
 #define KB_F_SGSTATS 21 /* surrogate blocks checked, fallbacks (int64[2]) */
 #define KB_F_RESID 22   /* surrogate residual per checked block (double[4096]) */
+#define KB_F_REDLOG 23  /* in-chain reduction log (double[4096][4]), see
+                           KB_OPT_REDUCE_EVERY                             */
+#define KB_F_REDCOUNT 24 /* entries appended to the log (one int64; it keeps
+                           counting past the log's 4096 rows)             */
 
 /* ---- options (kb_set_option) ------------------------------------------- */
 /* KB_OPT_BUILDER: how a batch graph is built.
@@ -161,7 +168,12 @@ extern "C" {
  *              2 = plain, 3 = next layer prefetched, 4 = prefetched with
  *              streaming stores.  Default: 4 if nx % 4 == 0 and
  *              ny*nx >= 2^20, else 1.
- *   KB_SKELETON: 1 = 4 elements per thread (default), 2 = 1, 3 = 8.     */
+ *   KB_SKELETON: 1 = 4 elements per thread (default), 2 = 1, 3 = 8.
+ *   KB_FDTD3D: 1 = one thread per cell, 2 = float4 rows (default).
+ *   KB_HEAT2D_SURROGATE: 1 = fused network, all activations in LDS, 3
+ *              kernels per block (default); 2 = one kernel per layer with
+ *              activations in HBM, 8 kernels per block.  The two agree to
+ *              float32 rounding of the last layer's sum, not bit for bit. */
 #define KB_OPT_TILE      2
 /* KB_OPT_TDEPTH: temporal-blocking depth t >= 1 for KB_HEAT2D: one launch
  *   of the LDS tile kernel advances t steps (1 <= t <= 16).                */
@@ -171,6 +183,29 @@ extern "C" {
 #define KB_OPT_GRAPH_CACHE 4
 /* KB_OPT_MAX_NODES: refuse graphs with more kernel nodes (default 65536). */
 #define KB_OPT_MAX_NODES 5
+/* KB_OPT_REDUCE_EVERY: m >= 1 appends a deterministic reduction of the
+ *   state after every m-th step to the iteration chain itself (two extra
+ *   kernels, recorded as graph nodes inside batch graphs, so a replayed
+ *   graph reduces with no host involvement): the sum of T (heat problems,
+ *   all grids together for KB_HEAT2D_MULTI), the sum of x (KB_SKELETON), or
+ *   E.E and H.H over the six FDTD fields.  Entry e of KB_F_REDLOG is
+ *   {(e+1)*m, value, second value or 0, 0}; KB_F_REDCOUNT counts entries.
+ *   Setting the option (also to 0 = off, the default) restarts the step
+ *   count and empties the log.  Needs one step per iteration (no temporal
+ *   blocking); not for KB_HEAT2D_SURROGATE.  Each graph batch is built for
+ *   its start phase (steps since the last reduction point), so b need not
+ *   divide m; at most 64 distinct batch graphs per kb_run.  Results are
+ *   bitwise independent of b and of the builder.                          */
+#define KB_OPT_REDUCE_EVERY 6
+/* KB_OPT_GRAPH_UPDATE: what a kb_write of arguments that are baked into
+ *   graph nodes (KB_F_A / KB_F_B of KB_SKELETON) does to the cached batch
+ *   graphs: 0 = drop them (the next kb_run rebuilds and pays T_C again;
+ *   default), 1 = refit each in place with hipGraphExecUpdate (the graph is
+ *   recorded again with the new arguments but not instantiated; a graph the
+ *   runtime refuses to update is dropped).  Either way the results are the
+ *   same bits.  The paper notes that graphs are hard to change once built
+ *   (Sec. II); this measures what an in-place update costs on MI355X.     */
+#define KB_OPT_GRAPH_UPDATE 7
 
 typedef struct kb_problem kb_problem;
 
@@ -186,6 +221,16 @@ typedef struct kb_timing {
     int64_t n_peeled;         /* iterations run per launch (remainder)     */
     int64_t n_kernel_launches;/* individual kernel launches                */
     int64_t n_graphs_built;   /* graphs built by this call (cache misses)  */
+    int64_t graph_mem_bytes;  /* drop of the device's free memory across
+                                 building, instantiating and uploading
+                                 those graphs (hipMemGetInfo; the graphs'
+                                 own footprint on an otherwise idle device,
+                                 the quantity of the paper's Fig. 2 bars) */
+    double t_update_s;        /* host time of the last kb_write that changed
+                                 arguments baked into graph nodes (skeleton
+                                 a_k, b_k): refitting (KB_OPT_GRAPH_UPDATE=1)
+                                 or dropping the cached graphs            */
+    int64_t n_graphs_updated; /* graphs refitted in place by that write    */
 } kb_timing;
 
 /* Device bytes kb_create() needs for this problem and shape; 0 if the

@@ -27,10 +27,12 @@ HEAT2D, HEAT3D, SKELETON, FDTD3D, HEAT2D_MULTI, HEAT2D_SURROGATE = 1, 2, 3, 4, 5
 F_T, F_P, F_X, F_A, F_B = 1, 2, 3, 4, 5
 F_EX, F_EY, F_EZ, F_HX, F_HY, F_HZ, F_PROBE, F_STEP = 10, 11, 12, 13, 14, 15, 16, 17
 F_W, F_SGSTATS, F_RESID = 20, 21, 22
+F_REDLOG, F_REDCOUNT = 23, 24
 SG_NW = 19393
 FDTD_FIELDS = {"Ex": F_EX, "Ey": F_EY, "Ez": F_EZ, "Hx": F_HX, "Hy": F_HY, "Hz": F_HZ}
 # options
-OPT_BUILDER, OPT_TILE, OPT_TDEPTH, OPT_GRAPH_CACHE, OPT_MAX_NODES = 1, 2, 3, 4, 5
+OPT_BUILDER, OPT_TILE, OPT_TDEPTH, OPT_GRAPH_CACHE, OPT_MAX_NODES, OPT_REDUCE_EVERY = 1, 2, 3, 4, 5, 6
+OPT_GRAPH_UPDATE = 7
 # status
 OK, EINVAL, ENOMEM, EHIP, ESTATE, WFALLBACK = 0, -1, -2, -3, -4, 1
 
@@ -45,7 +47,8 @@ class Timing(C.Structure):
     _fields_ = [("t_create_s", C.c_double), ("t_exec_s", C.c_double),
                 ("n_graph_launches", C.c_int64), ("n_nodes", C.c_int64),
                 ("n_peeled", C.c_int64), ("n_kernel_launches", C.c_int64),
-                ("n_graphs_built", C.c_int64)]
+                ("n_graphs_built", C.c_int64), ("graph_mem_bytes", C.c_int64),
+                ("t_update_s", C.c_double), ("n_graphs_updated", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -179,6 +182,10 @@ class Problem:
             return (2,), np.int64
         if field == F_RESID:
             return (4096,), np.float64
+        if field == F_REDLOG:
+            return (4096, 4), np.float64
+        if field == F_REDCOUNT:
+            return (1,), np.int64
         if field in (F_A, F_B):
             return (self.kernels_per_iter(),), np.float32
         if field == F_X:
@@ -191,6 +198,12 @@ class Problem:
             return (sum(s[1 + 2 * g] * s[2 + 2 * g] for g in range(s[0])),), np.float32
         raise KBError(EINVAL, f"unknown field {field}")
 
+    def reduction_log(self):
+        """Entries of the in-chain reduction log (KB_OPT_REDUCE_EVERY):
+        array [count][4] of {step, value, second value, 0}."""
+        n = int(self.read(F_REDCOUNT)[0])
+        return self.read(F_REDLOG)[:min(n, 4096)]
+
     def read(self, field):
         """Copy a field to a new host numpy array (synchronises the stream)."""
         shp, dt = self.field_shape(field)
@@ -198,9 +211,17 @@ class Problem:
         _check(lib().kb_read(self._h, field, out.ctypes.data_as(C.c_void_p), out.nbytes, 0))
         return out
 
+    def _after_torch(self):
+        """Order the problem's stream after the work torch has queued so
+        far (device tensors handed to the library may still be in flight on
+        torch's current stream)."""
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
     def read_device(self, field, out: torch.Tensor):
-        """Copy a field into a contiguous device tensor of the same byte size."""
+        """Copy a field into a contiguous device tensor of the same byte size
+        (synchronous: the copy is complete on return)."""
         assert out.is_cuda and out.is_contiguous()
+        self._after_torch()
         _check(lib().kb_read(self._h, field, C.c_void_p(out.data_ptr()), out.numel() * out.element_size(), 1))
         return out
 
@@ -226,6 +247,7 @@ class Problem:
         cr = np.ascontiguousarray(crops, dtype=np.int32)
         loss = C.c_double()
         grad = np.empty(SG_NW, np.float32)
+        self._after_torch()
         _check(lib().kb_sg_loss_grad(self._h, C.c_void_p(T0.data_ptr()), C.c_void_p(P.data_ptr()),
                                      C.c_void_p(T16.data_ptr()), nf, H, W, cr.ctypes.data_as(C.c_void_p),
                                      cr.shape[0], int(crop), C.byref(loss),
@@ -237,6 +259,7 @@ class Problem:
         nf, H, W = self._fields(T0, P, T16)
         cr = np.ascontiguousarray(crops, dtype=np.int32)
         loss = C.c_double()
+        self._after_torch()
         _check(lib().kb_sg_train_step(self._h, C.c_void_p(T0.data_ptr()), C.c_void_p(P.data_ptr()),
                                       C.c_void_p(T16.data_ptr()), nf, H, W, cr.ctypes.data_as(C.c_void_p),
                                       cr.shape[0], int(crop), float(lr), C.byref(loss)))

@@ -18,6 +18,7 @@
 // step (the FDTD source time) lives on the device instead.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -81,14 +82,19 @@ int64_t fdtd_pitch(int64_t N) { return (N + 1 + 3) / 4 * 4; }
 // shape.  Offsets are written to off[] in the order documented per problem.
 bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off) {
   if (!shape || ndim < 1) return false;
-  const size_t red = (size_t)reduce_max_blocks() * sizeof(double);
+  const size_t red = 2 * (size_t)reduce_max_blocks() * sizeof(double);
+  // reduction partials, result, and the log of in-chain reductions
+  auto common = [&]() {
+    off[3] = L.add(red); off[4] = L.add(64);
+    off[16] = L.add((size_t)kRedLogCap * 4 * sizeof(double)); off[17] = L.add(8);
+  };
   switch (problem) {
     case KB_HEAT2D: {
       if (ndim != 2 || !heat_shape_ok(shape[0]) || !heat_shape_ok(shape[1])) return false;
       const int64_t n = shape[0] * shape[1];
       if (n > ((int64_t)1 << 31) - 1) return false;
       off[0] = L.add(n * 4); off[1] = L.add(n * 4); off[2] = L.add(n * 4);
-      off[3] = L.add(red); off[4] = L.add(64);
+      common();
       return true;
     }
     case KB_HEAT3D: {
@@ -97,13 +103,13 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
       const int64_t n = shape[0] * plane;
       if (n > ((int64_t)1 << 31) - 1) return false;
       off[0] = L.add(n * 4); off[1] = L.add(n * 4); off[2] = L.add(plane * 4);
-      off[3] = L.add(red); off[4] = L.add(64);
+      common();
       return true;
     }
     case KB_SKELETON: {
       if (ndim != 1 || shape[0] < 1 || shape[0] > ((int64_t)1 << 31) - 1) return false;
       off[0] = L.add(shape[0] * 4);
-      off[3] = L.add(red); off[4] = L.add(64);
+      common();
       return true;
     }
     case KB_FDTD3D: {
@@ -115,7 +121,7 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
       off[11] = L.add(kGCap * 4);
       off[12] = L.add((pcap > 0 ? pcap : 1) * 4);
       off[13] = L.add(8);
-      off[3] = L.add(red); off[4] = L.add(64);
+      common();
       return true;
     }
     case KB_HEAT2D_MULTI: {
@@ -130,7 +136,7 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
       if (total > ((int64_t)1 << 31) - 1) return false;
       off[0] = L.add(total * 4); off[1] = L.add(total * 4); off[2] = L.add(total * 4);
       off[14] = L.add(G * sizeof(GridDesc)); off[15] = L.add((G + 1) * sizeof(int));
-      off[3] = L.add(red); off[4] = L.add(64);
+      common();
       return true;
     }
     case KB_HEAT2D_SURROGATE: {
@@ -171,9 +177,45 @@ int iter_depth(const kb_problem *h) {
   return (h->kind == KB_HEAT2D && heat2d_is_tile(heat2d_variant(h))) ? h->tdepth : 1;
 }
 
-// Fill the K launch descriptors of one iteration that starts from buffer
-// parity `cur` and advances `depth` steps.
-int fill_iter(const kb_problem *h, int cur, int depth, Launch *L) {
+// The two launches of an in-chain reduction of the state after an
+// iteration that started from parity `cur`: the sum of T (heat problems),
+// of x (skeleton), or E.E and H.H (FDTD).
+int fill_reduce(const kb_problem *h, int cur, Launch *L) {
+  RedLogArgs a{};
+  if (pingpong(h)) {
+    const float *f[1] = {h->Tbuf[1 - cur]};
+    const long long n = h->kind == KB_HEAT2D_MULTI ? h->total_cells : h->nz * h->ny * h->nx;
+    a = reduce_log_args(f, 1, 1, 0, n, h->partials, h->redlog, h->redcount, h->red_every);
+  } else if (h->kind == KB_SKELETON) {
+    const float *f[1] = {h->x};
+    a = reduce_log_args(f, 1, 1, 0, h->n, h->partials, h->redlog, h->redcount, h->red_every);
+  } else {
+    // padded FDTD arrays: the padding columns hold zeros and add nothing
+    const long long n = (long long)(h->N + 1) * (h->N + 1) * h->pitch;
+    a = reduce_log_args(h->F, 6, 2, 1, n, h->partials, h->redlog, h->redcount, h->red_every);
+  }
+  make_reduce_log(L[0], L[1], a);
+  return 2;
+}
+
+// Does the iteration that starts `steps_before` steps after the reduction
+// option was set end on a reduction point?
+bool reduce_due(const kb_problem *h, int64_t steps_before, int depth) {
+  return h->red_every > 0 && (steps_before + depth) % h->red_every == 0;
+}
+
+int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L);
+
+// Fill the launch descriptors of one iteration that starts from buffer
+// parity `cur` and advances `depth` steps, plus the reduction after it when
+// reduce_after is set.
+int fill_iter(const kb_problem *h, int cur, int depth, Launch *L, bool reduce_after) {
+  const int k = fill_iter_kernels(h, cur, depth, L);
+  if (k < 0 || !reduce_after) return k;
+  return k + fill_reduce(h, cur, L + k);
+}
+
+int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
   switch (h->kind) {
     case KB_HEAT2D: {
       Heat2DArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, (int)h->ny, (int)h->nx, h->hk, depth};
@@ -225,7 +267,8 @@ constexpr int kMaxK = 16;
 // Enqueue one iteration per launch on stream s; returns a KB status.
 int launch_iter(kb_problem *h, int depth, hipStream_t s) {
   Launch L[kMaxK];
-  const int k = fill_iter(h, h->cur, depth, L);
+  const int k = fill_iter(h, h->cur, depth, L, reduce_due(h, h->step_count, depth));
+  h->step_count += depth;
   if (k < 0) return fail(KB_EINVAL, "invalid kernel variant %d / depth %d", h->tile, depth);
   for (int q = 0; q < k; ++q) {
     HIPCHK(hipLaunchKernel(L[q].func, L[q].grid, L[q].block, L[q].params(), L[q].lds, s));
@@ -239,18 +282,20 @@ void clear_cache(kb_problem *h) {
   h->cache_map.clear();
 }
 
-// Build, instantiate and upload the graph of b iterations starting from
-// buffer parity `parity` (Listing 3, "Building").
-int build_graph(kb_problem *h, int64_t b, int depth, int parity, hipGraphExec_t *out) {
+// Record the graph of b iterations starting from buffer parity `parity`,
+// `phase` steps after a reduction point (Listing 3, "Building"): explicit
+// kernel nodes or stream capture of the per-launch loop.
+int make_graph(kb_problem *h, int64_t b, int depth, int parity, int64_t phase, hipGraph_t *out) {
   hipGraph_t g = nullptr;
   const int saved = h->cur;
+  const int64_t saved_steps = h->step_count;
   if (h->builder == 0) {
     HIPCHK(hipGraphCreate(&g, 0));
     hipGraphNode_t prev = nullptr;
     int c = parity;
     Launch L[kMaxK];
     for (int64_t j = 0; j < b; ++j) {
-      const int k = fill_iter(h, c, depth, L);
+      const int k = fill_iter(h, c, depth, L, reduce_due(h, phase + j * depth, depth));
       if (k < 0) { (void)hipGraphDestroy(g); return fail(KB_EINVAL, "invalid kernel variant"); }
       for (int q = 0; q < k; ++q) {
         hipKernelNodeParams np{};
@@ -273,13 +318,24 @@ int build_graph(kb_problem *h, int64_t b, int depth, int parity, hipGraphExec_t 
   } else {
     HIPCHK(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
     h->cur = parity;
+    h->step_count = phase;
     int rc = KB_OK;
     for (int64_t j = 0; j < b && rc == KB_OK; ++j) rc = launch_iter(h, depth, h->capture_stream);
     hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
     h->cur = saved;
+    h->step_count = saved_steps;
     if (rc != KB_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) return fail(KB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
   }
+  *out = g;
+  return KB_OK;
+}
+
+// Build, instantiate and upload one batch graph.
+int build_graph(kb_problem *h, int64_t b, int depth, int parity, int64_t phase, hipGraphExec_t *out) {
+  hipGraph_t g = nullptr;
+  const int rc = make_graph(h, b, depth, parity, phase, &g);
+  if (rc != KB_OK) return rc;
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipGraphInstantiateWithFlags(&exec, g, 0);
   (void)hipGraphDestroy(g);
@@ -288,6 +344,35 @@ int build_graph(kb_problem *h, int64_t b, int depth, int parity, hipGraphExec_t 
   if (e != hipSuccess) { (void)hipGraphExecDestroy(exec); return fail(KB_EHIP, "hipGraphUpload: %s", hipGetErrorString(e)); }
   *out = exec;
   return KB_OK;
+}
+
+// Kernel arguments baked into the nodes changed (skeleton coefficients):
+// refit every cached executable graph in place (record the graph again
+// with the new arguments, hipGraphExecUpdate: same topology, new node
+// parameters, no instantiation) or, where that is refused, drop it.
+// Returns the number of graphs updated.
+int64_t update_cached(kb_problem *h) {
+  int64_t updated = 0;
+  for (auto it = h->cache_map.begin(); it != h->cache_map.end();) {
+    const auto &k = it->first;
+    hipGraph_t g = nullptr;
+    bool ok = make_graph(h, std::get<0>(k), std::get<1>(k), std::get<3>(k), std::get<4>(k), &g) == KB_OK;
+    if (ok) {
+      hipGraphNode_t err_node = nullptr;
+      hipGraphExecUpdateResult res = hipGraphExecUpdateSuccess;
+      ok = hipGraphExecUpdate(it->second, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+      (void)hipGraphDestroy(g);
+    }
+    if (ok) {
+      ++updated;
+      ++it;
+    } else {
+      (void)hipGraphExecDestroy(it->second);
+      it = h->cache_map.erase(it);
+    }
+  }
+  g_err.clear();
+  return updated;
 }
 
 double now_s() {
@@ -347,6 +432,12 @@ bool field_info(const kb_problem *h, int field, float **dev, size_t *bytes, bool
     case KB_F_W: case KB_F_SGSTATS: case KB_F_RESID:
       if (h->kind != KB_HEAT2D_SURROGATE) return false;
       return sg_field(h, field, dev, bytes);
+    case KB_F_REDLOG:
+      if (!h->redlog) return false;
+      *dev = reinterpret_cast<float *>(h->redlog); *bytes = (size_t)kRedLogCap * 4 * sizeof(double); return true;
+    case KB_F_REDCOUNT:
+      if (!h->redcount) return false;
+      *dev = reinterpret_cast<float *>(h->redcount); *bytes = sizeof(long long); return true;
   }
   return false;
 }
@@ -371,13 +462,13 @@ int check_heat_coeffs(const double *c, int nc, int layers3d, HeatCoef *k) {
 
 extern "C" {
 
-int kb_abi_version(void) { return 1; }
+int kb_abi_version(void) { return 2; }
 
 const char *kb_last_error(void) { return g_err.c_str(); }
 
 size_t kb_workspace_bytes(int problem, const int64_t *shape, int ndim) {
   Layout L;
-  size_t off[16] = {0};
+  size_t off[20] = {0};
   if (!layout(problem, shape, ndim, L, off)) return 0;
   return L.total;
 }
@@ -391,7 +482,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
   *out = nullptr;
   if (ncoeffs < 0 || (ncoeffs > 0 && !coeffs)) return fail(KB_EINVAL, "bad coefficient array");
   Layout Lay;
-  size_t off[16] = {0};
+  size_t off[20] = {0};
   if (!layout(problem, shape, ndim, Lay, off)) return fail(KB_EINVAL, "invalid problem %d or shape", problem);
   if (!workspace || ws_bytes < Lay.total)
     return fail(KB_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, Lay.total);
@@ -407,6 +498,10 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
   auto P = [&](size_t o) { return reinterpret_cast<float *>(h->ws + o); };
   h->partials = reinterpret_cast<double *>(h->ws + off[3]);
   h->red = reinterpret_cast<double *>(h->ws + off[4]);
+  if (problem != KB_HEAT2D_SURROGATE) {
+    h->redlog = reinterpret_cast<double *>(h->ws + off[16]);
+    h->redcount = reinterpret_cast<long long *>(h->ws + off[17]);
+  }
 
   int rc = KB_OK;
   auto bail = [&](int code) { kb_destroy(h); return code; };
@@ -548,6 +643,8 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       break;
     }
   }
+  if (h->redcount && hipMemsetAsync(h->redcount, 0, sizeof(long long), h->stream) != hipSuccess)
+    return bail(fail(KB_EHIP, "hipMemsetAsync failed"));
   *out = h;
   return KB_OK;
 }
@@ -565,10 +662,12 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       else if (h->kind == KB_HEAT3D) ok = value == 0 || value == 1 || (value >= 2 && value <= 4 && h->nx % 4 == 0);
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
       else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 2;
+      else if (h->kind == KB_HEAT2D_SURROGATE) ok = value >= 0 && value <= 2;
       else ok = value == 0;
       if (!ok) return fail(KB_EINVAL, "kernel variant %lld not available for this problem", (long long)value);
       if (h->tile != value) clear_cache(h);
       h->tile = (int)value;
+      if (h->kind == KB_HEAT2D_SURROGATE) h->K = sg_kernels_per_block(h);
       break;
     }
     case KB_OPT_TDEPTH:
@@ -585,6 +684,18 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
     case KB_OPT_MAX_NODES:
       if (value < 1) return fail(KB_EINVAL, "max nodes must be >= 1");
       h->max_nodes = value;
+      break;
+    case KB_OPT_GRAPH_UPDATE:
+      if (value != 0 && value != 1) return fail(KB_EINVAL, "graph update must be 0 or 1");
+      h->graph_update = (int)value;
+      break;
+    case KB_OPT_REDUCE_EVERY:
+      if (h->kind == KB_HEAT2D_SURROGATE) return fail(KB_EINVAL, "the surrogate has its own residual check");
+      if (value < 0) return fail(KB_EINVAL, "reduction interval must be >= 0");
+      clear_cache(h);
+      h->red_every = value;
+      h->step_count = 0;
+      HIPCHK(hipMemsetAsync(h->redcount, 0, sizeof(long long), h->stream));
       break;
     default:
       return fail(KB_EINVAL, "unknown option %d", option);
@@ -606,25 +717,45 @@ int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b) {
     return fail(KB_EINVAL, "batch of %lld iterations x %d kernels exceeds %lld graph nodes", (long long)batch_b, h->K,
                 (long long)h->max_nodes);
 
+  if (h->red_every > 0 && (depth != 1 || rem_steps != 0))
+    return fail(KB_EINVAL, "in-chain reductions need one step per iteration (no temporal blocking)");
+
+  // Replay j starts from buffer parity cur_j and phase ph_j = steps since
+  // the last reduction point; both are periodic in j, and each distinct
+  // (parity, phase) pair has its own executable graph.
+  using Key = std::tuple<int64_t, int, int, int, int64_t>;
   int64_t nb = 0, peel = n_iter;
-  hipGraphExec_t execs[2] = {nullptr, nullptr};
+  std::map<std::pair<int, int64_t>, hipGraphExec_t> execs;
   if (batch_b > 0 && n_iter >= batch_b) {
     nb = n_iter / batch_b;
     peel = n_iter % batch_b;
-    // parities the replays start from
-    int need[2] = {h->cur, -1};
-    if (pp && (batch_b & 1) && nb > 1) need[1] = h->cur ^ 1;
+    const int64_t m = h->red_every;
+    const bool flip = pp && (batch_b & 1);
+    std::vector<std::pair<int, int64_t>> need;
+    int c = h->cur;
+    int64_t ph = m > 0 ? h->step_count % m : 0;
+    const int64_t period = 2 * (m > 0 ? m : 1);
+    for (int64_t j = 0; j < std::min(nb, period); ++j) {
+      std::pair<int, int64_t> q{pp ? c : 0, ph};
+      if (std::find(need.begin(), need.end(), q) == need.end()) need.push_back(q);
+      if (flip) c ^= 1;
+      if (m > 0) ph = (ph + batch_b * depth) % m;
+    }
+    if (need.size() > 64)
+      return fail(KB_EINVAL, "batch %lld and reduction interval %lld need %zu distinct graphs (max 64)",
+                  (long long)batch_b, (long long)m, need.size());
+    size_t free0 = 0, free1 = 0, total = 0;
+    const bool have_mem = hipMemGetInfo(&free0, &total) == hipSuccess;
     const double t0 = now_s();
-    for (int q = 0; q < 2 && status == KB_OK; ++q) {
-      if (need[q] < 0) continue;
-      auto key = std::make_tuple(batch_b, depth, h->tile, pp ? need[q] : 0);
+    for (const auto &q : need) {
+      const Key key = std::make_tuple(batch_b, depth, h->tile, q.first, q.second);
       auto it = h->cache_map.find(key);
-      if (it != h->cache_map.end()) { execs[need[q]] = it->second; continue; }
+      if (it != h->cache_map.end()) { execs[q] = it->second; continue; }
       hipGraphExec_t ex = nullptr;
-      int rc = build_graph(h, batch_b, depth, need[q], &ex);
+      int rc = build_graph(h, batch_b, depth, q.first, q.second, &ex);
       if (rc != KB_OK) { status = KB_WFALLBACK; break; }
       h->cache_map[key] = ex;
-      execs[need[q]] = ex;
+      execs[q] = ex;
       t.n_graphs_built++;
     }
     if (t.n_graphs_built > 0) {
@@ -632,14 +763,18 @@ int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b) {
       if (e != hipSuccess) return fail(KB_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
     }
     t.t_create_s = now_s() - t0;
+    if (have_mem && t.n_graphs_built > 0 && hipMemGetInfo(&free1, &total) == hipSuccess)
+      t.graph_mem_bytes = (int64_t)free0 - (int64_t)free1;
     if (status == KB_WFALLBACK) { nb = 0; peel = n_iter; }
   }
 
   HIPCHK(hipEventRecord(h->ev0, h->stream));
   for (int64_t j = 0; j < nb; ++j) {
-    hipGraphExec_t ex = execs[pp ? h->cur : 0];
+    const int64_t ph = h->red_every > 0 ? h->step_count % h->red_every : 0;
+    hipGraphExec_t ex = execs[std::make_pair(pp ? h->cur : 0, ph)];
     HIPCHK(hipGraphLaunch(ex, h->stream));
     if (pp && (batch_b & 1)) h->cur ^= 1;
+    h->step_count += batch_b * depth;
   }
   for (int64_t j = 0; j < peel; ++j) {
     int rc = launch_iter(h, depth, h->stream);
@@ -672,6 +807,8 @@ int kb_last_timing(kb_problem *h, kb_timing *out) {
   HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   *out = h->last;
   out->t_exec_s = ms * 1e-3;
+  out->t_update_s = h->t_update_s;
+  out->n_graphs_updated = h->n_updated;
   return KB_OK;
 }
 
@@ -713,7 +850,11 @@ int kb_write(kb_problem *h, int field, const void *src, size_t bytes, int src_on
     std::vector<float> &v = field == KB_F_A ? h->a : h->b;
     if (src_on_device) HIPCHK(hipMemcpy(v.data(), src, bytes, hipMemcpyDeviceToHost));
     else std::memcpy(v.data(), src, bytes);
-    clear_cache(h);   // a_k, b_k are baked into graph nodes
+    // a_k, b_k are baked into graph nodes
+    const double t0 = now_s();
+    if (h->graph_update) h->n_updated = update_cached(h);
+    else clear_cache(h);
+    h->t_update_s = now_s() - t0;
     return KB_OK;
   }
   const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;

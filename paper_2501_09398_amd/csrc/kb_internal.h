@@ -160,12 +160,31 @@ int sg_create(kb_problem *h, const int64_t *shape, int ndim, const double *c, in
 void sg_destroy(kb_problem *h);
 int sg_iter_depth(const kb_problem *h);
 int sg_fill_iter(const kb_problem *h, int cur, Launch *L);
+int sg_kernels_per_block(const kb_problem *h);
 bool sg_field(const kb_problem *h, int field, float **dev, size_t *bytes);
 hipError_t sg_repack(kb_problem *h);
 hipError_t sg_power_changed(kb_problem *h);
 
 // Record an error message for kb_last_error(); returns code.
 int kb_set_error(int code, const char *msg);
+
+// Reductions recorded inside the iteration chain (every m steps): pass 1
+// writes per-block partials of each group of fields, pass 2 sums them in a
+// fixed order and appends {step, value_0, value_1, 0} to a device log at
+// the index held by a device counter, which it then increments.
+struct RedLogArgs {
+  const float *f[6];
+  int nf, ngroups, square, nb;  // nf fields, split evenly into ngroups sums
+  long long n, chunk;           // elements per field, elements per block
+  double *partials;             // [ngroups][nb]
+  double *log;                  // [cap][4]
+  long long *count;
+  long long cap, every;
+};
+constexpr long long kRedLogCap = 4096;
+void make_reduce_log(Launch &L1, Launch &L2, const RedLogArgs &a);
+RedLogArgs reduce_log_args(const float *const *fields, int nf, int ngroups, int square, long long n, double *partials,
+                           double *log, long long *count, long long every);
 
 // Deterministic reductions (enqueued on s; partials has >= reduce_max_blocks doubles).
 int reduce_max_blocks();
@@ -200,6 +219,9 @@ struct kb_problem {
   int tdepth = 1;
   int cache = 1;
   int64_t max_nodes = 65536;
+  int graph_update = 0;         // 1: refit cached graphs when node arguments change
+  double t_update_s = 0;        // host time of the last refit / invalidation
+  int64_t n_updated = 0;        // graphs refitted by it
 
   // heat
   float *Tbuf[2] = {nullptr, nullptr};
@@ -231,11 +253,15 @@ struct kb_problem {
   // learned surrogate (KB_HEAT2D_SURROGATE)
   kb::SgState *sg = nullptr;
   // reductions
-  double *partials = nullptr;
+  double *partials = nullptr;   // 2 * reduce_max_blocks doubles
   double *red = nullptr;
+  int64_t red_every = 0;        // in-chain reduction every m steps (0: off)
+  int64_t step_count = 0;       // steps since red_every was set
+  double *redlog = nullptr;     // [kRedLogCap][4]
+  long long *redcount = nullptr;
 
-  // graphs: key (b, tdepth, tile, cur) -> exec graph
-  std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> cache_map;
+  // graphs: key (b, tdepth, tile, start parity, start step mod red_every)
+  std::map<std::tuple<int64_t, int, int, int, int64_t>, hipGraphExec_t> cache_map;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   kb_timing last{};
   bool timed = false;

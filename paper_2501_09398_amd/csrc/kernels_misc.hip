@@ -113,6 +113,62 @@ __global__ __launch_bounds__(256) void reduce_pass2(const double *partials, int 
   if (threadIdx.x == 0) *out = r;
 }
 
+// In-chain reductions (see RedLogArgs).  Pass 1: grid (nb, ngroups).
+__global__ __launch_bounds__(256) void reduce_log_pass1(const RedLogArgs a) {
+  const int g = blockIdx.y, per = a.nf / a.ngroups;
+  const long long lo = (long long)blockIdx.x * a.chunk;
+  const long long hi = min(lo + a.chunk, a.n);
+  double acc = 0.0;
+  for (int q = 0; q < per; ++q) {
+    const float *x = a.f[g * per + q];
+    for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+      const double v = (double)x[i];
+      acc += a.square ? v * v : v;
+    }
+  }
+  const double r = block_sum(acc);
+  if (threadIdx.x == 0) a.partials[g * a.nb + blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void reduce_log_pass2(const RedLogArgs a) {
+  double v[2] = {0.0, 0.0};
+  for (int g = 0; g < a.ngroups; ++g) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < a.nb; i += 256) acc += a.partials[g * a.nb + i];
+    v[g] = block_sum(acc);
+    __syncthreads();                       // block_sum's LDS is reused
+  }
+  if (threadIdx.x == 0) {
+    const long long c = *a.count;
+    if (c >= 0 && c < a.cap) {
+      double *e = a.log + c * 4;
+      e[0] = (double)((c + 1) * a.every);
+      e[1] = v[0];
+      e[2] = v[1];
+      e[3] = 0.0;
+    }
+    *a.count = c + 1;
+  }
+}
+
+RedLogArgs reduce_log_args(const float *const *fields, int nf, int ngroups, int square, long long n, double *partials,
+                           double *log, long long *count, long long every) {
+  RedLogArgs a{};
+  for (int q = 0; q < nf && q < 6; ++q) a.f[q] = fields[q];
+  long long chunk = (n + kRedBlocks - 1) / kRedBlocks;
+  chunk = ((chunk + 1023) / 1024) * 1024;
+  if (chunk < 1024) chunk = 1024;
+  a.nf = nf; a.ngroups = ngroups; a.square = square; a.n = n; a.chunk = chunk;
+  a.nb = n > 0 ? (int)((n + chunk - 1) / chunk) : 1;
+  a.partials = partials; a.log = log; a.count = count; a.cap = kRedLogCap; a.every = every;
+  return a;
+}
+
+void make_reduce_log(Launch &L1, Launch &L2, const RedLogArgs &a) {
+  L1.set((const void *)reduce_log_pass1, dim3(a.nb, a.ngroups), dim3(256), 0, a);
+  L2.set((const void *)reduce_log_pass2, dim3(1), dim3(256), 0, a);
+}
+
 static hipError_t reduce_impl(const float *const *f, int nf, int square, long long n, double *partials,
                               double *result, hipStream_t s) {
   long long chunk = (n + kRedBlocks - 1) / kRedBlocks;

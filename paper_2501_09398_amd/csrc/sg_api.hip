@@ -3,6 +3,7 @@
 // the training entry points (loss and gradient, Adam step).
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <new>
 
 #include "kb_internal.h"
@@ -16,6 +17,7 @@ constexpr int kSgHistCap = 4096;
 constexpr int kSgRedBlocks = 256;
 constexpr int kSgLossBlocks = 256;
 constexpr int kSgMaxCrops = 1024;
+constexpr int kSgMaxNet = 1024;           // persistent blocks of the fused kernel
 
 // Workspace offsets of the surrogate problem.
 struct SgLayout {
@@ -23,7 +25,7 @@ struct SgLayout {
   size_t T[2], P, x, act[2];
   size_t T0c, Pc, tgt, xt, a[3], z[3], yt, g4, g[2], pw, pb, lossp, loss, crops;
   size_t w, grad, m, v, fwd1, fwd2, fwd3, fwd4, bwd2, bwd3, bwd4;
-  size_t chk, psum, flag, hist, counters;
+  size_t chk, plain, psum, flag, hist, counters;
 };
 
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
@@ -46,7 +48,8 @@ bool sg_layout(const int64_t *shape, int ndim, SgLayout &L) {
   L.w = add(kSgNW * 4); L.grad = add(kSgNW * 4); L.m = add(kSgNW * 4); L.v = add(kSgNW * 4);
   L.fwd1 = add(1024 * 2); L.fwd2 = add(9216 * 2); L.fwd3 = add(9216 * 2); L.fwd4 = add(288 * 2);
   L.bwd2 = add(9216 * 2); L.bwd3 = add(9216 * 2); L.bwd4 = add(1024 * 2);
-  L.chk = add((kSgRedBlocks * 3 + 4) * 8); L.psum = add(8); L.flag = add(4);
+  L.chk = add((size_t)(kSgMaxNet > kSgRedBlocks ? kSgMaxNet : kSgRedBlocks) * 3 * 8);
+  L.plain = add(4 * 32 * 32 * 4); L.psum = add(8); L.flag = add(4);
   L.hist = add(kSgHistCap * 8); L.counters = add(16);
   L.total = o;
   return true;
@@ -61,6 +64,7 @@ struct SgState {
   double threshold = 1e-3;
   long long adam_t = 0;
   int tile_y[4], tile_x[4];
+  int tiles_x = 0, ntiles = 0, nnet = 0;   // fused kernel: output tiles, persistent blocks
   template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
 
@@ -109,7 +113,15 @@ int sg_create(kb_problem *h, const int64_t *shape, int ndim, const double *c, in
   h->Tbuf[0] = S->at<float>(S->L.T[0]);
   h->Tbuf[1] = S->at<float>(S->L.T[1]);
   h->P = S->at<float>(S->L.P);
-  h->K = 8;
+  h->K = 3;
+  // fused kernel: one persistent block per compute unit (at most one tile each)
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || ncu < 1) {
+    err = "hipDeviceGetAttribute failed";
+    return KB_EHIP;
+  }
+  S->ntiles = sg_fused_tiles((int)shape[0], (int)shape[1], &S->tiles_x);
+  S->nnet = std::min(std::min(S->ntiles, ncu), kSgMaxNet);
   // check tiles: four 32x32 tiles at seeded positions
   for (int t = 0; t < 4; ++t) {
     S->tile_y[t] = (int)host_randint(seed, 10, 2 * t, h->ny - 31);
@@ -135,38 +147,58 @@ void sg_destroy(kb_problem *h) {
 
 int sg_iter_depth(const kb_problem *h) { return h->sg->ksteps; }
 
-// The k-step block: network (5 kernels), residual check (2), predicated
-// plain fallback (1).  Reads T[cur], writes T[1-cur].
+int sg_kernels_per_block(const kb_problem *h) { return h->tile == 2 ? 8 : 3; }
+
+// The k-step block, reading T[cur] and writing T[1-cur]:
+//   fused (variant 0/1): network + check producers (1 kernel), check (1),
+//                        predicated plain fallback (1);
+//   per-layer (variant 2): input, 4 convolutions, check (2), fallback.
 int sg_fill_iter(const kb_problem *h, int cur, Launch *L) {
   const SgState &S = *h->sg;
   const int H = (int)h->ny, W = (int)h->nx;
   const float *Tc = h->Tbuf[cur];
   float *Tn = h->Tbuf[1 - cur];
-  unsigned short *x = S.at<unsigned short>(S.L.x);
-  unsigned short *A0 = S.at<unsigned short>(S.L.act[0]), *A1 = S.at<unsigned short>(S.L.act[1]);
   const float *w = S.at<float>(S.L.w);
-  sg_make_input(L[0], SgInputArgs{Tc, h->P, x, S.n});
-  SgConvArgs c{};
-  c.npix = S.n; c.H = H; c.W = W; c.s = S.s;
-  c.in = x; c.w = S.at<unsigned short>(S.L.fwd1); c.bias = w + kSgOffB[0]; c.out = A0;
-  sg_make_conv(L[1], c, 0);
-  c.in = A0; c.w = S.at<unsigned short>(S.L.fwd2); c.bias = w + kSgOffB[1]; c.out = A1;
-  sg_make_conv(L[2], c, 1);
-  c.in = A1; c.w = S.at<unsigned short>(S.L.fwd3); c.bias = w + kSgOffB[2]; c.out = A0;
-  sg_make_conv(L[3], c, 2);
-  c.in = A0; c.w = S.at<unsigned short>(S.L.fwd4); c.bias = w + kSgOffB[3]; c.out = nullptr;
-  c.T0 = Tc; c.Tout = Tn;
-  sg_make_conv(L[4], c, 3);
   SgCheckArgs k{};
   k.Tcur = Tc; k.Tnew = Tn; k.P = h->P; k.ny = H; k.nx = W; k.ksteps = S.ksteps; k.k = h->hk;
   for (int t = 0; t < 4; ++t) { k.tile_y[t] = S.tile_y[t]; k.tile_x[t] = S.tile_x[t]; }
-  k.partial = S.at<double>(S.L.chk); k.nred = kSgRedBlocks;
-  k.psum = S.at<double>(S.L.psum); k.threshold = S.threshold; k.flag = S.at<int>(S.L.flag);
-  k.hist = S.at<double>(S.L.hist); k.hist_cap = kSgHistCap; k.counters = S.at<long long>(S.L.counters);
-  sg_make_check(L[5], L[6], k);
+  k.partial = S.at<double>(S.L.chk); k.plain = S.at<float>(S.L.plain);
+  k.tail = SgCheckTail{S.at<double>(S.L.psum), std::pow(1.0 - (double)h->hk.cz, (double)S.ksteps), S.threshold,
+                       S.at<int>(S.L.flag), S.at<double>(S.L.hist), kSgHistCap, S.at<long long>(S.L.counters)};
+  int n = 0;
+  if (h->tile != 2) {
+    SgFusedArgs f{};
+    f.T0 = Tc; f.P = h->P; f.Tout = Tn;
+    f.w1 = S.at<unsigned short>(S.L.fwd1); f.w2 = S.at<unsigned short>(S.L.fwd2);
+    f.w3 = S.at<unsigned short>(S.L.fwd3); f.w4 = S.at<unsigned short>(S.L.fwd4);
+    f.bias = w; f.partial = k.partial; f.plain = k.plain; f.k = h->hk; f.s = S.s;
+    f.H = H; f.W = W; f.tiles_x = S.tiles_x; f.ntiles = S.ntiles; f.nnet = S.nnet; f.ksteps = S.ksteps;
+    for (int t = 0; t < 4; ++t) { f.tile_y[t] = S.tile_y[t]; f.tile_x[t] = S.tile_x[t]; }
+    sg_make_fused(L[n++], f);
+    k.nred = S.nnet;
+    sg_make_check_final(L[n++], k);
+  } else {
+    unsigned short *x = S.at<unsigned short>(S.L.x);
+    unsigned short *A0 = S.at<unsigned short>(S.L.act[0]), *A1 = S.at<unsigned short>(S.L.act[1]);
+    sg_make_input(L[n++], SgInputArgs{Tc, h->P, x, S.n});
+    SgConvArgs c{};
+    c.npix = S.n; c.H = H; c.W = W; c.s = S.s;
+    c.in = x; c.w = S.at<unsigned short>(S.L.fwd1); c.bias = w + kSgOffB[0]; c.out = A0;
+    sg_make_conv(L[n++], c, 0);
+    c.in = A0; c.w = S.at<unsigned short>(S.L.fwd2); c.bias = w + kSgOffB[1]; c.out = A1;
+    sg_make_conv(L[n++], c, 1);
+    c.in = A1; c.w = S.at<unsigned short>(S.L.fwd3); c.bias = w + kSgOffB[2]; c.out = A0;
+    sg_make_conv(L[n++], c, 2);
+    c.in = A0; c.w = S.at<unsigned short>(S.L.fwd4); c.bias = w + kSgOffB[3]; c.out = nullptr;
+    c.T0 = Tc; c.Tout = Tn;
+    sg_make_conv(L[n++], c, 3);
+    k.nred = kSgRedBlocks;
+    sg_make_check(L[n], L[n + 1], k);
+    n += 2;
+  }
   Heat2DArgs f{Tc, Tn, h->P, H, W, h->hk, S.ksteps, S.at<int>(S.L.flag)};
-  if (!make_heat2d_tile(L[7], f, 6)) return -1;
-  return 8;
+  if (!make_heat2d_tile(L[n++], f, 4)) return -1;
+  return n;
 }
 
 bool sg_field(const kb_problem *h, int field, float **dev, size_t *bytes) {

@@ -103,14 +103,10 @@ hipError_t sg_launch_crop(const SgCropArgs &a, hipStream_t s);
 
 namespace kb {
 
-struct SgCheckArgs {
-  const float *Tcur, *Tnew, *P;   // [ny][nx]
-  int ny, nx, ksteps;
-  HeatCoef k;                      // coefficients of the plain step
-  int tile_y[4], tile_x[4];       // 32x32 check tiles
-  double *partial;                // [nred*3 + 4]
-  int nred;
+// Inputs and outputs of the residual check's final pass.
+struct SgCheckTail {
   const double *psum;             // sum of P over the field
+  double decay;                   // (1 - c/Rz)^k of the mean recurrence (host pow)
   double threshold;
   int *flag;                      // set to (r > threshold)
   double *hist;                   // r of every checked block
@@ -118,8 +114,37 @@ struct SgCheckArgs {
   long long *counters;            // [0] blocks checked, [1] fallbacks
 };
 
+struct SgCheckArgs {
+  const float *Tcur, *Tnew, *P;   // [ny][nx]
+  int ny, nx, ksteps;
+  HeatCoef k;                      // coefficients of the plain step
+  int tile_y[4], tile_x[4];       // 32x32 check tiles
+  double *partial;                // [nred][3]: sum Tcur, sum Tnew, max|Tnew|
+  int nred;
+  float *plain;                   // [4][32*32] plain k-step values of the tiles
+  SgCheckTail tail;
+};
+
+// Fused inference of the whole network plus the residual check's
+// producer side (per-block partials, plain tiles).
+struct SgFusedArgs {
+  const float *T0, *P;
+  float *Tout;
+  const unsigned short *w1, *w2, *w3, *w4;   // packed forward weights
+  const float *bias;                          // float32 weight vector (biases at kSgOffB)
+  double *partial;                            // [nnet][3]
+  float *plain;                               // [4][32*32]
+  HeatCoef k;
+  float s;
+  int H, W, tiles_x, ntiles, nnet, ksteps;
+  int tile_y[4], tile_x[4];
+};
+
 void sg_make_conv(Launch &L, const SgConvArgs &a, int layer);
 void sg_make_input(Launch &L, const SgInputArgs &a);
 void sg_make_check(Launch &L0, Launch &L1, const SgCheckArgs &a);
+void sg_make_check_final(Launch &L, const SgCheckArgs &a);
+void sg_make_fused(Launch &L, const SgFusedArgs &a);
+int sg_fused_tiles(int H, int W, int *tiles_x);   // output tiles of the fused kernel
 int sg_check_tile();
 }  // namespace kb

@@ -31,12 +31,13 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-// float -> bf16 bits, round to nearest, ties to even (NaN kept quiet).
-__device__ __forceinline__ unsigned short f2bf(float f) {
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+// float -> bf16 bits, round to nearest, ties to even (the hardware
+// conversion, v_cvt_pk_bf16_f32).
+__device__ __forceinline__ unsigned short f2bf(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned f2bf2(float a, float b) {
+  const bf16x2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(unsigned, v);
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
@@ -110,11 +111,14 @@ __global__ __launch_bounds__(256) void sg_conv_fwd_kernel(const SgConvArgs a) {
     if (p >= a.npix) p = a.npix - 1;
     pg[g] = pix_of(p, a.H, a.W);
   }
+  // 32-channel layers start the accumulator at the bias (the fused kernel
+  // does the same, so both give the same hidden activations)
   f32x4 acc[MT][4];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int g = 0; g < 4; ++g) acc[m][g] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < 4; ++g)
+      acc[m][g] = COUT == 32 ? *reinterpret_cast<const f32x4 *>(a.bias + m * 16 + kq * 4) : f32x4{0.f, 0.f, 0.f, 0.f};
 
   if constexpr (CIN == 32) {
     for (int tap = 0; tap < 9; ++tap) {
@@ -171,7 +175,7 @@ __global__ __launch_bounds__(256) void sg_conv_fwd_kernel(const SgConvArgs a) {
         unsigned short h[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          z[j] = acc[m][g][j] + a.bias[c0 + j];
+          z[j] = acc[m][g][j];
           h[j] = f2bf(gelu(z[j]));
         }
         if (a.z) *reinterpret_cast<float4 *>(a.z + p * 32 + c0) = make_float4(z[0], z[1], z[2], z[3]);
@@ -537,108 +541,491 @@ __global__ __launch_bounds__(256) void sg_crop_kernel(const SgCropArgs a) {
 //   r_tile: on four 32x32 tiles the plain stencil is run k steps from Tcur
 //           (with a k-cell halo, in LDS) and compared with Tnew:
 //           r_tile = max |Tnew - plain| / max|Tnew|.
-// r = max(r_mean, r_tile); the block's flag is r > threshold.  Blocks
-// 0..nred-1 reduce the field in fixed chunks (double sums), blocks nred..
-// nred+3 run the tiles; one more kernel combines the partials in order.
+// r = max(r_mean, r_tile); the block's flag is r > threshold.
+// The producer side writes per-block partials (sum Tcur, sum Tnew,
+// max|Tnew|, all double) and the plain tile values; sg_check_final_kernel
+// combines them in a fixed order.  Producers: the fused network kernel
+// (partials of its own output tiles, plain tiles in blocks 0..3), or
+// sg_check_partial_kernel after the per-layer network.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 32, kHalo = 16, kRegion = kTile + 2 * kHalo;
+constexpr int kNT = 512;            // threads of the check and fused kernels
+constexpr int kNW = kNT / 64;
 
-__global__ __launch_bounds__(256) void sg_check_partial_kernel(const SgCheckArgs a) {
-  __shared__ double sh[4];
-  __shared__ float buf[2][kRegion * kRegion];
-  __shared__ float pw[kRegion * kRegion];
-  __shared__ float fsh[4];
+// Fixed-order sum / max over the block (result valid in thread 0).
+template <int NW>
+__device__ __forceinline__ double block_sum_w(double v, double *sh) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NW; ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+template <int NW>
+__device__ __forceinline__ float block_max_w(float v, float *sh) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = 0.f;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NW; ++w) r = fmaxf(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
+// k plain steps over the (tile + k halo) region of check tile (y0, x0);
+// writes the 32x32 tile values to out.  512 threads: thread (ty, tx) =
+// (tid / 64, tid % 64) keeps rows 8*ty .. 8*ty+7 of region column tx in
+// registers and publishes them in LDS (buf: 2 * kRegion^2 floats, double
+// buffered) for its east / west neighbours and the strips above and below:
+// one barrier per step.  Cells near a halo cut see a clamped neighbour that
+// is not the true one; the error moves inward one cell per step and so
+// never reaches the tile (the halo is k cells wide).
+__device__ void check_plain_tile(const float *Tcur, const float *P, int ny, int nx, int ks, const HeatCoef &k,
+                                 int y0, int x0, float *buf, float *out) {
+  const int ry_lo = max(y0 - ks, 0), ry_hi = min(y0 + kTile + ks, ny);
+  const int rx_lo = max(x0 - ks, 0), rx_hi = min(x0 + kTile + ks, nx);
+  const int H = ry_hi - ry_lo, W = rx_hi - rx_lo;
+  const int tx = threadIdx.x & 63, r0 = (threadIdx.x >> 6) * 8;
+  const bool col = tx < W;
+  const int xw = tx > 0 ? tx - 1 : 0, xe = tx < W - 1 ? tx + 1 : W - 1;
+  const int rn = r0 > 0 ? r0 - 1 : 0, rs = r0 + 8 < H ? r0 + 8 : H - 1;
+  float v[8], pw[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int yy = min(r0 + i, H - 1);
+    const long long g = (long long)(ry_lo + yy) * nx + rx_lo + (col ? tx : 0);
+    v[i] = Tcur[g];
+    pw[i] = P[g];
+  }
+  float *A = buf, *B = buf + kRegion * kRegion;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (col && r0 + i < H) A[(r0 + i) * kRegion + tx] = v[i];
+  __syncthreads();
+  for (int s = 0; s < ks; ++s) {
+    float w[8], e[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int yy = min(r0 + i, H - 1);
+      w[i] = A[yy * kRegion + xw];
+      e[i] = A[yy * kRegion + xe];
+    }
+    const float top = A[rn * kRegion + tx], bot = A[rs * kRegion + tx];
+    float nv[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int yy = r0 + i;
+      const float n = yy == 0 ? v[i] : (i == 0 ? top : v[i - 1]);
+      const float so = yy >= H - 1 ? v[i] : (i == 7 ? bot : v[i + 1]);
+      nv[i] = heat_update(v[i], n, so, w[i], e[i], pw[i], k);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      v[i] = nv[i];
+      if (col && r0 + i < H) B[(r0 + i) * kRegion + tx] = v[i];
+    }
+    __syncthreads();
+    float *t = A; A = B; B = t;
+  }
+  for (int c = threadIdx.x; c < kTile * kTile; c += kNT) {
+    const int yy = c >> 5, xx = c & 31;
+    out[c] = A[(y0 + yy - ry_lo) * kRegion + (x0 + xx - rx_lo)];
+  }
+}
+
+// Final pass: one block of 1024 threads combines the per-block partials in a
+// fixed order (thread i takes partials i, i+1024, ..., then a fixed tree
+// over the waves), compares the tiles, sets the flag and logs r.
+__global__ __launch_bounds__(1024) void sg_check_final_kernel(const SgCheckArgs a) {
+  __shared__ double dsh[2][16];
+  __shared__ float fsh[2][16];
+  double sc = 0.0, sn = 0.0;
+  float mx = 0.f, dt = 0.f;
+  for (int b = threadIdx.x; b < a.nred; b += 1024) {
+    sc += a.partial[b * 3 + 0];
+    sn += a.partial[b * 3 + 1];
+    mx = fmaxf(mx, (float)a.partial[b * 3 + 2]);
+  }
+  for (int q = threadIdx.x; q < 4 * kTile * kTile; q += 1024) {
+    const int t = q >> 10, yy = (q >> 5) & 31, xx = q & 31;
+    const float v = a.Tnew[(long long)(a.tile_y[t] + yy) * a.nx + a.tile_x[t] + xx];
+    dt = fmaxf(dt, fabsf(v - a.plain[q]));
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    sc += __shfl_xor(sc, o, 64);
+    sn += __shfl_xor(sn, o, 64);
+    mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    dt = fmaxf(dt, __shfl_xor(dt, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    dsh[0][w] = sc; dsh[1][w] = sn;
+    fsh[0][w] = mx; fsh[1][w] = dt;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double S1 = 0.0, S2 = 0.0;
+  float MX = 0.f, DT = 0.f;
+  for (int i = 0; i < 16; ++i) {
+    S1 += dsh[0][i]; S2 += dsh[1][i];
+    MX = fmaxf(MX, fsh[0][i]); DT = fmaxf(DT, fsh[1][i]);
+  }
+  const SgCheckTail &c = a.tail;
+  const double n = (double)a.ny * a.nx;
+  const double cP = a.k.cP, cz = a.k.cz, Tamb = a.k.Tamb;
+  const double A = Tamb + cP * (*c.psum / n) / cz;
+  const double mk = A + (S1 / n - A) * c.decay;
+  const double scale = MX > 0.f ? (double)MX : 1.0;
+  const double r = fmax(fabs(S2 / n - mk) / scale, (double)DT / scale);
+  const int f = r > c.threshold ? 1 : 0;
+  *c.flag = f;
+  const long long cnt = c.counters[0];
+  if (cnt >= 0 && cnt < c.hist_cap) c.hist[cnt] = r;
+  c.counters[0] = cnt + 1;
+  c.counters[1] += f;
+}
+
+// Producer after the per-layer network: blocks < nred reduce fixed chunks
+// of the field, blocks nred..nred+3 run the plain check tiles.
+__global__ __launch_bounds__(kNT) void sg_check_partial_kernel(const SgCheckArgs a) {
+  __shared__ double dsh[kNW];
+  __shared__ float fsh[kNW];
+  __shared__ float buf[2 * kRegion * kRegion];
   const long long n = (long long)a.ny * a.nx;
-  if ((int)blockIdx.x < a.nred) {
+  if ((int)blockIdx.x >= a.nred) {
+    const int t = blockIdx.x - a.nred;
+    check_plain_tile(a.Tcur, a.P, a.ny, a.nx, a.ksteps, a.k, a.tile_y[t], a.tile_x[t], buf,
+                     a.plain + t * kTile * kTile);
+  } else {
     const long long lo = n * blockIdx.x / a.nred, hi = n * (blockIdx.x + 1) / a.nred;
     double sc = 0.0, sn = 0.0;
     float mx = 0.f;
-    for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+    for (long long i = lo + threadIdx.x; i < hi; i += kNT) {
       sc += (double)a.Tcur[i];
       const float v = a.Tnew[i];
       sn += (double)v;
       mx = fmaxf(mx, fabsf(v));
     }
-    const double s1 = block_sum256(sc, sh);
-    const double s2 = block_sum256(sn, sh);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-    if ((threadIdx.x & 63) == 0) fsh[threadIdx.x >> 6] = mx;
-    __syncthreads();
+    const double s1 = block_sum_w<kNW>(sc, dsh);
+    const double s2 = block_sum_w<kNW>(sn, dsh);
+    const float m = block_max_w<kNW>(mx, fsh);
     if (threadIdx.x == 0) {
       a.partial[blockIdx.x * 3 + 0] = s1;
       a.partial[blockIdx.x * 3 + 1] = s2;
-      a.partial[blockIdx.x * 3 + 2] = (double)fmaxf(fmaxf(fsh[0], fsh[1]), fmaxf(fsh[2], fsh[3]));
+      a.partial[blockIdx.x * 3 + 2] = (double)m;
     }
-    return;
   }
-  const int t = blockIdx.x - a.nred;           // tile 0..3
-  const int y0 = a.tile_y[t], x0 = a.tile_x[t];
-  const int ks = a.ksteps;
-  const int ry_lo = max(y0 - ks, 0), ry_hi = min(y0 + kTile + ks, a.ny);
-  const int rx_lo = max(x0 - ks, 0), rx_hi = min(x0 + kTile + ks, a.nx);
-  const int H = ry_hi - ry_lo, W = rx_hi - rx_lo;
-  for (int e = threadIdx.x; e < H * W; e += 256) {
-    const int yy = e / W, xx = e - yy * W;
-    const long long g = (long long)(ry_lo + yy) * a.nx + rx_lo + xx;
-    buf[0][e] = a.Tcur[g];
-    pw[e] = a.P[g];
-  }
-  __syncthreads();
-  int c = 0;
-  for (int s = 0; s < ks; ++s) {
-    for (int e = threadIdx.x; e < H * W; e += 256) {
-      const int yy = e / W, xx = e - yy * W;
-      const int yn = yy > 0 ? yy - 1 : 0, ys = yy < H - 1 ? yy + 1 : H - 1;
-      const int xw = xx > 0 ? xx - 1 : 0, xe = xx < W - 1 ? xx + 1 : W - 1;
-      const float *A = buf[c];
-      buf[1 - c][e] = heat_update(A[e], A[yn * W + xx], A[ys * W + xx], A[yy * W + xw], A[yy * W + xe], pw[e], a.k);
-    }
-    __syncthreads();
-    c = 1 - c;
-  }
-  float mx = 0.f;
-  for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
-    const int yy = y0 + e / kTile, xx = x0 + e % kTile;
-    const float plain = buf[c][(yy - ry_lo) * W + (xx - rx_lo)];
-    mx = fmaxf(mx, fabsf(a.Tnew[(long long)yy * a.nx + xx] - plain));
-  }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-  if ((threadIdx.x & 63) == 0) fsh[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) a.partial[a.nred * 3 + t] = (double)fmaxf(fmaxf(fsh[0], fsh[1]), fmaxf(fsh[2], fsh[3]));
-}
-
-__global__ void sg_check_final_kernel(const SgCheckArgs a) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double sc = 0.0, sn = 0.0, mx = 0.0, tile = 0.0;
-  for (int b = 0; b < a.nred; ++b) {
-    sc += a.partial[b * 3 + 0];
-    sn += a.partial[b * 3 + 1];
-    mx = fmax(mx, a.partial[b * 3 + 2]);
-  }
-  for (int t = 0; t < 4; ++t) tile = fmax(tile, a.partial[a.nred * 3 + t]);
-  const double n = (double)a.ny * a.nx;
-  const double cP = a.k.cP, cz = a.k.cz, Tamb = a.k.Tamb;
-  const double A = Tamb + cP * (*a.psum / n) / cz;
-  const double mk = A + (sc / n - A) * pow(1.0 - cz, (double)a.ksteps);
-  const double scale = mx > 0.0 ? mx : 1.0;
-  const double r = fmax(fabs(sn / n - mk) / scale, tile / scale);
-  const int f = r > a.threshold ? 1 : 0;
-  *a.flag = f;
-  const long long cnt = a.counters[0];
-  if (cnt >= 0 && cnt < a.hist_cap) a.hist[cnt] = r;
-  a.counters[0] = cnt + 1;
-  a.counters[1] += f;
 }
 
 void sg_make_check(Launch &L0, Launch &L1, const SgCheckArgs &a) {
-  L0.set((const void *)sg_check_partial_kernel, dim3(a.nred + 4), dim3(256), 0, a);
-  L1.set((const void *)sg_check_final_kernel, dim3(1), dim3(64), 0, a);
+  L0.set((const void *)sg_check_partial_kernel, dim3(a.nred + 4), dim3(kNT), 0, a);
+  L1.set((const void *)sg_check_final_kernel, dim3(1), dim3(1024), 0, a);
+}
+
+void sg_make_check_final(Launch &L, const SgCheckArgs &a) {
+  L.set((const void *)sg_check_final_kernel, dim3(1), dim3(1024), 0, a);
 }
 
 int sg_check_tile() { return kTile; }
+
+// ---------------------------------------------------------------------------
+// Fused inference: one block evaluates the whole network on a 16x32 output
+// tile with every activation held in LDS, so HBM traffic is T0 and P in and
+// T_k out.  Each layer is computed on the tile grown by the receptive field
+// still ahead of it:
+//   input (t, p)   24 x 40   bf16 pairs
+//   layer 1 out    22 x 38   32 ch   (buffer A)
+//   layer 2 out    20 x 36   32 ch   (buffer B)
+//   layer 3 out    18 x 34   32 ch   (buffer A)
+//   layer 4        16 x 32
+// A region pixel takes its image coordinates clamped into the field and
+// reads taps at clamped coordinates, which is replicate padding at every
+// layer (a clamped tap always lies inside the previous, larger region).
+// Layers 1-3 are the forward implicit GEMM of sg_conv_fwd_kernel with the
+// B fragments read from LDS; the weight fragments of layers 2 and 3 stay in
+// registers for the whole launch.  Layer 4 (one output channel) is done in
+// transposed form: one MFMA per 16 pixels of layer 3 gives every pixel's
+// contribution to each of the 9 taps, D[pixel][tap], and an output pixel
+// sums the 9 entries of its clamped neighbours.
+// Activations are pixel-major, 64 bytes per pixel, with the four 16-byte
+// channel chunks of pixel p rotated by (p >> 2) & 3 so that the 16 pixels
+// of a fragment load hit distinct banks.
+// Blocks 0..3 run the plain check tiles; blocks 4.. are persistent over the
+// output tiles (tile i goes to block 4 + i % nnet) and write the check
+// partials of the tiles they produced.
+// ---------------------------------------------------------------------------
+namespace fz {
+constexpr int TH = 16, TW = 32;
+constexpr int H0 = TH + 8, W0 = TW + 8, N0 = H0 * W0;
+constexpr int H1 = TH + 6, W1 = TW + 6, N1 = H1 * W1;
+constexpr int H2 = TH + 4, W2 = TW + 4, N2 = H2 * W2;
+constexpr int H3 = TH + 2, W3 = TW + 2, N3 = H3 * W3;
+constexpr int G1 = (N1 + 15) / 16, G2 = (N2 + 15) / 16, G3 = (N3 + 15) / 16;
+constexpr int kPix = 80;                              // bytes per pixel: 64 of channels + 16 pad
+constexpr int kIn = 0;                                // N0 uint
+constexpr int kA = kIn + N0 * 4;                      // N1 * kPix bytes
+constexpr int kB = kA + N1 * kPix;                    // N2 * kPix bytes
+constexpr int kBytes = kB + N2 * kPix;
+static_assert(N3 * 9 * 4 <= N2 * kPix, "layer-4 partials must fit buffer B");
+static_assert(2 * kRegion * kRegion * 4 <= kBytes, "check tile must fit");
+static_assert(kA % 16 == 0 && kB % 16 == 0, "16-byte aligned buffers");
+static_assert(N0 <= 2 * kNT, "two input pixels per thread");
+}  // namespace fz
+
+// Source pixel (in the previous region) of tap (dy, dx) for region pixel p.
+// Interior tiles (EDGE = false): no clamping, so the nine taps are the
+// pixel's base index plus compile-time offsets.  Edge tiles clamp each
+// coordinate into the field.
+template <int Wr, bool EDGE>
+struct TapSrc {
+  int base;                 // interior: index of tap (0, 0)
+  int ro[3], co[3];         // edge: row and column offsets per dy / dx
+  __device__ __forceinline__ TapSrc(int p, int oy, int ox, int H, int W) {
+    const int i = p / Wr, j = p - (p / Wr) * Wr;
+    if constexpr (!EDGE) {
+      base = p + 2 * i;
+    } else {
+      const int cy = clampi(oy + i, H), cx = clampi(ox + j, W);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        ro[d] = (clampi(cy + d - 1, H) - oy + 1) * (Wr + 2);
+        co[d] = clampi(cx + d - 1, W) - ox + 1;
+      }
+    }
+  }
+  __device__ __forceinline__ int operator()(int tap) const {
+    if constexpr (!EDGE) return base + (tap / 3) * (Wr + 2) + tap % 3;
+    else return ro[tap / 3] + co[tap % 3];
+  }
+};
+
+// Epilogue of a 32-channel layer (bias already in the accumulator): GELU,
+// bf16, into the region buffer.  Lane (r, kq) holds channels m*16 + kq*4 ..
+// +3 of pixel p.
+__device__ __forceinline__ void store_act(unsigned char *dst, int p, int kq, const f32x4 (&acc)[2]) {
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    uint2 packed;
+    packed.x = f2bf2(gelu(acc[m][0]), gelu(acc[m][1]));
+    packed.y = f2bf2(gelu(acc[m][2]), gelu(acc[m][3]));
+    *reinterpret_cast<uint2 *>(dst + p * fz::kPix + m * 32 + kq * 8) = packed;
+  }
+}
+
+__device__ __forceinline__ void bias_init(f32x4 (&acc)[2], const float *bias, int kq) {
+  acc[0] = *reinterpret_cast<const f32x4 *>(bias + kq * 4);
+  acc[1] = *reinterpret_cast<const f32x4 *>(bias + 16 + kq * 4);
+}
+
+// One 32 -> 32 layer over a region (Wr wide, N pixels, G groups of 16).
+template <int Wr, int N, int G, bool EDGE>
+__device__ __forceinline__ void fused_layer32(const unsigned char *src, unsigned char *dst, const bf16x8 (&wa)[9][2],
+                                              const float *bias, int oy, int ox, int H, int W) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  for (int g = wave; g < G; g += kNW) {
+    const int p = min(g * 16 + r, N - 1);
+    const TapSrc<Wr, EDGE> ts(p, oy, ox, H, W);
+    f32x4 acc[2];
+    bias_init(acc, bias, kq);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const bf16x8 B = ld_frag(reinterpret_cast<const unsigned short *>(src + ts(tap) * fz::kPix + kq * 16));
+      acc[0] = mfma(wa[tap][0], B, acc[0]);
+      acc[1] = mfma(wa[tap][1], B, acc[1]);
+    }
+    const int po = g * 16 + r;
+    if (po < N) store_act(dst, po, kq, acc);
+  }
+}
+
+struct FusedRegs {
+  bf16x8 w1[2], w2[9][2], w3[9][2], w4;
+};
+
+// The network on one 16x32 output tile; in0 holds the tile's input region.
+// Returns after the last barrier that orders this tile's LDS use; the
+// output phase follows in the caller.
+template <bool EDGE>
+__device__ __forceinline__ void fused_tile(const SgFusedArgs &a, const FusedRegs &R, unsigned char *sm,
+                                           const float *sbias, int y0, int x0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  const unsigned *in0 = reinterpret_cast<const unsigned *>(sm + fz::kIn);
+  unsigned char *bA = sm + fz::kA, *bB = sm + fz::kB;
+  float *Dl = reinterpret_cast<float *>(bB);
+  // layer 1 (2 -> 32): k = tap*2 + cin; lane kq gathers taps kq*4 .. kq*4+3
+  for (int g = wave; g < fz::G1; g += kNW) {
+    const int p = min(g * 16 + r, fz::N1 - 1);
+    const TapSrc<fz::W1, EDGE> ts(p, y0 - 3, x0 - 3, a.H, a.W);
+    unsigned u[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int tap = kq * 4 + i;
+      u[i] = tap < 9 ? in0[ts(tap < 9 ? tap : 0)] : 0u;
+    }
+    const bf16x8 B = __builtin_bit_cast(bf16x8, uint4{u[0], u[1], u[2], u[3]});
+    f32x4 acc[2];
+    bias_init(acc, sbias, kq);
+    acc[0] = mfma(R.w1[0], B, acc[0]);
+    acc[1] = mfma(R.w1[1], B, acc[1]);
+    const int po = g * 16 + r;
+    if (po < fz::N1) store_act(bA, po, kq, acc);
+  }
+  __syncthreads();
+  fused_layer32<fz::W2, fz::N2, fz::G2, EDGE>(bA, bB, R.w2, sbias + 32, y0 - 2, x0 - 2, a.H, a.W);
+  __syncthreads();
+  fused_layer32<fz::W3, fz::N3, fz::G3, EDGE>(bB, bA, R.w3, sbias + 64, y0 - 1, x0 - 1, a.H, a.W);
+  __syncthreads();
+  // layer 4, transposed: D[pixel][tap] = sum_cin act3[pixel][cin] W4[tap][cin]
+  for (int g = wave; g < fz::G3; g += kNW) {
+    const int p = min(g * 16 + r, fz::N3 - 1);
+    const bf16x8 A = ld_frag(reinterpret_cast<const unsigned short *>(bA + p * fz::kPix + kq * 16));
+    const f32x4 d = mfma(A, R.w4, f32x4{0.f, 0.f, 0.f, 0.f});
+    if (r < 9) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int pp = g * 16 + kq * 4 + j;
+        if (pp < fz::N3) Dl[pp * 9 + r] = d[j];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Output pixel (i, j) of the tile: y = b4 + the nine tap partials at the
+// (clamped) neighbours.
+template <bool EDGE>
+__device__ __forceinline__ float fused_out(const SgFusedArgs &a, const float *Dl, int y0, int x0, int i, int j) {
+  float acc = 0.f;
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    int q;
+    if constexpr (!EDGE) {
+      q = (i + tap / 3) * fz::W3 + j + tap % 3;
+    } else {
+      const int sy = clampi(y0 + i + tap / 3 - 1, a.H) - (y0 - 1);
+      const int sx = clampi(x0 + j + tap % 3 - 1, a.W) - (x0 - 1);
+      q = sy * fz::W3 + sx;
+    }
+    acc += Dl[q * 9 + tap];
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(kNT) void sg_fused_kernel(const SgFusedArgs a) {
+  __shared__ __align__(16) unsigned char sm[fz::kBytes];
+  __shared__ __align__(16) float sbias[100];
+  __shared__ float t0s[2][fz::TH * fz::TW];   // by tile parity: written before the
+                                              // previous tile's output is read out
+  __shared__ double dsh[kNW];
+  __shared__ float fsh[kNW];
+  if (blockIdx.x < 4) {
+    const int t = blockIdx.x;
+    check_plain_tile(a.T0, a.P, a.H, a.W, a.ksteps, a.k, a.tile_y[t], a.tile_x[t], reinterpret_cast<float *>(sm),
+                     a.plain + t * kTile * kTile);
+    return;
+  }
+  const int nb = blockIdx.x - 4;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, kq = lane >> 4;
+  unsigned *in0 = reinterpret_cast<unsigned *>(sm + fz::kIn);
+  const float *Dl = reinterpret_cast<const float *>(sm + fz::kB);
+  if (threadIdx.x < 96) sbias[threadIdx.x] = a.bias[kSgOffB[threadIdx.x >> 5] + (threadIdx.x & 31)];
+  if (threadIdx.x == 96) sbias[96] = a.bias[kSgOffB[3]];
+
+  // weights: layer-1 and layer-2/3 A fragments, layer-4 B fragment (kept
+  // in registers for the whole launch)
+  FusedRegs R;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) R.w1[m] = ld_frag(a.w1 + (m * 16 + r) * 32 + kq * 8);
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      R.w2[tap][m] = ld_frag(a.w2 + (tap * 32 + m * 16 + r) * 32 + kq * 8);
+      R.w3[tap][m] = ld_frag(a.w3 + (tap * 32 + m * 16 + r) * 32 + kq * 8);
+    }
+  R.w4 = r < 9 ? ld_frag(a.w4 + r * 32 + kq * 8) : __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+
+  // input values of the 24 x 40 region, two per thread, loaded one tile ahead
+  float pT[2], pP[2];
+  auto fetch = [&](int tile) {
+    const int y0 = (tile / a.tiles_x) * fz::TH, x0 = (tile % a.tiles_x) * fz::TW;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int p = min((int)threadIdx.x + q * kNT, fz::N0 - 1);
+      const int i = p / fz::W0, j = p - (p / fz::W0) * fz::W0;
+      const long long g = (long long)clampi(y0 - 4 + i, a.H) * a.W + clampi(x0 - 4 + j, a.W);
+      pT[q] = a.T0[g];
+      pP[q] = a.P[g];
+    }
+  };
+  if (nb < a.ntiles) fetch(nb);
+
+  double s_cur = 0.0, s_new = 0.0;
+  float mx = 0.f;
+  int par = 0;
+  for (int tile = nb; tile < a.ntiles; tile += a.nnet, par ^= 1) {
+    const int y0 = (tile / a.tiles_x) * fz::TH, x0 = (tile % a.tiles_x) * fz::TW;
+    // network input; the tile's own T0 values are kept for the output
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int p = threadIdx.x + q * kNT;
+      if (p < fz::N0) {
+        const float t = (pT[q] - 333.0f) / 10.0f;
+        const float u = (pP[q] - 0.5f) / 0.29f;
+        in0[p] = f2bf2(t, u);
+        const int i = p / fz::W0 - 4, j = p - (p / fz::W0) * fz::W0 - 4;
+        if (i >= 0 && i < fz::TH && j >= 0 && j < fz::TW) t0s[par][i * fz::TW + j] = pT[q];
+      }
+    }
+    __syncthreads();
+    if (tile + a.nnet < a.ntiles) fetch(tile + a.nnet);
+    const bool interior = y0 >= 4 && x0 >= 4 && y0 + fz::TH + 4 <= a.H && x0 + fz::TW + 4 <= a.W;
+    if (interior) fused_tile<false>(a, R, sm, sbias, y0, x0);
+    else fused_tile<true>(a, R, sm, sbias, y0, x0);
+    // output (one pixel per thread)
+    const int i = threadIdx.x >> 5, j = threadIdx.x & 31;
+    const int yy = y0 + i, xx = x0 + j;
+    if (yy < a.H && xx < a.W) {
+      const float acc = interior ? fused_out<false>(a, Dl, y0, x0, i, j) : fused_out<true>(a, Dl, y0, x0, i, j);
+      const float y = acc + sbias[96];
+      const float t0 = t0s[par][i * fz::TW + j];
+      const float tn = t0 + a.s * y;
+      a.Tout[(long long)yy * a.W + xx] = tn;
+      s_cur += (double)t0;
+      s_new += (double)tn;
+      mx = fmaxf(mx, fabsf(tn));
+    }
+    // buffer B (D) is next written after two more barriers, t0s[par] after
+    // three; in0 and buffer A are no longer read by this tile.
+  }
+  const double s1 = block_sum_w<kNW>(s_cur, dsh);
+  const double s2 = block_sum_w<kNW>(s_new, dsh);
+  const float m = block_max_w<kNW>(mx, fsh);
+  if (threadIdx.x == 0) {
+    a.partial[nb * 3 + 0] = s1;
+    a.partial[nb * 3 + 1] = s2;
+    a.partial[nb * 3 + 2] = (double)m;
+  }
+}
+
+void sg_make_fused(Launch &L, const SgFusedArgs &a) {
+  L.set((const void *)sg_fused_kernel, dim3(a.nnet + 4), dim3(kNT), 0, a);
+}
+
+int sg_fused_tiles(int H, int W, int *tiles_x) {
+  *tiles_x = (W + fz::TW - 1) / fz::TW;
+  return ((H + fz::TH - 1) / fz::TH) * *tiles_x;
+}
 
 // ---------------------------------------------------------------------------
 // Launch helpers (host).

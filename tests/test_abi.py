@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(kb):
     L = kb.lib()
     missing = [n for n in declared_functions() if not hasattr(L, n)]
     assert not missing, missing
-    assert L.kb_abi_version() == 1
+    assert L.kb_abi_version() == 2
 
 
 def test_workspace_bytes_host_only(kb):
@@ -67,3 +67,34 @@ def test_binding_refuses_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(kb, "_lib", None)
     with pytest.raises(ImportError):
         kb.lib()
+
+
+def header_defines():
+    src = open(os.path.join(ROOT, "include", "kb.h")).read()
+    return {k: int(v) for k, v in re.findall(r"#define\s+(KB_[A-Z0-9_]+)\s+(-?\d+)", src)}
+
+
+def test_binding_constants_match_header(kb):
+    d = header_defines()
+    pairs = {"KB_OPT_REDUCE_EVERY": kb.OPT_REDUCE_EVERY, "KB_OPT_TILE": kb.OPT_TILE,
+             "KB_OPT_GRAPH_UPDATE": kb.OPT_GRAPH_UPDATE,
+             "KB_OPT_BUILDER": kb.OPT_BUILDER, "KB_OPT_TDEPTH": kb.OPT_TDEPTH,
+             "KB_OPT_GRAPH_CACHE": kb.OPT_GRAPH_CACHE, "KB_OPT_MAX_NODES": kb.OPT_MAX_NODES,
+             "KB_F_T": kb.F_T, "KB_F_P": kb.F_P, "KB_F_W": kb.F_W, "KB_F_SGSTATS": kb.F_SGSTATS,
+             "KB_F_RESID": kb.F_RESID, "KB_F_REDLOG": kb.F_REDLOG, "KB_F_REDCOUNT": kb.F_REDCOUNT,
+             "KB_HEAT2D": kb.HEAT2D, "KB_HEAT3D": kb.HEAT3D, "KB_SKELETON": kb.SKELETON,
+             "KB_FDTD3D": kb.FDTD3D, "KB_HEAT2D_MULTI": kb.HEAT2D_MULTI,
+             "KB_HEAT2D_SURROGATE": kb.HEAT2D_SURROGATE}
+    for name, val in pairs.items():
+        assert d[name] == val, name
+
+
+def test_timing_struct_matches_header(kb):
+    src = open(os.path.join(ROOT, "include", "kb.h")).read()
+    body = re.search(r"typedef struct kb_timing \{(.*?)\} kb_timing;", src, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(double|int64_t)\s+([a-z_0-9]+);", body)
+    assert [f for _, f in fields] == [f for f, _ in kb.Timing._fields_]
+    import ctypes as C
+    want = {"double": C.c_double, "int64_t": C.c_int64}
+    assert [want[t] for t, _ in fields] == [t for _, t in kb.Timing._fields_]

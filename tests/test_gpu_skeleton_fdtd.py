@@ -221,3 +221,38 @@ def test_fdtd_random_fields_both_variants(kb, N):
             p.run(9, 4)
             for k, fid in kb.FDTD_FIELDS.items():
                 assert np.array_equal(p.read(fid), ref[k]), (variant, k)
+
+
+@pytest.mark.parametrize("builder", [0, 1])
+@pytest.mark.parametrize("update", [0, 1])
+def test_skeleton_coefficient_write_updates_or_drops_graphs(kb, builder, update):
+    """New a_k, b_k after graphs are cached: with KB_OPT_GRAPH_UPDATE=1 the
+    cached graphs are refitted in place (no rebuild on the next run), with 0
+    they are dropped and rebuilt; both give the per-launch bits."""
+    announce(f"skeleton graph update builder={builder} update={update}")
+    n, b = 3000, 10
+    a2 = np.array([0.95, 0.97, 0.99, 0.93], np.float32)
+    b2 = np.array([0.001, -0.002, 0.003, -0.004], np.float32)
+    with kb.Problem(kb.SKELETON, (n,), (4,), 41) as p:
+        p.set_option(kb.OPT_BUILDER, builder)
+        p.set_option(kb.OPT_GRAPH_UPDATE, update)
+        p.run(100, b)
+        assert p.last_timing()["n_graphs_built"] == 1
+        x_mid = p.read(kb.F_X)
+        p.write(kb.F_A, a2)
+        p.write(kb.F_B, b2)
+        p.run(100, b)
+        t = p.last_timing()
+        got = p.read(kb.F_X)
+    if update:
+        assert t["n_graphs_updated"] == 1 and t["n_graphs_built"] == 0
+    else:
+        assert t["n_graphs_updated"] == 0 and t["n_graphs_built"] == 1
+    print(f"refit/drop {t['t_update_s'] * 1e6:.1f} us, next T_C {t['t_create_s'] * 1e6:.1f} us")
+    with kb.Problem(kb.SKELETON, (n,), (4,), 41) as q:
+        q.write(kb.F_X, x_mid)
+        q.write(kb.F_A, a2)
+        q.write(kb.F_B, b2)
+        q.run(100, 0)
+        assert np.array_equal(got, q.read(kb.F_X))
+    assert np.array_equal(got, oracle.skeleton(x_mid, a2, b2, 100, dtype=np.float32))
