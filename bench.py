@@ -138,6 +138,70 @@ def stored_traffic():
     return d.get("hbm_bytes_per_launch")
 
 
+def graph_memory(kb, np, torch, copies=8, batches=(250, 1000, 2500)):
+    """Device memory held by instantiated, uploaded batch graphs vs their
+    node count (the paper's Fig. 2 bars).  The free-memory reading moves in
+    2 MiB steps, so each point keeps `copies` graphs of K*b nodes alive (one
+    per problem handle, workspaces allocated before the first reading) and
+    bytes per node is the least-squares slope over the points."""
+    pts = []
+    for b in batches:
+        probs = [kb.Problem(kb.SKELETON, (N_ELEM,), (K,), SEED, device=0) for _ in range(copies)]
+        torch.cuda.synchronize()
+        f0 = torch.cuda.mem_get_info()[0]
+        for p in probs:
+            p.run(b, b)
+            p.last_timing()
+        torch.cuda.synchronize()
+        f1 = torch.cuda.mem_get_info()[0]
+        pts.append((copies * K * b, f0 - f1))
+        for p in probs:
+            p.destroy()
+    x = np.array([q[0] for q in pts], float)
+    y = np.array([q[1] for q in pts], float)
+    slope, icpt = np.polyfit(x, y, 1)
+    return {"bytes_per_node": float(slope), "bytes_fixed": float(icpt), "copies": copies,
+            "points_nodes_bytes": [[int(a), int(c)] for a, c in pts]}
+
+
+def builders_and_update(kb, np, batches=(100, 1000, 2500), reps=3):
+    """T_C of the two builders (explicit kernel nodes, stream capture of the
+    per-launch loop) vs batch size, and what a change of node arguments
+    costs: refitting the cached graphs in place (hipGraphExecUpdate) vs
+    dropping them and paying T_C again on the next run."""
+    out = {"t_create_ms": {}, "update": {}}
+    a_new = np.array([0.95, 0.97, 0.99, 0.93], np.float32)
+    for builder, name in ((0, "explicit"), (1, "capture")):
+        with kb.Problem(kb.SKELETON, (N_ELEM,), (K,), SEED, device=0) as p:
+            p.set_option(kb.OPT_BUILDER, builder)
+            p.set_option(kb.OPT_GRAPH_CACHE, 0)
+            row = {}
+            for b in batches:
+                tc = []
+                for _ in range(reps):
+                    p.run(b, b)
+                    tc.append(p.last_timing()["t_create_s"])
+                row[str(b)] = float(np.median(tc)) * 1e3
+            out["t_create_ms"][name] = row
+    for b in batches:
+        row = {}
+        for mode, name in ((0, "drop_and_rebuild"), (1, "refit_in_place")):
+            with kb.Problem(kb.SKELETON, (N_ELEM,), (K,), SEED, device=0) as p:
+                p.set_option(kb.OPT_GRAPH_UPDATE, mode)
+                p.run(b, b)
+                p.last_timing()
+                upd, tc = [], []
+                for r in range(reps):
+                    p.write(kb.F_A, a_new if r % 2 == 0 else a_new * np.float32(0.999))
+                    p.run(b, b)
+                    t = p.last_timing()
+                    upd.append(t["t_update_s"])
+                    tc.append(t["t_create_s"])
+                row[name] = {"write_ms": float(np.median(upd)) * 1e3, "next_run_t_create_ms": float(np.median(tc)) * 1e3}
+        out["update"][str(b)] = row
+    return out
+
+
 def workloads(kb, pm, autotune, np):
     """The other workloads of the study, each per launch vs graph batches,
     plus the large grids against the HBM roofline.  Seeded synthetic inputs
@@ -307,12 +371,10 @@ def main():
     model = None
     if not args.no_sweep and args.arm != "per_launch":
         job(100)
-        graph_mem = []                          # (nodes, bytes) of each built graph
         for b in cands:
             reps = [job(b) for _ in range(args.sweep_reps)]
             sweep.append((b, float(np.median([t["t_create_s"] for t in reps])),
                           float(np.median([t["t_exec_s"] for t in reps]))))
-            graph_mem.append((K * b, float(np.median([t["graph_mem_bytes"] for t in reps]))))
         S = np.array([s[0] for s in sweep], float)
         model = pm.Model(pm.fit_creation(K * S, [s[1] for s in sweep]),
                          pm.fit_execution(S, [s[2] for s in sweep]), K=K)
@@ -432,14 +494,8 @@ def main():
                          # gap of a graph launch over a node-to-node gap
                          "T_a_minus_T_i_us": model.execution.a / ITERS * 1e6}
         line["sweep"] = [[s[0], round(s[1] * 1e3, 4), round(s[2] * 1e3, 4)] for s in sweep]
-        # graph memory footprint vs node count (Fig. 2's bars): least-squares
-        # bytes = m_node * nodes + m_0 over the sweep's graphs
-        gx = np.array([g[0] for g in graph_mem], float)
-        gy = np.array([g[1] for g in graph_mem], float)
-        if len(gx) >= 2 and np.ptp(gx) > 0:
-            m_node, m_0 = np.polyfit(gx, gy, 1)
-            line["graph_memory"] = {"bytes_per_node": float(m_node), "bytes_fixed": float(m_0),
-                                    "points": [[int(a), int(b)] for a, b in graph_mem]}
+        line["graph_memory"] = graph_memory(kb, np, torch)
+        line["graph_builders"] = builders_and_update(kb, np)
     print(json.dumps(line), flush=True)
 
 
