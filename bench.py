@@ -76,6 +76,9 @@ KERNEL_RUNS = {
     "fdtd_256": ("FDTD3D", (256, 64), "FDTD_COEFFS", 2, 5),
     "surrogate_512": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 1, 160),
     "surrogate_512_layered": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 2, 160),
+    # 64 square grids of side round(64 * 16^u) (shape filled in from the seed)
+    "multigrid_64": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 2, 10),
+    "multigrid_64_cell": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 1, 10),
 }
 
 
@@ -86,6 +89,10 @@ def kernel_only(name):
     import paper_2501_09398_amd as kb
     prob, shape, co, var, steps = KERNEL_RUNS[name]
     coeffs = (K,) if co is None else getattr(kb, co)
+    if prob == "HEAT2D_MULTI":
+        import synth
+        sides = synth.multigrid_sides(SEED, 64)
+        shape = [64] + [v for sd in sides for v in (sd, sd)]
     if prob == "HEAT2D_SURROGATE":
         import numpy as np
         import synth
@@ -206,7 +213,11 @@ def workloads(kb, pm, autotune, np):
     """The other workloads of the study, each per launch vs graph batches,
     plus the large grids against the HBM roofline.  Seeded synthetic inputs
     of each workload's shape; every run starts from the device-resident state."""
+    import torch
     out = {}
+
+    def torch_sync():
+        torch.cuda.synchronize()
 
     def arm(p, n, b, reps=3):
         p.run(n, b)
@@ -262,10 +273,28 @@ def workloads(kb, pm, autotune, np):
     cells = sum(s * s for s in sides)
     d = {"steps": n, "grids": 64, "cells": cells}
     with kb.Problem(kb.HEAT2D_MULTI, shape, kb.HEAT_COEFFS, SEED) as p:
-        d["per_launch_us_step"] = arm(p, n, 0, 2) / n * 1e6
-        d["graph_b100_us_step"] = arm(p, n, 100, 2) / n * 1e6
-    d["gcell_upd_s"] = cells / d["graph_b100_us_step"] / 1e3
-    d["hbm_frac"] = 12.0 * cells / (d["graph_b100_us_step"] * 1e-6) / (HBM_PEAK_GBS * 1e9)
+        for v, name in ((2, "strip"), (1, "cell")):
+            p.set_option(kb.OPT_TILE, v)
+            d[f"{name}_per_launch_us_step"] = arm(p, n, 0, 2) / n * 1e6
+            d[f"{name}_graph_b100_us_step"] = arm(p, n, 100, 2) / n * 1e6
+    # the alternative the grouped kernel replaces: 64 separate problems, each
+    # advanced on its own (one launch per grid per step, or one graph each)
+    probs = [kb.Problem(kb.HEAT2D, (sd, sd), kb.HEAT_COEFFS, SEED + g) for g, sd in enumerate(sides)]
+    ns = 200
+    for b, name in ((0, "separate_per_launch_us_step"), (100, "separate_graph_b100_us_step")):
+        for q in probs:
+            q.run(ns, b)
+        torch_sync()
+        t0 = time.perf_counter()
+        for q in probs:
+            q.run(ns, b)
+        torch_sync()
+        d[name] = (time.perf_counter() - t0) / ns * 1e6
+    for q in probs:
+        q.destroy()
+    best = min(d["strip_graph_b100_us_step"], d["cell_graph_b100_us_step"])
+    d["gcell_upd_s"] = cells / best / 1e3
+    d["hbm_frac"] = 12.0 * cells / (best * 1e-6) / (HBM_PEAK_GBS * 1e9)
     out["multigrid_64_2000"] = d
 
     # FDTD cavities

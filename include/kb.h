@@ -170,6 +170,10 @@ extern "C" {
  *              ny*nx >= 2^20, else 1.
  *   KB_SKELETON: 1 = 4 elements per thread (default), 2 = 1, 3 = 8.
  *   KB_FDTD3D: 1 = one thread per cell, 2 = float4 rows (default).
+ *   KB_HEAT2D_MULTI: 1 = one thread per cell (64x4 tiles, grid found by
+ *              binary search); 2 = each wave walks 8 rows of 64 columns
+ *              with the neighbour rows in registers (64x32 tiles, grid from
+ *              a block table; default).
  *   KB_HEAT2D_SURROGATE: 1 = fused network, all activations in LDS, 3
  *              kernels per block (default); 2 = one kernel per layer with
  *              activations in HBM, 8 kernels per block.  The two agree to

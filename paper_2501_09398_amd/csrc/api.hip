@@ -136,6 +136,11 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
       if (total > ((int64_t)1 << 31) - 1) return false;
       off[0] = L.add(total * 4); off[1] = L.add(total * 4); off[2] = L.add(total * 4);
       off[14] = L.add(G * sizeof(GridDesc)); off[15] = L.add((G + 1) * sizeof(int));
+      int64_t nb2 = 0;
+      for (int64_t g = 0; g < G; ++g)
+        nb2 += ((shape[2 + 2 * g] + 63) / 64) * ((shape[1 + 2 * g] + kStripTileY - 1) / kStripTileY);
+      if (nb2 > ((int64_t)1 << 30)) return false;
+      off[18] = L.add(G * sizeof(GridDesc)); off[19] = L.add(nb2 * sizeof(int));
       common();
       return true;
     }
@@ -239,8 +244,13 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
       return 1;
     }
     case KB_HEAT2D_MULTI: {
-      MultiArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids_d, h->block_start_d, h->G, h->hk};
-      make_multi(L[0], a, h->total_blocks);
+      if (h->tile == 1) {
+        MultiArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids_d, h->block_start_d, h->G, h->hk};
+        make_multi(L[0], a, h->total_blocks);
+      } else {
+        MultiStripArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids2_d, h->block_grid_d, h->total_blocks2, h->hk};
+        make_multi_strip(L[0], a);
+      }
       return 1;
     }
     case KB_SKELETON: {
@@ -563,8 +573,21 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       h->total_blocks = blocks;
       h->total_cells = offc;
       h->K = 1;
+      // strip tiling: 64 columns x kStripTileY rows per block
+      h->grids2_d = reinterpret_cast<GridDesc *>(h->ws + off[18]);
+      h->block_grid_d = reinterpret_cast<int *>(h->ws + off[19]);
+      std::vector<GridDesc> gd2(h->G);
+      std::vector<int> bg;
+      for (int g = 0; g < h->G; ++g) {
+        const int tx = (gd[g].nx + 63) / 64, ty = (gd[g].ny + kStripTileY - 1) / kStripTileY;
+        gd2[g] = GridDesc{gd[g].off, gd[g].ny, gd[g].nx, tx, (int)bg.size()};
+        bg.insert(bg.end(), (size_t)tx * ty, g);
+      }
+      h->total_blocks2 = (int)bg.size();
       if (hipMemcpy(h->grids_d, gd.data(), gd.size() * sizeof(GridDesc), hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(h->block_start_d, bs.data(), bs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+          hipMemcpy(h->block_start_d, bs.data(), bs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(h->grids2_d, gd2.data(), gd2.size() * sizeof(GridDesc), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(h->block_grid_d, bg.data(), bg.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(KB_EHIP, "grid table upload failed"));
       if ((rc = enqueue_init(h, h->Tbuf[0], offc, seed, kTagT0, 0, 323.0, 343.0)) ||
           (rc = enqueue_init(h, h->P, offc, seed, kTagP, 0, 0.0, 1.0)))
@@ -663,6 +686,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
       else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 2;
       else if (h->kind == KB_HEAT2D_SURROGATE) ok = value >= 0 && value <= 2;
+      else if (h->kind == KB_HEAT2D_MULTI) ok = value >= 0 && value <= 2;
       else ok = value == 0;
       if (!ok) return fail(KB_EINVAL, "kernel variant %lld not available for this problem", (long long)value);
       if (h->tile != value) clear_cache(h);

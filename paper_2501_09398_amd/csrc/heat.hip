@@ -384,6 +384,47 @@ __global__ __launch_bounds__(256) void heat2d_multi_kernel(const MultiArgs a) {
   a.out[gd.off + c] = v;
 }
 
+// Many-grid strip kernel: wave w of a block walks rows i0 .. i0+7 of 64
+// consecutive columns (one per lane), keeping the rows above, at and below
+// the current one in registers; east / west neighbours come from the
+// adjacent lanes, lanes 0 and 63 load the cell beyond the wave (clamped at
+// the grid edge).  Same update, same bits as the one-cell kernel.
+__global__ __launch_bounds__(256) void heat2d_multi_strip_kernel(const MultiStripArgs a) {
+  const int lb = xcd_logical_block(a.nb);
+  if (lb >= a.nb) return;
+  const GridDesc gd = a.grids[a.block_grid[lb]];
+  const int local = lb - gd.block0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nx = gd.nx, ny = gd.ny;
+  const int j = (local % gd.tiles_x) * 64 + lane;
+  const int i0 = (local / gd.tiles_x) * kStripTileY + wave * kStripRows;
+  if (i0 >= ny) return;                       // uniform per wave
+  const bool col = j < nx;
+  const int jc = col ? j : nx - 1;
+  const float *T = a.T + gd.off;
+  const float *P = a.P + gd.off;
+  float *O = a.out + gd.off;
+  float up = T[(size_t)(i0 > 0 ? i0 - 1 : 0) * nx + jc];
+  float cur = T[(size_t)i0 * nx + jc];
+  const int i1 = min(i0 + kStripRows, ny);
+  for (int i = i0; i < i1; ++i) {
+    const float down = T[(size_t)(i + 1 < ny ? i + 1 : ny - 1) * nx + jc];
+    float wv = __shfl_up(cur, 1, 64);
+    float ev = __shfl_down(cur, 1, 64);
+    if (lane == 0) wv = jc > 0 ? T[(size_t)i * nx + jc - 1] : cur;
+    if (jc >= nx - 1) ev = cur;
+    else if (lane == 63) ev = T[(size_t)i * nx + jc + 1];
+    const float v = heat_update(cur, up, down, wv, ev, P[(size_t)i * nx + jc], a.k);
+    if (col) O[(size_t)i * nx + j] = v;
+    up = cur;
+    cur = down;
+  }
+}
+
+void make_multi_strip(Launch &L, const MultiStripArgs &a) {
+  L.set((const void *)heat2d_multi_strip_kernel, dim3(xcd_padded_grid(a.nb)), dim3(256), 0, a);
+}
+
 void make_multi(Launch &L, const MultiArgs &a, int total_blocks) {
   L.set((const void *)heat2d_multi_kernel, dim3(xcd_padded_grid(total_blocks)), dim3(kMultiBX, kMultiBY), 0, a);
 }

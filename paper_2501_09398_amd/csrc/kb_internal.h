@@ -113,6 +113,18 @@ struct MultiArgs {
   HeatCoef k;
 };
 
+// Many-grid strip kernel: a block of 4 waves covers 64 columns x 32 rows of
+// one grid; block -> grid by table.
+constexpr int kStripRows = 8;                 // rows per wave
+constexpr int kStripTileY = 4 * kStripRows;   // rows per block
+struct MultiStripArgs {
+  const float *T; float *out; const float *P;
+  const GridDesc *grids;        // tiles_x / block0 of the 64 x 32 tiling
+  const int *block_grid;        // grid of every block
+  int nb;
+  HeatCoef k;
+};
+
 struct SkelArgs {
   float *x; long long n; float a, b;
 };
@@ -147,6 +159,7 @@ bool make_heat3d(Launch &L, const Heat3DArgs &a, int variant);   // false: bad v
 bool make_heat2d_vec(Launch &L, const Heat2DArgs &a, int variant);  // false: bad variant / nx % 4
 constexpr int kMultiBX = 64, kMultiBY = 4;   // tile of the many-grid kernel
 void make_multi(Launch &L, const MultiArgs &a, int total_blocks);
+void make_multi_strip(Launch &L, const MultiStripArgs &a);
 void make_skeleton(Launch &L, const SkelArgs &a, int variant);
 bool make_fdtd_h(Launch &L, const FdtdArgs &a, int variant);   // false: bad variant
 bool make_fdtd_e(Launch &L, const FdtdArgs &a, int variant);
@@ -234,6 +247,9 @@ struct kb_problem {
   kb::GridDesc *grids_d = nullptr;
   int *block_start_d = nullptr;
   int total_blocks = 0;
+  kb::GridDesc *grids2_d = nullptr;   // 64 x 32 strip tiling
+  int *block_grid_d = nullptr;
+  int total_blocks2 = 0;
   int64_t total_cells = 0;
   std::vector<int64_t> grid_shape;
   // skeleton

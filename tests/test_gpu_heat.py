@@ -252,11 +252,15 @@ def test_heat3d_full_size_sampled(kb):
 
 # ---- many grids ------------------------------------------------------------
 
-def test_multigrid_matches_single_grids(kb):
-    announce("multigrid 6 grids")
-    sides = [(17, 70), (64, 64), (5, 130), (100, 33), (1, 1), (40, 250)]
+@pytest.mark.parametrize("variant", [1, 2])
+def test_multigrid_matches_single_grids(kb, variant):
+    """variant 1: one cell per thread; 2: 64 x 8 strips per wave.  Grids
+    narrower and wider than a wave, single rows and a single cell."""
+    announce(f"multigrid 8 grids variant {variant}")
+    sides = [(17, 70), (64, 64), (5, 130), (100, 33), (1, 1), (40, 250), (33, 1), (9, 65)]
     shape = [len(sides)] + [v for s in sides for v in s]
     with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 14) as p:
+        p.set_option(kb.OPT_TILE, variant)
         p.run(30, 7)
         allT = p.read(kb.F_T)
     T0 = synth.uniform_f32(14, synth.TAG_T0, allT.size, *synth.T0_RANGE)
@@ -280,8 +284,25 @@ def test_multigrid_graph_bitwise(kb):
     sides = synth.multigrid_sides(3, 8, 16, 200)
     shape = [len(sides)] + [v for s in sides for v in (s, s)]
     outs = []
-    for b in (0, 1, 5):
+    for v, b in ((2, 0), (2, 1), (2, 5), (1, 0), (1, 5)):
         with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 15) as p:
+            p.set_option(kb.OPT_TILE, v)
             p.run(23, b)
             outs.append(p.read(kb.F_T))
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+def test_multigrid_full_size_workload_strip_vs_cell(kb):
+    """64 grids of side round(64 * 16^u) (about 12.9 M cells): the two
+    variants give the same bits after 20 steps."""
+    announce("multigrid 64 grids full size")
+    sides = synth.multigrid_sides(20250116, 64)
+    shape = [64] + [v for s in sides for v in (s, s)]
+    outs = []
+    for v in (1, 2):
+        with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 20250116) as p:
+            p.set_option(kb.OPT_TILE, v)
+            p.run(20, 10)
+            outs.append(p.read(kb.F_T))
+    assert np.array_equal(outs[0], outs[1])
