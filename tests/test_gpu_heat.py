@@ -306,3 +306,31 @@ def test_multigrid_full_size_workload_strip_vs_cell(kb):
             p.run(20, 10)
             outs.append(p.read(kb.F_T))
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_multigrid_full_size_2000_steps_vs_oracle(kb):
+    """The 64-grid workload for 2000 steps in graph batches of 100 (the
+    benchmark's launch configuration, strip kernel): the three smallest grids
+    against the float32 oracle, and every grid's mean against its closed
+    form (the clamped Laplacian sums to zero on each grid)."""
+    announce("multigrid 64 grids 2000 steps b=100")
+    seed = 20250116
+    sides = synth.multigrid_sides(seed, 64)
+    shape = [64] + [v for s in sides for v in (s, s)]
+    with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), seed) as p:
+        p.run(2000, 100)
+        allT = p.read(kb.F_T)
+    T0s, Ps = synth.multigrid_init(seed, sides)
+    off = 0
+    grids = []
+    for s, T0, P in zip(sides, T0s, Ps):
+        grids.append((s, T0, P, allT[off:off + s * s].reshape(s, s)))
+        off += s * s
+    for s, T0, P, got in sorted(grids, key=lambda g: g[0])[:3]:
+        ref32 = oracle.heat2d(T0, P, 2000, dtype=np.float32)
+        assert rel_maxnorm(got, ref32) < 1e-5, s
+    for s, T0, P, got in grids:
+        m0 = np.mean(T0.astype(np.float64))
+        pbar = np.mean(P.astype(np.float64))
+        ref = 300 + pbar * 10 + (m0 - 300 - pbar * 10) * (1 - 1e-4) ** 2000
+        assert abs(np.mean(got.astype(np.float64)) - ref) / ref < 1e-5, s

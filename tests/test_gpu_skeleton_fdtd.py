@@ -4,6 +4,8 @@ Both are bit-identical to the float32 oracle: the skeleton update is one
 fused multiply-add per kernel on both sides, and every FDTD coefficient is
 0.5, so product and difference round the same way with or without fusion.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -256,3 +258,77 @@ def test_skeleton_coefficient_write_updates_or_drops_graphs(kb, builder, update)
         q.run(100, 0)
         assert np.array_equal(got, q.read(kb.F_X))
     assert np.array_equal(got, oracle.skeleton(x_mid, a2, b2, 100, dtype=np.float32))
+
+
+def yee_energy(E, Hm, Hp):
+    """Discrete energy conserved by the Yee update: 1/2 |E^n|^2 + 1/2 <H^(n-1/2), H^(n+1/2)>."""
+    e = sum(math.fsum(E[k].astype(np.float64).ravel() ** 2) for k in ("Ex", "Ey", "Ez"))
+    h = sum(math.fsum((Hm[k].astype(np.float64) * Hp[k].astype(np.float64)).ravel()) for k in ("Hx", "Hy", "Hz"))
+    return 0.5 * e + 0.5 * h
+
+
+def cavity_omega(N, dt, m, n, p):
+    """Phase per step of mode (m, n, p) of the Yee PEC cavity: the discrete
+    dispersion relation sin(w/2) = (dt/2) sqrt(4 (sin^2(m pi/2N) + ...))."""
+    lam = 4 * sum(np.sin(q * np.pi / (2 * N)) ** 2 for q in (m, n, p))
+    return 2 * np.arcsin(dt / 2 * np.sqrt(lam))
+
+
+def spectral_peaks(x, d, lo, hi, rel=0.05):
+    """Frequencies (rad per step) of the local maxima of |FFT| (Hann window,
+    linear trend removed, zero-padded) in (lo, hi) above rel of the largest."""
+    t = np.arange(x.size)
+    x = x - np.polyval(np.polyfit(t, x, 1), t)
+    nfft = 1 << 20
+    spec = np.abs(np.fft.rfft(x * np.hanning(x.size), nfft))
+    w = 2 * np.pi * np.fft.rfftfreq(nfft, d=d)
+    idx = np.where((w > lo) & (w < hi))[0]
+    s = spec[idx]
+    loc = [idx[i] for i in range(1, len(idx) - 1) if s[i] > s[i - 1] and s[i] > s[i + 1]]
+    big = max(spec[i] for i in loc)
+    return [w[i] for i in loc if spec[i] > rel * big]
+
+
+def test_fdtd_128_10000_steps_energy_and_lowest_mode(kb):
+    """The 128^3 cavity for 10,000 steps in graph batches of 100 (the
+    benchmark's launch configuration) with the in-chain reduction every 4
+    steps.  (1) Once the pulse has passed (g < 1e-30 after step 300) the
+    discrete energy is conserved: W at steps 300 and 9,998 agree to float32
+    round-off.  (2) The lowest cavity modes: H.H(t) = sum_m |h_m|^2
+    sin^2(w_m t + phi_m) (the modes are orthogonal), so the spectrum of the
+    logged H.H has lines at 2 w_m only; the probe (Ez at the source) has
+    lines at w_m.  The lowest three lines of each sit at the closed-form
+    frequencies of modes (1,1,0), (1,1,1), (2,1,0)."""
+    announce("fdtd 128^3 10000 steps b=100")
+    N, dt, seed = 128, 0.5, 20250116
+    with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, seed) as p:
+        p.set_option(kb.OPT_REDUCE_EVERY, 4)
+        p.run(300, 100)                      # fields E^300, H^(299.5)
+        E300 = {k: p.read(kb.FDTD_FIELDS[k]) for k in ("Ex", "Ey", "Ez")}
+        Hm300 = {k: p.read(kb.FDTD_FIELDS[k]) for k in ("Hx", "Hy", "Hz")}
+        p.run(1, 0)                          # H^(300.5)
+        Hp300 = {k: p.read(kb.FDTD_FIELDS[k]) for k in ("Hx", "Hy", "Hz")}
+        p.run(9998 - 301, 100)               # E^9998, H^(9997.5)
+        E2 = {k: p.read(kb.FDTD_FIELDS[k]) for k in ("Ex", "Ey", "Ez")}
+        Hm2 = {k: p.read(kb.FDTD_FIELDS[k]) for k in ("Hx", "Hy", "Hz")}
+        p.run(1, 0)                          # H^(9998.5)
+        Hp2 = {k: p.read(kb.FDTD_FIELDS[k]) for k in ("Hx", "Hy", "Hz")}
+        p.run(1, 0)
+        log = p.reduction_log()
+        probe = p.read(kb.F_PROBE)[:10000].astype(np.float64)
+        assert p.read(kb.F_STEP)[0] == 10000
+    W1, W2 = yee_energy(E300, Hm300, Hp300), yee_energy(E2, Hm2, Hp2)
+    print(f"energy W(300) {W1:.9e} W(9998) {W2:.9e} rel change {abs(W2 - W1) / W1:.2e}")
+    assert W1 > 0 and abs(W2 - W1) <= 1e-4 * W1
+    assert log.shape[0] == 2500 and log[-1, 0] == 10000
+    modes = [cavity_omega(N, dt, *m) for m in ((1, 1, 0), (1, 1, 1), (2, 1, 0))]
+    w110 = modes[0]
+    hh = log[log[:, 0] >= 300, 2]
+    pk_h = [w / 2 for w in spectral_peaks(hh, 4.0, 2 * 0.3 * w110, 2 * 1.7 * w110)]
+    pk_p = spectral_peaks(probe[300:], 1.0, 0.3 * w110, 1.7 * w110)
+    print("closed form", [f"{w:.6f}" for w in modes])
+    print("H.H lines / 2", [f"{w:.6f}" for w in pk_h[:4]], "probe lines", [f"{w:.6f}" for w in pk_p[:4]])
+    for pk in (pk_h, pk_p):
+        assert len(pk) >= 3
+        for got, want in zip(pk[:3], modes):
+            assert abs(got - want) <= 1e-3 * want, (got, want)
