@@ -4,8 +4,8 @@ Sec. VI of the paper names automatic characterisation and choice of the
 iteration batch size as the missing piece of the method.  Here it is done
 per problem and shape, in two stages, through the C ABI only:
 
-1. kernel stage -- for every kernel variant (and, for the LDS-tile variants
-   of the 2D stencil, every temporal depth t) time the warm execution of a
+1. kernel stage -- for every kernel variant (and, for the temporal-blocking
+   variants of the 2D and 3D stencils, every temporal depth t) time the warm execution of a
    fixed number of steps with a moderate batch (graph already built), and
    keep the fastest (warm microseconds per step; all variants give the same
    bits, so only time decides);
@@ -31,6 +31,7 @@ HEAT2D_DIRECT = [1]
 HEAT2D_TILE = [2, 3, 4, 5, 6, 7]
 HEAT2D_VEC = [8, 9, 10, 11, 13, 14]
 HEAT2D_DEPTHS = [1, 2, 4, 8, 16]
+HEAT3D_DEPTHS = [1, 2, 3, 4, 6]          # variant 5 (layer stacks of <= 8)
 
 
 def kernel_candidates(kb, problem, shape):
@@ -42,7 +43,10 @@ def kernel_candidates(kb, problem, shape):
             c += [(v, 1) for v in HEAT2D_VEC]
         return c
     if problem == kb.HEAT3D:
-        return [(1, 1)] + ([(2, 1), (3, 1), (4, 1)] if shape[2] % 4 == 0 else [])
+        c = [(1, 1)] + ([(2, 1), (3, 1), (4, 1)] if shape[2] % 4 == 0 else [])
+        if shape[0] <= 8:
+            c += [(5, t) for t in HEAT3D_DEPTHS]
+        return c
     if problem == kb.SKELETON:
         return [(1, 1), (2, 1), (3, 1)]
     if problem == kb.FDTD3D:

@@ -179,6 +179,7 @@ bool heat2d_is_tile(int v) { return v >= 2 && v <= 7; }
 // Temporal depth of one iteration.
 int iter_depth(const kb_problem *h) {
   if (h->kind == KB_HEAT2D_SURROGATE) return sg_iter_depth(h);
+  if (h->kind == KB_HEAT3D && heat3d_variant(h) == 5) return h->tdepth;
   return (h->kind == KB_HEAT2D && heat2d_is_tile(heat2d_variant(h))) ? h->tdepth : 1;
 }
 
@@ -233,7 +234,7 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
       return make_heat2d_vec(L[0], a, v) ? 1 : -1;
     }
     case KB_HEAT3D: {
-      Heat3DArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, (int)h->nz, (int)h->ny, (int)h->nx, h->hk};
+      Heat3DArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, (int)h->nz, (int)h->ny, (int)h->nx, h->hk, depth};
       return make_heat3d(L[0], a, heat3d_variant(h)) ? 1 : -1;
     }
     case KB_HEAT2D_SURROGATE: {
@@ -682,7 +683,8 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
     case KB_OPT_TILE: {
       bool ok = false;
       if (h->kind == KB_HEAT2D) ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0);
-      else if (h->kind == KB_HEAT3D) ok = value == 0 || value == 1 || (value >= 2 && value <= 4 && h->nx % 4 == 0);
+      else if (h->kind == KB_HEAT3D)
+        ok = value == 0 || value == 1 || (value >= 2 && value <= 4 && h->nx % 4 == 0) || (value == 5 && h->nz <= 8);
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
       else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 2;
       else if (h->kind == KB_HEAT2D_SURROGATE) ok = value >= 0 && value <= 2;
@@ -694,12 +696,15 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       if (h->kind == KB_HEAT2D_SURROGATE) h->K = sg_kernels_per_block(h);
       break;
     }
-    case KB_OPT_TDEPTH:
-      if (h->kind != KB_HEAT2D && value != 1) return fail(KB_EINVAL, "temporal depth > 1 only for KB_HEAT2D");
-      if (value < 1 || value > heat2d_tile_max_depth()) return fail(KB_EINVAL, "temporal depth must be 1..%d", heat2d_tile_max_depth());
+    case KB_OPT_TDEPTH: {
+      if (h->kind != KB_HEAT2D && h->kind != KB_HEAT3D && value != 1)
+        return fail(KB_EINVAL, "temporal depth > 1 only for KB_HEAT2D and KB_HEAT3D");
+      const int maxd = h->kind == KB_HEAT3D ? heat3d_tb_max_depth() : heat2d_tile_max_depth();
+      if (value < 1 || value > maxd) return fail(KB_EINVAL, "temporal depth must be 1..%d", maxd);
       if (h->tdepth != value) clear_cache(h);
       h->tdepth = (int)value;
       break;
+    }
     case KB_OPT_GRAPH_CACHE:
       if (value != 0 && value != 1) return fail(KB_EINVAL, "graph cache must be 0 or 1");
       h->cache = (int)value;

@@ -335,9 +335,120 @@ __global__ __launch_bounds__(256) void heat3d_kernel(const Heat3DArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Temporal blocking for layered stacks (nz <= 8): one launch advances t
+// (<= 6) steps.  A block owns a 32x32 tile of columns and loads the tile grown by
+// t columns on each side (clamped to the field) with all nz layers.  Each
+// of the 512 threads keeps up to kTbCols whole columns (every layer) in
+// registers; per
+// step it publishes them to an LDS plane stack, then updates them from the
+// four in-plane neighbours in LDS and the layers above and below in its own
+// registers.  Region cells next to a cut halo see a clamped neighbour that
+// is not the true one; the error moves inward one column per step and never
+// reaches the tile.  Same update, same bits as the one-step kernels.
+// ---------------------------------------------------------------------------
+constexpr int kTbX = 32, kTbY = 32, kTbMaxDepth = 6;   // 8 layers x 44^2 floats <= 64 KB of LDS
+constexpr int kTbThreads = 512;
+constexpr int kTbCols = ((kTbX + 2 * kTbMaxDepth) * (kTbY + 2 * kTbMaxDepth) + kTbThreads - 1) / kTbThreads;   // 4
+
+int heat3d_tb_max_depth() { return kTbMaxDepth; }
+
+template <int NZ>
+__global__ __launch_bounds__(kTbThreads) void heat3d_tb_kernel(const Heat3DArgs a) {
+  extern __shared__ float lds[];
+  const int t = a.tdepth;
+  const int tiles_x = (a.nx + kTbX - 1) / kTbX, tiles_y = (a.ny + kTbY - 1) / kTbY;
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const int x0 = (lb % tiles_x) * kTbX, y0 = (lb / tiles_x) * kTbY;
+  const int rx_lo = max(x0 - t, 0), rx_hi = min(x0 + kTbX + t, a.nx);
+  const int ry_lo = max(y0 - t, 0), ry_hi = min(y0 + kTbY + t, a.ny);
+  const int W = rx_hi - rx_lo, H = ry_hi - ry_lo, R = W * H;
+  const size_t plane = (size_t)a.ny * a.nx;
+  float v[kTbCols][NZ], p[kTbCols];
+  int rc[kTbCols];                      // (row << 8) | col in the region
+#pragma unroll
+  for (int q = 0; q < kTbCols; ++q) {
+    const int c = threadIdx.x + kTbThreads * q;
+    const int cc = c < R ? c : R - 1;
+    const int ry = cc / W, rx = cc - (cc / W) * W;
+    rc[q] = (ry << 8) | rx;
+    const size_t g = (size_t)(ry_lo + ry) * a.nx + rx_lo + rx;
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) v[q][z] = a.T[z * plane + g];
+    p[q] = a.P[g];
+  }
+  for (int s = 0; s < t; ++s) {
+#pragma unroll
+    for (int q = 0; q < kTbCols; ++q) {
+      const int c = threadIdx.x + kTbThreads * q;
+      if (c < R)
+#pragma unroll
+        for (int z = 0; z < NZ; ++z) lds[z * R + c] = v[q][z];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kTbCols; ++q) {
+      const int c = threadIdx.x + kTbThreads * q;
+      const int ry = rc[q] >> 8, rx = rc[q] & 255;
+      const int cc = ry * W + rx;
+      const int on = ry > 0 ? cc - W : cc, os = ry < H - 1 ? cc + W : cc;
+      const int ow = rx > 0 ? cc - 1 : cc, oe = rx < W - 1 ? cc + 1 : cc;
+      float nv[NZ];
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) {
+        const float tc = v[q][z];
+        const float tu = z + 1 < NZ ? v[q][z + 1] : tc;
+        const float td = z > 0 ? v[q][z - 1] : tc;
+        nv[z] = heat3d_update(tc, lds[z * R + on], lds[z * R + os], lds[z * R + ow], lds[z * R + oe], tu, td,
+                              z == 0 ? p[q] : 0.0f, z == 0, a.k);
+      }
+      if (c < R)
+#pragma unroll
+        for (int z = 0; z < NZ; ++z) v[q][z] = nv[z];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kTbCols; ++q) {
+    const int c = threadIdx.x + kTbThreads * q;
+    const int ry = rc[q] >> 8, rx = rc[q] & 255;
+    const int gy = ry_lo + ry, gx = rx_lo + rx;
+    if (c < R && gy >= y0 && gy < y0 + kTbY && gx >= x0 && gx < x0 + kTbX) {
+      const size_t g = (size_t)gy * a.nx + gx;
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) a.out[z * plane + g] = v[q][z];
+    }
+  }
+}
+
+static const void *heat3d_tb_fn(int nz) {
+  switch (nz) {
+    case 1: return (const void *)heat3d_tb_kernel<1>;
+    case 2: return (const void *)heat3d_tb_kernel<2>;
+    case 3: return (const void *)heat3d_tb_kernel<3>;
+    case 4: return (const void *)heat3d_tb_kernel<4>;
+    case 5: return (const void *)heat3d_tb_kernel<5>;
+    case 6: return (const void *)heat3d_tb_kernel<6>;
+    case 7: return (const void *)heat3d_tb_kernel<7>;
+    case 8: return (const void *)heat3d_tb_kernel<8>;
+  }
+  return nullptr;
+}
+
 // variant: 1 = scalar columns; vector rows (nx % 4 == 0): 2 = plain,
-// 3 = next layer prefetched, 4 = prefetched with streaming stores
+// 3 = next layer prefetched, 4 = prefetched with streaming stores;
+// 5 = temporal blocking over a.tdepth steps (nz <= 8)
 bool make_heat3d(Launch &L, const Heat3DArgs &a, int variant) {
+  if (variant == 5) {
+    const void *f = heat3d_tb_fn(a.nz);
+    if (!f || a.tdepth < 1 || a.tdepth > kTbMaxDepth) return false;
+    const int nb = ((a.nx + kTbX - 1) / kTbX) * ((a.ny + kTbY - 1) / kTbY);
+    const unsigned lds = (unsigned)(a.nz * (kTbX + 2 * a.tdepth) * (kTbY + 2 * a.tdepth) * sizeof(float));
+    L.set(f, dim3(xcd_padded_grid(nb)), dim3(kTbThreads), lds, a);
+    return true;
+  }
   if (variant >= 2 && variant <= 4) {
     if (a.nx % 4 != 0) return false;
     int nb = ((a.nx + 255) / 256) * ((a.ny + 3) / 4);

@@ -96,7 +96,9 @@ struct Heat3DArgs {
   const float *T; float *out; const float *P;   // P: plane of layer 0
   int nz, ny, nx;
   HeatCoef k;
+  int tdepth = 1;                               // steps per launch (variant 5)
 };
+int heat3d_tb_max_depth();
 
 struct GridDesc {               // one grid of the many-grid problem
   long long off;                // first cell in the concatenated arrays

@@ -80,7 +80,8 @@ def test_kernel_candidates_respect_alignment():
     c_ragged = autotune.kernel_candidates(kb, kb.HEAT2D, (64, 250))
     assert any(v >= 8 for v, _ in c_aligned)
     assert not any(v >= 8 for v, _ in c_ragged)
-    assert autotune.kernel_candidates(kb, kb.HEAT3D, (8, 64, 66)) == [(1, 1)]
+    assert autotune.kernel_candidates(kb, kb.HEAT3D, (8, 64, 66)) == [(1, 1)] + [(5, t) for t in autotune.HEAT3D_DEPTHS]
+    assert autotune.kernel_candidates(kb, kb.HEAT3D, (9, 64, 66)) == [(1, 1)]
 
 
 @pytest.mark.gpu

@@ -186,10 +186,11 @@ def test_heat2d_reduce_mean(kb):
 
 # ---- 3D ----------------------------------------------------------------------
 
-def run_heat3d(kb, shape, steps, b=0, seed=0, builder=0, tile=0):
+def run_heat3d(kb, shape, steps, b=0, seed=0, builder=0, tile=0, tdepth=1):
     with kb.Problem(kb.HEAT3D, shape, coeffs(HEAT), seed) as p:
         p.set_option(kb.OPT_BUILDER, builder)
         p.set_option(kb.OPT_TILE, tile)
+        p.set_option(kb.OPT_TDEPTH, tdepth)
         p.run(steps, b)
         return p.read(kb.F_T)
 
@@ -221,6 +222,40 @@ def test_heat3d_vector_variant_bitwise(kb, shape, tile):
     assert np.array_equal(base, run_heat3d(kb, shape, 17, b=4, seed=17, tile=tile))
     T0, P = synth.heat3d_init(17, *shape)
     assert rel_maxnorm(base, oracle.heat3d(T0, P, 17, dtype=np.float32)) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(8, 64, 64), (8, 70, 95), (3, 20, 72), (1, 3, 260), (5, 33, 33),
+                                   (2, 5, 4), (7, 100, 1), (8, 1, 1), (6, 45, 46)])
+@pytest.mark.parametrize("tdepth", [1, 2, 3, 6])
+def test_heat3d_temporal_blocking_bitwise(kb, shape, tdepth):
+    """Variant 5 (t steps per launch over 32x32 column tiles, columns in
+    registers, planes in LDS) against the one-step kernel: same bits for
+    every depth, with a step count that leaves a remainder (run per step),
+    per launch and in graph batches; tiles smaller than the halo, single
+    rows and columns, every layer count up to 8."""
+    announce(f"heat3d temporal {shape} t={tdepth}")
+    steps = 17
+    base = run_heat3d(kb, shape, steps, seed=19, tile=1)
+    assert np.array_equal(base, run_heat3d(kb, shape, steps, seed=19, tile=5, tdepth=tdepth))
+    assert np.array_equal(base, run_heat3d(kb, shape, steps, b=2, seed=19, tile=5, tdepth=tdepth))
+
+
+def test_heat3d_temporal_blocking_full_size(kb):
+    """8x512x512 at depth 4 in graph batches of 50 for 2000 steps: the same
+    bits as the one-step kernel."""
+    announce("heat3d temporal 8x512x512 2000 steps")
+    shape = (8, 512, 512)
+    base = run_heat3d(kb, shape, 2000, b=100, seed=20250116, tile=1)
+    assert np.array_equal(base, run_heat3d(kb, shape, 2000, b=50, seed=20250116, tile=5, tdepth=4))
+
+
+def test_heat3d_temporal_blocking_limits(kb):
+    with kb.Problem(kb.HEAT3D, (9, 16, 16), coeffs(HEAT), 0) as p:
+        with pytest.raises(kb.KBError):
+            p.set_option(kb.OPT_TILE, 5)              # more than 8 layers
+    with kb.Problem(kb.HEAT3D, (8, 16, 16), coeffs(HEAT), 0) as p:
+        with pytest.raises(kb.KBError):
+            p.set_option(kb.OPT_TDEPTH, 7)
 
 
 @pytest.mark.parametrize("b", [1, 4, 9])
