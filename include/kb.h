@@ -166,10 +166,15 @@ extern "C" {
  *              Default: 13 if nx % 4 == 0 and ny*nx >= 2^20, else 1.
  *   KB_HEAT3D: 1 = one thread per column; float4 rows (nx % 4 == 0):
  *              2 = plain, 3 = next layer prefetched, 4 = prefetched with
- *              streaming stores.  Default: 4 if nx % 4 == 0 and
- *              ny*nx >= 2^20, else 1.
+ *              streaming stores; 5 = temporal blocking (KB_OPT_TDEPTH
+ *              steps per launch, 1..6; nz <= 8); 6, 7, 8 = each wave
+ *              covers 2, 4, 8 rows with their neighbour rows in registers,
+ *              streaming stores (nx % 4 == 0); 9, 10 = 2, 4 rows with the
+ *              layer after next loaded one layer ahead.  Default: 6 if nx % 4 == 0
+ *              and ny*nx >= 2^20, else 1.
  *   KB_SKELETON: 1 = 4 elements per thread (default), 2 = 1, 3 = 8.
- *   KB_FDTD3D: 1 = one thread per cell, 2 = float4 rows (default).
+ *   KB_FDTD3D: 1 = one thread per cell, 2 = float4 rows (default),
+ *              3 / 4 = float4 rows, each thread walking 8 / 16 planes in k.
  *   KB_HEAT2D_MULTI: 1 = one thread per cell (64x4 tiles, grid found by
  *              binary search); 2 = each wave walks 8 rows of 64 columns
  *              with the neighbour rows in registers (64x32 tiles, grid from

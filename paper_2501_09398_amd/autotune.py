@@ -43,14 +43,14 @@ def kernel_candidates(kb, problem, shape):
             c += [(v, 1) for v in HEAT2D_VEC]
         return c
     if problem == kb.HEAT3D:
-        c = [(1, 1)] + ([(2, 1), (3, 1), (4, 1)] if shape[2] % 4 == 0 else [])
+        c = [(1, 1)] + ([(2, 1), (3, 1), (4, 1), (6, 1), (7, 1), (8, 1), (9, 1), (10, 1)] if shape[2] % 4 == 0 else [])
         if shape[0] <= 8:
             c += [(5, t) for t in HEAT3D_DEPTHS]
         return c
     if problem == kb.SKELETON:
         return [(1, 1), (2, 1), (3, 1)]
     if problem == kb.FDTD3D:
-        return [(1, 1), (2, 1)]
+        return [(1, 1), (2, 1), (3, 1), (4, 1)]
     return [(0, 1)]
 
 

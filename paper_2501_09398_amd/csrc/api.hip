@@ -172,7 +172,7 @@ int heat2d_variant(const kb_problem *h) {
 }
 int heat3d_variant(const kb_problem *h) {
   if (h->tile != 0) return h->tile;
-  return (h->nx % 4 == 0 && h->ny * h->nx >= (1 << 20)) ? 4 : 1;
+  return (h->nx % 4 == 0 && h->ny * h->nx >= (1 << 20)) ? 6 : 1;
 }
 bool heat2d_is_tile(int v) { return v >= 2 && v <= 7; }
 
@@ -684,9 +684,10 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       bool ok = false;
       if (h->kind == KB_HEAT2D) ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0);
       else if (h->kind == KB_HEAT3D)
-        ok = value == 0 || value == 1 || (value >= 2 && value <= 4 && h->nx % 4 == 0) || (value == 5 && h->nz <= 8);
+        ok = value == 0 || value == 1 || (((value >= 2 && value <= 4) || (value >= 6 && value <= 10)) && h->nx % 4 == 0) ||
+             (value == 5 && h->nz <= 8);
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
-      else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 2;
+      else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 4;
       else if (h->kind == KB_HEAT2D_SURROGATE) ok = value >= 0 && value <= 2;
       else if (h->kind == KB_HEAT2D_MULTI) ok = value >= 0 && value <= 2;
       else ok = value == 0;

@@ -213,16 +213,177 @@ __global__ __launch_bounds__(256) void fdtd_e_vec_kernel(const FdtdArgs f) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// k-marching vector kernels: a thread owns one float4 slot of a plane for KC
+// consecutive planes and walks them in increasing k, so the H kernel reuses
+// the k+1 row of Ex, Ey it loaded as the next plane's own row and the E
+// kernel the Hx, Hy it loaded as the next plane's k-1 row (8 float4 loads
+// per node instead of 10).  Blocks are numbered by (plane chunk, slot block)
+// and remapped to XCD bands as above.  Same arithmetic, same bits.
+// ---------------------------------------------------------------------------
+struct MarchPos {
+  int k0, k1, j, i0, lane;
+  bool qin;
+  size_t c;        // offset of node (i0, j, k0)
+};
+
+template <int KC>
+__device__ __forceinline__ bool march_pos(const FdtdArgs &f, MarchPos &p) {
+  const int M = f.N + 1, P4 = f.P / 4;
+  const int Q = M * P4;
+  const int bpp = (Q + 255) / 256;
+  const int nch = (M + KC - 1) / KC;
+  const int nb = bpp * nch;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return false;
+  const int ch = lb / bpp;
+  const int q = (lb - ch * bpp) * 256 + (int)threadIdx.x;
+  p.qin = q < Q;
+  const int qq = p.qin ? q : Q - 1;
+  p.j = qq / P4;
+  p.i0 = (qq - p.j * P4) * 4;
+  p.lane = threadIdx.x & 63;
+  p.k0 = ch * KC;
+  p.k1 = min(p.k0 + KC, M);
+  p.c = ((size_t)p.k0 * M + p.j) * f.P + p.i0;
+  return true;
+}
+
+template <int KC>
+__global__ __launch_bounds__(256) void fdtd_h_march_kernel(const FdtdArgs f) {
+  MarchPos p;
+  if (!march_pos<KC>(f, p)) return;
+  const int N = f.N;
+  const size_t sj = f.P, sk = (size_t)(N + 1) * f.P;
+  const float *__restrict__ Ex = f.Ex;
+  const float *__restrict__ Ey = f.Ey;
+  const float *__restrict__ Ez = f.Ez;
+  float *__restrict__ Hx = f.Hx;
+  float *__restrict__ Hy = f.Hy;
+  float *__restrict__ Hz = f.Hz;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const bool in = p.qin;
+  const bool jup = in && p.j < N;
+  const float dt = f.dt;
+  size_t c = p.c;
+  float4 ex = in ? ld4(Ex + c) : z4;
+  float4 ey = in ? ld4(Ey + c) : z4;
+  for (int k = p.k0; k < p.k1; ++k, c += sk) {
+    const bool kup = in && k < N;
+    const float4 ex_k = kup ? ld4(Ex + c + sk) : z4;   // k+1
+    const float4 ey_k = kup ? ld4(Ey + c + sk) : z4;
+    const float4 ez = in ? ld4(Ez + c) : z4;
+    const float4 hx = in ? ld4(Hx + c) : z4;
+    const float4 hy = in ? ld4(Hy + c) : z4;
+    const float4 hz = in ? ld4(Hz + c) : z4;
+    const float4 ez_j = jup ? ld4(Ez + c + sj) : z4;   // j+1
+    const float4 ex_j = jup ? ld4(Ex + c + sj) : z4;
+    float ey_e = __shfl_down(ey.x, 1, 64);
+    float ez_e = __shfl_down(ez.x, 1, 64);
+    if (p.lane == 63 && in && p.i0 + 4 < f.P) {
+      ey_e = Ey[c + 4];
+      ez_e = Ez[c + 4];
+    }
+    float ox[4], oy[4], oz[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = p.i0 + e;
+      const float eyc = comp(ey, e), ezc = comp(ez, e), exc = comp(ex, e);
+      const float eye = e < 3 ? comp(ey, e + 1) : ey_e;
+      const float eze = e < 3 ? comp(ez, e + 1) : ez_e;
+      ox[e] = (i <= N && p.j < N && k < N)
+                  ? comp(hx, e) - dt * ((comp(ez_j, e) - ezc) - (comp(ey_k, e) - eyc)) : comp(hx, e);
+      oy[e] = (i < N && k < N) ? comp(hy, e) - dt * ((comp(ex_k, e) - exc) - (eze - ezc)) : comp(hy, e);
+      oz[e] = (i < N && p.j < N) ? comp(hz, e) - dt * ((eye - eyc) - (comp(ex_j, e) - exc)) : comp(hz, e);
+    }
+    if (in) {
+      st4(Hx + c, make_float4(ox[0], ox[1], ox[2], ox[3]));
+      st4(Hy + c, make_float4(oy[0], oy[1], oy[2], oy[3]));
+      st4(Hz + c, make_float4(oz[0], oz[1], oz[2], oz[3]));
+    }
+    ex = ex_k;
+    ey = ey_k;
+  }
+}
+
+template <int KC>
+__global__ __launch_bounds__(256) void fdtd_e_march_kernel(const FdtdArgs f) {
+  MarchPos p;
+  if (!march_pos<KC>(f, p)) return;
+  const int N = f.N;
+  const size_t sj = f.P, sk = (size_t)(N + 1) * f.P;
+  float *__restrict__ Ex = f.Ex;
+  float *__restrict__ Ey = f.Ey;
+  float *__restrict__ Ez = f.Ez;
+  const float *__restrict__ Hx = f.Hx;
+  const float *__restrict__ Hy = f.Hy;
+  const float *__restrict__ Hz = f.Hz;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const bool in = p.qin;
+  const bool jdn = in && p.j > 0;
+  const bool jj = p.j >= 1 && p.j <= N - 1;
+  const float dt = f.dt;
+  size_t c = p.c;
+  float4 hx_k = in && p.k0 > 0 ? ld4(Hx + c - sk) : z4;   // k-1
+  float4 hy_k = in && p.k0 > 0 ? ld4(Hy + c - sk) : z4;
+  for (int k = p.k0; k < p.k1; ++k, c += sk) {
+    const float4 ex = in ? ld4(Ex + c) : z4;
+    const float4 ey = in ? ld4(Ey + c) : z4;
+    const float4 ez = in ? ld4(Ez + c) : z4;
+    const float4 hx = in ? ld4(Hx + c) : z4;
+    const float4 hy = in ? ld4(Hy + c) : z4;
+    const float4 hz = in ? ld4(Hz + c) : z4;
+    const float4 hz_j = jdn ? ld4(Hz + c - sj) : z4;   // j-1
+    const float4 hx_j = jdn ? ld4(Hx + c - sj) : z4;
+    float hz_w = __shfl_up(hz.w, 1, 64);
+    float hy_w = __shfl_up(hy.w, 1, 64);
+    if (p.lane == 0 && in && p.i0 > 0) {
+      hz_w = Hz[c - 1];
+      hy_w = Hy[c - 1];
+    }
+    const bool kk = k >= 1 && k <= N - 1;
+    float ox[4], oy[4], oz[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = p.i0 + e;
+      const bool ii = i >= 1 && i <= N - 1;
+      const float hzc = comp(hz, e), hyc = comp(hy, e), hxc = comp(hx, e);
+      const float hzw = e > 0 ? comp(hz, e - 1) : hz_w;
+      const float hyw = e > 0 ? comp(hy, e - 1) : hy_w;
+      ox[e] = (i < N && jj && kk) ? comp(ex, e) + dt * ((hzc - comp(hz_j, e)) - (hyc - comp(hy_k, e))) : comp(ex, e);
+      oy[e] = (p.j < N && ii && kk) ? comp(ey, e) + dt * ((hxc - comp(hx_k, e)) - (hzc - hzw)) : comp(ey, e);
+      oz[e] = (k < N && ii && jj) ? comp(ez, e) + dt * ((hyc - hyw) - (hxc - comp(hx_j, e))) : comp(ez, e);
+    }
+    if (in) {
+      st4(Ex + c, make_float4(ox[0], ox[1], ox[2], ox[3]));
+      st4(Ey + c, make_float4(oy[0], oy[1], oy[2], oy[3]));
+      st4(Ez + c, make_float4(oz[0], oz[1], oz[2], oz[3]));
+    }
+    hx_k = hx;
+    hy_k = hy;
+  }
+}
+
+template <int KC>
+static dim3 march_grid(const FdtdArgs &a) {
+  const int M = a.N + 1, P4 = a.P / 4;
+  const int bpp = (M * P4 + 255) / 256;
+  return dim3((unsigned)xcd_padded_grid(bpp * ((M + KC - 1) / KC)));
+}
+
 static dim3 vec_grid(const FdtdArgs &a) {
   const int M = a.N + 1, P4 = a.P / 4;
   const int bpp = (M * P4 + 255) / 256;
   return dim3((unsigned)xcd_padded_grid(bpp * M));
 }
 
-// variant: 1 = scalar, 2 = vector (default)
+// variant: 1 = scalar, 2 = vector (default), 3 / 4 = vector marching 8 / 16
+// planes per thread
 bool make_fdtd_h(Launch &L, const FdtdArgs &a, int variant) {
   if (variant == 1) L.set((const void *)fdtd_h_kernel, scalar_grid(a.N), dim3(64, 4), 0, a);
   else if (variant == 2) L.set((const void *)fdtd_h_vec_kernel, vec_grid(a), dim3(256), 0, a);
+  else if (variant == 3) L.set((const void *)fdtd_h_march_kernel<8>, march_grid<8>(a), dim3(256), 0, a);
+  else if (variant == 4) L.set((const void *)fdtd_h_march_kernel<16>, march_grid<16>(a), dim3(256), 0, a);
   else return false;
   return true;
 }
@@ -230,6 +391,8 @@ bool make_fdtd_h(Launch &L, const FdtdArgs &a, int variant) {
 bool make_fdtd_e(Launch &L, const FdtdArgs &a, int variant) {
   if (variant == 1) L.set((const void *)fdtd_e_kernel, scalar_grid(a.N), dim3(64, 4), 0, a);
   else if (variant == 2) L.set((const void *)fdtd_e_vec_kernel, vec_grid(a), dim3(256), 0, a);
+  else if (variant == 3) L.set((const void *)fdtd_e_march_kernel<8>, march_grid<8>(a), dim3(256), 0, a);
+  else if (variant == 4) L.set((const void *)fdtd_e_march_kernel<16>, march_grid<16>(a), dim3(256), 0, a);
   else return false;
   return true;
 }

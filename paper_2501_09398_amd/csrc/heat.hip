@@ -300,6 +300,95 @@ __global__ __launch_bounds__(256) void heat3d_vec_kernel(const Heat3DArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Register-blocked 3D rows: wave w of a block covers rows y0 .. y0+R-1 of
+// 256 consecutive columns (a float4 per lane) and marches up the layers.
+// For each layer it loads the R rows of the next layer together with the
+// row above and the row below them -- R + 2 row loads for R output rows,
+// where the one-row kernel issues three -- and keeps the layers below, at
+// and above the current one in registers.  NT: streaming stores.  PF: the
+// rows of the layer after next are loaded one iteration ahead.
+// ---------------------------------------------------------------------------
+template <int R, bool NT, bool PF>
+__global__ __launch_bounds__(256) void heat3d_rows_kernel(const Heat3DArgs a) {
+  const int tiles_x = (a.nx + 255) / 256;
+  const int tiles_y = (a.ny + 4 * R - 1) / (4 * R);
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const int lane = threadIdx.x;
+  const int y0 = (lb / tiles_x) * (4 * R) + threadIdx.y * R;
+  if (y0 >= a.ny) return;                       // uniform per wave
+  const int x = (lb % tiles_x) * 256 + lane * 4;
+  const bool xin = x < a.nx;
+  const size_t nx = (size_t)a.nx, ny = (size_t)a.ny;
+  const float *__restrict__ T = a.T;
+  const float *__restrict__ P = a.P;
+  float *__restrict__ out = a.out;
+  size_t rows[R + 2];                           // rows y0-1 .. y0+R, clamped
+#pragma unroll
+  for (int r = 0; r < R + 2; ++r) {
+    const int yy = y0 - 1 + r;
+    rows[r] = (size_t)(yy < 0 ? 0 : (yy >= a.ny ? a.ny - 1 : yy));
+  }
+  float4 c[R + 2], u[R + 2], d[R], u2[R + 2];
+#pragma unroll
+  for (int r = 0; r < R + 2; ++r) c[r] = load_row4(T, rows[r], nx, x, xin);
+#pragma unroll
+  for (int r = 0; r < R; ++r) d[r] = c[r + 1];  // below layer 0: itself
+  if constexpr (PF) {                           // layer 1 rows, one layer ahead
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) u2[r] = a.nz > 1 ? load_row4(T, ny + rows[r], nx, x, xin) : c[r];
+  }
+  for (int z = 0; z < a.nz; ++z) {
+    const size_t zr = (size_t)z * ny;
+    if constexpr (PF) {
+#pragma unroll
+      for (int r = 0; r < R + 2; ++r) u[r] = u2[r];
+      if (z + 2 < a.nz) {
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) u2[r] = load_row4(T, zr + 2 * ny + rows[r], nx, x, xin);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) u2[r] = u[r];
+      }
+      if (z + 1 >= a.nz) {
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) u[r] = c[r];        // above the top layer: itself
+      }
+    } else {
+      if (z + 1 < a.nz) {
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) u[r] = load_row4(T, zr + ny + rows[r], nx, x, xin);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) u[r] = c[r];        // above the top layer: itself
+      }
+    }
+    const bool hp = z == 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int yy = y0 + r;
+      if (yy < a.ny) {
+        const float4 tc = c[r + 1], tn = c[r], ts = c[r + 2], tu = u[r + 1], td = d[r];
+        const float4 p = hp ? load_row4(P, (size_t)yy, nx, x, xin) : make_float4(0.f, 0.f, 0.f, 0.f);
+        float wv, ev;
+        row_neighbours(T + (zr + yy) * nx, tc, x, a.nx, lane, wv, ev);
+        float4 o;
+        o.x = heat3d_update(tc.x, tn.x, ts.x, wv, tc.y, tu.x, td.x, p.x, hp, a.k);
+        o.y = heat3d_update(tc.y, tn.y, ts.y, tc.x, tc.z, tu.y, td.y, p.y, hp, a.k);
+        o.z = heat3d_update(tc.z, tn.z, ts.z, tc.y, tc.w, tu.z, td.z, p.z, hp, a.k);
+        o.w = heat3d_update(tc.w, tn.w, ts.w, tc.z, ev, tu.w, td.w, p.w, hp, a.k);
+        if (xin) store_row4<NT>(out + (zr + yy) * nx + x, o);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[r] = c[r + 1];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) c[r] = u[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 3D kernel: one thread per (x, y) column, marching up the layers with the
 // column's three consecutive layers in registers.  P is the plane of layer 0.
 // ---------------------------------------------------------------------------
@@ -439,7 +528,9 @@ static const void *heat3d_tb_fn(int nz) {
 
 // variant: 1 = scalar columns; vector rows (nx % 4 == 0): 2 = plain,
 // 3 = next layer prefetched, 4 = prefetched with streaming stores;
-// 5 = temporal blocking over a.tdepth steps (nz <= 8)
+// 5 = temporal blocking over a.tdepth steps (nz <= 8); register-blocked
+// rows with streaming stores (nx % 4 == 0): 6 = 2 rows, 7 = 4, 8 = 8 per
+// wave; 9 = 2 rows, 10 = 4 rows, with the layer after next loaded ahead
 bool make_heat3d(Launch &L, const Heat3DArgs &a, int variant) {
   if (variant == 5) {
     const void *f = heat3d_tb_fn(a.nz);
@@ -447,6 +538,18 @@ bool make_heat3d(Launch &L, const Heat3DArgs &a, int variant) {
     const int nb = ((a.nx + kTbX - 1) / kTbX) * ((a.ny + kTbY - 1) / kTbY);
     const unsigned lds = (unsigned)(a.nz * (kTbX + 2 * a.tdepth) * (kTbY + 2 * a.tdepth) * sizeof(float));
     L.set(f, dim3(xcd_padded_grid(nb)), dim3(kTbThreads), lds, a);
+    return true;
+  }
+  if (variant >= 6 && variant <= 10) {
+    if (a.nx % 4 != 0) return false;
+    const int R = variant == 6 || variant == 9 ? 2 : variant == 7 || variant == 10 ? 4 : 8;
+    const int nb = ((a.nx + 255) / 256) * ((a.ny + 4 * R - 1) / (4 * R));
+    const void *f = variant == 6  ? (const void *)heat3d_rows_kernel<2, true, false>
+                  : variant == 7  ? (const void *)heat3d_rows_kernel<4, true, false>
+                  : variant == 8  ? (const void *)heat3d_rows_kernel<8, true, false>
+                  : variant == 9  ? (const void *)heat3d_rows_kernel<2, true, true>
+                                  : (const void *)heat3d_rows_kernel<4, true, true>;
+    L.set(f, dim3(xcd_padded_grid(nb)), dim3(64, 4), 0, a);
     return true;
   }
   if (variant >= 2 && variant <= 4) {

@@ -214,7 +214,7 @@ def test_heat3d_vs_oracle(kb, shape, steps):
 
 
 @pytest.mark.parametrize("shape", [(3, 20, 72), (8, 64, 64), (2, 5, 4), (1, 3, 260), (5, 33, 516)])
-@pytest.mark.parametrize("tile", [2, 3, 4])
+@pytest.mark.parametrize("tile", [2, 3, 4, 6, 7, 8, 9, 10])
 def test_heat3d_vector_variant_bitwise(kb, shape, tile):
     announce(f"heat3d vec {tile} {shape}")
     base = run_heat3d(kb, shape, 17, seed=17, tile=1)

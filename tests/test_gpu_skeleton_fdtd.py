@@ -117,7 +117,7 @@ def test_fdtd_source_cell_from_seed(kb):
 
 
 @pytest.mark.parametrize("N,steps", [(8, 150), (17, 120), (32, 300), (5, 60), (6, 60)])
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 def test_fdtd_bitwise_vs_oracle(kb, N, steps, variant):
     announce(f"fdtd N={N} steps={steps} variant={variant}")
     seed = 32
@@ -215,7 +215,7 @@ def test_fdtd_random_fields_both_variants(kb, N):
     M = N + 1
     f0 = {k: rng.standard_normal((M, M, M)).astype(np.float32) for k in oracle.FDTD_FIELDS}
     ref, _ = oracle.fdtd(f0, N, 9, dtype=np.float32)
-    for variant in (1, 2):
+    for variant in (1, 2, 3, 4):
         with kb.Problem(kb.FDTD3D, (N, 16), (0.5, 0.0, 80.0), 0) as p:
             p.set_option(kb.OPT_TILE, variant)
             for k, fid in kb.FDTD_FIELDS.items():
