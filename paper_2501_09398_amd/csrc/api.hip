@@ -174,7 +174,7 @@ int heat3d_variant(const kb_problem *h) {
   if (h->tile != 0) return h->tile;
   return (h->nx % 4 == 0 && h->ny * h->nx >= (1 << 20)) ? 6 : 1;
 }
-bool heat2d_is_tile(int v) { return v >= 2 && v <= 7; }
+bool heat2d_is_tile(int v) { return (v >= 2 && v <= 7) || v == 15; }   // temporal blocking
 
 // Temporal depth of one iteration.
 int iter_depth(const kb_problem *h) {
@@ -230,6 +230,7 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
         make_heat2d_direct(L[0], a);
         return 1;
       }
+      if (v == 15) return make_heat2d_strip(L[0], a) ? 1 : -1;
       if (heat2d_is_tile(v)) return make_heat2d_tile(L[0], a, v) ? 1 : -1;
       return make_heat2d_vec(L[0], a, v) ? 1 : -1;
     }
@@ -682,7 +683,8 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       break;
     case KB_OPT_TILE: {
       bool ok = false;
-      if (h->kind == KB_HEAT2D) ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0);
+      if (h->kind == KB_HEAT2D)
+        ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0) || value == 15;
       else if (h->kind == KB_HEAT3D)
         ok = value == 0 || value == 1 || (((value >= 2 && value <= 4) || (value >= 6 && value <= 10)) && h->nx % 4 == 0) ||
              (value == 5 && h->nz <= 8);
