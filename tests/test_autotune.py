@@ -14,7 +14,8 @@ class FakeKB:
     OPT_BUILDER, OPT_TILE, OPT_TDEPTH, OPT_GRAPH_CACHE, OPT_MAX_NODES = 1, 2, 3, 4, 5
     # per-launch kernel time (s) per variant; variant 6 with depth 8 is best
     T_K = {1: 3e-6, 2: 4e-6, 3: 3.5e-6, 4: 3.6e-6, 5: 3.4e-6, 6: 3.2e-6, 7: 3.9e-6,
-           8: 2.9e-6, 9: 2.95e-6, 10: 3.1e-6, 11: 3.3e-6, 12: 3.5e-6, 13: 2.8e-6, 14: 2.85e-6}
+           8: 2.9e-6, 9: 2.95e-6, 10: 3.1e-6, 11: 3.3e-6, 12: 3.5e-6, 13: 2.8e-6, 14: 2.85e-6,
+           15: 3.3e-6}
     T_I, T_A, K_C, B_C = 0.5e-6, 8e-6, 3e-6, 2e-4
 
     class Problem:
@@ -37,7 +38,7 @@ class FakeKB:
                 self.t = val
 
         def run(self, n, b):
-            t = self.t if 2 <= self.v <= 7 else 1
+            t = self.t if 2 <= self.v <= 7 or self.v == 15 else 1
             iters = n // t
             tk = FakeKB.T_K[self.v] * (1 + 0.1 * t) / t * t    # deeper steps cost a little more each
             nb = iters // b
