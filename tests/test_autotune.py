@@ -79,8 +79,9 @@ def test_kernel_candidates_respect_alignment():
     kb = FakeKB()
     c_aligned = autotune.kernel_candidates(kb, kb.HEAT2D, (64, 256))
     c_ragged = autotune.kernel_candidates(kb, kb.HEAT2D, (64, 250))
-    assert any(v >= 8 for v, _ in c_aligned)
-    assert not any(v >= 8 for v, _ in c_ragged)
+    assert any(8 <= v <= 14 for v, _ in c_aligned)          # float4 rows need nx % 4 == 0
+    assert not any(8 <= v <= 14 for v, _ in c_ragged)
+    assert any(v == 15 for v, _ in c_ragged)                 # register strips do not
     assert autotune.kernel_candidates(kb, kb.HEAT3D, (8, 64, 66)) == [(1, 1)] + [(5, t) for t in autotune.HEAT3D_DEPTHS]
     assert autotune.kernel_candidates(kb, kb.HEAT3D, (9, 64, 66)) == [(1, 1)]
 
