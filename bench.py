@@ -69,7 +69,7 @@ def parse():
 
 
 KERNEL_RUNS = {
-    # name: (problem, shape, coeffs-attr, variant, steps per launch loop)
+    # name: (problem, shape, coeffs-attr, variant, steps per launch loop[, temporal depth])
     "skeleton_2p16": ("SKELETON", (N_ELEM,), None, 1, 100),
     "heat2d_16384": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 13, 5),
     "heat3d_8x4096": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 6, 5),
@@ -79,6 +79,7 @@ KERNEL_RUNS = {
     # 64 square grids of side round(64 * 16^u) (shape filled in from the seed)
     "multigrid_64": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 2, 10),
     "multigrid_64_cell": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 1, 10),
+    "multigrid_64_tb": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 3, 50, 5),    # 10 launches of 5 steps
 }
 
 
@@ -87,7 +88,8 @@ def kernel_only(name):
     (for hardware-counter runs, which serialise every dispatch)."""
     import torch
     import paper_2501_09398_amd as kb
-    prob, shape, co, var, steps = KERNEL_RUNS[name]
+    prob, shape, co, var, steps = KERNEL_RUNS[name][:5]
+    depth = KERNEL_RUNS[name][5] if len(KERNEL_RUNS[name]) > 5 else 1
     coeffs = (K,) if co is None else getattr(kb, co)
     if prob == "HEAT2D_MULTI":
         import synth
@@ -99,6 +101,7 @@ def kernel_only(name):
         coeffs = tuple(coeffs) + (0.8, 1e30, 16)          # check never falls back
     with kb.Problem(getattr(kb, prob), shape, coeffs, SEED, device=0) as p:
         p.set_option(kb.OPT_TILE, var)
+        p.set_option(kb.OPT_TDEPTH, depth)
         if prob == "HEAT2D_SURROGATE":                    # a network with every layer active
             w = synth.surrogate_init(SEED)
             w[19104:19393] = synth.uniform_f32(SEED, 9, 289, -0.06, 0.06)
@@ -278,10 +281,21 @@ def workloads(kb, pm, autotune, np):
     cells = sum(s * s for s in sides)
     d = {"steps": n, "grids": 64, "cells": cells}
     with kb.Problem(kb.HEAT2D_MULTI, shape, kb.HEAT_COEFFS, SEED) as p:
-        for v, name in ((2, "strip"), (1, "cell")):
+        for v, name in ((2, "strip"), (1, "cell"), (3, "tb_t1")):
             p.set_option(kb.OPT_TILE, v)
             d[f"{name}_per_launch_us_step"] = arm(p, n, 0, 2) / n * 1e6
             d[f"{name}_graph_b100_us_step"] = arm(p, n, 100, 2) / n * 1e6
+    # temporal blocking: variant, depth and b from the autotuner
+    tr = autotune.tune(kb, kb.HEAT2D_MULTI, shape, kb.HEAT_COEFFS, n, seed=SEED, reps=2)
+    d["autotuned"] = {"variant": tr.variant, "depth": tr.depth, "b": tr.b,
+                      "us_step": tr.us_per_step_warm, "cold_us_step": tr.us_per_step_cold,
+                      "t_create_ms": tr.t_create_s * 1e3, "b_measured_best": tr.b_measured,
+                      "kernel_table": [(v, t, round(us, 3)) for v, t, us in tr.kernel_table]}
+    with kb.Problem(kb.HEAT2D_MULTI, shape, kb.HEAT_COEFFS, SEED) as p:
+        p.set_option(kb.OPT_TILE, tr.variant)
+        p.set_option(kb.OPT_TDEPTH, tr.depth)
+        d["autotuned_per_launch_us_step"] = arm(p, n, 0, 2) / n * 1e6
+        d["autotuned_graph_us_step"] = arm(p, n, tr.b, 2) / n * 1e6
     # the alternative the grouped kernel replaces: 64 separate problems, each
     # advanced on its own (one launch per grid per step, or one graph each)
     probs = [kb.Problem(kb.HEAT2D, (sd, sd), kb.HEAT_COEFFS, SEED + g) for g, sd in enumerate(sides)]
@@ -297,9 +311,12 @@ def workloads(kb, pm, autotune, np):
         d[name] = (time.perf_counter() - t0) / ns * 1e6
     for q in probs:
         q.destroy()
-    best = min(d["strip_graph_b100_us_step"], d["cell_graph_b100_us_step"])
+    one_step = min(d["strip_graph_b100_us_step"], d["cell_graph_b100_us_step"], d["tb_t1_graph_b100_us_step"])
+    best = min(one_step, d["autotuned_graph_us_step"])
     d["gcell_upd_s"] = cells / best / 1e3
-    d["hbm_frac"] = 12.0 * cells / (best * 1e-6) / (HBM_PEAK_GBS * 1e9)
+    # one step per launch: 12 B per cell-step must cross HBM
+    d["hbm_frac_one_step_per_launch"] = 12.0 * cells / (one_step * 1e-6) / (HBM_PEAK_GBS * 1e9)
+    d["speedup_best_vs_separate_per_launch"] = d["separate_per_launch_us_step"] / best
     out["multigrid_64_2000"] = d
 
     # FDTD cavities

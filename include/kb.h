@@ -180,14 +180,22 @@ extern "C" {
  *   KB_HEAT2D_MULTI: 1 = one thread per cell (64x4 tiles, grid found by
  *              binary search); 2 = each wave walks 8 rows of 64 columns
  *              with the neighbour rows in registers (64x32 tiles, grid from
- *              a block table; default).
+ *              a block table); 3 (default), 4 = temporal blocking
+ *              (KB_OPT_TDEPTH steps per launch, 1..8) over regions of 64
+ *              columns x 64 (3) or 128 (4) rows around output tiles of
+ *              (64-2t) x (64-2t or 128-2t) cells, each region column's
+ *              rows in registers.
  *   KB_HEAT2D_SURROGATE: 1 = fused network, all activations in LDS, 3
  *              kernels per block (default); 2 = one kernel per layer with
  *              activations in HBM, 8 kernels per block.  The two agree to
  *              float32 rounding of the last layer's sum, not bit for bit. */
 #define KB_OPT_TILE      2
-/* KB_OPT_TDEPTH: temporal-blocking depth t >= 1 for KB_HEAT2D: one launch
- *   of the LDS tile kernel advances t steps (1 <= t <= 16).                */
+/* KB_OPT_TDEPTH: temporal-blocking depth t >= 1: one launch of a
+ *   temporal-blocking variant advances t steps (KB_HEAT2D LDS tile 1..16,
+ *   register strips 1..8; KB_HEAT3D variant 5 1..6; KB_HEAT2D_MULTI
+ *   variants 3, 4 1..8).  Other variants ignore it.  kb_run advances
+ *   floor(n_steps / t) iterations of t steps, then n_steps mod t single
+ *   steps per launch.                                                      */
 #define KB_OPT_TDEPTH    3
 /* KB_OPT_GRAPH_CACHE: 1 = keep instantiated batch graphs between kb_run
  *   calls (default), 0 = rebuild every call (each call then pays T_C).    */

@@ -5,9 +5,9 @@ iteration batch size as the missing piece of the method.  Here it is done
 per problem and shape, in two stages, through the C ABI only:
 
 1. kernel stage -- for every kernel variant (and, for the temporal-blocking
-   variants of the 2D and 3D stencils, every temporal depth t) time the warm execution of a
-   fixed number of steps with a moderate batch (graph already built), and
-   keep the fastest (warm microseconds per step; all variants give the same
+   variants of the 2D, 3D and many-grid stencils, every temporal depth t)
+   time the warm execution of a fixed number of steps with a moderate batch
+   (graph already built), and keep the fastest (warm microseconds per step; all variants give the same
    bits, so only time decides);
 2. batch stage -- for the chosen kernel, sweep b over the admissible batch
    sizes (divisors of the iteration count, Eq. 4), measure T_C and T_E with
@@ -32,6 +32,7 @@ HEAT2D_TILE = [2, 3, 4, 5, 6, 7]
 HEAT2D_VEC = [8, 9, 10, 11, 13, 14]
 HEAT2D_DEPTHS = [1, 2, 4, 8, 16]
 HEAT3D_DEPTHS = [1, 2, 3, 4, 6]          # variant 5 (layer stacks of <= 8)
+MULTI_DEPTHS = [1, 2, 3, 4, 5, 6, 7, 8]  # many-grid variants 3 and 4
 
 
 def kernel_candidates(kb, problem, shape):
@@ -52,6 +53,8 @@ def kernel_candidates(kb, problem, shape):
         return [(1, 1), (2, 1), (3, 1)]
     if problem == kb.FDTD3D:
         return [(1, 1), (2, 1), (3, 1), (4, 1)]
+    if problem == kb.HEAT2D_MULTI:
+        return [(1, 1), (2, 1)] + [(v, t) for v in (3, 4) for t in MULTI_DEPTHS]
     return [(0, 1)]
 
 
@@ -98,8 +101,7 @@ def tune(kb, problem, shape, coeffs, n_steps, seed=0, probe_steps=None, b_probe=
         K = p.kernels_per_iter()
         for v, t in cands:
             p.set_option(kb.OPT_TILE, v)
-            if problem == kb.HEAT2D:
-                p.set_option(kb.OPT_TDEPTH, t)
+            p.set_option(kb.OPT_TDEPTH, t)          # depth 1 is accepted by every problem
             iters = probe_steps // t
             bp = b_probe or max(1, min(iters, 400 // (K * 1)))
             sec = _warm_time(p, iters * t, bp, reps)
@@ -112,8 +114,7 @@ def tune(kb, problem, shape, coeffs, n_steps, seed=0, probe_steps=None, b_probe=
     sweep = []
     with kb.Problem(problem, shape, coeffs, seed) as p:
         p.set_option(kb.OPT_TILE, best_v)
-        if problem == kb.HEAT2D:
-            p.set_option(kb.OPT_TDEPTH, best_t)
+        p.set_option(kb.OPT_TDEPTH, best_t)
         p.set_option(kb.OPT_GRAPH_CACHE, 0)
         for b in b_candidates:
             tc, te = [], []

@@ -141,6 +141,16 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
         nb2 += ((shape[2 + 2 * g] + 63) / 64) * ((shape[1 + 2 * g] + kStripTileY - 1) / kStripTileY);
       if (nb2 > ((int64_t)1 << 30)) return false;
       off[18] = L.add(G * sizeof(GridDesc)); off[19] = L.add(nb2 * sizeof(int));
+      // temporal-blocking tilings, one per (region shape, depth)
+      int64_t nbt = 0;
+      for (int sh = 0; sh < kMtShapes; ++sh)
+        for (int t = 1; t <= kMtMaxDepth; ++t) {
+          const int64_t tx = multi_tb_tile_x(t), ty = multi_tb_tile_y(sh, t);
+          for (int64_t g = 0; g < G; ++g)
+            nbt += ((shape[2 + 2 * g] + tx - 1) / tx) * ((shape[1 + 2 * g] + ty - 1) / ty);
+        }
+      if (nbt > ((int64_t)1 << 30)) return false;
+      off[20] = L.add(kMtTilings * G * sizeof(GridDesc)); off[21] = L.add(nbt * sizeof(int));
       common();
       return true;
     }
@@ -176,10 +186,14 @@ int heat3d_variant(const kb_problem *h) {
 }
 bool heat2d_is_tile(int v) { return (v >= 2 && v <= 7) || v == 15; }   // temporal blocking
 
+// Many-grid variants 3 and 4 (and the default, 3) block in time.
+bool multi_is_tb(const kb_problem *h) { return h->tile == 0 || h->tile == 3 || h->tile == 4; }
+
 // Temporal depth of one iteration.
 int iter_depth(const kb_problem *h) {
   if (h->kind == KB_HEAT2D_SURROGATE) return sg_iter_depth(h);
   if (h->kind == KB_HEAT3D && heat3d_variant(h) == 5) return h->tdepth;
+  if (h->kind == KB_HEAT2D_MULTI && multi_is_tb(h)) return h->tdepth;
   return (h->kind == KB_HEAT2D && heat2d_is_tile(heat2d_variant(h))) ? h->tdepth : 1;
 }
 
@@ -249,6 +263,12 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
       if (h->tile == 1) {
         MultiArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids_d, h->block_start_d, h->G, h->hk};
         make_multi(L[0], a, h->total_blocks);
+      } else if (multi_is_tb(h)) {
+        if (depth < 1 || depth > kMtMaxDepth) return -1;
+        const int sh = h->tile == 4 ? 1 : 0, q = multi_tb_index(sh, depth);
+        MultiTbArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids_tb_d + (size_t)q * h->G,
+                      h->block_grid_tb_d + h->tb_start[q], h->tb_start[q + 1] - h->tb_start[q], depth, h->hk};
+        make_multi_tb(L[0], a, sh);
       } else {
         MultiStripArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids2_d, h->block_grid_d, h->total_blocks2, h->hk};
         make_multi_strip(L[0], a);
@@ -480,7 +500,7 @@ const char *kb_last_error(void) { return g_err.c_str(); }
 
 size_t kb_workspace_bytes(int problem, const int64_t *shape, int ndim) {
   Layout L;
-  size_t off[20] = {0};
+  size_t off[22] = {0};
   if (!layout(problem, shape, ndim, L, off)) return 0;
   return L.total;
 }
@@ -494,7 +514,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
   *out = nullptr;
   if (ncoeffs < 0 || (ncoeffs > 0 && !coeffs)) return fail(KB_EINVAL, "bad coefficient array");
   Layout Lay;
-  size_t off[20] = {0};
+  size_t off[22] = {0};
   if (!layout(problem, shape, ndim, Lay, off)) return fail(KB_EINVAL, "invalid problem %d or shape", problem);
   if (!workspace || ws_bytes < Lay.total)
     return fail(KB_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, Lay.total);
@@ -586,10 +606,29 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
         bg.insert(bg.end(), (size_t)tx * ty, g);
       }
       h->total_blocks2 = (int)bg.size();
+      // temporal-blocking tilings: (64 - 2t) x (64 or 128 - 2t) output
+      // tiles, t = 1..8; block0 counts from the start of each tiling's table
+      h->grids_tb_d = reinterpret_cast<GridDesc *>(h->ws + off[20]);
+      h->block_grid_tb_d = reinterpret_cast<int *>(h->ws + off[21]);
+      std::vector<GridDesc> gdt((size_t)kMtTilings * h->G);
+      std::vector<int> bgt;
+      for (int sh = 0; sh < kMtShapes; ++sh)
+        for (int t = 1; t <= kMtMaxDepth; ++t) {
+          const int q = multi_tb_index(sh, t), tile_x = multi_tb_tile_x(t), tile_y = multi_tb_tile_y(sh, t);
+          h->tb_start[q] = (int)bgt.size();
+          for (int g = 0; g < h->G; ++g) {
+            const int tx = (gd[g].nx + tile_x - 1) / tile_x, ty = (gd[g].ny + tile_y - 1) / tile_y;
+            gdt[(size_t)q * h->G + g] = GridDesc{gd[g].off, gd[g].ny, gd[g].nx, tx, (int)bgt.size() - h->tb_start[q]};
+            bgt.insert(bgt.end(), (size_t)tx * ty, g);
+          }
+        }
+      h->tb_start[kMtTilings] = (int)bgt.size();
       if (hipMemcpy(h->grids_d, gd.data(), gd.size() * sizeof(GridDesc), hipMemcpyHostToDevice) != hipSuccess ||
           hipMemcpy(h->block_start_d, bs.data(), bs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
           hipMemcpy(h->grids2_d, gd2.data(), gd2.size() * sizeof(GridDesc), hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(h->block_grid_d, bg.data(), bg.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+          hipMemcpy(h->block_grid_d, bg.data(), bg.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(h->grids_tb_d, gdt.data(), gdt.size() * sizeof(GridDesc), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(h->block_grid_tb_d, bgt.data(), bgt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(KB_EHIP, "grid table upload failed"));
       if ((rc = enqueue_init(h, h->Tbuf[0], offc, seed, kTagT0, 0, 323.0, 343.0)) ||
           (rc = enqueue_init(h, h->P, offc, seed, kTagP, 0, 0.0, 1.0)))
@@ -691,7 +730,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
       else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 4;
       else if (h->kind == KB_HEAT2D_SURROGATE) ok = value >= 0 && value <= 2;
-      else if (h->kind == KB_HEAT2D_MULTI) ok = value >= 0 && value <= 2;
+      else if (h->kind == KB_HEAT2D_MULTI) ok = value >= 0 && value <= 4;
       else ok = value == 0;
       if (!ok) return fail(KB_EINVAL, "kernel variant %lld not available for this problem", (long long)value);
       if (h->tile != value) clear_cache(h);
@@ -700,9 +739,10 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       break;
     }
     case KB_OPT_TDEPTH: {
-      if (h->kind != KB_HEAT2D && h->kind != KB_HEAT3D && value != 1)
-        return fail(KB_EINVAL, "temporal depth > 1 only for KB_HEAT2D and KB_HEAT3D");
-      const int maxd = h->kind == KB_HEAT3D ? heat3d_tb_max_depth() : heat2d_tile_max_depth();
+      if (h->kind != KB_HEAT2D && h->kind != KB_HEAT3D && h->kind != KB_HEAT2D_MULTI && value != 1)
+        return fail(KB_EINVAL, "temporal depth > 1 only for KB_HEAT2D, KB_HEAT3D and KB_HEAT2D_MULTI");
+      const int maxd = h->kind == KB_HEAT3D ? heat3d_tb_max_depth()
+                     : h->kind == KB_HEAT2D_MULTI ? kMtMaxDepth : heat2d_tile_max_depth();
       if (value < 1 || value > maxd) return fail(KB_EINVAL, "temporal depth must be 1..%d", maxd);
       if (h->tdepth != value) clear_cache(h);
       h->tdepth = (int)value;

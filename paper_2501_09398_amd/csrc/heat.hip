@@ -715,6 +715,119 @@ __global__ __launch_bounds__(256) void heat2d_multi_strip_kernel(const MultiStri
   }
 }
 
+// Value of the neighbouring lane of a full wave, by a DPP wave shift; the
+// lane at the end of the wave reads 0 (callers clamp where that matters).
+__device__ __forceinline__ float lane_west_open(float v) {   // lane - 1 (wave_shr:1)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_east_open(float v) {   // lane + 1 (wave_shl:1)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+
+// Many-grid temporal blocking (variants 3 and 4): t steps per launch.  Each
+// grid is cut into output tiles of (64 - 2t) x (16*NW - 2t) cells; a block
+// of NW waves loads its tile grown by t cells on each side (at most 64 x
+// 16*NW, clamped to its grid) and advances that region t steps with the
+// rows in registers: wave w holds region rows 16w .. 16w+15 of column
+// `lane`, east / west neighbours come from the adjacent lanes, north /
+// south from the wave's own registers except at its strip ends, which are
+// exchanged through LDS (double buffered: one barrier per step).  Cells
+// next to a cut halo see a wrong neighbour; that error moves inward one
+// cell per step and never reaches the tile, so the result equals t single
+// steps bit for bit.  Only a region side that lies on its grid's edge needs
+// the clamped neighbour, so the step loop is specialised on which of the
+// west, east and south sides do (the north one never needs a select: the
+// top row's "row above" starts as the row itself); most regions of a large
+// grid take the loop with no clamp at all.
+constexpr int kMtRows = 16;                  // region rows per wave
+
+template <int NW, bool CW, bool CE, bool CS>
+__device__ __forceinline__ void multi_tb_advance(float (&v)[kMtRows], const float (&pw)[kMtRows],
+                                                 float (*ends)[2][NW][kMtRegionX], int t, int W, int H,
+                                                 int cx, int w, const HeatCoef &k) {
+  const int last = H - 1 - kMtRows * w;       // this wave's index of the grid's bottom row (CS)
+  int b = 0;
+  for (int s = 0; s < t; ++s) {
+    float prev = w > 0 ? ends[b][1][w - 1][cx] : v[0];          // old row above
+    const float bot = w < NW - 1 ? ends[b][0][w + 1][cx] : v[kMtRows - 1];
+#pragma unroll
+    for (int i = 0; i < kMtRows; ++i) {
+      const float c = v[i];
+      float so = i == kMtRows - 1 ? bot : v[i + 1];
+      if (CS && i == last) so = c;
+      float ev = lane_east_open(c), wv = lane_west_open(c);
+      if (CE && cx >= W - 1) ev = c;
+      if (CW && cx == 0) wv = c;
+      const float n = prev;
+      prev = c;
+      v[i] = heat_update(c, n, so, wv, ev, pw[i], k);
+    }
+    b ^= 1;
+    ends[b][0][w][cx] = v[0];
+    ends[b][1][w][cx] = v[kMtRows - 1];
+    __syncthreads();
+  }
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void heat2d_multi_tb_kernel(const MultiTbArgs a) {
+  __shared__ float ends[2][2][NW][kMtRegionX];  // [buffer][top, bottom][wave][column]
+  const int lb = xcd_logical_block(a.nb);
+  if (lb >= a.nb) return;
+  const GridDesc gd = a.grids[a.block_grid[lb]];
+  const int t = a.tdepth, tile_x = kMtRegionX - 2 * t, tile_y = kMtRows * NW - 2 * t;
+  const int local = lb - gd.block0;
+  const int x0 = (local % gd.tiles_x) * tile_x, y0 = (local / gd.tiles_x) * tile_y;
+  const int rx_lo = max(x0 - t, 0), rx_hi = min(x0 + tile_x + t, gd.nx);
+  const int ry_lo = max(y0 - t, 0), ry_hi = min(y0 + tile_y + t, gd.ny);
+  const int W = rx_hi - rx_lo, H = ry_hi - ry_lo;
+  const int cx = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int r0 = kMtRows * w;
+  const int col = cx < W ? cx : W - 1;
+  const unsigned nx = (unsigned)gd.nx;
+  const size_t base = (size_t)gd.off + (size_t)ry_lo * nx + rx_lo;
+  const float *T = a.T + base;
+  const float *P = a.P + base;
+  float v[kMtRows], pw[kMtRows];
+#pragma unroll
+  for (int i = 0; i < kMtRows; ++i) {
+    const unsigned r = r0 + i < H ? r0 + i : H - 1;
+    const unsigned o = r * nx + col;           // < 2^31: a region spans at most 128 rows of a grid
+    v[i] = T[o];
+    pw[i] = P[o];
+  }
+  ends[0][0][w][cx] = v[0];
+  ends[0][1][w][cx] = v[kMtRows - 1];
+  __syncthreads();
+  switch ((rx_lo == 0) | (rx_hi == gd.nx) << 1 | (ry_hi == gd.ny) << 2) {
+    case 0: multi_tb_advance<NW, false, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 1: multi_tb_advance<NW, true, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 2: multi_tb_advance<NW, false, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 3: multi_tb_advance<NW, true, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 4: multi_tb_advance<NW, false, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 5: multi_tb_advance<NW, true, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 6: multi_tb_advance<NW, false, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    default: multi_tb_advance<NW, true, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+  }
+  const int gx = rx_lo + cx;
+  if (cx < W && gx >= x0 && gx < x0 + tile_x) {
+    float *O = a.out + base;
+#pragma unroll
+    for (int i = 0; i < kMtRows; ++i) {
+      const int gy = ry_lo + r0 + i;
+      if (r0 + i < H && gy >= y0 && gy < y0 + tile_y) O[(unsigned)(r0 + i) * nx + cx] = v[i];
+    }
+  }
+}
+
+void make_multi_tb(Launch &L, const MultiTbArgs &a, int shape) {
+  if (shape == 0)
+    L.set((const void *)heat2d_multi_tb_kernel<4>, dim3(xcd_padded_grid(a.nb)), dim3(256), 0, a);
+  else
+    L.set((const void *)heat2d_multi_tb_kernel<8>, dim3(xcd_padded_grid(a.nb)), dim3(512), 0, a);
+}
+
 void make_multi_strip(Launch &L, const MultiStripArgs &a) {
   L.set((const void *)heat2d_multi_strip_kernel, dim3(xcd_padded_grid(a.nb)), dim3(256), 0, a);
 }

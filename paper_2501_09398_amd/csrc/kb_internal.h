@@ -127,6 +127,25 @@ struct MultiStripArgs {
   HeatCoef k;
 };
 
+// Many-grid temporal blocking: t <= kMtMaxDepth steps per launch over a
+// region of at most 64 columns x multi_tb_region_y(s) rows around an output
+// tile of (64 - 2t) x (region rows - 2t) cells; region shape s = 0 (64
+// rows, 4 waves) or 1 (128 rows, 8 waves); one block table per (s, t).
+constexpr int kMtRegionX = 64, kMtMaxDepth = 8, kMtShapes = 2;
+constexpr int kMtTilings = kMtShapes * kMtMaxDepth;
+__host__ __device__ inline int multi_tb_region_y(int s) { return s ? 128 : 64; }
+__host__ __device__ inline int multi_tb_tile_x(int t) { return kMtRegionX - 2 * t; }
+__host__ __device__ inline int multi_tb_tile_y(int s, int t) { return multi_tb_region_y(s) - 2 * t; }
+inline int multi_tb_index(int s, int t) { return s * kMtMaxDepth + t - 1; }
+struct MultiTbArgs {
+  const float *T; float *out; const float *P;
+  const GridDesc *grids;        // tiles_x / block0 of the tiling at this depth
+  const int *block_grid;        // grid of every block
+  int nb, tdepth;
+  HeatCoef k;
+};
+void make_multi_tb(Launch &L, const MultiTbArgs &a, int shape);
+
 struct SkelArgs {
   float *x; long long n; float a, b;
 };
@@ -254,6 +273,9 @@ struct kb_problem {
   kb::GridDesc *grids2_d = nullptr;   // 64 x 32 strip tiling
   int *block_grid_d = nullptr;
   int total_blocks2 = 0;
+  kb::GridDesc *grids_tb_d = nullptr;  // temporal-blocking tilings, per (region shape, depth)
+  int *block_grid_tb_d = nullptr;
+  int tb_start[kb::kMtTilings + 1] = {0};    // first entry of each tiling's block table
   int64_t total_cells = 0;
   std::vector<int64_t> grid_shape;
   // skeleton

@@ -9,8 +9,11 @@ from paper_2501_09398_amd import autotune, perfmodel as pm
 
 
 class FakeKB:
-    """Stands in for the binding: timings follow Eqs. 2 and 3 exactly."""
+    """Stands in for the binding: timings follow Eqs. 2 and 3 exactly.
+    Temporal depth counts only for the temporal-blocking variants of the
+    problem the fake was created for."""
     HEAT2D, HEAT3D, SKELETON, FDTD3D, HEAT2D_MULTI = 1, 2, 3, 4, 5
+    TB = {1: {2, 3, 4, 5, 6, 7, 15}, 2: {5}, 5: {3, 4}}
     OPT_BUILDER, OPT_TILE, OPT_TDEPTH, OPT_GRAPH_CACHE, OPT_MAX_NODES = 1, 2, 3, 4, 5
     # per-launch kernel time (s) per variant; variant 6 with depth 8 is best
     T_K = {1: 3e-6, 2: 4e-6, 3: 3.5e-6, 4: 3.6e-6, 5: 3.4e-6, 6: 3.2e-6, 7: 3.9e-6,
@@ -20,7 +23,7 @@ class FakeKB:
 
     class Problem:
         def __init__(self, kbm, problem, shape, coeffs, seed):
-            self.kbm, self.v, self.t, self.last = kbm, 1, 1, None
+            self.kbm, self.problem, self.v, self.t, self.last = kbm, problem, 1, 1, None
 
         def __enter__(self):
             return self
@@ -38,7 +41,7 @@ class FakeKB:
                 self.t = val
 
         def run(self, n, b):
-            t = self.t if 2 <= self.v <= 7 or self.v == 15 else 1
+            t = self.t if self.v in FakeKB.TB.get(self.problem, ()) else 1
             iters = n // t
             tk = FakeKB.T_K[self.v] * (1 + 0.1 * t) / t * t    # deeper steps cost a little more each
             nb = iters // b
@@ -73,6 +76,19 @@ def test_tuner_picks_fastest_kernel_and_model_batch():
     cands = [d for d in pm.divisors(n_iter) if d <= 4096]
     expect = min(cands, key=lambda b: FakeKB.K_C * b + a / b)
     assert res.b == expect
+
+
+@pytest.mark.parametrize("problem,shape", [(3, (8, 64, 64)), (5, (3, 100, 100, 70, 70, 64, 64))])
+def test_tuner_applies_depth_for_3d_and_many_grids(problem, shape):
+    """The winning depth of a temporal-blocking variant is the one timed:
+    the tuner sets the depth option for every problem, not only the 2D one."""
+    kb = fake_kb()
+    prob = {3: kb.HEAT3D, 5: kb.HEAT2D_MULTI}[problem]
+    res = autotune.tune(kb, prob, shape, (), 1200, reps=1)
+    assert res.variant in FakeKB.TB[prob] and res.depth > 1
+    per_step = {(v, t): (FakeKB.T_K[v] * (1 + 0.1 * t) + FakeKB.T_I) / (t if v in FakeKB.TB[prob] else 1)
+                for v, t in autotune.kernel_candidates(kb, prob, shape)}
+    assert (res.variant, res.depth) == min(per_step, key=per_step.get)
 
 
 def test_kernel_candidates_respect_alignment():

@@ -309,15 +309,18 @@ def test_heat3d_full_size_sampled(kb):
 
 # ---- many grids ------------------------------------------------------------
 
-@pytest.mark.parametrize("variant", [1, 2])
-def test_multigrid_matches_single_grids(kb, variant):
-    """variant 1: one cell per thread; 2: 64 x 8 strips per wave.  Grids
-    narrower and wider than a wave, single rows and a single cell."""
-    announce(f"multigrid 8 grids variant {variant}")
-    sides = [(17, 70), (64, 64), (5, 130), (100, 33), (1, 1), (40, 250), (33, 1), (9, 65)]
+@pytest.mark.parametrize("variant,depth", [(1, 1), (2, 1), (3, 1), (3, 3), (3, 8), (4, 2), (4, 8)])
+def test_multigrid_matches_single_grids(kb, variant, depth):
+    """variant 1: one cell per thread; 2: 64 x 8 strips per wave; 3:
+    temporal blocking over (64 - 2t)-square tiles (30 steps = whole
+    iterations of t steps plus single steps).  Grids narrower and wider than
+    a wave and than a tile, single rows and a single cell."""
+    announce(f"multigrid 8 grids variant {variant} depth {depth}")
+    sides = [(17, 70), (64, 64), (5, 130), (100, 33), (1, 1), (40, 250), (33, 1), (9, 65), (130, 127), (300, 290)]
     shape = [len(sides)] + [v for s in sides for v in s]
     with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 14) as p:
         p.set_option(kb.OPT_TILE, variant)
+        p.set_option(kb.OPT_TDEPTH, depth)
         p.run(30, 7)
         allT = p.read(kb.F_T)
     T0 = synth.uniform_f32(14, synth.TAG_T0, allT.size, *synth.T0_RANGE)
@@ -341,41 +344,54 @@ def test_multigrid_graph_bitwise(kb):
     sides = synth.multigrid_sides(3, 8, 16, 200)
     shape = [len(sides)] + [v for s in sides for v in (s, s)]
     outs = []
-    for v, b in ((2, 0), (2, 1), (2, 5), (1, 0), (1, 5)):
+    for v, t, b in ((2, 1, 0), (2, 1, 1), (2, 1, 5), (1, 1, 0), (1, 1, 5), (3, 4, 0), (3, 4, 2), (3, 5, 3),
+                    (4, 3, 2)):
         with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 15) as p:
             p.set_option(kb.OPT_TILE, v)
+            p.set_option(kb.OPT_TDEPTH, t)
             p.run(23, b)
+            outs.append(p.read(kb.F_T))
+            if v >= 3:
+                with pytest.raises(kb.KBError):
+                    p.set_option(kb.OPT_TDEPTH, 9)
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+def test_multigrid_full_size_workload_all_variants(kb):
+    """64 grids of side round(64 * 16^u) (about 12.9 M cells): every
+    variant (temporal blocking at depths 4 and 8 included) gives the same
+    bits after 24 steps."""
+    announce("multigrid 64 grids full size")
+    sides = synth.multigrid_sides(20250116, 64)
+    shape = [64] + [v for s in sides for v in (s, s)]
+    outs = []
+    for v, t in ((1, 1), (2, 1), (3, 4), (3, 8), (4, 6)):
+        with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 20250116) as p:
+            p.set_option(kb.OPT_TILE, v)
+            p.set_option(kb.OPT_TDEPTH, t)
+            p.run(24, 3 if t == 1 else 1)
             outs.append(p.read(kb.F_T))
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
 
 
-def test_multigrid_full_size_workload_strip_vs_cell(kb):
-    """64 grids of side round(64 * 16^u) (about 12.9 M cells): the two
-    variants give the same bits after 20 steps."""
-    announce("multigrid 64 grids full size")
-    sides = synth.multigrid_sides(20250116, 64)
-    shape = [64] + [v for s in sides for v in (s, s)]
-    outs = []
-    for v in (1, 2):
-        with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 20250116) as p:
-            p.set_option(kb.OPT_TILE, v)
-            p.run(20, 10)
-            outs.append(p.read(kb.F_T))
-    assert np.array_equal(outs[0], outs[1])
-
-
-def test_multigrid_full_size_2000_steps_vs_oracle(kb):
-    """The 64-grid workload for 2000 steps in graph batches of 100 (the
-    benchmark's launch configuration, strip kernel): the three smallest grids
-    against the float32 oracle, and every grid's mean against its closed
-    form (the clamped Laplacian sums to zero on each grid)."""
-    announce("multigrid 64 grids 2000 steps b=100")
+@pytest.mark.parametrize("variant,depth,b", [(2, 1, 100), (3, 6, 37)])
+def test_multigrid_full_size_2000_steps_vs_oracle(kb, variant, depth, b):
+    """The 64-grid workload for 2000 steps as the benchmark runs it: the
+    strip kernel in graph batches of 100, and temporal blocking at the depth
+    and batch the autotuner picks on MI355X (333 launches of 6 steps in 9
+    graphs of 37, then 2 single steps).  The three smallest grids against
+    the float32 oracle, and every grid's mean against its closed form (the
+    clamped Laplacian sums to zero on each grid)."""
+    announce(f"multigrid 64 grids 2000 steps variant {variant} depth {depth} b={b}")
     seed = 20250116
     sides = synth.multigrid_sides(seed, 64)
     shape = [64] + [v for s in sides for v in (s, s)]
     with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), seed) as p:
-        p.run(2000, 100)
+        p.set_option(kb.OPT_TILE, variant)
+        p.set_option(kb.OPT_TDEPTH, depth)
+        p.run(2000, b)
         allT = p.read(kb.F_T)
     T0s, Ps = synth.multigrid_init(seed, sides)
     off = 0
