@@ -79,7 +79,7 @@ KERNEL_RUNS = {
     # 64 square grids of side round(64 * 16^u) (shape filled in from the seed)
     "multigrid_64": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 2, 10),
     "multigrid_64_cell": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 1, 10),
-    "multigrid_64_tb": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 3, 50, 5),    # 10 launches of 5 steps
+    "multigrid_64_tb": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 3, 60, 6),    # 10 launches of 6 steps
 }
 
 
@@ -296,6 +296,12 @@ def workloads(kb, pm, autotune, np):
         p.set_option(kb.OPT_TDEPTH, tr.depth)
         d["autotuned_per_launch_us_step"] = arm(p, n, 0, 2) / n * 1e6
         d["autotuned_graph_us_step"] = arm(p, n, tr.b, 2) / n * 1e6
+        # the persistent arm: one cooperative launch for all 2000 steps,
+        # super-steps of t steps separated by grid-wide barriers
+        p.set_option(kb.OPT_PERSISTENT, 1)
+        for t in (1, tr.depth, 8):
+            p.set_option(kb.OPT_TDEPTH, t)
+            d[f"persistent_t{t}_us_step"] = arm(p, n, 0, 2) / n * 1e6
     # the alternative the grouped kernel replaces: 64 separate problems, each
     # advanced on its own (one launch per grid per step, or one graph each)
     probs = [kb.Problem(kb.HEAT2D, (sd, sd), kb.HEAT_COEFFS, SEED + g) for g, sd in enumerate(sides)]

@@ -225,6 +225,18 @@ extern "C" {
  *   same bits.  The paper notes that graphs are hard to change once built
  *   (Sec. II); this measures what an in-place update costs on MI355X.     */
 #define KB_OPT_GRAPH_UPDATE 7
+/* KB_OPT_PERSISTENT (KB_HEAT2D_MULTI only): 1 = kb_run advances all grids
+ *   in ONE cooperative launch of a persistent kernel (every block resident)
+ *   instead of per-launch iterations or graph batches: super-steps of
+ *   KB_OPT_TDEPTH steps over the 64 x 64-region temporal-blocking tiles
+ *   (variant 3's), each ended by a grid-wide barrier, and one super-step
+ *   of n_steps mod t steps at the end.  batch_b is ignored; the kernel
+ *   variant option is not consulted.  The run is synchronous (kb_run waits
+ *   for the launch and checks the barrier's error flag: KB_EHIP if a
+ *   barrier wait timed out).  Not with KB_OPT_REDUCE_EVERY.  Same bits as
+ *   every other variant.  0 = off (default).  The alternative to graphs
+ *   that the paper sets against them (Sec. V): no launch per step at all. */
+#define KB_OPT_PERSISTENT 8
 
 typedef struct kb_problem kb_problem;
 

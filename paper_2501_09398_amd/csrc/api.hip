@@ -151,6 +151,7 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
         }
       if (nbt > ((int64_t)1 << 30)) return false;
       off[20] = L.add(kMtTilings * G * sizeof(GridDesc)); off[21] = L.add(nbt * sizeof(int));
+      off[22] = L.add(64);                  // persistent kernel's barrier
       common();
       return true;
     }
@@ -500,7 +501,7 @@ const char *kb_last_error(void) { return g_err.c_str(); }
 
 size_t kb_workspace_bytes(int problem, const int64_t *shape, int ndim) {
   Layout L;
-  size_t off[22] = {0};
+  size_t off[23] = {0};
   if (!layout(problem, shape, ndim, L, off)) return 0;
   return L.total;
 }
@@ -514,7 +515,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
   *out = nullptr;
   if (ncoeffs < 0 || (ncoeffs > 0 && !coeffs)) return fail(KB_EINVAL, "bad coefficient array");
   Layout Lay;
-  size_t off[22] = {0};
+  size_t off[23] = {0};
   if (!layout(problem, shape, ndim, Lay, off)) return fail(KB_EINVAL, "invalid problem %d or shape", problem);
   if (!workspace || ws_bytes < Lay.total)
     return fail(KB_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, Lay.total);
@@ -608,6 +609,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       h->total_blocks2 = (int)bg.size();
       // temporal-blocking tilings: (64 - 2t) x (64 or 128 - 2t) output
       // tiles, t = 1..8; block0 counts from the start of each tiling's table
+      h->grid_bar_d = reinterpret_cast<unsigned *>(h->ws + off[22]);
       h->grids_tb_d = reinterpret_cast<GridDesc *>(h->ws + off[20]);
       h->block_grid_tb_d = reinterpret_cast<int *>(h->ws + off[21]);
       std::vector<GridDesc> gdt((size_t)kMtTilings * h->G);
@@ -761,6 +763,17 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       if (value != 0 && value != 1) return fail(KB_EINVAL, "graph update must be 0 or 1");
       h->graph_update = (int)value;
       break;
+    case KB_OPT_PERSISTENT: {
+      if (value != 0 && value != 1) return fail(KB_EINVAL, "persistent must be 0 or 1");
+      if (value && h->kind != KB_HEAT2D_MULTI) return fail(KB_EINVAL, "persistent runs only for KB_HEAT2D_MULTI");
+      if (value) {
+        int coop = 0;
+        HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, h->device));
+        if (!coop) return fail(KB_EHIP, "device has no cooperative launch");
+      }
+      h->persistent = (int)value;
+      break;
+    }
     case KB_OPT_REDUCE_EVERY:
       if (h->kind == KB_HEAT2D_SURROGATE) return fail(KB_EINVAL, "the surrogate has its own residual check");
       if (value < 0) return fail(KB_EINVAL, "reduction interval must be >= 0");
@@ -775,9 +788,71 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
   return KB_OK;
 }
 
+// One cooperative launch of the persistent many-grid kernel for n steps.
+int run_persistent(kb_problem *h, int64_t n_steps) {
+  if (h->red_every > 0) return fail(KB_EINVAL, "in-chain reductions are not available in a persistent run");
+  const int t = h->tdepth;
+  const int64_t nfull = n_steps / t;
+  const int rem = (int)(n_steps % t);
+  if (nfull > (int64_t)1 << 30) return fail(KB_EINVAL, "too many steps for one persistent launch");
+  const void *f = multi_persistent_fn();
+  if (h->persist_blocks == 0) {
+    int per_cu = 0, cus = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    // Resident blocks, a multiple of the XCD count (the kernel splits the
+    // tile list into one part per XCD).  Half of what the occupancy query
+    // reports: the query counts registers and LDS but not the scalar
+    // register file, which limits this kernel (about 106 SGPRs) to 7 waves
+    // per SIMD, not the 8 the query assumes; a grid that is not entirely
+    // resident would never pass its first barrier.
+    h->persist_blocks = std::max(1, per_cu / 2) * cus / kXcds * kXcds;
+    if (h->persist_blocks < kXcds) return fail(KB_EHIP, "persistent kernel does not fit the device");
+  }
+  int most = 0;                                 // tiles of the busiest super-step
+  for (int d : {t, rem})
+    if (d > 0) most = std::max(most, h->tb_start[d] - h->tb_start[d - 1]);
+  const int blocks = std::max(kXcds, std::min(h->persist_blocks, (most + kXcds - 1) / kXcds * kXcds));
+  MultiPersistArgs a{};
+  a.T0 = h->Tbuf[h->cur];
+  a.T1 = h->Tbuf[1 - h->cur];
+  a.P = h->P;
+  a.grids = h->grids_tb_d;                      // region shape 0 (64 x 64): tilings 0 .. kMtMaxDepth-1
+  a.block_grid = h->block_grid_tb_d;
+  for (int d = 0; d <= kMtMaxDepth; ++d) a.tb_start[d] = h->tb_start[d];
+  a.G = h->G;
+  a.tdepth = t;
+  a.nfull = (int)nfull;
+  a.rem = rem;
+  a.bar = h->grid_bar_d;
+  // polls of a barrier wait before it gives up: about a second (one poll is
+  // an uncached load and a short sleep), more for huge super-steps
+  a.spin_limit = (unsigned)std::min<int64_t>(INT32_MAX, std::max<int64_t>(1 << 20, h->total_cells * t >> 14));
+  a.k = h->hk;
+  void *args[] = {&a};
+  kb_timing tm{};
+  HIPCHK(hipMemsetAsync(h->grid_bar_d, 0, 3 * sizeof(unsigned), h->stream));
+  HIPCHK(hipEventRecord(h->ev0, h->stream));
+  if (n_steps > 0) HIPCHK(hipLaunchCooperativeKernel(f, dim3(blocks), dim3(256), args, 0, h->stream));
+  HIPCHK(hipEventRecord(h->ev1, h->stream));
+  unsigned err = 0;
+  HIPCHK(hipMemcpyAsync(&err, h->grid_bar_d + 2, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int64_t nsuper = nfull + (rem > 0 ? 1 : 0);
+  if (nsuper & 1) h->cur ^= 1;
+  h->step_count += n_steps;
+  h->host_steps += n_steps;
+  tm.n_kernel_launches = n_steps > 0 ? 1 : 0;
+  h->last = tm;
+  h->timed = true;
+  if (err) return fail(KB_EHIP, "persistent kernel: a grid barrier wait timed out; the state is invalid");
+  return KB_OK;
+}
+
 int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b) {
   if (!h) return fail(KB_EINVAL, "null handle");
   if (n_steps < 0 || batch_b < 0) return fail(KB_EINVAL, "n_steps and batch_b must be >= 0");
+  if (h->persistent) return run_persistent(h, n_steps);
   const int depth = iter_depth(h);
   const int64_t n_iter = n_steps / depth;
   const int64_t rem_steps = n_steps % depth;

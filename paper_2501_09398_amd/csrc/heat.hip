@@ -769,11 +769,10 @@ __device__ __forceinline__ void multi_tb_advance(float (&v)[kMtRows], const floa
   }
 }
 
+// One tile of the many-grid temporal blocking: load, t steps, store.  ends:
+// the block's LDS strip-end buffers [buffer][top, bottom][wave][column].
 template <int NW>
-__global__ __launch_bounds__(64 * NW) void heat2d_multi_tb_kernel(const MultiTbArgs a) {
-  __shared__ float ends[2][2][NW][kMtRegionX];  // [buffer][top, bottom][wave][column]
-  const int lb = xcd_logical_block(a.nb);
-  if (lb >= a.nb) return;
+__device__ __forceinline__ void multi_tb_tile(const MultiTbArgs &a, int lb, float (*ends)[2][NW][kMtRegionX]) {
   const GridDesc gd = a.grids[a.block_grid[lb]];
   const int t = a.tdepth, tile_x = kMtRegionX - 2 * t, tile_y = kMtRows * NW - 2 * t;
   const int local = lb - gd.block0;
@@ -820,6 +819,80 @@ __global__ __launch_bounds__(64 * NW) void heat2d_multi_tb_kernel(const MultiTbA
     }
   }
 }
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void heat2d_multi_tb_kernel(const MultiTbArgs a) {
+  __shared__ float ends[2][2][NW][kMtRegionX];
+  const int lb = xcd_logical_block(a.nb);
+  if (lb >= a.nb) return;
+  multi_tb_tile<NW>(a, lb, ends);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent many-grid kernel: one cooperative launch advances every grid by
+// n steps, as nfull super-steps of t steps and one of rem steps, each a pass
+// of the temporal-blocking tiles over the whole set of grids followed by a
+// grid-wide barrier (the buffers then swap).  The blocks of XCD x take the
+// x-th eighth of the tile list, so neighbouring tiles share an L2.
+// ---------------------------------------------------------------------------
+
+// Grid-wide barrier of a cooperative launch (every block resident).  Each
+// wave first waits until its own stores have reached the L2 (vmcnt 0; on
+// gfx9 this counter covers stores), so after the block barrier one device-
+// scope release by thread 0 writes the whole block's results back from the
+// XCD's L2.  Thread 0 then counts in and waits for the generation to move
+// on, and its device-scope acquire invalidates the CU's L1 and the XCD's
+// L2 for every wave of the block.  A wait longer than spin_limit polls
+// raises the error flag, after which no block waits any more, so the grid
+// always drains (the host then reports the run as failed).
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, unsigned spin_limit) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nblocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      // relaxed polls: an acquiring load would invalidate the XCD's L2 on
+      // every poll, under the blocks that are still working
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen &&
+             __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+        if (++spins > spin_limit) {
+          __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  ++gen;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void heat2d_multi_persistent_kernel(const MultiPersistArgs a) {
+  __shared__ float ends[2][2][4][kMtRegionX];
+  float *src = a.T0, *dst = a.T1;
+  unsigned gen = 0;
+  const int nsuper = a.nfull + (a.rem > 0 ? 1 : 0);
+  const int per_xcd = gridDim.x / kXcds, x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+  for (int s = 0; s < nsuper; ++s) {
+    const int d = s < a.nfull ? a.tdepth : a.rem;
+    const MultiTbArgs ta{src, dst, a.P, a.grids + (size_t)(d - 1) * a.G, a.block_grid + a.tb_start[d - 1],
+                         a.tb_start[d] - a.tb_start[d - 1], d, a.k};
+    const int per = (ta.nb + kXcds - 1) / kXcds;
+    const int hi = min((x + 1) * per, ta.nb);
+    for (int lb = x * per + i; lb < hi; lb += per_xcd) multi_tb_tile<4>(ta, lb, ends);
+    grid_barrier(a.bar, gridDim.x, gen, a.spin_limit);
+    float *tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+}
+
+const void *multi_persistent_fn() { return (const void *)heat2d_multi_persistent_kernel; }
 
 void make_multi_tb(Launch &L, const MultiTbArgs &a, int shape) {
   if (shape == 0)

@@ -146,6 +146,22 @@ struct MultiTbArgs {
 };
 void make_multi_tb(Launch &L, const MultiTbArgs &a, int shape);
 
+// Persistent many-grid run (one cooperative launch of 256-thread blocks):
+// nfull super-steps of tdepth steps, then one of rem steps (if rem > 0),
+// over the 64 x 64-region tilings.
+struct MultiPersistArgs {
+  float *T0, *T1;                  // T0 holds the state at entry
+  const float *P;
+  const GridDesc *grids;           // the G descriptors of each depth's tiling, depth 1 first
+  const int *block_grid;           // block tables of those tilings, concatenated
+  int tb_start[kMtMaxDepth + 1];   // entries of depth d: tb_start[d-1] .. tb_start[d]
+  int G, tdepth, nfull, rem;
+  unsigned *bar;                   // arrivals, generation, error flag: zero at launch
+  unsigned spin_limit;             // polls before a barrier wait gives up
+  HeatCoef k;
+};
+const void *multi_persistent_fn();
+
 struct SkelArgs {
   float *x; long long n; float a, b;
 };
@@ -256,6 +272,7 @@ struct kb_problem {
   int cache = 1;
   int64_t max_nodes = 65536;
   int graph_update = 0;         // 1: refit cached graphs when node arguments change
+  int persistent = 0;           // 1: one cooperative launch per kb_run (many grids)
   double t_update_s = 0;        // host time of the last refit / invalidation
   int64_t n_updated = 0;        // graphs refitted by it
 
@@ -276,6 +293,8 @@ struct kb_problem {
   kb::GridDesc *grids_tb_d = nullptr;  // temporal-blocking tilings, per (region shape, depth)
   int *block_grid_tb_d = nullptr;
   int tb_start[kb::kMtTilings + 1] = {0};    // first entry of each tiling's block table
+  unsigned *grid_bar_d = nullptr;             // persistent kernel's barrier words
+  int persist_blocks = 0;                     // resident 256-thread blocks (0: not queried yet)
   int64_t total_cells = 0;
   std::vector<int64_t> grid_shape;
   // skeleton

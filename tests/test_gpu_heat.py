@@ -407,3 +407,62 @@ def test_multigrid_full_size_2000_steps_vs_oracle(kb, variant, depth, b):
         pbar = np.mean(P.astype(np.float64))
         ref = 300 + pbar * 10 + (m0 - 300 - pbar * 10) * (1 - 1e-4) ** 2000
         assert abs(np.mean(got.astype(np.float64)) - ref) / ref < 1e-5, s
+
+
+@pytest.mark.parametrize("depth", [1, 4, 6])
+def test_multigrid_persistent_matches_per_launch(kb, depth):
+    """One cooperative launch for all steps (super-steps of t steps with a
+    grid barrier between them, then n mod t steps) gives the bits of the
+    per-launch strip kernel, over two consecutive runs (the buffer parity
+    carries over) and a run of zero steps."""
+    announce(f"multigrid persistent depth {depth}")
+    sides = [(17, 70), (64, 64), (5, 130), (100, 33), (1, 1), (40, 250), (33, 1), (9, 65), (130, 127), (300, 290)]
+    shape = [len(sides)] + [v for s in sides for v in s]
+    with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 21) as p:
+        p.set_option(kb.OPT_TILE, 2)
+        p.run(23, 0)
+        ref1 = p.read(kb.F_T)
+        p.run(14, 0)
+        ref2 = p.read(kb.F_T)
+    with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 21) as p:
+        p.set_option(kb.OPT_PERSISTENT, 1)
+        p.set_option(kb.OPT_TDEPTH, depth)
+        p.run(23, 5)                              # batch_b is ignored
+        assert p.last_timing()["n_kernel_launches"] == 1
+        assert np.array_equal(p.read(kb.F_T), ref1)
+        p.run(0, 0)
+        p.run(14, 0)
+        assert np.array_equal(p.read(kb.F_T), ref2)
+
+
+def test_multigrid_persistent_full_size(kb):
+    """The 64-grid workload: 100 steps in one persistent launch at depth 6
+    equal 100 steps of the strip kernel in graph batches."""
+    announce("multigrid persistent full size")
+    seed = 20250116
+    sides = synth.multigrid_sides(seed, 64)
+    shape = [64] + [v for s in sides for v in (s, s)]
+    outs = []
+    for persistent in (0, 1):
+        with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), seed) as p:
+            if persistent:
+                p.set_option(kb.OPT_PERSISTENT, 1)
+                p.set_option(kb.OPT_TDEPTH, 6)
+            else:
+                p.set_option(kb.OPT_TILE, 2)
+            p.run(100, 10)
+            outs.append(p.read(kb.F_T))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_persistent_option_rejections(kb):
+    with kb.Problem(kb.HEAT2D, (64, 64), coeffs(HEAT), 1) as p:
+        with pytest.raises(kb.KBError):
+            p.set_option(kb.OPT_PERSISTENT, 1)
+    with kb.Problem(kb.HEAT2D_MULTI, [2, 64, 64, 70, 70], coeffs(HEAT), 1) as p:
+        with pytest.raises(kb.KBError):
+            p.set_option(kb.OPT_PERSISTENT, 2)
+        p.set_option(kb.OPT_PERSISTENT, 1)
+        p.set_option(kb.OPT_REDUCE_EVERY, 10)
+        with pytest.raises(kb.KBError):
+            p.run(20, 0)
