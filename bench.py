@@ -74,6 +74,7 @@ KERNEL_RUNS = {
     "heat2d_16384": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 13, 5),
     "heat3d_8x4096": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 6, 5),
     "fdtd_256": ("FDTD3D", (256, 64), "FDTD_COEFFS", 2, 5),
+    "fdtd_256_fused": ("FDTD3D", (256, 64), "FDTD_COEFFS", 7, 10),
     "surrogate_512": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 1, 160),
     "surrogate_512_layered": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 2, 160),
     # 64 square grids of side round(64 * 16^u) (shape filled in from the seed)
@@ -326,13 +327,19 @@ def workloads(kb, pm, autotune, np):
     out["multigrid_64_2000"] = d
 
     # FDTD cavities
+    # (separate H and E kernels: 72 B per node-step; the fused step: 48 B)
     for N, n in ((128, 10000), (256, 2000)):
         d = {"steps": n, "cells": N ** 3}
         with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, SEED) as p:
-            d["per_launch_us_step"] = arm(p, n, 0, 1) / n * 1e6
-            d["graph_b100_us_step"] = arm(p, n, 100, 1) / n * 1e6
+            for v, name in ((2, "separate"), (0, "fused")):     # 0: the default fused variant for N
+                p.set_option(kb.OPT_TILE, v)
+                d[f"{name}_per_launch_us_step"] = arm(p, n, 0, 1) / n * 1e6
+                d[f"{name}_graph_b100_us_step"] = arm(p, n, 100, 1) / n * 1e6
+        d["graph_b100_us_step"] = min(d["separate_graph_b100_us_step"], d["fused_graph_b100_us_step"])
         d["gcell_upd_s"] = N ** 3 / d["graph_b100_us_step"] / 1e3
-        d["hbm_frac"] = 72.0 * (N + 1) ** 3 / (d["graph_b100_us_step"] * 1e-6) / (HBM_PEAK_GBS * 1e9)
+        for name, B in (("separate", 72.0), ("fused", 48.0)):
+            d[f"{name}_hbm_frac"] = B * (N + 1) ** 3 / (d[f"{name}_graph_b100_us_step"] * 1e-6) / (HBM_PEAK_GBS * 1e9)
+        d["speedup_fused_vs_separate"] = d["separate_graph_b100_us_step"] / d["fused_graph_b100_us_step"]
         out[f"fdtd_{N}^3_{n}"] = d
 
     # learned 16-step surrogate at 512^2 (network, residual check and the
@@ -383,8 +390,10 @@ def workloads(kb, pm, autotune, np):
         gbs = bytes_per_cell * cells / t / 1e9
         big[name] = {"us_step": t * 1e6, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS, "gcell_upd_s": cells / t / 1e9}
     d = out["fdtd_256^3_2000"]
-    big["fdtd_256^3"] = {"us_step": d["graph_b100_us_step"], "frac": d["hbm_frac"],
-                         "GB_s": d["hbm_frac"] * HBM_PEAK_GBS, "gcell_upd_s": d["gcell_upd_s"]}
+    for name in ("separate", "fused"):
+        big[f"fdtd_256^3_{name}"] = {"us_step": d[f"{name}_graph_b100_us_step"], "frac": d[f"{name}_hbm_frac"],
+                                     "GB_s": d[f"{name}_hbm_frac"] * HBM_PEAK_GBS,
+                                     "gcell_upd_s": 256 ** 3 / d[f"{name}_graph_b100_us_step"] / 1e3}
     out["large_grids_hbm"] = big
     return out
 

@@ -70,8 +70,9 @@ extern "C" {
  *   fields : KB_F_X (n float), KB_F_A (K float), KB_F_B (K float)
  *   initial: x ~ U[-1,1).
  *
- * KB_FDTD3D  (FDTD Maxwell solver of a PEC cavity, three kernels per step:
- *   H update, E update, soft source)
+ * KB_FDTD3D  (FDTD Maxwell solver of a PEC cavity: per step an H update, an
+ *   E update and the soft source -- two kernels with the fused H + E step
+ *   (default), three with the separate ones)
  *   shape  = {N} or {N, probe_capacity}: cells per edge (4 <= N <= 1024)
  *            and the number of steps of Ez(src) recorded (default 16384).
  *   coeffs = {courant, width, delay} or {courant, width, delay, i, j, k}
@@ -175,8 +176,17 @@ extern "C" {
  *              layer after next loaded one layer ahead.  Default: 6 if nx % 4 == 0
  *              and ny*nx >= 2^20, else 1.
  *   KB_SKELETON: 1 = 4 elements per thread (default), 2 = 1, 3 = 8.
- *   KB_FDTD3D: 1 = one thread per cell, 2 = float4 rows (default),
- *              3 / 4 = float4 rows, each thread walking 8 / 16 planes in k.
+ *   KB_FDTD3D: separate H and E kernels (3 kernels per iteration with the
+ *              source): 1 = one thread per cell, 2 = float4 rows, 3 / 4 =
+ *              float4 rows, each thread walking 8 / 16 planes in k;
+ *              fused H + E step (2 kernels per iteration): 5 = float4 rows,
+ *              one plane per thread, 6 = walking 8 planes, 7 = as 5 with
+ *              streaming (non-temporal) stores.  Default: 7 when the two
+ *              field sets exceed 256 MiB (N >= 176), else 5.  The
+ *              fused step reads one set of six fields and writes the other
+ *              (48 instead of 72 bytes per node-step), so the state
+ *              alternates between two sets like the stencils' ping-pong
+ *              buffers; every variant continues from the current set.
  *   KB_HEAT2D_MULTI: 1 = one thread per cell (64x4 tiles, grid found by
  *              binary search); 2 = each wave walks 8 rows of 64 columns
  *              with the neighbour rows in registers (64x32 tiles, grid from

@@ -52,7 +52,7 @@ def kernel_candidates(kb, problem, shape):
     if problem == kb.SKELETON:
         return [(1, 1), (2, 1), (3, 1)]
     if problem == kb.FDTD3D:
-        return [(1, 1), (2, 1), (3, 1), (4, 1)]
+        return [(1, 1), (2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1)]
     if problem == kb.HEAT2D_MULTI:
         return [(1, 1), (2, 1)] + [(v, t) for v in (3, 4) for t in MULTI_DEPTHS]
     return [(0, 1)]

@@ -117,7 +117,9 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
       const int64_t pcap = ndim == 2 ? shape[1] : kDefaultProbe;
       if (pcap < 0 || pcap > ((int64_t)1 << 28)) return false;
       const int64_t M = shape[0] + 1;
+      // two sets of the six fields
       for (int f = 0; f < 6; ++f) off[5 + f] = L.add(M * M * fdtd_pitch(shape[0]) * 4);
+      for (int f = 0; f < 6; ++f) off[23 + f] = L.add(M * M * fdtd_pitch(shape[0]) * 4);
       off[11] = L.add(kGCap * 4);
       off[12] = L.add((pcap > 0 ? pcap : 1) * 4);
       off[13] = L.add(8);
@@ -172,6 +174,23 @@ bool pingpong(const kb_problem *h) {
          h->kind == KB_HEAT2D_SURROGATE;
 }
 
+// FDTD kernel variant: the fused H + E step unless another is chosen, with
+// streaming stores once the two field sets outgrow the 256 MB last-level
+// cache (they then go to HBM anyway; keeping them out of L2 leaves it to the
+// neighbouring rows and planes being read), plain stores below that (where
+// the next step reads them back from that cache).
+int fdtd_variant(const kb_problem *h) {
+  if (h->tile != 0) return h->tile;
+  const double sets = 12.0 * (h->N + 1) * (h->N + 1) * h->pitch * 4;
+  return sets > 256.0 * (1 << 20) ? 7 : 5;
+}
+
+// Does an iteration move the state to the other buffer set?  The stencils'
+// ping-pong buffers, and the FDTD fields under the fused step.
+bool alternates(const kb_problem *h) {
+  return pingpong(h) || (h->kind == KB_FDTD3D && fdtd_variant(h) >= 5);
+}
+
 // Kernel variant in use: the option, or the default for the shape (vector
 // rows when every row is 16-byte aligned, else one thread per cell).
 // Measured on MI355X: the vector kernels win once a plane has about a
@@ -211,9 +230,12 @@ int fill_reduce(const kb_problem *h, int cur, Launch *L) {
     const float *f[1] = {h->x};
     a = reduce_log_args(f, 1, 1, 0, h->n, h->partials, h->redlog, h->redcount, h->red_every);
   } else {
-    // padded FDTD arrays: the padding columns hold zeros and add nothing
+    // padded FDTD arrays: the padding columns hold zeros and add nothing;
+    // the set the iteration wrote: the other one after a fused step
     const long long n = (long long)(h->N + 1) * (h->N + 1) * h->pitch;
-    a = reduce_log_args(h->F, 6, 2, 1, n, h->partials, h->redlog, h->redcount, h->red_every);
+    const float *F[6];
+    for (int f = 0; f < 6; ++f) F[f] = h->F[alternates(h) ? 1 - cur : cur][f];
+    a = reduce_log_args(F, 6, 2, 1, n, h->partials, h->redlog, h->redcount, h->red_every);
   }
   make_reduce_log(L[0], L[1], a);
   return 2;
@@ -284,10 +306,21 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
       return h->K;
     }
     case KB_FDTD3D: {
-      FdtdArgs f{h->F[0], h->F[1], h->F[2], h->F[3], h->F[4], h->F[5], h->N, h->pitch, h->dt};
-      const int v = h->tile == 0 ? 2 : h->tile;
+      float *const *A = h->F[cur];
+      const int v = fdtd_variant(h);
+      if (v >= 5) {
+        float *const *B = h->F[1 - cur];
+        FdtdFusedArgs f{A[0], A[1], A[2], A[3], A[4], A[5], B[0], B[1], B[2], B[3], B[4], B[5],
+                        h->N, h->pitch, h->dt};
+        // variant 5: one plane per thread; 6: 8 planes; 7: one plane, streaming stores
+        if (!make_fdtd_fused(L[0], f, v == 6 ? 8 : 1, v == 7)) return -1;
+        SrcArgs s{B[2], h->src, h->g, h->glen, h->probe, h->pcap, h->step};
+        make_fdtd_src(L[1], s);
+        return 2;
+      }
+      FdtdArgs f{A[0], A[1], A[2], A[3], A[4], A[5], h->N, h->pitch, h->dt};
       if (!make_fdtd_h(L[0], f, v) || !make_fdtd_e(L[1], f, v)) return -1;
-      SrcArgs s{h->F[2], h->src, h->g, h->glen, h->probe, h->pcap, h->step};
+      SrcArgs s{A[2], h->src, h->g, h->glen, h->probe, h->pcap, h->step};
       make_fdtd_src(L[2], s);
       return 3;
     }
@@ -306,7 +339,7 @@ int launch_iter(kb_problem *h, int depth, hipStream_t s) {
   for (int q = 0; q < k; ++q) {
     HIPCHK(hipLaunchKernel(L[q].func, L[q].grid, L[q].block, L[q].params(), L[q].lds, s));
   }
-  if (pingpong(h)) h->cur ^= 1;
+  if (alternates(h)) h->cur ^= 1;
   return KB_OK;
 }
 
@@ -346,7 +379,7 @@ int make_graph(kb_problem *h, int64_t b, int depth, int parity, int64_t phase, h
         }
         prev = node;
       }
-      if (pingpong(h)) c ^= 1;
+      if (alternates(h)) c ^= 1;
     }
   } else {
     HIPCHK(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
@@ -424,8 +457,8 @@ int enqueue_init(kb_problem *h, float *dst, long long n, uint64_t seed, uint64_t
 
 // Device location and user-visible size of a field.  *host_vec: the field
 // lives in host memory of the handle.  *rows/*pitch: > 0 for the FDTD fields,
-// whose rows of N+1 floats are stored with a pitch of h->P floats on the
-// device (the caller sees them dense).
+// whose rows of N+1 floats are stored with a pitch of h->pitch floats on
+// the device (the caller sees them dense).
 bool field_info(const kb_problem *h, int field, float **dev, size_t *bytes, bool *host_vec, size_t *rows,
                 size_t *pitch) {
   *host_vec = false;
@@ -451,7 +484,7 @@ bool field_info(const kb_problem *h, int field, float **dev, size_t *bytes, bool
     case KB_F_EX: case KB_F_EY: case KB_F_EZ: case KB_F_HX: case KB_F_HY: case KB_F_HZ: {
       if (h->kind != KB_FDTD3D) return false;
       const int64_t M = h->N + 1;
-      *dev = h->F[field - KB_F_EX]; *bytes = M * M * M * 4;
+      *dev = h->F[h->cur][field - KB_F_EX]; *bytes = M * M * M * 4;
       *rows = M * M;
       *pitch = h->pitch;
       return true;
@@ -501,7 +534,7 @@ const char *kb_last_error(void) { return g_err.c_str(); }
 
 size_t kb_workspace_bytes(int problem, const int64_t *shape, int ndim) {
   Layout L;
-  size_t off[23] = {0};
+  size_t off[29] = {0};
   if (!layout(problem, shape, ndim, L, off)) return 0;
   return L.total;
 }
@@ -515,7 +548,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
   *out = nullptr;
   if (ncoeffs < 0 || (ncoeffs > 0 && !coeffs)) return fail(KB_EINVAL, "bad coefficient array");
   Layout Lay;
-  size_t off[23] = {0};
+  size_t off[29] = {0};
   if (!layout(problem, shape, ndim, Lay, off)) return fail(KB_EINVAL, "invalid problem %d or shape", problem);
   if (!workspace || ws_bytes < Lay.total)
     return fail(KB_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, Lay.total);
@@ -664,8 +697,11 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       h->N = N;
       h->pitch = (int)fdtd_pitch(N);
       h->dt = (float)courant;
-      h->K = 3;
-      for (int f = 0; f < 6; ++f) h->F[f] = P(off[5 + f]);
+      h->K = 2;                                 // the fused step and the source
+      for (int f = 0; f < 6; ++f) {
+        h->F[0][f] = P(off[5 + f]);
+        h->F[1][f] = P(off[23 + f]);
+      }
       h->g = P(off[11]);
       h->probe = P(off[12]);
       h->pcap = (int)(ndim == 2 ? shape[1] : kDefaultProbe);
@@ -697,9 +733,10 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
         }
       }
       h->glen = (int)gt.size();
-      for (int f = 0; f < 6; ++f)
-        if (hipMemsetAsync(h->F[f], 0, M * M * h->pitch * 4, h->stream) != hipSuccess)
-          return bail(fail(KB_EHIP, "hipMemsetAsync failed"));
+      for (int q = 0; q < 2; ++q)
+        for (int f = 0; f < 6; ++f)
+          if (hipMemsetAsync(h->F[q][f], 0, M * M * h->pitch * 4, h->stream) != hipSuccess)
+            return bail(fail(KB_EHIP, "hipMemsetAsync failed"));
       if (hipMemsetAsync(h->probe, 0, (size_t)(h->pcap > 0 ? h->pcap : 1) * 4, h->stream) != hipSuccess ||
           hipMemsetAsync(h->step, 0, 8, h->stream) != hipSuccess)
         return bail(fail(KB_EHIP, "hipMemsetAsync failed"));
@@ -730,7 +767,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
         ok = value == 0 || value == 1 || (((value >= 2 && value <= 4) || (value >= 6 && value <= 10)) && h->nx % 4 == 0) ||
              (value == 5 && h->nz <= 8);
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
-      else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 4;
+      else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 7;
       else if (h->kind == KB_HEAT2D_SURROGATE) ok = value >= 0 && value <= 2;
       else if (h->kind == KB_HEAT2D_MULTI) ok = value >= 0 && value <= 4;
       else ok = value == 0;
@@ -738,6 +775,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       if (h->tile != value) clear_cache(h);
       h->tile = (int)value;
       if (h->kind == KB_HEAT2D_SURROGATE) h->K = sg_kernels_per_block(h);
+      if (h->kind == KB_FDTD3D) h->K = fdtd_variant(h) >= 5 ? 2 : 3;
       break;
     }
     case KB_OPT_TDEPTH: {
@@ -858,7 +896,7 @@ int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b) {
   const int64_t rem_steps = n_steps % depth;
   kb_timing t{};
   int status = KB_OK;
-  const bool pp = pingpong(h);
+  const bool pp = alternates(h);
 
   if (batch_b > 0 && (batch_b > h->max_nodes / h->K))
     return fail(KB_EINVAL, "batch of %lld iterations x %d kernels exceeds %lld graph nodes", (long long)batch_b, h->K,
@@ -883,7 +921,10 @@ int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b) {
     int64_t ph = m > 0 ? h->step_count % m : 0;
     const int64_t period = 2 * (m > 0 ? m : 1);
     for (int64_t j = 0; j < std::min(nb, period); ++j) {
-      std::pair<int, int64_t> q{pp ? c : 0, ph};
+      // the buffer set a replay starts from: it alternates between replays
+      // only if the state moves every iteration and b is odd (FDTD's
+      // in-place kernels run on whichever set is current)
+      std::pair<int, int64_t> q{c, ph};
       if (std::find(need.begin(), need.end(), q) == need.end()) need.push_back(q);
       if (flip) c ^= 1;
       if (m > 0) ph = (ph + batch_b * depth) % m;
@@ -918,7 +959,7 @@ int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b) {
   HIPCHK(hipEventRecord(h->ev0, h->stream));
   for (int64_t j = 0; j < nb; ++j) {
     const int64_t ph = h->red_every > 0 ? h->step_count % h->red_every : 0;
-    hipGraphExec_t ex = execs[std::make_pair(pp ? h->cur : 0, ph)];
+    hipGraphExec_t ex = execs[std::make_pair(h->cur, ph)];
     HIPCHK(hipGraphLaunch(ex, h->stream));
     if (pp && (batch_b & 1)) h->cur ^= 1;
     h->step_count += batch_b * depth;
@@ -1031,8 +1072,9 @@ int kb_reduce(kb_problem *h, double *out, int nout) {
   } else {
     // padded arrays: the padding columns hold zeros and add nothing
     const long long n = (long long)(h->N + 1) * (h->N + 1) * h->pitch;
-    const float *E[3] = {h->F[0], h->F[1], h->F[2]};
-    const float *H[3] = {h->F[3], h->F[4], h->F[5]};
+    float *const *F = h->F[h->cur];
+    const float *E[3] = {F[0], F[1], F[2]};
+    const float *H[3] = {F[3], F[4], F[5]};
     e = reduce_sumsq(E, 3, n, h->partials, h->red, h->stream);
     if (e == hipSuccess) e = reduce_sumsq(H, 3, n, h->partials, h->red + 1, h->stream);
     nres = 2;

@@ -228,8 +228,8 @@ struct MarchPos {
 };
 
 template <int KC>
-__device__ __forceinline__ bool march_pos(const FdtdArgs &f, MarchPos &p) {
-  const int M = f.N + 1, P4 = f.P / 4;
+__device__ __forceinline__ bool march_pos(int N, int P, MarchPos &p) {
+  const int M = N + 1, P4 = P / 4;
   const int Q = M * P4;
   const int bpp = (Q + 255) / 256;
   const int nch = (M + KC - 1) / KC;
@@ -245,14 +245,14 @@ __device__ __forceinline__ bool march_pos(const FdtdArgs &f, MarchPos &p) {
   p.lane = threadIdx.x & 63;
   p.k0 = ch * KC;
   p.k1 = min(p.k0 + KC, M);
-  p.c = ((size_t)p.k0 * M + p.j) * f.P + p.i0;
+  p.c = ((size_t)p.k0 * M + p.j) * P + p.i0;
   return true;
 }
 
 template <int KC>
 __global__ __launch_bounds__(256) void fdtd_h_march_kernel(const FdtdArgs f) {
   MarchPos p;
-  if (!march_pos<KC>(f, p)) return;
+  if (!march_pos<KC>(f.N, f.P, p)) return;
   const int N = f.N;
   const size_t sj = f.P, sk = (size_t)(N + 1) * f.P;
   const float *__restrict__ Ex = f.Ex;
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void fdtd_h_march_kernel(const FdtdArgs f) {
 template <int KC>
 __global__ __launch_bounds__(256) void fdtd_e_march_kernel(const FdtdArgs f) {
   MarchPos p;
-  if (!march_pos<KC>(f, p)) return;
+  if (!march_pos<KC>(f.N, f.P, p)) return;
   const int N = f.N;
   const size_t sj = f.P, sk = (size_t)(N + 1) * f.P;
   float *__restrict__ Ex = f.Ex;
@@ -365,8 +365,8 @@ __global__ __launch_bounds__(256) void fdtd_e_march_kernel(const FdtdArgs f) {
 }
 
 template <int KC>
-static dim3 march_grid(const FdtdArgs &a) {
-  const int M = a.N + 1, P4 = a.P / 4;
+static dim3 march_grid(int N, int P) {
+  const int M = N + 1, P4 = P / 4;
   const int bpp = (M * P4 + 255) / 256;
   return dim3((unsigned)xcd_padded_grid(bpp * ((M + KC - 1) / KC)));
 }
@@ -382,8 +382,8 @@ static dim3 vec_grid(const FdtdArgs &a) {
 bool make_fdtd_h(Launch &L, const FdtdArgs &a, int variant) {
   if (variant == 1) L.set((const void *)fdtd_h_kernel, scalar_grid(a.N), dim3(64, 4), 0, a);
   else if (variant == 2) L.set((const void *)fdtd_h_vec_kernel, vec_grid(a), dim3(256), 0, a);
-  else if (variant == 3) L.set((const void *)fdtd_h_march_kernel<8>, march_grid<8>(a), dim3(256), 0, a);
-  else if (variant == 4) L.set((const void *)fdtd_h_march_kernel<16>, march_grid<16>(a), dim3(256), 0, a);
+  else if (variant == 3) L.set((const void *)fdtd_h_march_kernel<8>, march_grid<8>(a.N, a.P), dim3(256), 0, a);
+  else if (variant == 4) L.set((const void *)fdtd_h_march_kernel<16>, march_grid<16>(a.N, a.P), dim3(256), 0, a);
   else return false;
   return true;
 }
@@ -391,8 +391,185 @@ bool make_fdtd_h(Launch &L, const FdtdArgs &a, int variant) {
 bool make_fdtd_e(Launch &L, const FdtdArgs &a, int variant) {
   if (variant == 1) L.set((const void *)fdtd_e_kernel, scalar_grid(a.N), dim3(64, 4), 0, a);
   else if (variant == 2) L.set((const void *)fdtd_e_vec_kernel, vec_grid(a), dim3(256), 0, a);
-  else if (variant == 3) L.set((const void *)fdtd_e_march_kernel<8>, march_grid<8>(a), dim3(256), 0, a);
-  else if (variant == 4) L.set((const void *)fdtd_e_march_kernel<16>, march_grid<16>(a), dim3(256), 0, a);
+  else if (variant == 3) L.set((const void *)fdtd_e_march_kernel<8>, march_grid<8>(a.N, a.P), dim3(256), 0, a);
+  else if (variant == 4) L.set((const void *)fdtd_e_march_kernel<16>, march_grid<16>(a.N, a.P), dim3(256), 0, a);
+  else return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Fused H + E kernel (variant 5): one launch per step reads E^n and H^{n-1/2}
+// from one set of buffers and writes H^{n+1/2} and E^{n+1} to the other, so
+// a node-step moves 48 bytes (six fields read, six written) instead of 72.
+// A thread owns a float4 slot of a row and walks KC planes in increasing k
+// (KC = 1: one plane).  The E update needs H^{n+1/2} at its own node and at
+// i-1, j-1 and k-1: the own value is computed, the k-1 value is the
+// previous plane's (recomputed from the old fields for the first plane),
+// i-1 comes from the neighbouring lane (recomputed from memory by the first
+// lane of a wave), and the j-1 row is recomputed from the old fields.  The
+// extra loads hit L2 (the neighbouring rows and planes are other threads'
+// own data); HBM sees each field read once and written once.  Every
+// recomputed value uses the H kernel's formula and operand order, so it
+// equals the owner's bit for bit, and the whole step equals the H kernel
+// followed by the E kernel.
+// ---------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Float4 store; NT = non-temporal (streaming) store that does not keep the
+// line in cache, leaving L2 to the neighbouring rows and planes being read.
+template <bool NT>
+__device__ __forceinline__ void st4o(float *p, float a, float b, float c, float d) {
+  if constexpr (NT) {
+    f4v v = {a, b, c, d};
+    __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(p));
+  } else {
+    *reinterpret_cast<float4 *>(p) = make_float4(a, b, c, d);
+  }
+}
+
+template <int KC, bool NT>
+__global__ __launch_bounds__(256) void fdtd_fused_kernel(const FdtdFusedArgs f) {
+  MarchPos p;
+  if (!march_pos<KC>(f.N, f.P, p)) return;
+  const int N = f.N;
+  const size_t sj = f.P, sk = (size_t)(N + 1) * f.P;
+  const float *__restrict__ Ex = f.Ex;
+  const float *__restrict__ Ey = f.Ey;
+  const float *__restrict__ Ez = f.Ez;
+  const float *__restrict__ Hx = f.Hx;
+  const float *__restrict__ Hy = f.Hy;
+  const float *__restrict__ Hz = f.Hz;
+  float *__restrict__ oEx = f.oEx;
+  float *__restrict__ oEy = f.oEy;
+  float *__restrict__ oEz = f.oEz;
+  float *__restrict__ oHx = f.oHx;
+  float *__restrict__ oHy = f.oHy;
+  float *__restrict__ oHz = f.oHz;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const bool in = p.qin;
+  const int j = p.j;
+  const bool jup = in && j < N, jdn = in && j > 0;
+  const bool jj = j >= 1 && j <= N - 1;
+  const float dt = f.dt;
+  size_t c = p.c;
+  // E^n at (j, k0) and, for the j-1 row, Ey^n at (j-1, k0)
+  float4 ex = in ? ld4(Ex + c) : z4;
+  float4 ey = in ? ld4(Ey + c) : z4;
+  float4 ey_m = jdn ? ld4(Ey + c - sj) : z4;
+  // H^{n+1/2} at (j, k0-1): Hx and Hy, recomputed
+  float hxp[4] = {0.f, 0.f, 0.f, 0.f}, hyp[4] = {0.f, 0.f, 0.f, 0.f};
+  if (p.k0 > 0) {
+    const size_t cb = c - sk;
+    const float4 hx0 = in ? ld4(Hx + cb) : z4;
+    const float4 hy0 = in ? ld4(Hy + cb) : z4;
+    const float4 ez0 = in ? ld4(Ez + cb) : z4;
+    const float4 ex0 = in ? ld4(Ex + cb) : z4;
+    const float4 ey0 = in ? ld4(Ey + cb) : z4;
+    const float4 ez0_j = jup ? ld4(Ez + cb + sj) : z4;
+    float ez0_e = __shfl_down(ez0.x, 1, 64);
+    if (p.lane == 63 && in && p.i0 + 4 < f.P) ez0_e = Ez[cb + 4];
+    const int k = p.k0 - 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = p.i0 + e;
+      const float eze = e < 3 ? comp(ez0, e + 1) : ez0_e;
+      hxp[e] = (i <= N && j < N && k < N)
+                   ? comp(hx0, e) - dt * ((comp(ez0_j, e) - comp(ez0, e)) - (comp(ey, e) - comp(ey0, e))) : comp(hx0, e);
+      hyp[e] = (i < N && k < N) ? comp(hy0, e) - dt * ((comp(ex, e) - comp(ex0, e)) - (eze - comp(ez0, e))) : comp(hy0, e);
+    }
+  }
+  for (int k = p.k0; k < p.k1; ++k, c += sk) {
+    const bool kup = in && k < N;
+    const float4 ez = in ? ld4(Ez + c) : z4;
+    const float4 hx = in ? ld4(Hx + c) : z4;
+    const float4 hy = in ? ld4(Hy + c) : z4;
+    const float4 hz = in ? ld4(Hz + c) : z4;
+    const float4 ex_k = kup ? ld4(Ex + c + sk) : z4;    // k+1
+    const float4 ey_k = kup ? ld4(Ey + c + sk) : z4;
+    const float4 ez_j = jup ? ld4(Ez + c + sj) : z4;    // j+1
+    const float4 ex_j = jup ? ld4(Ex + c + sj) : z4;
+    // the j-1 row: E^n and H^{n-1/2}
+    const float4 ex_m = jdn ? ld4(Ex + c - sj) : z4;
+    const float4 ez_m = jdn ? ld4(Ez + c - sj) : z4;
+    const float4 hx_m = jdn ? ld4(Hx + c - sj) : z4;
+    const float4 hz_m = jdn ? ld4(Hz + c - sj) : z4;
+    const float4 ey_mk = jdn && k < N ? ld4(Ey + c - sj + sk) : z4;
+    // i+4 of Ey, Ez (row j) and Ey (row j-1): next lane, else memory
+    float ey_e = __shfl_down(ey.x, 1, 64);
+    float ez_e = __shfl_down(ez.x, 1, 64);
+    float eym_e = __shfl_down(ey_m.x, 1, 64);
+    if (p.lane == 63 && in && p.i0 + 4 < f.P) {
+      ey_e = Ey[c + 4];
+      ez_e = Ez[c + 4];
+      if (jdn) eym_e = Ey[c - sj + 4];
+    }
+    // H^{n+1/2} at (j, k) (stored) and at (j-1, k) (Hx, Hz, recomputed)
+    float hxn[4], hyn[4], hzn[4], hxm[4], hzm[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = p.i0 + e;
+      const float eyc = comp(ey, e), ezc = comp(ez, e), exc = comp(ex, e);
+      const float eye = e < 3 ? comp(ey, e + 1) : ey_e;
+      const float eze = e < 3 ? comp(ez, e + 1) : ez_e;
+      hxn[e] = (i <= N && j < N && k < N)
+                   ? comp(hx, e) - dt * ((comp(ez_j, e) - ezc) - (comp(ey_k, e) - eyc)) : comp(hx, e);
+      hyn[e] = (i < N && k < N) ? comp(hy, e) - dt * ((comp(ex_k, e) - exc) - (eze - ezc)) : comp(hy, e);
+      hzn[e] = (i < N && j < N) ? comp(hz, e) - dt * ((eye - eyc) - (comp(ex_j, e) - exc)) : comp(hz, e);
+      const float eymc = comp(ey_m, e);
+      const float eyme = e < 3 ? comp(ey_m, e + 1) : eym_e;
+      hxm[e] = (i <= N && k < N)
+                   ? comp(hx_m, e) - dt * ((ezc - comp(ez_m, e)) - (comp(ey_mk, e) - eymc)) : comp(hx_m, e);
+      hzm[e] = i < N ? comp(hz_m, e) - dt * ((eyme - eymc) - (exc - comp(ex_m, e))) : comp(hz_m, e);
+    }
+    if (!jdn) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) hxm[e] = hzm[e] = 0.f;
+    }
+    // H^{n+1/2} at i0-1 (Hz, Hy): previous lane, else recomputed
+    float hz_w = __shfl_up(hzn[3], 1, 64);
+    float hy_w = __shfl_up(hyn[3], 1, 64);
+    if (p.lane == 0 && in && p.i0 > 0) {
+      const int i = p.i0 - 1;
+      const size_t w = c - 1;
+      const float eyw = Ey[w], exw = Ex[w], ezw = Ez[w];
+      hz_w = (i < N && j < N) ? Hz[w] - dt * ((ey.x - eyw) - (Ex[w + sj] - exw)) : Hz[w];
+      hy_w = (i < N && k < N) ? Hy[w] - dt * ((Ex[w + sk] - exw) - (ez.x - ezw)) : Hy[w];
+    }
+    const bool kk = k >= 1 && k <= N - 1;
+    float ox[4], oy[4], oz[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = p.i0 + e;
+      const bool ii = i >= 1 && i <= N - 1;
+      const float hzw = e > 0 ? hzn[e - 1] : hz_w;
+      const float hyw = e > 0 ? hyn[e - 1] : hy_w;
+      ox[e] = (i < N && jj && kk) ? comp(ex, e) + dt * ((hzn[e] - hzm[e]) - (hyn[e] - hyp[e])) : comp(ex, e);
+      oy[e] = (j < N && ii && kk) ? comp(ey, e) + dt * ((hxn[e] - hxp[e]) - (hzn[e] - hzw)) : comp(ey, e);
+      oz[e] = (k < N && ii && jj) ? comp(ez, e) + dt * ((hyn[e] - hyw) - (hxn[e] - hxm[e])) : comp(ez, e);
+    }
+    if (in) {
+      st4o<NT>(oHx + c, hxn[0], hxn[1], hxn[2], hxn[3]);
+      st4o<NT>(oHy + c, hyn[0], hyn[1], hyn[2], hyn[3]);
+      st4o<NT>(oHz + c, hzn[0], hzn[1], hzn[2], hzn[3]);
+      st4o<NT>(oEx + c, ox[0], ox[1], ox[2], ox[3]);
+      st4o<NT>(oEy + c, oy[0], oy[1], oy[2], oy[3]);
+      st4o<NT>(oEz + c, oz[0], oz[1], oz[2], oz[3]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      hxp[e] = hxn[e];
+      hyp[e] = hyn[e];
+    }
+    ex = ex_k;
+    ey = ey_k;
+    ey_m = ey_mk;
+  }
+}
+
+bool make_fdtd_fused(Launch &L, const FdtdFusedArgs &a, int kc, bool nt) {
+  if (kc == 1 && nt) L.set((const void *)fdtd_fused_kernel<1, true>, march_grid<1>(a.N, a.P), dim3(256), 0, a);
+  else if (kc == 1) L.set((const void *)fdtd_fused_kernel<1, false>, march_grid<1>(a.N, a.P), dim3(256), 0, a);
+  else if (kc == 8) L.set((const void *)fdtd_fused_kernel<8, false>, march_grid<8>(a.N, a.P), dim3(256), 0, a);
   else return false;
   return true;
 }

@@ -173,6 +173,16 @@ struct FdtdArgs {
   float dt;
 };
 
+// Fused H + E step: reads E^n, H^{n-1/2} from one buffer set and writes
+// H^{n+1/2}, E^{n+1} to the other.
+struct FdtdFusedArgs {
+  const float *Ex, *Ey, *Ez, *Hx, *Hy, *Hz;
+  float *oEx, *oEy, *oEz, *oHx, *oHy, *oHz;
+  int N, P;
+  float dt;
+};
+bool make_fdtd_fused(Launch &L, const FdtdFusedArgs &a, int kc, bool nt);   // kc: planes per thread (1, 8); nt: streaming stores (kc 1)
+
 struct SrcArgs {
   float *Ez; long long src;     // flat index of the source node
   const float *g; int glen;     // amplitude per absolute step
@@ -305,7 +315,7 @@ struct kb_problem {
   int N = 0;
   int pitch = 0;                // FDTD row pitch in floats (multiple of 4)
   float dt = 0.5f;
-  float *F[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  float *F[2][6] = {};          // two buffer sets; the current one is F[cur]
   float *g = nullptr; int glen = 0;
   float *probe = nullptr; int pcap = 0;
   long long *step = nullptr;

@@ -152,11 +152,13 @@ def test_skeleton_reduction_log(kb, b):
         assert close(log[e, 1], fsum(x), n)
 
 
-@pytest.mark.parametrize("b", [0, 6])
-def test_fdtd_energy_log(kb, b):
-    announce(f"fdtd energy reductions b={b}")
+@pytest.mark.parametrize("b", [0, 6, 7])
+@pytest.mark.parametrize("variant", [2, 5])
+def test_fdtd_energy_log(kb, b, variant):
+    announce(f"fdtd energy reductions b={b} variant={variant}")
     N, m, steps, seed = 12, 5, 40, 8
     with kb.Problem(kb.FDTD3D, (N, 64), kb.FDTD_COEFFS, seed) as p:
+        p.set_option(kb.OPT_TILE, variant)
         p.set_option(kb.OPT_REDUCE_EVERY, m)
         p.run(steps, b)
         log = p.reduction_log()

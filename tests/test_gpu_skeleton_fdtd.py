@@ -117,7 +117,7 @@ def test_fdtd_source_cell_from_seed(kb):
 
 
 @pytest.mark.parametrize("N,steps", [(8, 150), (17, 120), (32, 300), (5, 60), (6, 60)])
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 def test_fdtd_bitwise_vs_oracle(kb, N, steps, variant):
     announce(f"fdtd N={N} steps={steps} variant={variant}")
     seed = 32
@@ -139,19 +139,46 @@ def test_fdtd_bitwise_vs_oracle(kb, N, steps, variant):
 
 @pytest.mark.parametrize("b", [1, 7, 40])
 @pytest.mark.parametrize("builder", [0, 1])
-def test_fdtd_graph_bitwise(kb, b, builder):
-    announce(f"fdtd graph b={b} builder={builder}")
+@pytest.mark.parametrize("variant", [2, 5])
+def test_fdtd_graph_bitwise(kb, b, builder, variant):
+    """Graph batches equal the per-launch loop; with the fused step (two
+    buffer sets) an odd b needs the graph of each start parity."""
+    announce(f"fdtd graph b={b} builder={builder} variant={variant}")
     N, steps = 20, 203
     outs = []
     for bb in (0, b):
         with kb.Problem(kb.FDTD3D, (N, 256), kb.FDTD_COEFFS, 33) as p:
             p.set_option(kb.OPT_BUILDER, builder)
+            p.set_option(kb.OPT_TILE, variant)
             p.run(steps, bb)
             outs.append((gpu_fields(kb, p), p.read(kb.F_PROBE), p.read(kb.F_STEP)))
     for k in oracle.FDTD_FIELDS:
         assert np.array_equal(outs[0][0][k], outs[1][0][k])
     assert np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][2][0] == outs[1][2][0] == steps
+
+
+def test_fdtd_fused_variant_switching(kb):
+    """The fused step leaves the state in the other buffer set after an odd
+    number of steps; switching to the in-place kernels and back continues
+    from the current set, bit for bit with the oracle."""
+    announce("fdtd fused / in-place switching")
+    N, seed = 18, 35
+    src = synth.fdtd_source_cell(seed, N)
+    _, g32 = oracle.fdtd_pulse(200)
+    ref, probe_ref = oracle.fdtd(oracle.fdtd_zero_fields(N, np.float32), N, 63, src=src, g=g32,
+                                 dtype=np.float32)
+    with kb.Problem(kb.FDTD3D, (N, 256), kb.FDTD_COEFFS, seed) as p:
+        assert p.kernels_per_iter() == 2                   # fused by default
+        for v, n, b in ((5, 33, 4), (2, 20, 3), (6, 7, 0), (3, 3, 0)):
+            p.set_option(kb.OPT_TILE, v)
+            assert p.kernels_per_iter() == (2 if v >= 5 else 3)
+            p.run(n, b)
+        got = gpu_fields(kb, p)
+        probe = p.read(kb.F_PROBE)
+    for k in oracle.FDTD_FIELDS:
+        assert np.array_equal(got[k], ref[k]), k
+    assert np.array_equal(probe[:63], probe_ref)
 
 
 def test_fdtd_explicit_source_and_cavity_mode(kb):
@@ -176,10 +203,12 @@ def test_fdtd_explicit_source_and_cavity_mode(kb):
     assert np.max(np.abs(e[2:] + e[:-2] - (2 - dt * dt * lam) * e[1:-1])) < 1e-5
 
 
-def test_fdtd_energy_reduce(kb):
+@pytest.mark.parametrize("variant,steps", [(2, 120), (5, 121)])
+def test_fdtd_energy_reduce(kb, variant, steps):
     N = 16
     with kb.Problem(kb.FDTD3D, (N, 64), kb.FDTD_COEFFS, 34) as p:
-        p.run(120, 10)
+        p.set_option(kb.OPT_TILE, variant)
+        p.run(steps, 10)
         f = gpu_fields(kb, p)
         e2, h2 = p.reduce()
     ref_e = sum(np.sum(f[k].astype(np.float64) ** 2) for k in ("Ex", "Ey", "Ez"))
@@ -187,16 +216,18 @@ def test_fdtd_energy_reduce(kb):
     assert abs(e2 - ref_e) <= 1e-12 * ref_e and abs(h2 - ref_h) <= 1e-12 * ref_h
 
 
-def test_fdtd_full_size_sampled(kb):
+@pytest.mark.parametrize("variant", [2, 5, 7])
+def test_fdtd_full_size_sampled(kb, variant):
     # 128^3 at the benchmark's launch configuration: 100 steps (source on)
     # against the float32 oracle, bit for bit.
-    announce("fdtd 128^3 100 steps b=50")
+    announce(f"fdtd 128^3 100 steps b=50 variant {variant}")
     N, steps, seed = 128, 100, 20250116
     src = synth.fdtd_source_cell(seed, N)
     _, g32 = oracle.fdtd_pulse(steps + 1)
     ref, probe_ref = oracle.fdtd(oracle.fdtd_zero_fields(N, np.float32), N, steps, src=src, g=g32,
                                  dtype=np.float32)
     with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, seed) as p:
+        p.set_option(kb.OPT_TILE, variant)
         p.run(steps, 50)
         got = gpu_fields(kb, p)
         probe = p.read(kb.F_PROBE)
@@ -215,7 +246,7 @@ def test_fdtd_random_fields_both_variants(kb, N):
     M = N + 1
     f0 = {k: rng.standard_normal((M, M, M)).astype(np.float32) for k in oracle.FDTD_FIELDS}
     ref, _ = oracle.fdtd(f0, N, 9, dtype=np.float32)
-    for variant in (1, 2, 3, 4):
+    for variant in (1, 2, 3, 4, 5, 6, 7):
         with kb.Problem(kb.FDTD3D, (N, 16), (0.5, 0.0, 80.0), 0) as p:
             p.set_option(kb.OPT_TILE, variant)
             for k, fid in kb.FDTD_FIELDS.items():
