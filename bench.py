@@ -270,6 +270,12 @@ def workloads(kb, pm, autotune, np):
         p.set_option(kb.OPT_TDEPTH, 4)
         d["v5_t4_per_launch_us_step"] = arm(p, n, 0, 2) / n * 1e6
         d["v5_t4_graph_b100_us_step"] = arm(p, n, 100, 2) / n * 1e6
+    # variant, depth and b from the autotuner
+    tr = autotune.tune(kb, kb.HEAT3D, (8, 512, 512), kb.HEAT_COEFFS, n, seed=SEED, reps=2)
+    d["autotuned"] = {"variant": tr.variant, "depth": tr.depth, "b": tr.b,
+                      "us_step": tr.us_per_step_warm, "cold_us_step": tr.us_per_step_cold,
+                      "t_create_ms": tr.t_create_s * 1e3, "b_measured_best": tr.b_measured}
+    d["autotuned_graph_us_step"] = tr.us_per_step_warm
     best = min(d[k] for k in d if "graph" in k and k.endswith("us_step"))
     d["gcell_upd_s"] = 8 * 512 * 512 / best / 1e3
     out["heat3d_8x512x512_2000"] = d
@@ -340,6 +346,11 @@ def workloads(kb, pm, autotune, np):
         for name, B in (("separate", 72.0), ("fused", 48.0)):
             d[f"{name}_hbm_frac"] = B * (N + 1) ** 3 / (d[f"{name}_graph_b100_us_step"] * 1e-6) / (HBM_PEAK_GBS * 1e9)
         d["speedup_fused_vs_separate"] = d["separate_graph_b100_us_step"] / d["fused_graph_b100_us_step"]
+        if N == 128:
+            tr = autotune.tune(kb, kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, n, seed=SEED, reps=2,
+                               b_candidates=[10, 20, 50, 100, 200, 500, 1000, 2000])
+            d["autotuned"] = {"variant": tr.variant, "b": tr.b, "us_step": tr.us_per_step_warm,
+                              "t_create_ms": tr.t_create_s * 1e3, "b_measured_best": tr.b_measured}
         out[f"fdtd_{N}^3_{n}"] = d
 
     # learned 16-step surrogate at 512^2 (network, residual check and the
