@@ -173,7 +173,9 @@ extern "C" {
  *              steps per launch, 1..6; nz <= 8); 6, 7, 8 = each wave
  *              covers 2, 4, 8 rows with their neighbour rows in registers,
  *              streaming stores (nx % 4 == 0); 9, 10 = 2, 4 rows with the
- *              layer after next loaded one layer ahead.  Default: 6 if nx % 4 == 0
+ *              layer after next loaded one layer ahead; 11 = temporal
+ *              blocking with every layer of a region column's rows in
+ *              registers (KB_OPT_TDEPTH 1..8; nz <= 8).  Default: 6 if nx % 4 == 0
  *              and ny*nx >= 2^20, else 1.
  *   KB_SKELETON: 1 = 4 elements per thread (default), 2 = 1, 3 = 8.
  *   KB_FDTD3D: separate H and E kernels (3 kernels per iteration with the
@@ -202,7 +204,7 @@ extern "C" {
 #define KB_OPT_TILE      2
 /* KB_OPT_TDEPTH: temporal-blocking depth t >= 1: one launch of a
  *   temporal-blocking variant advances t steps (KB_HEAT2D LDS tile 1..16,
- *   register strips 1..8; KB_HEAT3D variant 5 1..6; KB_HEAT2D_MULTI
+ *   register strips 1..8; KB_HEAT3D variant 5 1..6, variant 11 1..8; KB_HEAT2D_MULTI
  *   variants 3, 4 1..8).  Other variants ignore it.  kb_run advances
  *   floor(n_steps / t) iterations of t steps, then n_steps mod t single
  *   steps per launch.                                                      */

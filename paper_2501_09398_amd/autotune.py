@@ -32,6 +32,7 @@ HEAT2D_TILE = [2, 3, 4, 5, 6, 7]
 HEAT2D_VEC = [8, 9, 10, 11, 13, 14]
 HEAT2D_DEPTHS = [1, 2, 4, 8, 16]
 HEAT3D_DEPTHS = [1, 2, 3, 4, 6]          # variant 5 (layer stacks of <= 8)
+HEAT3D_STRIP_DEPTHS = [2, 3, 4, 5, 6, 8]  # variant 11 (layer stacks of <= 8)
 MULTI_DEPTHS = [1, 2, 3, 4, 5, 6, 7, 8]  # many-grid variants 3 and 4
 
 
@@ -47,7 +48,7 @@ def kernel_candidates(kb, problem, shape):
     if problem == kb.HEAT3D:
         c = [(1, 1)] + ([(2, 1), (3, 1), (4, 1), (6, 1), (7, 1), (8, 1), (9, 1), (10, 1)] if shape[2] % 4 == 0 else [])
         if shape[0] <= 8:
-            c += [(5, t) for t in HEAT3D_DEPTHS]
+            c += [(5, t) for t in HEAT3D_DEPTHS] + [(11, t) for t in HEAT3D_STRIP_DEPTHS]
         return c
     if problem == kb.SKELETON:
         return [(1, 1), (2, 1), (3, 1)]

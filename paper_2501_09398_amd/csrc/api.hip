@@ -212,7 +212,7 @@ bool multi_is_tb(const kb_problem *h) { return h->tile == 0 || h->tile == 3 || h
 // Temporal depth of one iteration.
 int iter_depth(const kb_problem *h) {
   if (h->kind == KB_HEAT2D_SURROGATE) return sg_iter_depth(h);
-  if (h->kind == KB_HEAT3D && heat3d_variant(h) == 5) return h->tdepth;
+  if (h->kind == KB_HEAT3D && (heat3d_variant(h) == 5 || heat3d_variant(h) == 11)) return h->tdepth;
   if (h->kind == KB_HEAT2D_MULTI && multi_is_tb(h)) return h->tdepth;
   return (h->kind == KB_HEAT2D && heat2d_is_tile(heat2d_variant(h))) ? h->tdepth : 1;
 }
@@ -765,7 +765,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
         ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0) || value == 15;
       else if (h->kind == KB_HEAT3D)
         ok = value == 0 || value == 1 || (((value >= 2 && value <= 4) || (value >= 6 && value <= 10)) && h->nx % 4 == 0) ||
-             (value == 5 && h->nz <= 8);
+             ((value == 5 || value == 11) && h->nz <= 8);
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
       else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 7;
       else if (h->kind == KB_HEAT2D_SURROGATE) ok = value >= 0 && value <= 2;

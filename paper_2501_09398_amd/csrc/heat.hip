@@ -18,6 +18,15 @@
 
 namespace kb {
 
+// Value of the neighbouring lane of a full wave, by a DPP wave shift; the
+// lane at the end of the wave reads 0 (callers clamp where that matters).
+__device__ __forceinline__ float lane_west_open(float v) {   // lane - 1 (wave_shr:1)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_east_open(float v) {   // lane + 1 (wave_shl:1)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+
 // ---------------------------------------------------------------------------
 // 2D direct kernel: one thread per cell, 64x4 threads per block.
 // ---------------------------------------------------------------------------
@@ -520,7 +529,9 @@ constexpr int kTbX = 32, kTbY = 32, kTbMaxDepth = 6;   // 8 layers x 44^2 floats
 constexpr int kTbThreads = 512;
 constexpr int kTbCols = ((kTbX + 2 * kTbMaxDepth) * (kTbY + 2 * kTbMaxDepth) + kTbThreads - 1) / kTbThreads;   // 4
 
-int heat3d_tb_max_depth() { return kTbMaxDepth; }
+// deepest temporal blocking of any 3D variant (variant 5: 6, variant 11: 8;
+// a launch checks its own variant's limit)
+int heat3d_tb_max_depth() { return 8; }
 
 template <int NZ>
 __global__ __launch_bounds__(kTbThreads) void heat3d_tb_kernel(const Heat3DArgs a) {
@@ -606,12 +617,150 @@ static const void *heat3d_tb_fn(int nz) {
   return nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// 3D register-strip temporal blocking (variant 11, nz <= 8): t <= 8 steps
+// per launch.  Output tiles of (64 - 2t) x (32 - 2t) columns, each block of
+// 8 waves loads its tile grown by t on each side (at most 64 x 32 columns,
+// clamped to the grid) with every layer: wave w holds region rows
+// 4w .. 4w+3 of column `lane`, all nz layers, in registers.  Vertical
+// neighbours are the thread's own registers, east / west come from the
+// adjacent lanes, north / south from the wave's registers except at its
+// strip ends, which are exchanged through LDS (double buffered: one
+// barrier per step).  As in the 2D kernels, only the region sides on a
+// grid edge need the clamp, and the step loop is specialised on them.
+// ---------------------------------------------------------------------------
+constexpr int kH3Waves = 8, kH3Rows = 4, kH3RegionY = kH3Waves * kH3Rows, kH3MaxDepth = 8;
+
+template <int NZ, bool CW, bool CE, bool CS>
+__device__ __forceinline__ void heat3d_strip_advance(float (&v)[NZ][kH3Rows], const float (&pw)[kH3Rows],
+                                                     float (*ends)[2][kH3Waves][NZ][64], int t, int W, int H,
+                                                     int cx, int w, const HeatCoef &k) {
+  const int last = H - 1 - kH3Rows * w;        // this wave's index of the grid's bottom row (CS)
+  int b = 0;
+  for (int s = 0; s < t; ++s) {
+    float prev[NZ], bot[NZ];
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) {
+      prev[z] = w > 0 ? ends[b][1][w - 1][z][cx] : v[z][0];          // old row above
+      bot[z] = w < kH3Waves - 1 ? ends[b][0][w + 1][z][cx] : v[z][kH3Rows - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < kH3Rows; ++i) {
+      float nv[NZ];
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) {
+        const float c = v[z][i];
+        float so = i == kH3Rows - 1 ? bot[z] : v[z][i + 1];
+        if (CS && i == last) so = c;
+        float ev = lane_east_open(c), wv = lane_west_open(c);
+        if (CE && cx >= W - 1) ev = c;
+        if (CW && cx == 0) wv = c;
+        const float up = z + 1 < NZ ? v[z + 1][i] : c;
+        const float dn = z > 0 ? v[z - 1][i] : c;
+        nv[z] = heat3d_update(c, prev[z], so, wv, ev, up, dn, z == 0 ? pw[i] : 0.0f, z == 0, k);
+      }
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) {
+        prev[z] = v[z][i];
+        v[z][i] = nv[z];
+      }
+    }
+    b ^= 1;
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) {
+      ends[b][0][w][z][cx] = v[z][0];
+      ends[b][1][w][z][cx] = v[z][kH3Rows - 1];
+    }
+    __syncthreads();
+  }
+}
+
+template <int NZ>
+__global__ __launch_bounds__(64 * kH3Waves) void heat3d_strip_tb_kernel(const Heat3DArgs a) {
+  __shared__ float ends[2][2][kH3Waves][NZ][64];   // [buffer][top, bottom][wave][layer][column]
+  const int t = a.tdepth, tile_x = 64 - 2 * t, tile_y = kH3RegionY - 2 * t;
+  const int tiles_x = (a.nx + tile_x - 1) / tile_x, tiles_y = (a.ny + tile_y - 1) / tile_y;
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const int x0 = (lb % tiles_x) * tile_x, y0 = (lb / tiles_x) * tile_y;
+  const int rx_lo = max(x0 - t, 0), rx_hi = min(x0 + tile_x + t, a.nx);
+  const int ry_lo = max(y0 - t, 0), ry_hi = min(y0 + tile_y + t, a.ny);
+  const int W = rx_hi - rx_lo, H = ry_hi - ry_lo;
+  const int cx = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int r0 = kH3Rows * w;
+  const int col = cx < W ? cx : W - 1;
+  const size_t nx = (size_t)a.nx, plane = (size_t)a.ny * nx;
+  const size_t base = (size_t)ry_lo * nx + rx_lo;
+  float v[NZ][kH3Rows], pw[kH3Rows];
+#pragma unroll
+  for (int i = 0; i < kH3Rows; ++i) {
+    const int r = r0 + i < H ? r0 + i : H - 1;
+    const size_t g = base + (size_t)r * nx + col;
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) v[z][i] = a.T[z * plane + g];
+    pw[i] = a.P[g];
+  }
+#pragma unroll
+  for (int z = 0; z < NZ; ++z) {
+    ends[0][0][w][z][cx] = v[z][0];
+    ends[0][1][w][z][cx] = v[z][kH3Rows - 1];
+  }
+  __syncthreads();
+  switch ((rx_lo == 0) | (rx_hi == a.nx) << 1 | (ry_hi == a.ny) << 2) {
+    case 0: heat3d_strip_advance<NZ, false, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 1: heat3d_strip_advance<NZ, true, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 2: heat3d_strip_advance<NZ, false, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 3: heat3d_strip_advance<NZ, true, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 4: heat3d_strip_advance<NZ, false, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 5: heat3d_strip_advance<NZ, true, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 6: heat3d_strip_advance<NZ, false, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    default: heat3d_strip_advance<NZ, true, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+  }
+  const int gx = rx_lo + cx;
+  if (cx < W && gx >= x0 && gx < x0 + tile_x) {
+#pragma unroll
+    for (int i = 0; i < kH3Rows; ++i) {
+      const int gy = ry_lo + r0 + i;
+      if (r0 + i < H && gy >= y0 && gy < y0 + tile_y) {
+        const size_t g = (size_t)gy * nx + gx;
+#pragma unroll
+        for (int z = 0; z < NZ; ++z) a.out[z * plane + g] = v[z][i];
+      }
+    }
+  }
+}
+
+static const void *heat3d_strip_fn(int nz) {
+  switch (nz) {
+    case 1: return (const void *)heat3d_strip_tb_kernel<1>;
+    case 2: return (const void *)heat3d_strip_tb_kernel<2>;
+    case 3: return (const void *)heat3d_strip_tb_kernel<3>;
+    case 4: return (const void *)heat3d_strip_tb_kernel<4>;
+    case 5: return (const void *)heat3d_strip_tb_kernel<5>;
+    case 6: return (const void *)heat3d_strip_tb_kernel<6>;
+    case 7: return (const void *)heat3d_strip_tb_kernel<7>;
+    case 8: return (const void *)heat3d_strip_tb_kernel<8>;
+  }
+  return nullptr;
+}
+
 // variant: 1 = scalar columns; vector rows (nx % 4 == 0): 2 = plain,
 // 3 = next layer prefetched, 4 = prefetched with streaming stores;
 // 5 = temporal blocking over a.tdepth steps (nz <= 8); register-blocked
 // rows with streaming stores (nx % 4 == 0): 6 = 2 rows, 7 = 4, 8 = 8 per
-// wave; 9 = 2 rows, 10 = 4 rows, with the layer after next loaded ahead
+// wave; 9 = 2 rows, 10 = 4 rows, with the layer after next loaded ahead;
+// 11 = register-strip temporal blocking (nz <= 8, a.tdepth <= 8)
 bool make_heat3d(Launch &L, const Heat3DArgs &a, int variant) {
+  if (variant == 11) {
+    const void *f = heat3d_strip_fn(a.nz);
+    if (!f || a.tdepth < 1 || a.tdepth > kH3MaxDepth) return false;
+    const int tx = 64 - 2 * a.tdepth, ty = kH3RegionY - 2 * a.tdepth;
+    const int nb = ((a.nx + tx - 1) / tx) * ((a.ny + ty - 1) / ty);
+    L.set(f, dim3(xcd_padded_grid(nb)), dim3(64 * kH3Waves), 0, a);
+    return true;
+  }
   if (variant == 5) {
     const void *f = heat3d_tb_fn(a.nz);
     if (!f || a.tdepth < 1 || a.tdepth > kTbMaxDepth) return false;
@@ -713,15 +862,6 @@ __global__ __launch_bounds__(256) void heat2d_multi_strip_kernel(const MultiStri
     up = cur;
     cur = down;
   }
-}
-
-// Value of the neighbouring lane of a full wave, by a DPP wave shift; the
-// lane at the end of the wave reads 0 (callers clamp where that matters).
-__device__ __forceinline__ float lane_west_open(float v) {   // lane - 1 (wave_shr:1)
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float lane_east_open(float v) {   // lane + 1 (wave_shl:1)
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
 
 // Many-grid temporal blocking (variants 3 and 4): t steps per launch.  Each

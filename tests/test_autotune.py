@@ -13,7 +13,7 @@ class FakeKB:
     Temporal depth counts only for the temporal-blocking variants of the
     problem the fake was created for."""
     HEAT2D, HEAT3D, SKELETON, FDTD3D, HEAT2D_MULTI = 1, 2, 3, 4, 5
-    TB = {1: {2, 3, 4, 5, 6, 7, 15}, 2: {5}, 5: {3, 4}}
+    TB = {1: {2, 3, 4, 5, 6, 7, 15}, 2: {5, 11}, 5: {3, 4}}
     OPT_BUILDER, OPT_TILE, OPT_TDEPTH, OPT_GRAPH_CACHE, OPT_MAX_NODES = 1, 2, 3, 4, 5
     # per-launch kernel time (s) per variant; variant 6 with depth 8 is best
     T_K = {1: 3e-6, 2: 4e-6, 3: 3.5e-6, 4: 3.6e-6, 5: 3.4e-6, 6: 3.2e-6, 7: 3.9e-6,
@@ -98,7 +98,8 @@ def test_kernel_candidates_respect_alignment():
     assert any(8 <= v <= 14 for v, _ in c_aligned)          # float4 rows need nx % 4 == 0
     assert not any(8 <= v <= 14 for v, _ in c_ragged)
     assert any(v == 15 for v, _ in c_ragged)                 # register strips do not
-    assert autotune.kernel_candidates(kb, kb.HEAT3D, (8, 64, 66)) == [(1, 1)] + [(5, t) for t in autotune.HEAT3D_DEPTHS]
+    assert autotune.kernel_candidates(kb, kb.HEAT3D, (8, 64, 66)) == (
+        [(1, 1)] + [(5, t) for t in autotune.HEAT3D_DEPTHS] + [(11, t) for t in autotune.HEAT3D_STRIP_DEPTHS])
     assert autotune.kernel_candidates(kb, kb.HEAT3D, (9, 64, 66)) == [(1, 1)]
 
 

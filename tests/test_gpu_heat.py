@@ -247,37 +247,47 @@ def test_heat3d_vector_variant_bitwise(kb, shape, tile):
 
 
 @pytest.mark.parametrize("shape", [(8, 64, 64), (8, 70, 95), (3, 20, 72), (1, 3, 260), (5, 33, 33),
-                                   (2, 5, 4), (7, 100, 1), (8, 1, 1), (6, 45, 46)])
-@pytest.mark.parametrize("tdepth", [1, 2, 3, 6])
-def test_heat3d_temporal_blocking_bitwise(kb, shape, tdepth):
+                                   (2, 5, 4), (7, 100, 1), (8, 1, 1), (6, 45, 46), (8, 130, 200)])
+@pytest.mark.parametrize("tile,tdepth", [(5, 1), (5, 2), (5, 3), (5, 6), (11, 1), (11, 2), (11, 5), (11, 8)])
+def test_heat3d_temporal_blocking_bitwise(kb, shape, tile, tdepth):
     """Variant 5 (t steps per launch over 32x32 column tiles, columns in
-    registers, planes in LDS) against the one-step kernel: same bits for
-    every depth, with a step count that leaves a remainder (run per step),
-    per launch and in graph batches; tiles smaller than the halo, single
-    rows and columns, every layer count up to 8."""
-    announce(f"heat3d temporal {shape} t={tdepth}")
+    registers, planes in LDS) and variant 11 (64-column regions, every
+    layer of a column's rows in registers, edge clamps specialised) against
+    the one-step kernel: same bits for every depth, with a step count that
+    leaves a remainder (run per step), per launch and in graph batches;
+    tiles smaller than the halo, single rows and columns, interior regions,
+    every layer count up to 8."""
+    announce(f"heat3d temporal {shape} variant {tile} t={tdepth}")
     steps = 17
     base = run_heat3d(kb, shape, steps, seed=19, tile=1)
-    assert np.array_equal(base, run_heat3d(kb, shape, steps, seed=19, tile=5, tdepth=tdepth))
-    assert np.array_equal(base, run_heat3d(kb, shape, steps, b=2, seed=19, tile=5, tdepth=tdepth))
+    assert np.array_equal(base, run_heat3d(kb, shape, steps, seed=19, tile=tile, tdepth=tdepth))
+    assert np.array_equal(base, run_heat3d(kb, shape, steps, b=2, seed=19, tile=tile, tdepth=tdepth))
 
 
-def test_heat3d_temporal_blocking_full_size(kb):
-    """8x512x512 at depth 4 in graph batches of 50 for 2000 steps: the same
-    bits as the one-step kernel."""
-    announce("heat3d temporal 8x512x512 2000 steps")
+@pytest.mark.parametrize("tile,tdepth,b", [(5, 4, 50), (11, 5, 40)])
+def test_heat3d_temporal_blocking_full_size(kb, tile, tdepth, b):
+    """8x512x512 for 2000 steps in graph batches: the same bits as the
+    one-step kernel."""
+    announce(f"heat3d temporal 8x512x512 2000 steps variant {tile} t={tdepth}")
     shape = (8, 512, 512)
     base = run_heat3d(kb, shape, 2000, b=100, seed=20250116, tile=1)
-    assert np.array_equal(base, run_heat3d(kb, shape, 2000, b=50, seed=20250116, tile=5, tdepth=4))
+    assert np.array_equal(base, run_heat3d(kb, shape, 2000, b=b, seed=20250116, tile=tile, tdepth=tdepth))
 
 
 def test_heat3d_temporal_blocking_limits(kb):
     with kb.Problem(kb.HEAT3D, (9, 16, 16), coeffs(HEAT), 0) as p:
-        with pytest.raises(kb.KBError):
-            p.set_option(kb.OPT_TILE, 5)              # more than 8 layers
+        for v in (5, 11):
+            with pytest.raises(kb.KBError):
+                p.set_option(kb.OPT_TILE, v)          # more than 8 layers
     with kb.Problem(kb.HEAT3D, (8, 16, 16), coeffs(HEAT), 0) as p:
         with pytest.raises(kb.KBError):
-            p.set_option(kb.OPT_TDEPTH, 7)
+            p.set_option(kb.OPT_TDEPTH, 9)
+        p.set_option(kb.OPT_TILE, 5)
+        p.set_option(kb.OPT_TDEPTH, 7)                # variant 5 stops at 6
+        with pytest.raises(kb.KBError):
+            p.run(14, 0)
+        p.set_option(kb.OPT_TILE, 11)
+        p.run(16, 0)
 
 
 @pytest.mark.parametrize("b", [1, 4, 9])
