@@ -571,7 +571,16 @@ def main():
                          # gap of a graph launch over a node-to-node gap
                          "T_a_minus_T_i_us": model.execution.a / ITERS * 1e6}
         line["sweep"] = [[s[0], round(s[1] * 1e3, 4), round(s[2] * 1e3, 4)] for s in sweep]
-        line["graph_memory"] = graph_memory(kb, np, torch)
+        gm = graph_memory(kb, np, torch)
+        # the model's optimum under a device-memory budget for the batch
+        # graph, from the measured bytes per node (the memory side of b*)
+        mm = pm.MemoryModel(gm["bytes_per_node"], max(gm["bytes_fixed"], 0.0))
+        divs = [b for b in pm.divisors(ITERS, 1, 2000)]
+        gm["b_model_under_budget"] = {}
+        for budget in (1 << 20, 4 << 20):
+            ok = [b for b in divs if b * K <= mm.max_nodes(budget)] or [1]
+            gm["b_model_under_budget"][f"{budget >> 20}MiB"] = model.best(ok)[0]
+        line["graph_memory"] = gm
         line["graph_builders"] = builders_and_update(kb, np)
     print(json.dumps(line), flush=True)
 

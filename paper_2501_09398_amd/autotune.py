@@ -87,13 +87,21 @@ def _warm_time(p, n, b, reps):
 
 
 def tune(kb, problem, shape, coeffs, n_steps, seed=0, probe_steps=None, b_probe=None,
-         b_candidates=None, reps=3, kernel_candidates_override=None, max_nodes=4096):
+         b_candidates=None, reps=3, kernel_candidates_override=None, max_nodes=4096,
+         graph_mem_budget=None, mem_model=None):
     """Tune (variant, depth, b) for running n_steps of the problem.
 
     kb: the binding module.  probe_steps: steps timed per kernel candidate
-    (default min(n_steps, 200), rounded to a multiple of 16).  Returns a
-    TuneResult; the problem objects it creates are destroyed again.
+    (default min(n_steps, 200), rounded to a multiple of 16).
+    graph_mem_budget: bytes of device memory the batch graph may hold; b
+    is then limited to graphs that fit by the linear memory model
+    (`mem_model`, a perfmodel.MemoryModel; the MI355X fit by default).
+    Returns a TuneResult; the problem objects it creates are destroyed
+    again.
     """
+    if graph_mem_budget is not None:
+        mm = mem_model or pm.MemoryModel()
+        max_nodes = min(max_nodes, mm.max_nodes(graph_mem_budget))
     if probe_steps is None:
         probe_steps = max(16, min(n_steps, 200) // 16 * 16)
     cands = kernel_candidates_override or kernel_candidates(kb, problem, shape)
@@ -112,6 +120,8 @@ def tune(kb, problem, shape, coeffs, n_steps, seed=0, probe_steps=None, b_probe=
     n_iter = n_steps // best_t
     if b_candidates is None:
         b_candidates = [d for d in pm.divisors(n_iter) if d * K <= max_nodes] or [1]
+    else:
+        b_candidates = [b for b in b_candidates if b * K <= max_nodes] or [1]
     sweep = []
     with kb.Problem(problem, shape, coeffs, seed) as p:
         p.set_option(kb.OPT_TILE, best_v)

@@ -116,6 +116,34 @@ class Model:
                 "S_closed_form": self.s_closed_form()}
 
 
+@dataclass
+class MemoryModel:
+    """Device memory an instantiated, uploaded graph holds: linear in its
+    kernel nodes (the footprint the paper's Fig. 2 bars grow with).  The
+    defaults are the MI355X fit of the benchmark (skeleton chain, ROCm
+    7.2): about 206 bytes per node plus about 150 KB per graph."""
+    bytes_per_node: float = 206.0
+    bytes_fixed: float = 150e3
+
+    def __call__(self, nodes):
+        return self.bytes_fixed + self.bytes_per_node * np.asarray(nodes, dtype=np.float64)
+
+    def max_nodes(self, budget):
+        """Largest node count whose graph fits `budget` bytes (0 if none)."""
+        if budget <= self.bytes_fixed:
+            return 0
+        return int((budget - self.bytes_fixed) // self.bytes_per_node)
+
+
+def fit_memory(nodes, mem_bytes) -> MemoryModel:
+    """Least-squares fit of graph bytes = fixed + per_node * nodes."""
+    x = np.asarray(nodes, dtype=np.float64)
+    y = np.asarray(mem_bytes, dtype=np.float64)
+    A = np.stack([x, np.ones_like(x)], axis=1)
+    (k, c), *_ = np.linalg.lstsq(A, y, rcond=None)
+    return MemoryModel(float(k), float(c))
+
+
 def speedup(base_times, graph_times):
     """Speed-up as the ratio of mean times, with the error of Sec. III-C:
     the relative standard deviations of the two arms added in quadrature

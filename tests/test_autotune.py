@@ -91,6 +91,24 @@ def test_tuner_applies_depth_for_3d_and_many_grids(problem, shape):
     assert (res.variant, res.depth) == min(per_step, key=per_step.get)
 
 
+def test_graph_memory_budget_limits_b():
+    """With a device-memory budget for the batch graph, b stays within the
+    node count the linear memory model allows (fixed + per-node bytes), and
+    the unconstrained optimum is kept when it fits."""
+    kb = fake_kb()
+    free = autotune.tune(kb, kb.SKELETON, (1024,), (), 1000, reps=1)
+    mm = pm.MemoryModel(bytes_per_node=200.0, bytes_fixed=1e5)
+    budget = 1e5 + 200.0 * 20                         # 20 nodes
+    res = autotune.tune(kb, kb.SKELETON, (1024,), (), 1000, reps=1, graph_mem_budget=budget, mem_model=mm)
+    assert res.b * 1 <= 20 and 1000 % res.b == 0
+    assert free.b > 20                                # the budget did bind
+    roomy = autotune.tune(kb, kb.SKELETON, (1024,), (), 1000, reps=1, graph_mem_budget=1e9)
+    assert roomy.b == free.b
+    assert mm.max_nodes(1e5) == 0 and mm.max_nodes(1e5 + 401) == 2
+    fit = pm.fit_memory([100, 1000, 5000], [1e5 + 2e4, 1e5 + 2e5, 1e5 + 1e6])
+    assert math.isclose(fit.bytes_per_node, 200.0) and math.isclose(fit.bytes_fixed, 1e5)
+
+
 def test_kernel_candidates_respect_alignment():
     kb = FakeKB()
     c_aligned = autotune.kernel_candidates(kb, kb.HEAT2D, (64, 256))
