@@ -175,6 +175,52 @@ def graph_memory(kb, np, torch, copies=8, batches=(250, 1000, 2500)):
             "points_nodes_bytes": [[int(a), int(c)] for a, c in pts]}
 
 
+def table1_sweep(kb, pm, np, sizes=tuple(1 << e for e in range(10, 23, 2)), reps=2):
+    """The structure of the paper's Table I on MI355X: for each vector size
+    of the K = 4 skeleton chain (2^10 .. 2^22), 10,000 iterations per launch
+    and in graph batches over the 22 divisors of 10^4 up to 2000, Eq. 2 and
+    Eq. 6 fitted by least squares (MAE as in the table), the model's b*
+    against the measured best, and the speed-up at b*."""
+    cands = pm.divisors(ITERS, 1, 2000)
+    rows = []
+    for n in sizes:
+        with kb.Problem(kb.SKELETON, (n,), (K,), SEED) as p:
+            p.set_option(kb.OPT_GRAPH_CACHE, 0)         # every run pays its own T_C
+            p.run(ITERS, 0)
+            p.last_timing()
+            per_launch = float(np.median([_run_exec(p, 0) for _ in range(reps)]))
+            sweep = []
+            for b in cands:
+                ts = [_run_both(p, b) for _ in range(reps)]
+                sweep.append((b, float(np.median([t[0] for t in ts])), float(np.median([t[1] for t in ts]))))
+        S = np.array([q[0] for q in sweep], float)
+        model = pm.Model(pm.fit_creation(K * S, [q[1] for q in sweep]),
+                         pm.fit_execution(S, [q[2] for q in sweep]), K=K)
+        b_model, t_model = model.best(cands)
+        total = {q[0]: q[1] + q[2] for q in sweep}
+        b_meas = min(total, key=total.get)
+        rows.append({"n": n, "per_launch_ms": per_launch * 1e3,
+                     "k_c_us_per_node": model.creation.k_c * 1e6, "b_c_ms": model.creation.b_c * 1e3,
+                     "mae_c_ms": model.creation.mae * 1e3,
+                     "a_ms": model.execution.a * 1e3, "b_ms": model.execution.b * 1e3,
+                     "mae_e_ms": model.execution.mae * 1e3,
+                     "b_model": b_model, "b_closed_form": model.s_closed_form(), "b_measured_best": b_meas,
+                     "total_at_b_model_ms": total[b_model] * 1e3, "total_at_b_measured_ms": total[b_meas] * 1e3,
+                     "speedup_at_b_model": per_launch / total[b_model]})
+    return rows
+
+
+def _run_exec(p, b):
+    p.run(ITERS, b)
+    return p.last_timing()["t_exec_s"]
+
+
+def _run_both(p, b):
+    p.run(ITERS, b)
+    t = p.last_timing()
+    return t["t_create_s"], t["t_exec_s"]
+
+
 def builders_and_update(kb, np, batches=(100, 1000, 2500), reps=3):
     """T_C of the two builders (explicit kernel nodes, stream capture of the
     per-launch loop) vs batch size, and what a change of node arguments
@@ -582,6 +628,8 @@ def main():
             gm["b_model_under_budget"][f"{budget >> 20}MiB"] = model.best(ok)[0]
         line["graph_memory"] = gm
         line["graph_builders"] = builders_and_update(kb, np)
+        if not args.no_workloads:
+            line["table1_sizes"] = table1_sweep(kb, pm, np)
     print(json.dumps(line), flush=True)
 
 
