@@ -249,6 +249,11 @@ extern "C" {
  *   every other variant.  0 = off (default).  The alternative to graphs
  *   that the paper sets against them (Sec. V): no launch per step at all. */
 #define KB_OPT_PERSISTENT 8
+/* KB_OPT_SPIN_LIMIT: polls a grid-barrier wait of the persistent kernel
+ *   makes before it gives up (raising the error flag that makes kb_run
+ *   return KB_EHIP; no block waits after that, so the launch always ends).
+ *   0 = automatic (about a second, more for very large super-steps).     */
+#define KB_OPT_SPIN_LIMIT 9
 
 typedef struct kb_problem kb_problem;
 

@@ -34,6 +34,7 @@ FDTD_FIELDS = {"Ex": F_EX, "Ey": F_EY, "Ez": F_EZ, "Hx": F_HX, "Hy": F_HY, "Hz":
 OPT_BUILDER, OPT_TILE, OPT_TDEPTH, OPT_GRAPH_CACHE, OPT_MAX_NODES, OPT_REDUCE_EVERY = 1, 2, 3, 4, 5, 6
 OPT_GRAPH_UPDATE = 7
 OPT_PERSISTENT = 8
+OPT_SPIN_LIMIT = 9
 # status
 OK, EINVAL, ENOMEM, EHIP, ESTATE, WFALLBACK = 0, -1, -2, -3, -4, 1
 

@@ -812,6 +812,10 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       h->persistent = (int)value;
       break;
     }
+    case KB_OPT_SPIN_LIMIT:
+      if (value < 0 || value > INT32_MAX) return fail(KB_EINVAL, "spin limit must be 0..2^31-1");
+      h->spin_limit = value;
+      break;
     case KB_OPT_REDUCE_EVERY:
       if (h->kind == KB_HEAT2D_SURROGATE) return fail(KB_EINVAL, "the surrogate has its own residual check");
       if (value < 0) return fail(KB_EINVAL, "reduction interval must be >= 0");
@@ -865,7 +869,8 @@ int run_persistent(kb_problem *h, int64_t n_steps) {
   a.bar = h->grid_bar_d;
   // polls of a barrier wait before it gives up: about a second (one poll is
   // an uncached load and a short sleep), more for huge super-steps
-  a.spin_limit = (unsigned)std::min<int64_t>(INT32_MAX, std::max<int64_t>(1 << 20, h->total_cells * t >> 14));
+  a.spin_limit = h->spin_limit > 0 ? (unsigned)h->spin_limit
+               : (unsigned)std::min<int64_t>(INT32_MAX, std::max<int64_t>(1 << 20, h->total_cells * t >> 14));
   a.k = h->hk;
   void *args[] = {&a};
   kb_timing tm{};

@@ -283,6 +283,7 @@ struct kb_problem {
   int64_t max_nodes = 65536;
   int graph_update = 0;         // 1: refit cached graphs when node arguments change
   int persistent = 0;           // 1: one cooperative launch per kb_run (many grids)
+  int64_t spin_limit = 0;       // polls per barrier wait of that launch (0: automatic)
   double t_update_s = 0;        // host time of the last refit / invalidation
   int64_t n_updated = 0;        // graphs refitted by it
 

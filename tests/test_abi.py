@@ -78,6 +78,7 @@ def test_binding_constants_match_header(kb):
     d = header_defines()
     pairs = {"KB_OPT_REDUCE_EVERY": kb.OPT_REDUCE_EVERY, "KB_OPT_TILE": kb.OPT_TILE,
              "KB_OPT_GRAPH_UPDATE": kb.OPT_GRAPH_UPDATE, "KB_OPT_PERSISTENT": kb.OPT_PERSISTENT,
+             "KB_OPT_SPIN_LIMIT": kb.OPT_SPIN_LIMIT,
              "KB_OPT_BUILDER": kb.OPT_BUILDER, "KB_OPT_TDEPTH": kb.OPT_TDEPTH,
              "KB_OPT_GRAPH_CACHE": kb.OPT_GRAPH_CACHE, "KB_OPT_MAX_NODES": kb.OPT_MAX_NODES,
              "KB_F_T": kb.F_T, "KB_F_P": kb.F_P, "KB_F_W": kb.F_W, "KB_F_SGSTATS": kb.F_SGSTATS,

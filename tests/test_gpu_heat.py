@@ -476,3 +476,29 @@ def test_persistent_option_rejections(kb):
         p.set_option(kb.OPT_REDUCE_EVERY, 10)
         with pytest.raises(kb.KBError):
             p.run(20, 0)
+
+
+def test_persistent_barrier_timeout_is_reported(kb):
+    """The bounded barrier wait: with a spin limit of one poll, a block that
+    reaches a barrier before the others gives up at once, raises the error
+    flag, and every block runs to its end; kb_run reports the failure.  The
+    next run with the automatic limit is correct again (from a rewritten
+    state)."""
+    announce("multigrid persistent barrier time-out")
+    sides = synth.multigrid_sides(20250116, 64)
+    shape = [64] + [v for s in sides for v in (s, s)]
+    with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 5) as p:
+        T0 = p.read(kb.F_T)
+        p.set_option(kb.OPT_PERSISTENT, 1)
+        p.set_option(kb.OPT_TDEPTH, 4)
+        p.set_option(kb.OPT_SPIN_LIMIT, 1)
+        with pytest.raises(kb.KBError):
+            p.run(40, 0)
+        p.set_option(kb.OPT_SPIN_LIMIT, 0)
+        p.write(kb.F_T, T0)
+        p.run(40, 0)
+        got = p.read(kb.F_T)
+    with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 5) as q:
+        q.set_option(kb.OPT_TILE, 2)
+        q.run(40, 0)
+        assert np.array_equal(q.read(kb.F_T), got)
