@@ -62,6 +62,9 @@ def parse():
                     help="skip the other workloads (2D/3D stencils, many grids, FDTD, large grids)")
     ap.add_argument("--kernel-only", choices=sorted(KERNEL_RUNS),
                     help="run only one workload's kernels per launch for a few steps (counter runs)")
+    ap.add_argument("--stream-calibration", action="store_true",
+                    help="only time the streaming probe for the read / write stream mixes of the "
+                         "stencil and FDTD kernels (attainable DRAM throughput per mix)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (2^26 floats read and written by the "
                          "element-wise kernel with a=1, b=0), to scale hardware byte counters")
@@ -111,6 +114,27 @@ def kernel_only(name):
         p.last_timing()
     torch.cuda.synchronize()
     print(json.dumps({"kernel_only": name, "steps": steps}), flush=True)
+
+
+# (reads, writes) of the kernels whose HBM fraction the benchmark reports:
+# copy; heat2d (T, P -> T); FDTD H or E kernel (6 -> 3); fused FDTD step
+# (6 -> 6); a wider read-heavy mix
+STREAM_MIXES = ((1, 1), (2, 1), (3, 1), (2, 2), (3, 3), (6, 3), (6, 6), (8, 1))
+
+
+def stream_calibration():
+    """Attainable DRAM throughput per stream mix: 2^26 floats per array
+    (256 MiB, far beyond the 256 MB last-level cache), 10 timed launches."""
+    import torch
+    import paper_2501_09398_amd as kb
+    n = 1 << 26
+    rows = []
+    for nin, nout in STREAM_MIXES:
+        sec = kb.stream_probe(nin, nout, n, reps=10)
+        gbs = (nin + nout) * n * 4 / sec / 1e9
+        rows.append({"reads": nin, "writes": nout, "us": sec * 1e6, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS})
+    torch.cuda.synchronize()
+    print(json.dumps({"stream_calibration": rows, "elements_per_array": n}), flush=True)
 
 
 def copy_calibration():
@@ -461,6 +485,9 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU decomposition is described in DESIGN.md but not built)", file=sys.stderr)
         sys.exit(2)
+    if args.stream_calibration:
+        stream_calibration()
+        return
     if args.copy_calibration:
         copy_calibration()
         return

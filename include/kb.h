@@ -376,6 +376,23 @@ int kb_destroy(kb_problem *h);
  * until the next kb_* call on the same thread.                             */
 const char *kb_last_error(void);
 
+/* Streaming calibration (a measurement helper, not part of a solver): time
+ * one kernel that reads nin arrays and writes nout arrays of n floats each
+ * (1 <= nin, nout <= 8; n a multiple of 4), element-wise, float4 per thread
+ * -- the access pattern of a stencil or FDTD kernel with that many
+ * concurrent HBM streams, with no reuse and no arithmetic to speak of.  It
+ * gives the DRAM throughput attainable for a kernel's stream mix, against
+ * which the kernel's own throughput can be read.
+ *   workspace: device pointer of >= (nin + nout) * n * 4 bytes, 256-B
+ *              aligned (the caller's; contents overwritten); array k
+ *              starts at byte k * n * 4.
+ *   stream   : hipStream_t to run on (NULL = default stream).
+ *   reps     : timed launches after one untimed launch.
+ *   seconds  : out, mean seconds per launch (HIP events; synchronises).
+ * Returns KB_OK, KB_EINVAL (bad counts, n, size or alignment), KB_EHIP.   */
+int kb_stream_probe(int nin, int nout, int64_t n, void *workspace, size_t ws_bytes, void *stream, int reps,
+                    double *seconds);
+
 /* ABI version of this header (increments on incompatible change).         */
 int kb_abi_version(void);
 

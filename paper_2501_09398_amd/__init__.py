@@ -98,6 +98,9 @@ def lib():
         L.kb_last_error.argtypes = []
         L.kb_last_error.restype = C.c_char_p
         L.kb_abi_version.restype = C.c_int
+        L.kb_stream_probe.argtypes = [C.c_int, C.c_int, C.c_int64, vp, C.c_size_t, vp, C.c_int,
+                                      C.POINTER(C.c_double)]
+        L.kb_stream_probe.restype = C.c_int
         _lib = L
     return _lib
 
@@ -116,6 +119,24 @@ def _shape_arr(shape):
 def workspace_bytes(problem, shape):
     arr, nd = _shape_arr(shape)
     return int(lib().kb_workspace_bytes(problem, arr, nd))
+
+
+def stream_probe(nin, nout, n, reps=10, device=0):
+    """kb_stream_probe: mean seconds per launch of a kernel reading nin and
+    writing nout arrays of n floats (the attainable DRAM throughput of that
+    stream mix).  The workspace is a torch uint8 tensor on the device."""
+    lib()
+    dev = torch.device("cuda", device)
+    with torch.cuda.device(dev):
+        nbytes = (nin + nout) * int(n) * 4
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        aligned = (ws.data_ptr() + 255) // 256 * 256
+        stream = torch.cuda.current_stream(dev)
+        sec = C.c_double()
+        _check(lib().kb_stream_probe(int(nin), int(nout), int(n), C.c_void_p(aligned), nbytes,
+                                     C.c_void_p(stream.cuda_stream), int(reps), C.byref(sec)))
+        del ws
+    return sec.value
 
 
 class Problem:

@@ -530,6 +530,21 @@ extern "C" {
 
 int kb_abi_version(void) { return 2; }
 
+int kb_stream_probe(int nin, int nout, int64_t n, void *workspace, size_t ws_bytes, void *stream, int reps,
+                    double *seconds) {
+  g_err.clear();
+  if (!seconds || !workspace) return fail(KB_EINVAL, "null argument");
+  if (nin < 1 || nin > 8 || nout < 1 || nout > 8) return fail(KB_EINVAL, "1 <= nin, nout <= 8");
+  if (n < 4 || n % 4 != 0) return fail(KB_EINVAL, "n must be a positive multiple of 4");
+  if (reps < 1) return fail(KB_EINVAL, "reps must be >= 1");
+  if (ws_bytes < (size_t)(nin + nout) * (size_t)n * 4) return fail(KB_ENOMEM, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(KB_EINVAL, "workspace must be 256-byte aligned");
+  const hipError_t e = stream_probe(nin, nout, n, static_cast<float *>(workspace),
+                                    reinterpret_cast<hipStream_t>(stream), reps, seconds);
+  if (e != hipSuccess) return fail(KB_EHIP, "stream probe: %s", hipGetErrorString(e));
+  return KB_OK;
+}
+
 const char *kb_last_error(void) { return g_err.c_str(); }
 
 size_t kb_workspace_bytes(int problem, const int64_t *shape, int ndim) {

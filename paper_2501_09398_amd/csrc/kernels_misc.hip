@@ -195,4 +195,60 @@ hipError_t reduce_sumsq(const float *const *fields, int nf, long long n, double 
   return reduce_impl(fields, nf, 1, n, partials, result, s);
 }
 
+// ---------------------------------------------------------------------------
+// Streaming calibration: out_j[i] = sum_k in_k[i], one float4 i per thread
+// over a full grid (the launch shape of the stencil kernels).  Used only to
+// measure the DRAM throughput a given number of concurrent read / write
+// streams reaches.
+// ---------------------------------------------------------------------------
+struct StreamArgs {
+  const float4 *in[8];
+  float4 *out[8];
+  int nin, nout;
+  long long n4;
+};
+
+__global__ __launch_bounds__(256) void stream_probe_kernel(const StreamArgs a) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n4) return;
+  float4 v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k < a.nin) v[k] = a.in[k][i];            // all loads in flight before the sum
+  float4 s = v[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    if (k < a.nin) { s.x += v[k].x; s.y += v[k].y; s.z += v[k].z; s.w += v[k].w; }
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < a.nout) a.out[j][i] = s;
+}
+
+hipError_t stream_probe(int nin, int nout, long long n, float *ws, hipStream_t s, int reps, double *seconds) {
+  StreamArgs a{};
+  for (int k = 0; k < nin; ++k) a.in[k] = reinterpret_cast<const float4 *>(ws + (size_t)k * n);
+  for (int j = 0; j < nout; ++j) a.out[j] = reinterpret_cast<float4 *>(ws + (size_t)(nin + j) * n);
+  a.nin = nin; a.nout = nout; a.n4 = n / 4;
+  const long long blocks = (a.n4 + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipError_t e;
+  hipEvent_t e0, e1;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return e; }
+  hipLaunchKernelGGL(stream_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  e = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    hipLaunchKernelGGL(stream_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e == hipSuccess) *seconds = ms * 1e-3 / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return e;
+}
+
 }  // namespace kb

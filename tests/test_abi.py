@@ -99,3 +99,19 @@ def test_timing_struct_matches_header(kb):
     import ctypes as C
     want = {"double": C.c_double, "int64_t": C.c_int64}
     assert [want[t] for t, _ in fields] == [t for _, t in kb.Timing._fields_]
+
+
+def test_stream_probe_rejects_bad_arguments_without_a_gpu(kb):
+    """Argument checks of the streaming calibration entry point happen
+    before any HIP call."""
+    import ctypes as C
+    L = kb.lib()
+    sec = C.c_double()
+    buf = C.create_string_buffer(4096 + 256)
+    aligned = (C.addressof(buf) + 255) // 256 * 256
+    for nin, nout, n, ws, reps in ((0, 1, 64, 4096, 1), (1, 9, 64, 4096, 1), (1, 1, 6, 4096, 1),
+                                   (2, 2, 1024, 4096, 1), (1, 1, 64, 4096, 0)):
+        rc = L.kb_stream_probe(nin, nout, n, C.c_void_p(aligned), ws, None, reps, C.byref(sec))
+        assert rc < 0, (nin, nout, n, ws, reps)
+    rc = L.kb_stream_probe(1, 1, 64, C.c_void_p(aligned + 4), 4096, None, 1, C.byref(sec))
+    assert rc == kb.EINVAL                            # misaligned workspace
