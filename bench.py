@@ -123,11 +123,12 @@ STREAM_MIXES = ((1, 1), (2, 1), (3, 1), (2, 2), (3, 3), (6, 3), (6, 6), (8, 1))
 
 
 def stream_calibration():
-    """Attainable DRAM throughput per stream mix: 2^26 floats per array
-    (256 MiB, far beyond the 256 MB last-level cache), 10 timed launches."""
+    """Attainable DRAM throughput per stream mix: 2^28 floats per array
+    (1 GiB each, four times the 256 MB last-level cache, so repeated
+    launches cannot be served from it), 10 timed launches."""
     import torch
     import paper_2501_09398_amd as kb
-    n = 1 << 26
+    n = 1 << 28
     rows = []
     for nin, nout in STREAM_MIXES:
         sec = kb.stream_probe(nin, nout, n, reps=10)

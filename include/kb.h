@@ -163,16 +163,17 @@ extern "C" {
  *                     tiles 64x4, 64x8, 64x16, 32x8, 16x16, 32x4;
  *              8..12 = float4 rows, a wave walking 1, 2, 4, 8, 16 rows;
  *              13, 14 = 1 and 2 rows with streaming (non-temporal) stores
+ *                     and loads of P
  *                     (8..14 need nx % 4 == 0);
  *              15 = temporal blocking over 16x16 tiles with the rows of each
  *                     region column in registers (KB_OPT_TDEPTH 1..8).
  *              Default: 13 if nx % 4 == 0 and ny*nx >= 2^20, else 1.
  *   KB_HEAT3D: 1 = one thread per column; float4 rows (nx % 4 == 0):
  *              2 = plain, 3 = next layer prefetched, 4 = prefetched with
- *              streaming stores; 5 = temporal blocking (KB_OPT_TDEPTH
+ *              streaming stores and P loads; 5 = temporal blocking (KB_OPT_TDEPTH
  *              steps per launch, 1..6; nz <= 8); 6, 7, 8 = each wave
  *              covers 2, 4, 8 rows with their neighbour rows in registers,
- *              streaming stores (nx % 4 == 0); 9, 10 = 2, 4 rows with the
+ *              streaming stores and P loads (nx % 4 == 0); 9, 10 = 2, 4 rows with the
  *              layer after next loaded one layer ahead; 11 = temporal
  *              blocking with every layer of a region column's rows in
  *              registers (KB_OPT_TDEPTH 1..8; nz <= 8).  Default: 6 if nx % 4 == 0

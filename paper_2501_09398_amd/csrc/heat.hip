@@ -234,6 +234,21 @@ bool make_heat2d_tile(Launch &L, const Heat2DArgs &a, int variant) {
 // rows above, at and below the current one in registers, so a row of T is
 // read from memory once per strip plus one halo row at each end.
 // ---------------------------------------------------------------------------
+// Load of a float4 row segment read once per step (the power map P): with
+// NT, a non-temporal (streaming) load, as the streaming-store variants use
+// for data that no other wave of the step reads again.
+template <bool NT>
+__device__ __forceinline__ float4 load_once4(const float *base, size_t row, size_t nx, int x, bool xin) {
+  if (!xin) return make_float4(0.f, 0.f, 0.f, 0.f);
+  if constexpr (NT) {
+    typedef float f4l __attribute__((ext_vector_type(4)));
+    const f4l v = __builtin_nontemporal_load(reinterpret_cast<const f4l *>(base + row * nx + x));
+    return make_float4(v.x, v.y, v.z, v.w);
+  } else {
+    return *reinterpret_cast<const float4 *>(base + row * nx + x);
+  }
+}
+
 __device__ __forceinline__ float4 load_row4(const float *base, size_t row, size_t nx, int x, bool xin) {
   return xin ? *reinterpret_cast<const float4 *>(base + row * nx + x) : make_float4(0.f, 0.f, 0.f, 0.f);
 }
@@ -285,7 +300,7 @@ __global__ __launch_bounds__(256) void heat2d_vec_kernel(const Heat2DArgs a) {
     const int y = y0 + r;
     if (y >= a.ny) break;
     const float4 dn = load_row4(T, y + 1 < a.ny ? y + 1 : a.ny - 1, nx, x, xin);
-    const float4 p = load_row4(P, y, nx, x, xin);
+    const float4 p = load_once4<NT>(P, y, nx, x, xin);
     float wv, ev;
     row_neighbours(T + (size_t)y * nx, cur, x, a.nx, lane, wv, ev);
     float4 o;
@@ -369,7 +384,7 @@ __global__ __launch_bounds__(256) void heat3d_vec_kernel(const Heat3DArgs a) {
       }
     }
     const bool hp = z == 0;
-    const float4 p = hp ? load_row4(P, y, nx, x, xin) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 p = hp ? load_once4<NT>(P, y, nx, x, xin) : make_float4(0.f, 0.f, 0.f, 0.f);
     float wv, ev;
     row_neighbours(T + (zr + y) * nx, tc, x, a.nx, lane, wv, ev);
     float4 o;
@@ -459,7 +474,7 @@ __global__ __launch_bounds__(256) void heat3d_rows_kernel(const Heat3DArgs a) {
       const int yy = y0 + r;
       if (yy < a.ny) {
         const float4 tc = c[r + 1], tn = c[r], ts = c[r + 2], tu = u[r + 1], td = d[r];
-        const float4 p = hp ? load_row4(P, (size_t)yy, nx, x, xin) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 p = hp ? load_once4<NT>(P, (size_t)yy, nx, x, xin) : make_float4(0.f, 0.f, 0.f, 0.f);
         float wv, ev;
         row_neighbours(T + (zr + yy) * nx, tc, x, a.nx, lane, wv, ev);
         float4 o;
