@@ -165,8 +165,9 @@ extern "C" {
  *              13, 14 = 1 and 2 rows with streaming (non-temporal) stores
  *                     and loads of P
  *                     (8..14 need nx % 4 == 0);
- *              15 = temporal blocking over 16x16 tiles with the rows of each
- *                     region column in registers (KB_OPT_TDEPTH 1..8).
+ *              15, 16, 17 = temporal blocking over 16x16 tiles with the rows
+ *                     of each region column in registers, 4, 2 or 1 per
+ *                     thread (KB_OPT_TDEPTH 1..8).
  *              Default: 13 if nx % 4 == 0 and ny*nx >= 2^20, else 1.
  *   KB_HEAT3D: 1 = one thread per column; float4 rows (nx % 4 == 0):
  *              2 = plain, 3 = next layer prefetched, 4 = prefetched with

@@ -41,7 +41,7 @@ def kernel_candidates(kb, problem, shape):
     if problem == kb.HEAT2D:
         c = [(v, 1) for v in HEAT2D_DIRECT]
         c += [(v, t) for v in HEAT2D_TILE for t in HEAT2D_DEPTHS]
-        c += [(15, t) for t in HEAT2D_DEPTHS if t <= 8]
+        c += [(v, t) for v in (15, 16, 17) for t in HEAT2D_DEPTHS if t <= 8]
         if shape[1] % 4 == 0:
             c += [(v, 1) for v in HEAT2D_VEC]
         return c

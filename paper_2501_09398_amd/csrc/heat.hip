@@ -132,20 +132,25 @@ static void set_tile(Launch &L, const Heat2DArgs &a) {
 int heat2d_tile_max_depth() { return kMaxDepth; }
 
 // ---------------------------------------------------------------------------
-// Register-strip temporal blocking (variant 15): 16x16 output tiles, t <= 8
-// steps per launch over the tile grown by t cells on each side (at most
-// 32x32, clamped to the grid).  Thread (g, cx) = (tid / 32, tid % 32) keeps
-// rows 4g .. 4g+3 of region column cx in registers: east / west neighbours
-// come from the adjacent lanes of its 32-lane half-wave, north / south from
-// its own registers except at the strip ends, which are exchanged through
-// LDS (double buffered: one barrier per step).  Cells near a cut halo see a
-// clamped neighbour; the error moves inward one cell per step and never
-// reaches the tile.  Same update, same bits as every other variant.
+// Register-strip temporal blocking (variants 15, 16, 17): 16x16 output
+// tiles, t <= 8 steps per launch over the tile grown by t cells on each
+// side (at most 32x32, clamped to the grid).  Thread (g, cx) = (tid / 32,
+// tid % 32) keeps RPT = 4, 2 or 1 rows RPT*g .. RPT*g+RPT-1 of region column
+// cx in registers (256, 512 or 1024 threads): east / west neighbours come
+// from the adjacent lanes by whole-wave DPP shifts (the value that crosses
+// between the two 32-lane halves of a wave lands on a column the clamps
+// replace), north / south from its own registers except at the strip ends,
+// which are exchanged through LDS (double buffered: one barrier per step).
+// Cells near a cut halo see a clamped neighbour; the error moves inward one
+// cell per step and never reaches the tile.  Same update, same bits as
+// every other variant.
 // ---------------------------------------------------------------------------
 constexpr int kStX = 16, kStY = 16, kStMaxDepth = 8;
 
-__global__ __launch_bounds__(256) void heat2d_strip_tb_kernel(const Heat2DArgs a) {
-  __shared__ float ends[2][2][8][32];          // [buffer][top, bottom][group][column]
+template <int RPT>
+__global__ __launch_bounds__(32 * (32 / RPT)) void heat2d_strip_tb_kernel(const Heat2DArgs a) {
+  constexpr int NG = 32 / RPT;                 // row groups
+  __shared__ float ends[2][2][NG][32];         // [buffer][top, bottom][group][column]
   if (a.flag && *a.flag == 0) return;          // predicated launch (whole grid)
   const int t = a.tdepth;
   const int tiles_x = (a.nx + kStX - 1) / kStX, tiles_y = (a.ny + kStY - 1) / kStY;
@@ -156,12 +161,12 @@ __global__ __launch_bounds__(256) void heat2d_strip_tb_kernel(const Heat2DArgs a
   const int rx_lo = max(x0 - t, 0), rx_hi = min(x0 + kStX + t, a.nx);
   const int ry_lo = max(y0 - t, 0), ry_hi = min(y0 + kStY + t, a.ny);
   const int W = rx_hi - rx_lo, H = ry_hi - ry_lo;
-  const int cx = threadIdx.x & 31, g = threadIdx.x >> 5, r0 = 4 * g;
+  const int cx = threadIdx.x & 31, g = threadIdx.x >> 5, r0 = RPT * g;
   const int col = cx < W ? cx : W - 1;
   const size_t nx = (size_t)a.nx;
-  float v[4], pw[4];
+  float v[RPT], pw[RPT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < RPT; ++i) {
     const int r = r0 + i < H ? r0 + i : H - 1;
     const size_t gi = (size_t)(ry_lo + r) * nx + rx_lo + col;
     v[i] = a.T[gi];
@@ -169,44 +174,49 @@ __global__ __launch_bounds__(256) void heat2d_strip_tb_kernel(const Heat2DArgs a
   }
   int b = 0;
   ends[0][0][g][cx] = v[0];
-  ends[0][1][g][cx] = v[3];
+  ends[0][1][g][cx] = v[RPT - 1];
   __syncthreads();
   for (int s = 0; s < t; ++s) {
-    // north of row r0 and south of row r0+3 (clamped at the region edge)
+    // north of row r0 and south of row r0+RPT-1 (clamped at the region edge)
     const float top = g > 0 ? ends[b][1][g - 1][cx] : v[0];
-    const float bot = g < 7 ? ends[b][0][g + 1][cx] : v[3];
-    float nv[4];
+    const float bot = g < NG - 1 ? ends[b][0][g + 1][cx] : v[RPT - 1];
+    float nv[RPT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < RPT; ++i) {
       const int r = r0 + i;
-      float wv = __shfl_up(v[i], 1, 32), ev = __shfl_down(v[i], 1, 32);
+      float wv = lane_west_open(v[i]), ev = lane_east_open(v[i]);
       if (cx == 0) wv = v[i];
       if (cx >= W - 1) ev = v[i];
       const float n = r == 0 ? v[i] : (i == 0 ? top : v[i - 1]);
-      const float so = r >= H - 1 ? v[i] : (i == 3 ? bot : v[i + 1]);
+      const float so = r >= H - 1 ? v[i] : (i == RPT - 1 ? bot : v[i + 1]);
       nv[i] = heat_update(v[i], n, so, wv, ev, pw[i], a.k);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = nv[i];
+    for (int i = 0; i < RPT; ++i) v[i] = nv[i];
     b ^= 1;
     ends[b][0][g][cx] = v[0];
-    ends[b][1][g][cx] = v[3];
+    ends[b][1][g][cx] = v[RPT - 1];
     __syncthreads();
   }
   if (cx < W) {
     const int gx = rx_lo + cx;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < RPT; ++i) {
       const int gy = ry_lo + r0 + i;
       if (r0 + i < H && gy >= y0 && gy < y0 + kStY && gx >= x0 && gx < x0 + kStX) a.out[(size_t)gy * nx + gx] = v[i];
     }
   }
 }
 
-bool make_heat2d_strip(Launch &L, const Heat2DArgs &a) {
+// variant 15: 4 rows per thread, 16: 2, 17: 1
+bool make_heat2d_strip(Launch &L, const Heat2DArgs &a, int variant) {
   if (a.tdepth < 1 || a.tdepth > kStMaxDepth) return false;
   const int nb = ((a.nx + kStX - 1) / kStX) * ((a.ny + kStY - 1) / kStY);
-  L.set((const void *)heat2d_strip_tb_kernel, dim3(xcd_padded_grid(nb)), dim3(256), 0, a);
+  const dim3 grid(xcd_padded_grid(nb));
+  if (variant == 15) L.set((const void *)heat2d_strip_tb_kernel<4>, grid, dim3(256), 0, a);
+  else if (variant == 16) L.set((const void *)heat2d_strip_tb_kernel<2>, grid, dim3(512), 0, a);
+  else if (variant == 17) L.set((const void *)heat2d_strip_tb_kernel<1>, grid, dim3(1024), 0, a);
+  else return false;
   return true;
 }
 int heat2d_strip_max_depth() { return kStMaxDepth; }

@@ -125,21 +125,24 @@ def test_heat2d_tile_variants_bitwise(kb, tile, tdepth):
 
 @pytest.mark.parametrize("shape", [(70, 133), (256, 256), (16, 16), (17, 33), (1, 40), (40, 1), (3, 5), (100, 9)])
 @pytest.mark.parametrize("tdepth", [1, 2, 3, 5, 8])
-def test_heat2d_strip_temporal_variant_bitwise(kb, shape, tdepth):
-    """Variant 15 (16x16 tiles, region columns in registers, strip ends in
-    LDS): same bits as the one-cell kernel for every depth, with a step count
-    that leaves a remainder, per launch and in graph batches; tiles at every
-    edge, grids smaller than a tile, single rows and columns."""
-    announce(f"heat2d strip {shape} t={tdepth}")
+@pytest.mark.parametrize("tile", [15, 16, 17])
+def test_heat2d_strip_temporal_variant_bitwise(kb, shape, tdepth, tile):
+    """Variants 15-17 (16x16 tiles, region columns' rows in registers -- 4,
+    2 or 1 per thread -- strip ends in LDS): same bits as the one-cell
+    kernel for every depth, with a step count that leaves a remainder, per
+    launch and in graph batches; tiles at every edge, grids smaller than a
+    tile, single rows and columns."""
+    announce(f"heat2d strip {shape} variant {tile} t={tdepth}")
     steps = 37
     base = run_heat2d(kb, shape, steps, seed=8)
-    assert np.array_equal(base, run_heat2d(kb, shape, steps, seed=8, tile=15, tdepth=tdepth))
-    assert np.array_equal(base, run_heat2d(kb, shape, steps, b=3, seed=8, tile=15, tdepth=tdepth))
+    assert np.array_equal(base, run_heat2d(kb, shape, steps, seed=8, tile=tile, tdepth=tdepth))
+    assert np.array_equal(base, run_heat2d(kb, shape, steps, b=3, seed=8, tile=tile, tdepth=tdepth))
 
 
-def test_heat2d_strip_depth_limit(kb):
+@pytest.mark.parametrize("tile", [15, 16, 17])
+def test_heat2d_strip_depth_limit(kb, tile):
     with kb.Problem(kb.HEAT2D, (64, 64), coeffs(HEAT), 0) as p:
-        p.set_option(kb.OPT_TILE, 15)
+        p.set_option(kb.OPT_TILE, tile)
         p.set_option(kb.OPT_TDEPTH, 16)
         with pytest.raises(kb.KBError):
             p.run(32, 0)
