@@ -132,8 +132,8 @@ __global__ __launch_bounds__(256) void fdtd_h_vec_kernel(const FdtdArgs f) {
   const float4 ex_j = jup ? ld4(Ex + c + sj) : z4;
   // i+4 (east of the last component): the next lane's first component when
   // it is in the same row, else memory; past the row it is never used.
-  float ey_e = __shfl_down(ey.x, 1, 64);
-  float ez_e = __shfl_down(ez.x, 1, 64);
+  float ey_e = lane_east_open(ey.x);
+  float ez_e = lane_east_open(ez.x);
   if (p.lane == 63 && in && p.i0 + 4 < f.P) {
     ey_e = Ey[c + 4];
     ez_e = Ez[c + 4];
@@ -185,8 +185,8 @@ __global__ __launch_bounds__(256) void fdtd_e_vec_kernel(const FdtdArgs f) {
   const float4 hx_j = jdn ? ld4(Hx + c - sj) : z4;
   // i-1 (west of the first component): the previous lane's last component
   // when it is in the same row, else memory; at i = 0 it is never used.
-  float hz_w = __shfl_up(hz.w, 1, 64);
-  float hy_w = __shfl_up(hy.w, 1, 64);
+  float hz_w = lane_west_open(hz.w);
+  float hy_w = lane_west_open(hy.w);
   if (p.lane == 0 && in && p.i0 > 0) {
     hz_w = Hz[c - 1];
     hy_w = Hy[c - 1];
@@ -278,8 +278,8 @@ __global__ __launch_bounds__(256) void fdtd_h_march_kernel(const FdtdArgs f) {
     const float4 hz = in ? ld4(Hz + c) : z4;
     const float4 ez_j = jup ? ld4(Ez + c + sj) : z4;   // j+1
     const float4 ex_j = jup ? ld4(Ex + c + sj) : z4;
-    float ey_e = __shfl_down(ey.x, 1, 64);
-    float ez_e = __shfl_down(ez.x, 1, 64);
+    float ey_e = lane_east_open(ey.x);
+    float ez_e = lane_east_open(ez.x);
     if (p.lane == 63 && in && p.i0 + 4 < f.P) {
       ey_e = Ey[c + 4];
       ez_e = Ez[c + 4];
@@ -335,8 +335,8 @@ __global__ __launch_bounds__(256) void fdtd_e_march_kernel(const FdtdArgs f) {
     const float4 hz = in ? ld4(Hz + c) : z4;
     const float4 hz_j = jdn ? ld4(Hz + c - sj) : z4;   // j-1
     const float4 hx_j = jdn ? ld4(Hx + c - sj) : z4;
-    float hz_w = __shfl_up(hz.w, 1, 64);
-    float hy_w = __shfl_up(hy.w, 1, 64);
+    float hz_w = lane_west_open(hz.w);
+    float hy_w = lane_west_open(hy.w);
     if (p.lane == 0 && in && p.i0 > 0) {
       hz_w = Hz[c - 1];
       hy_w = Hy[c - 1];
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(256) void fdtd_fused_kernel(const FdtdFusedArgs f) 
     const float4 ex0 = in ? ld4(Ex + cb) : z4;
     const float4 ey0 = in ? ld4(Ey + cb) : z4;
     const float4 ez0_j = jup ? ld4(Ez + cb + sj) : z4;
-    float ez0_e = __shfl_down(ez0.x, 1, 64);
+    float ez0_e = lane_east_open(ez0.x);
     if (p.lane == 63 && in && p.i0 + 4 < f.P) ez0_e = Ez[cb + 4];
     const int k = p.k0 - 1;
 #pragma unroll
@@ -495,9 +495,9 @@ __global__ __launch_bounds__(256) void fdtd_fused_kernel(const FdtdFusedArgs f) 
     const float4 hz_m = jdn ? ld4(Hz + c - sj) : z4;
     const float4 ey_mk = jdn && k < N ? ld4(Ey + c - sj + sk) : z4;
     // i+4 of Ey, Ez (row j) and Ey (row j-1): next lane, else memory
-    float ey_e = __shfl_down(ey.x, 1, 64);
-    float ez_e = __shfl_down(ez.x, 1, 64);
-    float eym_e = __shfl_down(ey_m.x, 1, 64);
+    float ey_e = lane_east_open(ey.x);
+    float ez_e = lane_east_open(ez.x);
+    float eym_e = lane_east_open(ey_m.x);
     if (p.lane == 63 && in && p.i0 + 4 < f.P) {
       ey_e = Ey[c + 4];
       ez_e = Ez[c + 4];
@@ -526,8 +526,8 @@ __global__ __launch_bounds__(256) void fdtd_fused_kernel(const FdtdFusedArgs f) 
       for (int e = 0; e < 4; ++e) hxm[e] = hzm[e] = 0.f;
     }
     // H^{n+1/2} at i0-1 (Hz, Hy): previous lane, else recomputed
-    float hz_w = __shfl_up(hzn[3], 1, 64);
-    float hy_w = __shfl_up(hyn[3], 1, 64);
+    float hz_w = lane_west_open(hzn[3]);
+    float hy_w = lane_west_open(hyn[3]);
     if (p.lane == 0 && in && p.i0 > 0) {
       const int i = p.i0 - 1;
       const size_t w = c - 1;

@@ -18,15 +18,6 @@
 
 namespace kb {
 
-// Value of the neighbouring lane of a full wave, by a DPP wave shift; the
-// lane at the end of the wave reads 0 (callers clamp where that matters).
-__device__ __forceinline__ float lane_west_open(float v) {   // lane - 1 (wave_shr:1)
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float lane_east_open(float v) {   // lane + 1 (wave_shl:1)
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
-}
-
 // ---------------------------------------------------------------------------
 // 2D direct kernel: one thread per cell, 64x4 threads per block.
 // ---------------------------------------------------------------------------
@@ -266,8 +257,8 @@ __device__ __forceinline__ float4 load_row4(const float *base, size_t row, size_
 // West and east neighbours of a lane's four cells in one row.
 __device__ __forceinline__ void row_neighbours(const float *row, const float4 &c, int x, int nx, int lane,
                                                float &wv, float &ev) {
-  wv = __shfl_up(c.w, 1, 64);
-  ev = __shfl_down(c.x, 1, 64);
+  wv = lane_west_open(c.w);
+  ev = lane_east_open(c.x);
   if (lane == 0) wv = x > 0 ? row[x - 1] : c.x;
   if (x + 4 >= nx) ev = c.w;
   else if (lane == 63) ev = row[x + 4];
@@ -877,8 +868,8 @@ __global__ __launch_bounds__(256) void heat2d_multi_strip_kernel(const MultiStri
   const int i1 = min(i0 + kStripRows, ny);
   for (int i = i0; i < i1; ++i) {
     const float down = T[(size_t)(i + 1 < ny ? i + 1 : ny - 1) * nx + jc];
-    float wv = __shfl_up(cur, 1, 64);
-    float ev = __shfl_down(cur, 1, 64);
+    float wv = lane_west_open(cur);
+    float ev = lane_east_open(cur);
     if (lane == 0) wv = jc > 0 ? T[(size_t)i * nx + jc - 1] : cur;
     if (jc >= nx - 1) ev = cur;
     else if (lane == 63) ev = T[(size_t)i * nx + jc + 1];

@@ -77,6 +77,16 @@ __device__ __forceinline__ int xcd_logical_block(int nblocks) {
 
 inline int xcd_padded_grid(int nblocks) { return (nblocks + kXcds - 1) / kXcds * kXcds; }
 
+// Value of the neighbouring lane of a full wave, by a DPP wave shift; the
+// lane at the end of the wave reads 0 (callers clamp where that matters).
+__device__ __forceinline__ float lane_west_open(float v) {   // lane - 1 (wave_shr:1)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_east_open(float v) {   // lane + 1 (wave_shl:1)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+
+
 // ---------------------------------------------------------------------------
 // Kernel argument structs (passed by value).
 // ---------------------------------------------------------------------------
