@@ -153,7 +153,7 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
         }
       if (nbt > ((int64_t)1 << 30)) return false;
       off[20] = L.add(kMtTilings * G * sizeof(GridDesc)); off[21] = L.add(nbt * sizeof(int));
-      off[22] = L.add(64);                  // persistent kernel's barrier
+      off[22] = L.add(kBarWords * sizeof(unsigned));   // persistent kernel's barrier
       common();
       return true;
     }
@@ -889,7 +889,7 @@ int run_persistent(kb_problem *h, int64_t n_steps) {
   a.k = h->hk;
   void *args[] = {&a};
   kb_timing tm{};
-  HIPCHK(hipMemsetAsync(h->grid_bar_d, 0, 3 * sizeof(unsigned), h->stream));
+  HIPCHK(hipMemsetAsync(h->grid_bar_d, 0, kBarWords * sizeof(unsigned), h->stream));
   HIPCHK(hipEventRecord(h->ev0, h->stream));
   if (n_steps > 0) HIPCHK(hipLaunchCooperativeKernel(f, dim3(blocks), dim3(256), args, 0, h->stream));
   HIPCHK(hipEventRecord(h->ev1, h->stream));

@@ -996,20 +996,35 @@ __global__ __launch_bounds__(64 * NW) void heat2d_multi_tb_kernel(const MultiTbA
 // wave first waits until its own stores have reached the L2 (vmcnt 0; on
 // gfx9 this counter covers stores), so after the block barrier one device-
 // scope release by thread 0 writes the whole block's results back from the
-// XCD's L2.  Thread 0 then counts in and waits for the generation to move
-// on, and its device-scope acquire invalidates the CU's L1 and the XCD's
-// L2 for every wave of the block.  A wait longer than spin_limit polls
-// raises the error flag, after which no block waits any more, so the grid
-// always drains (the host then reports the run as failed).
+// XCD's L2.  Arrival is counted in two levels so that no counter takes more
+// than a few dozen atomics per barrier: a block counts in at the counter of
+// its group (blockIdx mod kBarGroups), the group's last block counts in at
+// the top counter, and the last group's block moves the generation on.  The
+// other blocks poll the generation; the device-scope acquire of thread 0
+// then invalidates the CU's L1 and the XCD's L2 for every wave of the block.
+// A wait longer than spin_limit polls raises the error flag, after which no
+// block waits any more, so the grid always drains (the host then reports
+// the run as failed).
 __device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, unsigned spin_limit) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nblocks - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar[1], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    const unsigned groups = nblocks < kBarGroups ? nblocks : kBarGroups;
+    const unsigned g = blockIdx.x % groups;
+    const unsigned members = (nblocks - g + groups - 1) / groups;   // blocks of group g
+    unsigned *sub = bar + kBarStride * (1 + g);
+    bool released = false;
+    if (__hip_atomic_fetch_add(sub, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");           // the group's results
+      __hip_atomic_store(sub, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == groups - 1) {
+        __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&bar[1], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        released = true;
+      }
+    }
+    if (!released) {
       unsigned spins = 0;
       // relaxed polls: an acquiring load would invalidate the XCD's L2 on
       // every poll, under the blocks that are still working

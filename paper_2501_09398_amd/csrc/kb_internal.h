@@ -166,11 +166,16 @@ struct MultiPersistArgs {
   const int *block_grid;           // block tables of those tilings, concatenated
   int tb_start[kMtMaxDepth + 1];   // entries of depth d: tb_start[d-1] .. tb_start[d]
   int G, tdepth, nfull, rem;
-  unsigned *bar;                   // arrivals, generation, error flag: zero at launch
+  unsigned *bar;                   // barrier words (kBarWords), zero at launch
   unsigned spin_limit;             // polls before a barrier wait gives up
   HeatCoef k;
 };
 const void *multi_persistent_fn();
+// The persistent kernel's barrier words: [0] top arrival count, [1]
+// generation, [2] error flag; the group counters at kBarStride * (1 + g),
+// each on its own 128-byte line.
+constexpr unsigned kBarGroups = 8, kBarStride = 32;
+constexpr size_t kBarWords = (size_t)kBarStride * (1 + kBarGroups);
 
 struct SkelArgs {
   float *x; long long n; float a, b;
