@@ -858,12 +858,15 @@ int run_persistent(kb_problem *h, int64_t n_steps) {
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
     // Resident blocks, a multiple of the XCD count (the kernel splits the
-    // tile list into one part per XCD).  Half of what the occupancy query
-    // reports: the query counts registers and LDS but not the scalar
+    // tile list into one part per XCD).  At most half of what the occupancy
+    // query reports: the query counts registers and LDS but not the scalar
     // register file, which limits this kernel (about 106 SGPRs) to 7 waves
     // per SIMD, not the 8 the query assumes; a grid that is not entirely
-    // resident would never pass its first barrier.
-    h->persist_blocks = std::max(1, per_cu / 2) * cus / kXcds * kXcds;
+    // resident would never pass its first barrier.  And at most 2 per CU:
+    // every block adds a writeback and an invalidate to each barrier
+    // (measured at depth 1: 45 us per step with 2 per CU, 54 with 4, 50
+    // with 1; equal at depth 6 for 2 and 4).
+    h->persist_blocks = std::min(2, std::max(1, per_cu / 2)) * cus / kXcds * kXcds;
     if (h->persist_blocks < kXcds) return fail(KB_EHIP, "persistent kernel does not fit the device");
   }
   int most = 0;                                 // tiles of the busiest super-step
