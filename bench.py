@@ -575,6 +575,18 @@ def main():
     bytes_per_launch = N_ELEM * 8                  # read x, write x
     achieved = bytes_per_launch / kern_s / 1e9
     prob.destroy()
+    # the graph-node floor: the same chain on 2^10 elements (4 KB per kernel,
+    # no work to speak of) at the same b, per node from the replay events
+    floor_s = None
+    if b_star > 0:
+        with kb.Problem(kb.SKELETON, (1 << 10,), (K,), SEED, device=0) as q:
+            q.run(ITERS, b_star)
+            q.last_timing()
+            te = []
+            for _ in range(3):
+                q.run(ITERS, b_star)
+                te.append(q.last_timing()["t_exec_s"])
+        floor_s = float(np.median(te)) / n_launch
 
     wl = None
     if not args.no_workloads and args.arm == "both":
@@ -632,7 +644,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
                      "kernel": "skeleton_kernel<4>", "kernel_us": kern_s * 1e6,
-                     "bytes_per_launch": bytes_per_launch},
+                     "bytes_per_launch": bytes_per_launch,
+                     # a launch-bound kernel: its time per graph node against
+                     # the node time of the same chain with no work (2^10)
+                     "node_floor_us": floor_s * 1e6 if floor_s else None,
+                     "frac_of_node_floor": floor_s / kern_s if floor_s else None},
         "cpu_baseline": cpu,
         "workloads": wl,
     }
