@@ -116,7 +116,7 @@ def test_fdtd_source_cell_from_seed(kb):
             assert np.count_nonzero(ez) == 1
 
 
-@pytest.mark.parametrize("N,steps", [(8, 150), (17, 120), (32, 300), (5, 60), (6, 60)])
+@pytest.mark.parametrize("N,steps", [(8, 150), (17, 120), (32, 300), (4, 60), (5, 60), (6, 60)])
 @pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 def test_fdtd_bitwise_vs_oracle(kb, N, steps, variant):
     announce(f"fdtd N={N} steps={steps} variant={variant}")
