@@ -224,8 +224,10 @@ extern "C" {
  *   E.E and H.H over the six FDTD fields.  Entry e of KB_F_REDLOG is
  *   {(e+1)*m, value, second value or 0, 0}; KB_F_REDCOUNT counts entries.
  *   Setting the option (also to 0 = off, the default) restarts the step
- *   count and empties the log.  Needs one step per iteration (no temporal
- *   blocking); not for KB_HEAT2D_SURROGATE.  Each graph batch is built for
+ *   count and empties the log.  With temporal blocking (t steps per
+ *   iteration) m, n_steps and the steps run since the option was set must
+ *   be multiples of t, so that every reduction point ends an iteration;
+ *   not for KB_HEAT2D_SURROGATE.  Each graph batch is built for
  *   its start phase (steps since the last reduction point), so b need not
  *   divide m; at most 64 distinct batch graphs per kb_run.  Results are
  *   bitwise independent of b and of the builder.                          */

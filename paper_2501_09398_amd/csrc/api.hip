@@ -925,8 +925,11 @@ int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b) {
     return fail(KB_EINVAL, "batch of %lld iterations x %d kernels exceeds %lld graph nodes", (long long)batch_b, h->K,
                 (long long)h->max_nodes);
 
-  if (h->red_every > 0 && (depth != 1 || rem_steps != 0))
-    return fail(KB_EINVAL, "in-chain reductions need one step per iteration (no temporal blocking)");
+  // in-chain reductions: every reduction point (a multiple of m steps since
+  // the option was set) must fall on an iteration boundary
+  if (h->red_every > 0 && (rem_steps != 0 || h->red_every % depth != 0 || h->step_count % depth != 0))
+    return fail(KB_EINVAL, "in-chain reductions need m and the steps run so far to be multiples of the "
+                           "temporal depth %d, and n_steps too", depth);
 
   // Replay j starts from buffer parity cur_j and phase ph_j = steps since
   // the last reduction point; both are periodic in j, and each distinct

@@ -109,13 +109,45 @@ def test_reduction_option_resets_and_switches_off(kb):
         assert p.reduction_log().shape[0] == 0
 
 
-def test_reduction_rejects_temporal_blocking_and_surrogate(kb):
+@pytest.mark.parametrize("problem,shape,tile,t,b", [
+    ("HEAT2D", (64, 72), 6, 4, 0), ("HEAT2D", (64, 72), 16, 4, 3), ("HEAT3D", (8, 40, 70), 11, 2, 5),
+    ("HEAT2D_MULTI", [3, 100, 90, 64, 64, 17, 150], 3, 4, 2)])
+def test_reduction_log_with_temporal_blocking(kb, problem, shape, tile, t, b):
+    """With t steps per iteration and m a multiple of t, every reduction
+    point ends an iteration: the log equals the one-step kernels' bit for
+    bit (same states, same fixed-order sums), per launch and in graphs."""
+    announce(f"reductions with temporal blocking {problem} variant {tile} t={t} b={b}")
+    prob = getattr(kb, problem)
+    m, n = 8, 96
+    logs = []
+    for v, d, bb in ((1 if problem != "HEAT2D_MULTI" else 2, 1, 0), (tile, t, b)):
+        with kb.Problem(prob, shape, HEAT, 5) as p:
+            p.set_option(kb.OPT_TILE, v)
+            p.set_option(kb.OPT_TDEPTH, d)
+            p.set_option(kb.OPT_REDUCE_EVERY, m)
+            p.run(40, bb)
+            p.run(56, bb)
+            logs.append(p.reduction_log())
+    assert logs[0].shape == (n // m, 4)
+    assert np.array_equal(logs[0], logs[1])
+
+
+def test_reduction_rejects_misaligned_temporal_blocking_and_surrogate(kb):
     with kb.Problem(kb.HEAT2D, (64, 64), HEAT, 5) as p:
         p.set_option(kb.OPT_TILE, 6)
         p.set_option(kb.OPT_TDEPTH, 4)
-        p.set_option(kb.OPT_REDUCE_EVERY, 8)
+        p.set_option(kb.OPT_REDUCE_EVERY, 6)          # not a multiple of t
         with pytest.raises(kb.KBError):
             p.run(16, 0)
+        p.set_option(kb.OPT_REDUCE_EVERY, 8)
+        with pytest.raises(kb.KBError):
+            p.run(18, 0)                                # leaves single steps
+        p.run(16, 0)
+        p.set_option(kb.OPT_TDEPTH, 1)
+        p.run(2, 0)                                     # 18 steps so far
+        p.set_option(kb.OPT_TDEPTH, 4)
+        with pytest.raises(kb.KBError):
+            p.run(8, 0)                                 # iterations off the grid of t
     with kb.Problem(kb.HEAT2D_SURROGATE, (64, 64), HEAT, 5) as p:
         with pytest.raises(kb.KBError):
             p.set_option(kb.OPT_REDUCE_EVERY, 8)
