@@ -89,7 +89,9 @@ extern "C" {
  *   initial: all fields zero.
  *
  * KB_HEAT2D_MULTI  (many independent 2D grids of uneven sizes advanced
- *   together, one kernel per step over all grids)
+ *   together: one kernel per iteration over all grids, an iteration being
+ *   one step or, with temporal blocking, KB_OPT_TDEPTH steps; or all steps
+ *   in one persistent launch, KB_OPT_PERSISTENT)
  *   shape  = {G, ny_0, nx_0, ny_1, nx_1, ...}; coeffs as KB_HEAT2D.
  *   fields : KB_F_T, KB_F_P as the concatenation of the grids, row-major each.
  *   initial: grid g draws its cells at flat offset sum_{h<g} ny_h*nx_h of the
