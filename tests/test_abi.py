@@ -19,6 +19,10 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def kb():
     import paper_2501_09398_amd as kb
+    if not os.path.exists(kb.LIB_PATH):
+        # a fresh checkout: hipcc cross-compiles gfx950 without a GPU
+        from paper_2501_09398_amd import build
+        build.build()
     try:
         kb.lib()
     except ImportError as e:
