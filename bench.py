@@ -483,8 +483,8 @@ def workloads(kb, pm, autotune, np):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU decomposition is described in DESIGN.md but not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(a decomposition over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.stream_calibration:
         stream_calibration()
