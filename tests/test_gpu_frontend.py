@@ -97,3 +97,4 @@ def test_tune_picks_an_admissible_batch(torch):
     assert torch.equal(x, x_ref)
     print(f"per launch {t_e * 1e3:.2f} ms, batched b={res['b']} {t_g * 1e3:.2f} ms")
     assert t_g < t_e
+
