@@ -612,10 +612,17 @@ def main():
 
     us_iter_graph = float(np.mean(graph_T)) / ITERS * 1e6
     per_launch = None
+    crossover = None
     if base_T:
         per_launch = {"us_per_iter": float(np.mean(base_T)) / ITERS * 1e6,
                       "us_per_iter_device": float(np.mean(base_TE)) / ITERS * 1e6,
                       "gcell_upd_s": elem_updates / float(np.mean(base_T)) / 1e9}
+        # crossover: the number of graph launches (iteration batches of b)
+        # after which building the graph has paid for itself, T_C over the
+        # saving per batch (the paper reports 2-3 batches on the A100)
+        save_per_iter = (float(np.mean(base_TE)) - float(np.mean(graph_TE))) / ITERS
+        if b_star > 0 and save_per_iter > 0:
+            crossover = float(np.mean(graph_TC)) / (b_star * save_per_iter)
     line = {
         "metric": "µs/iter & Gcell-upd/s: hipGraph batch-b vs per-launch; % HBM peak",
         "value": value,
@@ -639,7 +646,7 @@ def main():
                       "t_create_ms": float(np.mean(graph_TC)) * 1e3,
                       "gcell_upd_s": elem_updates / float(np.mean(graph_T)) / 1e9},
             "per_launch": per_launch,
-            "speedup": sp, "speedup_err": sp_err,
+            "speedup": sp, "speedup_err": sp_err, "crossover_batches": crossover,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
