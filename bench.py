@@ -119,7 +119,7 @@ def kernel_only(name):
 # (reads, writes) of the kernels whose HBM fraction the benchmark reports:
 # copy; heat2d (T, P -> T); FDTD H or E kernel (6 -> 3); fused FDTD step
 # (6 -> 6); a wider read-heavy mix
-STREAM_MIXES = ((1, 1), (2, 1), (3, 1), (2, 2), (3, 3), (6, 3), (6, 6), (8, 1))
+STREAM_MIXES = ((1, 1), (2, 1), (3, 1), (2, 2), (3, 3), (6, 3), (6, 6), (8, 1), (8, 8))
 
 
 def stream_calibration():
