@@ -84,6 +84,8 @@ KERNEL_RUNS = {
     "multigrid_64": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 2, 10),
     "multigrid_64_cell": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 1, 10),
     "multigrid_64_tb": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 3, 60, 6),    # 10 launches of 6 steps
+    "heat2d_16384_region": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 19, 30, 6),   # 5 launches of 6 steps
+    "heat3d_8x4096_strip_tb": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 11, 20, 4),   # 5 launches of 4
 }
 
 
@@ -471,6 +473,28 @@ def workloads(kb, pm, autotune, np):
         cells = int(np.prod(shp))
         gbs = bytes_per_cell * cells / t / 1e9
         big[name] = {"us_step": t * 1e6, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS, "gcell_upd_s": cells / t / 1e9}
+    # the same grids with temporal blocking: t steps per launch from one read
+    # of T and P and one write of T, so the one-step roofline above no longer
+    # bounds the step; frac is the kernel's own bytes per launch over its
+    # duration, effective_frac the one-step bytes per step over the step time
+    for name, prob, shp, cands, bytes_per_cell in (
+            ("heat2d_16384^2", kb.HEAT2D, (16384, 16384), [(18, 6), (18, 8), (19, 6), (19, 8)], 12.0),
+            ("heat2d_8192^2", kb.HEAT2D, (8192, 8192), [(18, 6), (18, 8), (19, 6), (19, 8)], 12.0),
+            ("heat3d_8x4096^2", kb.HEAT3D, (8, 4096, 4096), [(11, 2), (11, 3), (11, 4), (11, 6)], 8.5)):
+        cells = int(np.prod(shp))
+        rows = []
+        with kb.Problem(prob, shp, kb.HEAT_COEFFS, SEED) as p:
+            for v, t in cands:
+                p.set_option(kb.OPT_TILE, v)
+                p.set_option(kb.OPT_TDEPTH, t)
+                rows.append((arm(p, 24, 0, 2) / 24, v, t))
+        ts, v, t = min(rows)
+        gbs = bytes_per_cell * cells / (ts * t) / 1e9
+        big[f"{name}_temporal"] = {"variant": v, "depth": t, "us_step": ts * 1e6, "gcell_upd_s": cells / ts / 1e9,
+                                   "speedup_vs_one_step": big[name]["us_step"] / (ts * 1e6),
+                                   "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS,
+                                   "effective_frac": bytes_per_cell * cells / ts / 1e9 / HBM_PEAK_GBS,
+                                   "tried": [{"variant": vv, "depth": tt, "us_step": x * 1e6} for x, vv, tt in rows]}
     d = out["fdtd_256^3_2000"]
     for name in ("separate", "fused"):
         big[f"fdtd_256^3_{name}"] = {"us_step": d[f"{name}_graph_b100_us_step"], "frac": d[f"{name}_hbm_frac"],

@@ -169,7 +169,11 @@ extern "C" {
  *                     (8..14 need nx % 4 == 0);
  *              15, 16, 17 = temporal blocking over 16x16 tiles with the rows
  *                     of each region column in registers, 4, 2 or 1 per
- *                     thread (KB_OPT_TDEPTH 1..8).
+ *                     thread (KB_OPT_TDEPTH 1..8);
+ *              18, 19 = temporal blocking over regions of 64 columns x 64
+ *                     or 128 rows, a wave holding 16 rows of one column
+ *                     per lane in registers (KB_OPT_TDEPTH 1..8; the
+ *                     many-grid problem's variants 3 and 4 on one grid).
  *              Default: 13 if nx % 4 == 0 and ny*nx >= 2^20, else 1.
  *   KB_HEAT3D: 1 = one thread per column; float4 rows (nx % 4 == 0):
  *              2 = plain, 3 = next layer prefetched, 4 = prefetched with

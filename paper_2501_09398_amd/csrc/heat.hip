@@ -925,13 +925,14 @@ __device__ __forceinline__ void multi_tb_advance(float (&v)[kMtRows], const floa
   }
 }
 
-// One tile of the many-grid temporal blocking: load, t steps, store.  ends:
-// the block's LDS strip-end buffers [buffer][top, bottom][wave][column].
+// One temporal-blocking tile of grid `gd` (tile number `local` within the
+// grid): load, t steps, store.  ends: the block's LDS strip-end buffers
+// [buffer][top, bottom][wave][column].
 template <int NW>
-__device__ __forceinline__ void multi_tb_tile(const MultiTbArgs &a, int lb, float (*ends)[2][NW][kMtRegionX]) {
-  const GridDesc gd = a.grids[a.block_grid[lb]];
-  const int t = a.tdepth, tile_x = kMtRegionX - 2 * t, tile_y = kMtRows * NW - 2 * t;
-  const int local = lb - gd.block0;
+__device__ __forceinline__ void region_tb_tile(const GridDesc &gd, int local, const float *__restrict__ Tg,
+                                               float *__restrict__ Og, const float *__restrict__ Pg, int t,
+                                               const HeatCoef &k, float (*ends)[2][NW][kMtRegionX]) {
+  const int tile_x = kMtRegionX - 2 * t, tile_y = kMtRows * NW - 2 * t;
   const int x0 = (local % gd.tiles_x) * tile_x, y0 = (local / gd.tiles_x) * tile_y;
   const int rx_lo = max(x0 - t, 0), rx_hi = min(x0 + tile_x + t, gd.nx);
   const int ry_lo = max(y0 - t, 0), ry_hi = min(y0 + tile_y + t, gd.ny);
@@ -942,8 +943,8 @@ __device__ __forceinline__ void multi_tb_tile(const MultiTbArgs &a, int lb, floa
   const int col = cx < W ? cx : W - 1;
   const unsigned nx = (unsigned)gd.nx;
   const size_t base = (size_t)gd.off + (size_t)ry_lo * nx + rx_lo;
-  const float *T = a.T + base;
-  const float *P = a.P + base;
+  const float *T = Tg + base;
+  const float *P = Pg + base;
   float v[kMtRows], pw[kMtRows];
 #pragma unroll
   for (int i = 0; i < kMtRows; ++i) {
@@ -956,18 +957,18 @@ __device__ __forceinline__ void multi_tb_tile(const MultiTbArgs &a, int lb, floa
   ends[0][1][w][cx] = v[kMtRows - 1];
   __syncthreads();
   switch ((rx_lo == 0) | (rx_hi == gd.nx) << 1 | (ry_hi == gd.ny) << 2) {
-    case 0: multi_tb_advance<NW, false, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 1: multi_tb_advance<NW, true, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 2: multi_tb_advance<NW, false, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 3: multi_tb_advance<NW, true, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 4: multi_tb_advance<NW, false, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 5: multi_tb_advance<NW, true, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 6: multi_tb_advance<NW, false, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    default: multi_tb_advance<NW, true, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 0: multi_tb_advance<NW, false, false, false>(v, pw, ends, t, W, H, cx, w, k); break;
+    case 1: multi_tb_advance<NW, true, false, false>(v, pw, ends, t, W, H, cx, w, k); break;
+    case 2: multi_tb_advance<NW, false, true, false>(v, pw, ends, t, W, H, cx, w, k); break;
+    case 3: multi_tb_advance<NW, true, true, false>(v, pw, ends, t, W, H, cx, w, k); break;
+    case 4: multi_tb_advance<NW, false, false, true>(v, pw, ends, t, W, H, cx, w, k); break;
+    case 5: multi_tb_advance<NW, true, false, true>(v, pw, ends, t, W, H, cx, w, k); break;
+    case 6: multi_tb_advance<NW, false, true, true>(v, pw, ends, t, W, H, cx, w, k); break;
+    default: multi_tb_advance<NW, true, true, true>(v, pw, ends, t, W, H, cx, w, k); break;
   }
   const int gx = rx_lo + cx;
   if (cx < W && gx >= x0 && gx < x0 + tile_x) {
-    float *O = a.out + base;
+    float *O = Og + base;
 #pragma unroll
     for (int i = 0; i < kMtRows; ++i) {
       const int gy = ry_lo + r0 + i;
@@ -976,12 +977,50 @@ __device__ __forceinline__ void multi_tb_tile(const MultiTbArgs &a, int lb, floa
   }
 }
 
+// The tile of many-grid block lb.
+template <int NW>
+__device__ __forceinline__ void multi_tb_tile(const MultiTbArgs &a, int lb, float (*ends)[2][NW][kMtRegionX]) {
+  const GridDesc gd = a.grids[a.block_grid[lb]];
+  region_tb_tile<NW>(gd, lb - gd.block0, a.T, a.out, a.P, a.tdepth, a.k, ends);
+}
+
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void heat2d_multi_tb_kernel(const MultiTbArgs a) {
   __shared__ float ends[2][2][NW][kMtRegionX];
   const int lb = xcd_logical_block(a.nb);
   if (lb >= a.nb) return;
   multi_tb_tile<NW>(a, lb, ends);
+}
+
+// One large grid with the same region tiles (variants 18 and 19): the
+// tiling of a single grid of the many-grid kernel, with no tables.  Honours
+// the run flag of the tile kernels.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void heat2d_region_tb_kernel(const Heat2DArgs a) {
+  __shared__ float ends[2][2][NW][kMtRegionX];
+  if (a.flag && *a.flag == 0) return;
+  const int t = a.tdepth;
+  const int tiles_x = (a.nx + multi_tb_tile_x(t) - 1) / multi_tb_tile_x(t);
+  const int tiles_y = (a.ny + kMtRows * NW - 2 * t - 1) / (kMtRows * NW - 2 * t);
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const GridDesc gd{0, a.ny, a.nx, tiles_x, 0};
+  region_tb_tile<NW>(gd, lb, a.T, a.out, a.P, t, a.k, ends);
+}
+
+// variant 18: 64 x 64 regions (4 waves), 19: 64 x 128 (8 waves)
+bool make_heat2d_region(Launch &L, const Heat2DArgs &a, int variant) {
+  if (a.tdepth < 1 || a.tdepth > kMtMaxDepth) return false;
+  const int nw = variant == 19 ? 8 : 4;
+  const long long tiles_x = (a.nx + multi_tb_tile_x(a.tdepth) - 1) / multi_tb_tile_x(a.tdepth);
+  const long long tiles_y = (a.ny + kMtRows * nw - 2 * a.tdepth - 1) / (kMtRows * nw - 2 * a.tdepth);
+  if (tiles_x * tiles_y > (1LL << 30)) return false;
+  const dim3 grid(xcd_padded_grid((int)(tiles_x * tiles_y)));
+  if (variant == 18) L.set((const void *)heat2d_region_tb_kernel<4>, grid, dim3(256), 0, a);
+  else if (variant == 19) L.set((const void *)heat2d_region_tb_kernel<8>, grid, dim3(512), 0, a);
+  else return false;
+  return true;
 }
 
 // ---------------------------------------------------------------------------

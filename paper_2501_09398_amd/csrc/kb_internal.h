@@ -217,7 +217,8 @@ void make_init(Launch &L, const InitArgs &a);
 void make_heat2d_direct(Launch &L, const Heat2DArgs &a);
 bool make_heat2d_tile(Launch &L, const Heat2DArgs &a, int variant);   // false: bad variant
 int heat2d_tile_max_depth();
-bool make_heat2d_strip(Launch &L, const Heat2DArgs &a, int variant);  // 15-17; false: depth > 8
+bool make_heat2d_strip(Launch &L, const Heat2DArgs &a, int variant);
+bool make_heat2d_region(Launch &L, const Heat2DArgs &a, int variant);  // 15-17; false: depth > 8
 int heat2d_strip_max_depth();
 bool make_heat3d(Launch &L, const Heat3DArgs &a, int variant);   // false: bad variant
 bool make_heat2d_vec(Launch &L, const Heat2DArgs &a, int variant);  // false: bad variant / nx % 4

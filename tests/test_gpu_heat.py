@@ -148,6 +148,52 @@ def test_heat2d_strip_depth_limit(kb, tile):
             p.run(32, 0)
 
 
+@pytest.mark.parametrize("shape", [(70, 133), (256, 256), (130, 300), (64, 64), (1, 40), (40, 1), (3, 5), (257, 49)])
+@pytest.mark.parametrize("tdepth", [1, 2, 3, 6, 8])
+@pytest.mark.parametrize("tile", [18, 19])
+def test_heat2d_region_temporal_variant_bitwise(kb, shape, tdepth, tile):
+    """Variants 18 and 19 (regions of 64 columns x 64 or 128 rows, 16 rows
+    of a column per lane in registers, strip ends in LDS): same bits as the
+    one-cell kernel for every depth, with a step count that leaves a
+    remainder, per launch and in graph batches; regions cut at every edge,
+    grids smaller than a region, single rows and columns; within 1e-5 of
+    the float32 oracle."""
+    announce(f"heat2d region {shape} variant {tile} t={tdepth}")
+    steps = 37
+    base = run_heat2d(kb, shape, steps, seed=9)
+    assert np.array_equal(base, run_heat2d(kb, shape, steps, seed=9, tile=tile, tdepth=tdepth))
+    assert np.array_equal(base, run_heat2d(kb, shape, steps, b=3, seed=9, tile=tile, tdepth=tdepth))
+    T0, P = synth.heat2d_init(9, *shape)
+    assert rel_maxnorm(base, oracle.heat2d(T0, P, steps, dtype=np.float32)) < 1e-5
+
+
+@pytest.mark.parametrize("tile,tdepth", [(18, 8), (19, 6)])
+def test_heat2d_region_large_grid(kb, tile, tdepth):
+    """A large-grid case (8192^2, 256 MiB per field) in the launch shape the
+    large-grid benchmark times: 13 steps as full-depth launches of the
+    region kernel plus the remainder, bit-identical to the streaming
+    one-step kernel, and sampled rows within 1e-5 of the float32 oracle
+    (13 steps only reach 13 rows, so the first 20 rows of the grid are an
+    exact sub-problem of the full one)."""
+    announce(f"heat2d region 8192^2 variant {tile} t={tdepth}")
+    shape, steps = (8192, 8192), 13
+    base = run_heat2d(kb, shape, steps, seed=10, tile=13)
+    got = run_heat2d(kb, shape, steps, seed=10, tile=tile, tdepth=tdepth)
+    assert np.array_equal(base, got)
+    T0, P = synth.heat2d_init(10, *shape)
+    ref = oracle.heat2d(np.ascontiguousarray(T0[:40]), np.ascontiguousarray(P[:40]), steps, dtype=np.float32)
+    assert rel_maxnorm(got[:20], ref[:20]) < 1e-5
+
+
+@pytest.mark.parametrize("tile", [18, 19])
+def test_heat2d_region_depth_limit(kb, tile):
+    with kb.Problem(kb.HEAT2D, (64, 64), coeffs(HEAT), 0) as p:
+        p.set_option(kb.OPT_TILE, tile)
+        p.set_option(kb.OPT_TDEPTH, 9)
+        with pytest.raises(kb.KBError):
+            p.run(18, 0)
+
+
 @pytest.mark.parametrize("shape", [(70, 132), (33, 260), (5, 4), (1, 4), (4, 8), (130, 1024), (9, 516)])
 @pytest.mark.parametrize("tile", [8, 9, 10, 11, 12, 13, 14])
 def test_heat2d_vector_variants_bitwise(kb, shape, tile):
