@@ -84,7 +84,7 @@ KERNEL_RUNS = {
     "multigrid_64": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 2, 10),
     "multigrid_64_cell": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 1, 10),
     "multigrid_64_tb": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 3, 60, 6),    # 10 launches of 6 steps
-    "heat2d_16384_region": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 19, 30, 6),   # 5 launches of 6 steps
+    "heat2d_16384_region": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 21, 40, 8),   # 5 launches of 8 steps
     "heat3d_8x4096_strip_tb": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 11, 20, 4),   # 5 launches of 4
 }
 
@@ -478,8 +478,8 @@ def workloads(kb, pm, autotune, np):
     # bounds the step; frac is the kernel's own bytes per launch over its
     # duration, effective_frac the one-step bytes per step over the step time
     for name, prob, shp, cands, bytes_per_cell in (
-            ("heat2d_16384^2", kb.HEAT2D, (16384, 16384), [(18, 6), (18, 8), (19, 6), (19, 8)], 12.0),
-            ("heat2d_8192^2", kb.HEAT2D, (8192, 8192), [(18, 6), (18, 8), (19, 6), (19, 8)], 12.0),
+            ("heat2d_16384^2", kb.HEAT2D, (16384, 16384), [(19, 6), (19, 8), (20, 6), (20, 8), (21, 6), (21, 8)], 12.0),
+            ("heat2d_8192^2", kb.HEAT2D, (8192, 8192), [(19, 6), (19, 8), (20, 6), (20, 8), (21, 6), (21, 8)], 12.0),
             ("heat3d_8x4096^2", kb.HEAT3D, (8, 4096, 4096), [(11, 2), (11, 3), (11, 4), (11, 6)], 8.5)):
         cells = int(np.prod(shp))
         rows = []

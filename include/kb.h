@@ -173,7 +173,9 @@ extern "C" {
  *              18, 19 = temporal blocking over regions of 64 columns x 64
  *                     or 128 rows, a wave holding 16 rows of one column
  *                     per lane in registers (KB_OPT_TDEPTH 1..8; the
- *                     many-grid problem's variants 3 and 4 on one grid).
+ *                     many-grid problem's variants 3 and 4 on one grid);
+ *              20, 21 = the same over regions of 128 columns x 64 or 128
+ *                     rows, two columns per lane (KB_OPT_TDEPTH 1..8).
  *              Default: 13 if nx % 4 == 0 and ny*nx >= 2^20, else 1.
  *   KB_HEAT3D: 1 = one thread per column; float4 rows (nx % 4 == 0):
  *              2 = plain, 3 = next layer prefetched, 4 = prefetched with
@@ -204,7 +206,8 @@ extern "C" {
  *              (KB_OPT_TDEPTH steps per launch, 1..8) over regions of 64
  *              columns x 64 (3) or 128 (4) rows around output tiles of
  *              (64-2t) x (64-2t or 128-2t) cells, each region column's
- *              rows in registers.
+ *              rows in registers; 5, 6 = the same over regions of 128
+ *              columns x 64 (5) or 128 (6) rows, two columns per lane.
  *   KB_HEAT2D_SURROGATE: 1 = fused network, all activations in LDS, 3
  *              kernels per block (default); 2 = one kernel per layer with
  *              activations in HBM, 8 kernels per block.  The two agree to

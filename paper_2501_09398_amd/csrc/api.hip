@@ -147,7 +147,7 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
       int64_t nbt = 0;
       for (int sh = 0; sh < kMtShapes; ++sh)
         for (int t = 1; t <= kMtMaxDepth; ++t) {
-          const int64_t tx = multi_tb_tile_x(t), ty = multi_tb_tile_y(sh, t);
+          const int64_t tx = multi_tb_tile_x(sh, t), ty = multi_tb_tile_y(sh, t);
           for (int64_t g = 0; g < G; ++g)
             nbt += ((shape[2 + 2 * g] + tx - 1) / tx) * ((shape[1 + 2 * g] + ty - 1) / ty);
         }
@@ -204,10 +204,12 @@ int heat3d_variant(const kb_problem *h) {
   if (h->tile != 0) return h->tile;
   return (h->nx % 4 == 0 && h->ny * h->nx >= (1 << 20)) ? 6 : 1;
 }
-bool heat2d_is_tile(int v) { return (v >= 2 && v <= 7) || (v >= 15 && v <= 19); }   // temporal blocking
+bool heat2d_is_tile(int v) { return (v >= 2 && v <= 7) || (v >= 15 && v <= 21); }   // temporal blocking
 
-// Many-grid variants 3 and 4 (and the default, 3) block in time.
-bool multi_is_tb(const kb_problem *h) { return h->tile == 0 || h->tile == 3 || h->tile == 4; }
+// Many-grid variants 3 to 6 (and the default, 3) block in time.
+bool multi_is_tb(const kb_problem *h) { return h->tile == 0 || (h->tile >= 3 && h->tile <= 6); }
+// Their region shapes: variant 3 -> 0, 4 -> 1, 5 -> 2, 6 -> 3.
+int multi_tb_shape(const kb_problem *h) { return h->tile >= 4 ? h->tile - 3 : 0; }
 
 // Temporal depth of one iteration.
 int iter_depth(const kb_problem *h) {
@@ -289,7 +291,7 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
         make_multi(L[0], a, h->total_blocks);
       } else if (multi_is_tb(h)) {
         if (depth < 1 || depth > kMtMaxDepth) return -1;
-        const int sh = h->tile == 4 ? 1 : 0, q = multi_tb_index(sh, depth);
+        const int sh = multi_tb_shape(h), q = multi_tb_index(sh, depth);
         MultiTbArgs a{h->Tbuf[cur], h->Tbuf[1 - cur], h->P, h->grids_tb_d + (size_t)q * h->G,
                       h->block_grid_tb_d + h->tb_start[q], h->tb_start[q + 1] - h->tb_start[q], depth, h->hk};
         make_multi_tb(L[0], a, sh);
@@ -665,7 +667,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       std::vector<int> bgt;
       for (int sh = 0; sh < kMtShapes; ++sh)
         for (int t = 1; t <= kMtMaxDepth; ++t) {
-          const int q = multi_tb_index(sh, t), tile_x = multi_tb_tile_x(t), tile_y = multi_tb_tile_y(sh, t);
+          const int q = multi_tb_index(sh, t), tile_x = multi_tb_tile_x(sh, t), tile_y = multi_tb_tile_y(sh, t);
           h->tb_start[q] = (int)bgt.size();
           for (int g = 0; g < h->G; ++g) {
             const int tx = (gd[g].nx + tile_x - 1) / tile_x, ty = (gd[g].ny + tile_y - 1) / tile_y;
@@ -778,14 +780,14 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
     case KB_OPT_TILE: {
       bool ok = false;
       if (h->kind == KB_HEAT2D)
-        ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0) || (value >= 15 && value <= 19);
+        ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0) || (value >= 15 && value <= 21);
       else if (h->kind == KB_HEAT3D)
         ok = value == 0 || value == 1 || (((value >= 2 && value <= 4) || (value >= 6 && value <= 10)) && h->nx % 4 == 0) ||
              ((value == 5 || value == 11) && h->nz <= 8);
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
       else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 7;
       else if (h->kind == KB_HEAT2D_SURROGATE) ok = value >= 0 && value <= 2;
-      else if (h->kind == KB_HEAT2D_MULTI) ok = value >= 0 && value <= 4;
+      else if (h->kind == KB_HEAT2D_MULTI) ok = value >= 0 && value <= 6;
       else ok = value == 0;
       if (!ok) return fail(KB_EINVAL, "kernel variant %lld not available for this problem", (long long)value);
       if (h->tile != value) clear_cache(h);

@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(64 * NW) void heat2d_region_tb_kernel(const Heat2DA
   __shared__ float ends[2][2][NW][kMtRegionX];
   if (a.flag && *a.flag == 0) return;
   const int t = a.tdepth;
-  const int tiles_x = (a.nx + multi_tb_tile_x(t) - 1) / multi_tb_tile_x(t);
+  const int tiles_x = (a.nx + multi_tb_tile_x(0, t) - 1) / multi_tb_tile_x(0, t);
   const int tiles_y = (a.ny + kMtRows * NW - 2 * t - 1) / (kMtRows * NW - 2 * t);
   const int nb = tiles_x * tiles_y;
   const int lb = xcd_logical_block(nb);
@@ -1009,16 +1009,150 @@ __global__ __launch_bounds__(64 * NW) void heat2d_region_tb_kernel(const Heat2DA
   region_tb_tile<NW>(gd, lb, a.T, a.out, a.P, t, a.k, ends);
 }
 
-// variant 18: 64 x 64 regions (4 waves), 19: 64 x 128 (8 waves)
+// Regions two columns per lane wide (variants 20 and 21): 128 columns x
+// 16*NW rows, lane cx holding region columns 2cx and 2cx+1 of 16 rows.  The
+// wider region recomputes fewer halo cells per output cell (at t = 6,
+// 128 x 128 regions around 116 x 116 tiles instead of 64 x 128 around
+// 52 x 116), and the two columns of a lane are each other's east / west
+// neighbours, so a cell pair needs two lane shifts instead of four.  The
+// clamps and the strip-end exchange are those of the one-column regions.
+constexpr int kRg2X = 128;
+
+template <int NW, bool CW, bool CE, bool CS>
+__device__ __forceinline__ void region2_advance(float (&v0)[kMtRows], float (&v1)[kMtRows],
+                                                const float (&p0)[kMtRows], const float (&p1)[kMtRows],
+                                                float (*ends)[2][NW][kRg2X], int t, int W, int H, int cx,
+                                                int w, const HeatCoef &k) {
+  const int last = H - 1 - kMtRows * w;
+  const int c0 = 2 * cx, c1 = 2 * cx + 1;
+  int b = 0;
+  for (int s = 0; s < t; ++s) {
+    float prev0 = w > 0 ? ends[b][1][w - 1][c0] : v0[0];
+    float prev1 = w > 0 ? ends[b][1][w - 1][c1] : v1[0];
+    const float bot0 = w < NW - 1 ? ends[b][0][w + 1][c0] : v0[kMtRows - 1];
+    const float bot1 = w < NW - 1 ? ends[b][0][w + 1][c1] : v1[kMtRows - 1];
+#pragma unroll
+    for (int i = 0; i < kMtRows; ++i) {
+      const float a0 = v0[i], a1 = v1[i];
+      float s0 = i == kMtRows - 1 ? bot0 : v0[i + 1];
+      float s1 = i == kMtRows - 1 ? bot1 : v1[i + 1];
+      if (CS && i == last) {
+        s0 = a0;
+        s1 = a1;
+      }
+      float w0 = lane_west_open(a1), e1 = lane_east_open(a0);
+      float e0 = a1;
+      if (CW && cx == 0) w0 = a0;
+      if (CE && c0 >= W - 1) e0 = a0;
+      if (CE && c1 >= W - 1) e1 = a1;
+      const float n0 = prev0, n1 = prev1;
+      prev0 = a0;
+      prev1 = a1;
+      v0[i] = heat_update(a0, n0, s0, w0, e0, p0[i], k);
+      v1[i] = heat_update(a1, n1, s1, a0, e1, p1[i], k);
+    }
+    b ^= 1;
+    ends[b][0][w][c0] = v0[0];
+    ends[b][0][w][c1] = v1[0];
+    ends[b][1][w][c0] = v0[kMtRows - 1];
+    ends[b][1][w][c1] = v1[kMtRows - 1];
+    __syncthreads();
+  }
+}
+
+template <int NW>
+__device__ __forceinline__ void region2_tile(const GridDesc &gd, int local, const float *__restrict__ Tg,
+                                             float *__restrict__ Og, const float *__restrict__ Pg, int t,
+                                             const HeatCoef &k, float (*ends)[2][NW][kRg2X]) {
+  const int tile_x = kRg2X - 2 * t, tile_y = kMtRows * NW - 2 * t;
+  const int x0 = (local % gd.tiles_x) * tile_x, y0 = (local / gd.tiles_x) * tile_y;
+  const int rx_lo = max(x0 - t, 0), rx_hi = min(x0 + tile_x + t, gd.nx);
+  const int ry_lo = max(y0 - t, 0), ry_hi = min(y0 + tile_y + t, gd.ny);
+  const int W = rx_hi - rx_lo, H = ry_hi - ry_lo;
+  const int cx = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = kMtRows * w;
+  const int col0 = 2 * cx < W ? 2 * cx : W - 1;
+  const int col1 = 2 * cx + 1 < W ? 2 * cx + 1 : W - 1;
+  const unsigned nx = (unsigned)gd.nx;
+  const size_t base = (size_t)gd.off + (size_t)ry_lo * nx + rx_lo;
+  const float *T = Tg + base;
+  const float *P = Pg + base;
+  float v0[kMtRows], v1[kMtRows], p0[kMtRows], p1[kMtRows];
+#pragma unroll
+  for (int i = 0; i < kMtRows; ++i) {
+    const unsigned r = r0 + i < H ? r0 + i : H - 1;
+    v0[i] = T[r * nx + col0];                  // < 2^31: a region spans at most 128 rows
+    v1[i] = T[r * nx + col1];
+    p0[i] = P[r * nx + col0];
+    p1[i] = P[r * nx + col1];
+  }
+  ends[0][0][w][2 * cx] = v0[0];
+  ends[0][0][w][2 * cx + 1] = v1[0];
+  ends[0][1][w][2 * cx] = v0[kMtRows - 1];
+  ends[0][1][w][2 * cx + 1] = v1[kMtRows - 1];
+  __syncthreads();
+  switch ((rx_lo == 0) | (rx_hi == gd.nx) << 1 | (ry_hi == gd.ny) << 2) {
+    case 0: region2_advance<NW, false, false, false>(v0, v1, p0, p1, ends, t, W, H, cx, w, k); break;
+    case 1: region2_advance<NW, true, false, false>(v0, v1, p0, p1, ends, t, W, H, cx, w, k); break;
+    case 2: region2_advance<NW, false, true, false>(v0, v1, p0, p1, ends, t, W, H, cx, w, k); break;
+    case 3: region2_advance<NW, true, true, false>(v0, v1, p0, p1, ends, t, W, H, cx, w, k); break;
+    case 4: region2_advance<NW, false, false, true>(v0, v1, p0, p1, ends, t, W, H, cx, w, k); break;
+    case 5: region2_advance<NW, true, false, true>(v0, v1, p0, p1, ends, t, W, H, cx, w, k); break;
+    case 6: region2_advance<NW, false, true, true>(v0, v1, p0, p1, ends, t, W, H, cx, w, k); break;
+    default: region2_advance<NW, true, true, true>(v0, v1, p0, p1, ends, t, W, H, cx, w, k); break;
+  }
+  float *O = Og + base;
+#pragma unroll
+  for (int i = 0; i < kMtRows; ++i) {
+    const int gy = ry_lo + r0 + i;
+    if (r0 + i < H && gy >= y0 && gy < y0 + tile_y) {
+      const int g0 = rx_lo + 2 * cx;
+      if (2 * cx < W && g0 >= x0 && g0 < x0 + tile_x) O[(unsigned)(r0 + i) * nx + 2 * cx] = v0[i];
+      if (2 * cx + 1 < W && g0 + 1 >= x0 && g0 + 1 < x0 + tile_x) O[(unsigned)(r0 + i) * nx + 2 * cx + 1] = v1[i];
+    }
+  }
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void heat2d_region2_tb_kernel(const Heat2DArgs a) {
+  __shared__ float ends[2][2][NW][kRg2X];
+  if (a.flag && *a.flag == 0) return;
+  const int t = a.tdepth;
+  const int tiles_x = (a.nx + kRg2X - 2 * t - 1) / (kRg2X - 2 * t);
+  const int tiles_y = (a.ny + kMtRows * NW - 2 * t - 1) / (kMtRows * NW - 2 * t);
+  const int nb = tiles_x * tiles_y;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;
+  const GridDesc gd{0, a.ny, a.nx, tiles_x, 0};
+  region2_tile<NW>(gd, lb, a.T, a.out, a.P, t, a.k, ends);
+}
+
+// Many-grid temporal blocking over regions two columns per lane wide
+// (variants 5 and 6).
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void heat2d_multi_tb2_kernel(const MultiTbArgs a) {
+  __shared__ float ends[2][2][NW][kRg2X];
+  const int lb = xcd_logical_block(a.nb);
+  if (lb >= a.nb) return;
+  const GridDesc gd = a.grids[a.block_grid[lb]];
+  region2_tile<NW>(gd, lb - gd.block0, a.T, a.out, a.P, a.tdepth, a.k, ends);
+}
+
+// variant 18: 64 x 64 regions (4 waves), 19: 64 x 128 (8 waves); two
+// columns per lane: 20: 128 x 64, 21: 128 x 128
 bool make_heat2d_region(Launch &L, const Heat2DArgs &a, int variant) {
   if (a.tdepth < 1 || a.tdepth > kMtMaxDepth) return false;
-  const int nw = variant == 19 ? 8 : 4;
-  const long long tiles_x = (a.nx + multi_tb_tile_x(a.tdepth) - 1) / multi_tb_tile_x(a.tdepth);
+  const int nw = variant == 19 || variant == 21 ? 8 : 4;
+  const int tx = variant >= 20 ? kRg2X - 2 * a.tdepth : multi_tb_tile_x(0, a.tdepth);
+  const long long tiles_x = (a.nx + tx - 1) / tx;
   const long long tiles_y = (a.ny + kMtRows * nw - 2 * a.tdepth - 1) / (kMtRows * nw - 2 * a.tdepth);
   if (tiles_x * tiles_y > (1LL << 30)) return false;
   const dim3 grid(xcd_padded_grid((int)(tiles_x * tiles_y)));
   if (variant == 18) L.set((const void *)heat2d_region_tb_kernel<4>, grid, dim3(256), 0, a);
   else if (variant == 19) L.set((const void *)heat2d_region_tb_kernel<8>, grid, dim3(512), 0, a);
+  else if (variant == 20) L.set((const void *)heat2d_region2_tb_kernel<4>, grid, dim3(256), 0, a);
+  else if (variant == 21) L.set((const void *)heat2d_region2_tb_kernel<8>, grid, dim3(512), 0, a);
   else return false;
   return true;
 }
@@ -1105,10 +1239,11 @@ __global__ __launch_bounds__(256) void heat2d_multi_persistent_kernel(const Mult
 const void *multi_persistent_fn() { return (const void *)heat2d_multi_persistent_kernel; }
 
 void make_multi_tb(Launch &L, const MultiTbArgs &a, int shape) {
-  if (shape == 0)
-    L.set((const void *)heat2d_multi_tb_kernel<4>, dim3(xcd_padded_grid(a.nb)), dim3(256), 0, a);
-  else
-    L.set((const void *)heat2d_multi_tb_kernel<8>, dim3(xcd_padded_grid(a.nb)), dim3(512), 0, a);
+  const dim3 grid(xcd_padded_grid(a.nb));
+  if (shape == 0) L.set((const void *)heat2d_multi_tb_kernel<4>, grid, dim3(256), 0, a);
+  else if (shape == 1) L.set((const void *)heat2d_multi_tb_kernel<8>, grid, dim3(512), 0, a);
+  else if (shape == 2) L.set((const void *)heat2d_multi_tb2_kernel<4>, grid, dim3(256), 0, a);
+  else L.set((const void *)heat2d_multi_tb2_kernel<8>, grid, dim3(512), 0, a);
 }
 
 void make_multi_strip(Launch &L, const MultiStripArgs &a) {

@@ -138,13 +138,16 @@ struct MultiStripArgs {
 };
 
 // Many-grid temporal blocking: t <= kMtMaxDepth steps per launch over a
-// region of at most 64 columns x multi_tb_region_y(s) rows around an output
-// tile of (64 - 2t) x (region rows - 2t) cells; region shape s = 0 (64
-// rows, 4 waves) or 1 (128 rows, 8 waves); one block table per (s, t).
-constexpr int kMtRegionX = 64, kMtMaxDepth = 8, kMtShapes = 2;
+// region of at most multi_tb_region_x(s) columns x multi_tb_region_y(s)
+// rows around an output tile of (region columns - 2t) x (region rows - 2t)
+// cells; region shape s = 0 (64 x 64, 4 waves), 1 (64 x 128, 8 waves),
+// 2 (128 x 64, two columns per lane, 4 waves) or 3 (128 x 128, two
+// columns per lane, 8 waves); one block table per (s, t).
+constexpr int kMtRegionX = 64, kMtMaxDepth = 8, kMtShapes = 4;
 constexpr int kMtTilings = kMtShapes * kMtMaxDepth;
-__host__ __device__ inline int multi_tb_region_y(int s) { return s ? 128 : 64; }
-__host__ __device__ inline int multi_tb_tile_x(int t) { return kMtRegionX - 2 * t; }
+__host__ __device__ inline int multi_tb_region_x(int s) { return s >= 2 ? 128 : 64; }
+__host__ __device__ inline int multi_tb_region_y(int s) { return (s & 1) ? 128 : 64; }
+__host__ __device__ inline int multi_tb_tile_x(int s, int t) { return multi_tb_region_x(s) - 2 * t; }
 __host__ __device__ inline int multi_tb_tile_y(int s, int t) { return multi_tb_region_y(s) - 2 * t; }
 inline int multi_tb_index(int s, int t) { return s * kMtMaxDepth + t - 1; }
 struct MultiTbArgs {

@@ -150,10 +150,11 @@ def test_heat2d_strip_depth_limit(kb, tile):
 
 @pytest.mark.parametrize("shape", [(70, 133), (256, 256), (130, 300), (64, 64), (1, 40), (40, 1), (3, 5), (257, 49)])
 @pytest.mark.parametrize("tdepth", [1, 2, 3, 6, 8])
-@pytest.mark.parametrize("tile", [18, 19])
+@pytest.mark.parametrize("tile", [18, 19, 20, 21])
 def test_heat2d_region_temporal_variant_bitwise(kb, shape, tdepth, tile):
-    """Variants 18 and 19 (regions of 64 columns x 64 or 128 rows, 16 rows
-    of a column per lane in registers, strip ends in LDS): same bits as the
+    """Variants 18-21 (regions of 64 or 128 columns x 64 or 128 rows, 16
+    rows of one or two columns per lane in registers, strip ends in LDS):
+    same bits as the
     one-cell kernel for every depth, with a step count that leaves a
     remainder, per launch and in graph batches; regions cut at every edge,
     grids smaller than a region, single rows and columns; within 1e-5 of
@@ -167,7 +168,7 @@ def test_heat2d_region_temporal_variant_bitwise(kb, shape, tdepth, tile):
     assert rel_maxnorm(base, oracle.heat2d(T0, P, steps, dtype=np.float32)) < 1e-5
 
 
-@pytest.mark.parametrize("tile,tdepth", [(18, 8), (19, 6)])
+@pytest.mark.parametrize("tile,tdepth", [(18, 8), (19, 6), (21, 6)])
 def test_heat2d_region_large_grid(kb, tile, tdepth):
     """A large-grid case (8192^2, 256 MiB per field) in the launch shape the
     large-grid benchmark times: 13 steps as full-depth launches of the
@@ -185,7 +186,7 @@ def test_heat2d_region_large_grid(kb, tile, tdepth):
     assert rel_maxnorm(got[:20], ref[:20]) < 1e-5
 
 
-@pytest.mark.parametrize("tile", [18, 19])
+@pytest.mark.parametrize("tile", [18, 19, 20, 21])
 def test_heat2d_region_depth_limit(kb, tile):
     with kb.Problem(kb.HEAT2D, (64, 64), coeffs(HEAT), 0) as p:
         p.set_option(kb.OPT_TILE, tile)
@@ -368,12 +369,14 @@ def test_heat3d_full_size_sampled(kb):
 
 # ---- many grids ------------------------------------------------------------
 
-@pytest.mark.parametrize("variant,depth", [(1, 1), (2, 1), (3, 1), (3, 3), (3, 8), (4, 2), (4, 8)])
+@pytest.mark.parametrize("variant,depth", [(1, 1), (2, 1), (3, 1), (3, 3), (3, 8), (4, 2), (4, 8),
+                                           (5, 1), (5, 3), (5, 8), (6, 2), (6, 7), (6, 8)])
 def test_multigrid_matches_single_grids(kb, variant, depth):
     """variant 1: one cell per thread; 2: 64 x 8 strips per wave; 3:
-    temporal blocking over (64 - 2t)-square tiles (30 steps = whole
-    iterations of t steps plus single steps).  Grids narrower and wider than
-    a wave and than a tile, single rows and a single cell."""
+    temporal blocking over (64 - 2t)-square tiles, 4: over 64 x 128
+    regions, 5 and 6: over 128-column regions two columns per lane (30
+    steps = whole iterations of t steps plus single steps).  Grids narrower
+    and wider than a wave and than a tile, single rows and a single cell."""
     announce(f"multigrid 8 grids variant {variant} depth {depth}")
     sides = [(17, 70), (64, 64), (5, 130), (100, 33), (1, 1), (40, 250), (33, 1), (9, 65), (130, 127), (300, 290)]
     shape = [len(sides)] + [v for s in sides for v in s]
@@ -425,7 +428,7 @@ def test_multigrid_full_size_workload_all_variants(kb):
     sides = synth.multigrid_sides(20250116, 64)
     shape = [64] + [v for s in sides for v in (s, s)]
     outs = []
-    for v, t in ((1, 1), (2, 1), (3, 4), (3, 8), (4, 6)):
+    for v, t in ((1, 1), (2, 1), (3, 4), (3, 8), (4, 6), (5, 6), (6, 8)):
         with kb.Problem(kb.HEAT2D_MULTI, shape, coeffs(HEAT), 20250116) as p:
             p.set_option(kb.OPT_TILE, v)
             p.set_option(kb.OPT_TDEPTH, t)
@@ -435,12 +438,13 @@ def test_multigrid_full_size_workload_all_variants(kb):
         assert np.array_equal(outs[0], o)
 
 
-@pytest.mark.parametrize("variant,depth,b", [(2, 1, 100), (3, 6, 37)])
+@pytest.mark.parametrize("variant,depth,b", [(2, 1, 100), (3, 6, 37), (6, 8, 25)])
 def test_multigrid_full_size_2000_steps_vs_oracle(kb, variant, depth, b):
     """The 64-grid workload for 2000 steps as the benchmark runs it: the
-    strip kernel in graph batches of 100, and temporal blocking at the depth
-    and batch the autotuner picks on MI355X (333 launches of 6 steps in 9
-    graphs of 37, then 2 single steps).  The three smallest grids against
+    strip kernel in graph batches of 100, and temporal blocking at depths
+    and batches the autotuner picks on MI355X (333 launches of 6 steps in 9
+    graphs of 37, then 2 single steps; 250 launches of 8 steps over
+    two-column regions in 10 graphs of 25).  The three smallest grids against
     the float32 oracle, and every grid's mean against its closed form (the
     clamped Laplacian sums to zero on each grid)."""
     announce(f"multigrid 64 grids 2000 steps variant {variant} depth {depth} b={b}")
