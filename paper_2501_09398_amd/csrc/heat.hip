@@ -897,31 +897,48 @@ __global__ __launch_bounds__(256) void heat2d_multi_strip_kernel(const MultiStri
 // grid take the loop with no clamp at all.
 constexpr int kMtRows = 16;                  // region rows per wave
 
+// One step of a region column's 16 rows from `a` to `o` (strip ends read
+// from LDS buffer b, written to b^1).  Writing the step into other
+// registers than it reads keeps the old row alive as the next row's north
+// neighbour without register copies.
+template <int NW, bool CW, bool CE, bool CS>
+__device__ __forceinline__ void multi_tb_step(const float (&a)[kMtRows], float (&o)[kMtRows],
+                                              const float (&pw)[kMtRows], float (*ends)[2][NW][kMtRegionX],
+                                              int b, int W, int last, int cx, int w, const HeatCoef &k) {
+  const float top = w > 0 ? ends[b][1][w - 1][cx] : a[0];            // old row above
+  const float bot = w < NW - 1 ? ends[b][0][w + 1][cx] : a[kMtRows - 1];
+#pragma unroll
+  for (int i = 0; i < kMtRows; ++i) {
+    const float c = a[i];
+    const float n = i == 0 ? top : a[i - 1];
+    float so = i == kMtRows - 1 ? bot : a[i + 1];
+    if (CS && i == last) so = c;
+    float ev = lane_east_open(c), wv = lane_west_open(c);
+    if (CE && cx >= W - 1) ev = c;
+    if (CW && cx == 0) wv = c;
+    o[i] = heat_update(c, n, so, wv, ev, pw[i], k);
+  }
+  ends[b ^ 1][0][w][cx] = o[0];
+  ends[b ^ 1][1][w][cx] = o[kMtRows - 1];
+  __syncthreads();
+}
+
+// t steps, two at a time between two register sets.
 template <int NW, bool CW, bool CE, bool CS>
 __device__ __forceinline__ void multi_tb_advance(float (&v)[kMtRows], const float (&pw)[kMtRows],
                                                  float (*ends)[2][NW][kMtRegionX], int t, int W, int H,
                                                  int cx, int w, const HeatCoef &k) {
   const int last = H - 1 - kMtRows * w;       // this wave's index of the grid's bottom row (CS)
-  int b = 0;
-  for (int s = 0; s < t; ++s) {
-    float prev = w > 0 ? ends[b][1][w - 1][cx] : v[0];          // old row above
-    const float bot = w < NW - 1 ? ends[b][0][w + 1][cx] : v[kMtRows - 1];
+  float u[kMtRows];
+  int s = 0;
+  for (; s + 2 <= t; s += 2) {
+    multi_tb_step<NW, CW, CE, CS>(v, u, pw, ends, 0, W, last, cx, w, k);
+    multi_tb_step<NW, CW, CE, CS>(u, v, pw, ends, 1, W, last, cx, w, k);
+  }
+  if (s < t) {
+    multi_tb_step<NW, CW, CE, CS>(v, u, pw, ends, 0, W, last, cx, w, k);
 #pragma unroll
-    for (int i = 0; i < kMtRows; ++i) {
-      const float c = v[i];
-      float so = i == kMtRows - 1 ? bot : v[i + 1];
-      if (CS && i == last) so = c;
-      float ev = lane_east_open(c), wv = lane_west_open(c);
-      if (CE && cx >= W - 1) ev = c;
-      if (CW && cx == 0) wv = c;
-      const float n = prev;
-      prev = c;
-      v[i] = heat_update(c, n, so, wv, ev, pw[i], k);
-    }
-    b ^= 1;
-    ends[b][0][w][cx] = v[0];
-    ends[b][1][w][cx] = v[kMtRows - 1];
-    __syncthreads();
+    for (int i = 0; i < kMtRows; ++i) v[i] = u[i];
   }
 }
 
@@ -1018,6 +1035,12 @@ __global__ __launch_bounds__(64 * NW) void heat2d_region_tb_kernel(const Heat2DA
 // clamps and the strip-end exchange are those of the one-column regions.
 constexpr int kRg2X = 128;
 
+// t steps of a two-column region (columns 2cx, 2cx+1 of 16 rows in v0,
+// v1).  Strip ends go through LDS with region column c at LDS column
+// (c & 1) * 64 + c / 2, so that a wave's accesses are to consecutive
+// words.  Unlike the one-column regions the steps update the rows in place:
+// a second register set would take the kernel past 128 VGPRs and halve the
+// waves per SIMD.
 template <int NW, bool CW, bool CE, bool CS>
 __device__ __forceinline__ void region2_advance(float (&v0)[kMtRows], float (&v1)[kMtRows],
                                                 const float (&p0)[kMtRows], const float (&p1)[kMtRows],
@@ -1027,10 +1050,10 @@ __device__ __forceinline__ void region2_advance(float (&v0)[kMtRows], float (&v1
   const int c0 = 2 * cx, c1 = 2 * cx + 1;
   int b = 0;
   for (int s = 0; s < t; ++s) {
-    float prev0 = w > 0 ? ends[b][1][w - 1][c0] : v0[0];
-    float prev1 = w > 0 ? ends[b][1][w - 1][c1] : v1[0];
-    const float bot0 = w < NW - 1 ? ends[b][0][w + 1][c0] : v0[kMtRows - 1];
-    const float bot1 = w < NW - 1 ? ends[b][0][w + 1][c1] : v1[kMtRows - 1];
+    float prev0 = w > 0 ? ends[b][1][w - 1][cx] : v0[0];
+    float prev1 = w > 0 ? ends[b][1][w - 1][64 + cx] : v1[0];
+    const float bot0 = w < NW - 1 ? ends[b][0][w + 1][cx] : v0[kMtRows - 1];
+    const float bot1 = w < NW - 1 ? ends[b][0][w + 1][64 + cx] : v1[kMtRows - 1];
 #pragma unroll
     for (int i = 0; i < kMtRows; ++i) {
       const float a0 = v0[i], a1 = v1[i];
@@ -1052,10 +1075,10 @@ __device__ __forceinline__ void region2_advance(float (&v0)[kMtRows], float (&v1
       v1[i] = heat_update(a1, n1, s1, a0, e1, p1[i], k);
     }
     b ^= 1;
-    ends[b][0][w][c0] = v0[0];
-    ends[b][0][w][c1] = v1[0];
-    ends[b][1][w][c0] = v0[kMtRows - 1];
-    ends[b][1][w][c1] = v1[kMtRows - 1];
+    ends[b][0][w][cx] = v0[0];
+    ends[b][0][w][64 + cx] = v1[0];
+    ends[b][1][w][cx] = v0[kMtRows - 1];
+    ends[b][1][w][64 + cx] = v1[kMtRows - 1];
     __syncthreads();
   }
 }
@@ -1087,10 +1110,10 @@ __device__ __forceinline__ void region2_tile(const GridDesc &gd, int local, cons
     p0[i] = P[r * nx + col0];
     p1[i] = P[r * nx + col1];
   }
-  ends[0][0][w][2 * cx] = v0[0];
-  ends[0][0][w][2 * cx + 1] = v1[0];
-  ends[0][1][w][2 * cx] = v0[kMtRows - 1];
-  ends[0][1][w][2 * cx + 1] = v1[kMtRows - 1];
+  ends[0][0][w][cx] = v0[0];
+  ends[0][0][w][64 + cx] = v1[0];
+  ends[0][1][w][cx] = v0[kMtRows - 1];
+  ends[0][1][w][64 + cx] = v1[kMtRows - 1];
   __syncthreads();
   switch ((rx_lo == 0) | (rx_hi == gd.nx) << 1 | (ry_hi == gd.ny) << 2) {
     case 0: region2_advance<NW, false, false, false>(v0, v1, p0, p1, ends, t, W, H, cx, w, k); break;
