@@ -646,52 +646,75 @@ static const void *heat3d_tb_fn(int nz) {
 // grid edge need the clamp, and the step loop is specialised on them.
 // ---------------------------------------------------------------------------
 constexpr int kH3Waves = 8, kH3Rows = 4, kH3RegionY = kH3Waves * kH3Rows, kH3MaxDepth = 8;
+constexpr int kH3TwoSetBlocks = 256;
 
+// One step of a region column's rows (every layer) from `a` to `o`, strip
+// ends read from LDS buffer b and written to b^1.  Writing into other
+// registers than the step reads keeps the old rows alive as the next row's
+// north neighbours without register copies.
 template <int NZ, bool CW, bool CE, bool CS>
+__device__ __forceinline__ void heat3d_strip_step(const float (&a)[NZ][kH3Rows], float (&o)[NZ][kH3Rows],
+                                                  const float (&pw)[kH3Rows],
+                                                  float (*ends)[2][kH3Waves][NZ][64], int b, int W, int last,
+                                                  int cx, int w, const HeatCoef &k) {
+  float top[NZ], bot[NZ];
+#pragma unroll
+  for (int z = 0; z < NZ; ++z) {
+    top[z] = w > 0 ? ends[b][1][w - 1][z][cx] : a[z][0];          // old row above
+    bot[z] = w < kH3Waves - 1 ? ends[b][0][w + 1][z][cx] : a[z][kH3Rows - 1];
+  }
+#pragma unroll
+  for (int i = 0; i < kH3Rows; ++i) {
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) {
+      const float c = a[z][i];
+      const float n = i == 0 ? top[z] : a[z][i - 1];
+      float so = i == kH3Rows - 1 ? bot[z] : a[z][i + 1];
+      if (CS && i == last) so = c;
+      float ev = lane_east_open(c), wv = lane_west_open(c);
+      if (CE && cx >= W - 1) ev = c;
+      if (CW && cx == 0) wv = c;
+      const float up = z + 1 < NZ ? a[z + 1][i] : c;
+      const float dn = z > 0 ? a[z - 1][i] : c;
+      o[z][i] = heat3d_update(c, n, so, wv, ev, up, dn, z == 0 ? pw[i] : 0.0f, z == 0, k);
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < NZ; ++z) {
+    ends[b ^ 1][0][w][z][cx] = o[z][0];
+    ends[b ^ 1][1][w][z][cx] = o[z][kH3Rows - 1];
+  }
+  __syncthreads();
+}
+
+// t steps.  TWO: two at a time between two register sets (no register
+// copies, but about 40 more VGPRs at NZ = 8, which halves the blocks per
+// CU); otherwise one set, each step through a copy of the rows.
+template <int NZ, bool TWO, bool CW, bool CE, bool CS>
 __device__ __forceinline__ void heat3d_strip_advance(float (&v)[NZ][kH3Rows], const float (&pw)[kH3Rows],
                                                      float (*ends)[2][kH3Waves][NZ][64], int t, int W, int H,
                                                      int cx, int w, const HeatCoef &k) {
   const int last = H - 1 - kH3Rows * w;        // this wave's index of the grid's bottom row (CS)
+  float u[NZ][kH3Rows];
+  int s = 0;
+  if constexpr (TWO) {
+    for (; s + 2 <= t; s += 2) {
+      heat3d_strip_step<NZ, CW, CE, CS>(v, u, pw, ends, 0, W, last, cx, w, k);
+      heat3d_strip_step<NZ, CW, CE, CS>(u, v, pw, ends, 1, W, last, cx, w, k);
+    }
+  }
   int b = 0;
-  for (int s = 0; s < t; ++s) {
-    float prev[NZ], bot[NZ];
-#pragma unroll
-    for (int z = 0; z < NZ; ++z) {
-      prev[z] = w > 0 ? ends[b][1][w - 1][z][cx] : v[z][0];          // old row above
-      bot[z] = w < kH3Waves - 1 ? ends[b][0][w + 1][z][cx] : v[z][kH3Rows - 1];
-    }
-#pragma unroll
-    for (int i = 0; i < kH3Rows; ++i) {
-      float nv[NZ];
-#pragma unroll
-      for (int z = 0; z < NZ; ++z) {
-        const float c = v[z][i];
-        float so = i == kH3Rows - 1 ? bot[z] : v[z][i + 1];
-        if (CS && i == last) so = c;
-        float ev = lane_east_open(c), wv = lane_west_open(c);
-        if (CE && cx >= W - 1) ev = c;
-        if (CW && cx == 0) wv = c;
-        const float up = z + 1 < NZ ? v[z + 1][i] : c;
-        const float dn = z > 0 ? v[z - 1][i] : c;
-        nv[z] = heat3d_update(c, prev[z], so, wv, ev, up, dn, z == 0 ? pw[i] : 0.0f, z == 0, k);
-      }
-#pragma unroll
-      for (int z = 0; z < NZ; ++z) {
-        prev[z] = v[z][i];
-        v[z][i] = nv[z];
-      }
-    }
+  for (; s < t; ++s) {
+    heat3d_strip_step<NZ, CW, CE, CS>(v, u, pw, ends, b, W, last, cx, w, k);
     b ^= 1;
 #pragma unroll
-    for (int z = 0; z < NZ; ++z) {
-      ends[b][0][w][z][cx] = v[z][0];
-      ends[b][1][w][z][cx] = v[z][kH3Rows - 1];
-    }
-    __syncthreads();
+    for (int z = 0; z < NZ; ++z)
+#pragma unroll
+      for (int i = 0; i < kH3Rows; ++i) v[z][i] = u[z][i];
   }
 }
 
-template <int NZ>
+template <int NZ, bool TWO>
 __global__ __launch_bounds__(64 * kH3Waves) void heat3d_strip_tb_kernel(const Heat3DArgs a) {
   __shared__ float ends[2][2][kH3Waves][NZ][64];   // [buffer][top, bottom][wave][layer][column]
   const int t = a.tdepth, tile_x = 64 - 2 * t, tile_y = kH3RegionY - 2 * t;
@@ -725,14 +748,14 @@ __global__ __launch_bounds__(64 * kH3Waves) void heat3d_strip_tb_kernel(const He
   }
   __syncthreads();
   switch ((rx_lo == 0) | (rx_hi == a.nx) << 1 | (ry_hi == a.ny) << 2) {
-    case 0: heat3d_strip_advance<NZ, false, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 1: heat3d_strip_advance<NZ, true, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 2: heat3d_strip_advance<NZ, false, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 3: heat3d_strip_advance<NZ, true, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 4: heat3d_strip_advance<NZ, false, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 5: heat3d_strip_advance<NZ, true, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    case 6: heat3d_strip_advance<NZ, false, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
-    default: heat3d_strip_advance<NZ, true, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 0: heat3d_strip_advance<NZ, TWO, false, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 1: heat3d_strip_advance<NZ, TWO, true, false, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 2: heat3d_strip_advance<NZ, TWO, false, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 3: heat3d_strip_advance<NZ, TWO, true, true, false>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 4: heat3d_strip_advance<NZ, TWO, false, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 5: heat3d_strip_advance<NZ, TWO, true, false, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    case 6: heat3d_strip_advance<NZ, TWO, false, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
+    default: heat3d_strip_advance<NZ, TWO, true, true, true>(v, pw, ends, t, W, H, cx, w, a.k); break;
   }
   const int gx = rx_lo + cx;
   if (cx < W && gx >= x0 && gx < x0 + tile_x) {
@@ -748,16 +771,16 @@ __global__ __launch_bounds__(64 * kH3Waves) void heat3d_strip_tb_kernel(const He
   }
 }
 
-static const void *heat3d_strip_fn(int nz) {
+static const void *heat3d_strip_fn(int nz, bool two) {
   switch (nz) {
-    case 1: return (const void *)heat3d_strip_tb_kernel<1>;
-    case 2: return (const void *)heat3d_strip_tb_kernel<2>;
-    case 3: return (const void *)heat3d_strip_tb_kernel<3>;
-    case 4: return (const void *)heat3d_strip_tb_kernel<4>;
-    case 5: return (const void *)heat3d_strip_tb_kernel<5>;
-    case 6: return (const void *)heat3d_strip_tb_kernel<6>;
-    case 7: return (const void *)heat3d_strip_tb_kernel<7>;
-    case 8: return (const void *)heat3d_strip_tb_kernel<8>;
+    case 1: return two ? (const void *)heat3d_strip_tb_kernel<1, true> : (const void *)heat3d_strip_tb_kernel<1, false>;
+    case 2: return two ? (const void *)heat3d_strip_tb_kernel<2, true> : (const void *)heat3d_strip_tb_kernel<2, false>;
+    case 3: return two ? (const void *)heat3d_strip_tb_kernel<3, true> : (const void *)heat3d_strip_tb_kernel<3, false>;
+    case 4: return two ? (const void *)heat3d_strip_tb_kernel<4, true> : (const void *)heat3d_strip_tb_kernel<4, false>;
+    case 5: return two ? (const void *)heat3d_strip_tb_kernel<5, true> : (const void *)heat3d_strip_tb_kernel<5, false>;
+    case 6: return two ? (const void *)heat3d_strip_tb_kernel<6, true> : (const void *)heat3d_strip_tb_kernel<6, false>;
+    case 7: return two ? (const void *)heat3d_strip_tb_kernel<7, true> : (const void *)heat3d_strip_tb_kernel<7, false>;
+    case 8: return two ? (const void *)heat3d_strip_tb_kernel<8, true> : (const void *)heat3d_strip_tb_kernel<8, false>;
   }
   return nullptr;
 }
@@ -770,10 +793,14 @@ static const void *heat3d_strip_fn(int nz) {
 // 11 = register-strip temporal blocking (nz <= 8, a.tdepth <= 8)
 bool make_heat3d(Launch &L, const Heat3DArgs &a, int variant) {
   if (variant == 11) {
-    const void *f = heat3d_strip_fn(a.nz);
-    if (!f || a.tdepth < 1 || a.tdepth > kH3MaxDepth) return false;
+    if (a.tdepth < 1 || a.tdepth > kH3MaxDepth) return false;
     const int tx = 64 - 2 * a.tdepth, ty = kH3RegionY - 2 * a.tdepth;
     const int nb = ((a.nx + tx - 1) / tx) * ((a.ny + ty - 1) / ty);
+    // grids of at most one block per compute unit (256 on MI355X) take the
+    // two-register-set loop: fewer instructions per step, and the blocks
+    // per CU it costs are not needed
+    const void *f = heat3d_strip_fn(a.nz, nb <= kH3TwoSetBlocks);
+    if (!f) return false;
     L.set(f, dim3(xcd_padded_grid(nb)), dim3(64 * kH3Waves), 0, a);
     return true;
   }
