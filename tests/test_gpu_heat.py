@@ -314,6 +314,24 @@ def test_heat3d_temporal_blocking_bitwise(kb, shape, tile, tdepth):
     assert np.array_equal(base, run_heat3d(kb, shape, steps, b=2, seed=19, tile=tile, tdepth=tdepth))
 
 
+@pytest.mark.parametrize("shape", [(8, 1100, 1000), (5, 700, 903)])
+@pytest.mark.parametrize("tdepth", [1, 2, 4, 7])
+def test_heat3d_strip_many_blocks_bitwise(kb, shape, tdepth):
+    """Variant 11 on grids of more than one region per compute unit, where
+    the kernel updates the rows with one register set (smaller grids use
+    two): the same bits as the one-step kernel per launch and in graph
+    batches, and the first rows within 1e-5 of the float32 oracle (17
+    steps reach 17 rows, so the first 20 rows of a 40-row cut are exact)."""
+    announce(f"heat3d strip many blocks {shape} t={tdepth}")
+    steps = 17
+    base = run_heat3d(kb, shape, steps, seed=21, tile=1)
+    assert np.array_equal(base, run_heat3d(kb, shape, steps, seed=21, tile=11, tdepth=tdepth))
+    assert np.array_equal(base, run_heat3d(kb, shape, steps, b=2, seed=21, tile=11, tdepth=tdepth))
+    T0, P = synth.heat3d_init(21, *shape)
+    ref = oracle.heat3d(np.ascontiguousarray(T0[:, :40]), np.ascontiguousarray(P[:40]), steps, dtype=np.float32)
+    assert rel_maxnorm(base[:, :20], ref[:, :20]) < 1e-5
+
+
 @pytest.mark.parametrize("tile,tdepth,b", [(5, 4, 50), (11, 5, 40)])
 def test_heat3d_temporal_blocking_full_size(kb, tile, tdepth, b):
     """8x512x512 for 2000 steps in graph batches: the same bits as the
