@@ -175,7 +175,10 @@ extern "C" {
  *                     per lane in registers (KB_OPT_TDEPTH 1..8; the
  *                     many-grid problem's variants 3 and 4 on one grid);
  *              20, 21 = the same over regions of 128 columns x 64 or 128
- *                     rows, two columns per lane (KB_OPT_TDEPTH 1..8).
+ *                     rows, two columns per lane (KB_OPT_TDEPTH 1..8);
+ *              22, 23 = the register strips of 15..17 over 32x32 tiles in
+ *                     regions of up to 64 x 64 cells, 4 or 8 rows per
+ *                     thread (KB_OPT_TDEPTH 1..16).
  *              Default: 13 if nx % 4 == 0 and ny*nx >= 2^20, else 1.
  *   KB_HEAT3D: 1 = one thread per column; float4 rows (nx % 4 == 0):
  *              2 = plain, 3 = next layer prefetched, 4 = prefetched with

@@ -32,6 +32,7 @@ HEAT2D_TILE = [2, 3, 4, 5, 6, 7]
 HEAT2D_VEC = [8, 9, 10, 11, 13, 14]
 HEAT2D_DEPTHS = [1, 2, 4, 8, 16]
 HEAT2D_REGION_DEPTHS = [2, 4, 6, 8]      # variants 18 to 21
+HEAT2D_WIDE_STRIP_DEPTHS = [8, 12, 16]   # variants 22 and 23
 HEAT3D_DEPTHS = [1, 2, 3, 4, 6]          # variant 5 (layer stacks of <= 8)
 HEAT3D_STRIP_DEPTHS = [2, 3, 4, 5, 6, 8]  # variant 11 (layer stacks of <= 8)
 MULTI_DEPTHS = [1, 2, 3, 4, 5, 6, 7, 8]  # many-grid variants 3 to 6
@@ -44,6 +45,7 @@ def kernel_candidates(kb, problem, shape):
         c += [(v, t) for v in HEAT2D_TILE for t in HEAT2D_DEPTHS]
         c += [(v, t) for v in (15, 16, 17) for t in HEAT2D_DEPTHS if t <= 8]
         c += [(v, t) for v in (18, 19, 20, 21) for t in HEAT2D_REGION_DEPTHS]
+        c += [(v, t) for v in (22, 23) for t in HEAT2D_WIDE_STRIP_DEPTHS]
         if shape[1] % 4 == 0:
             c += [(v, 1) for v in HEAT2D_VEC]
         return c

@@ -204,7 +204,7 @@ int heat3d_variant(const kb_problem *h) {
   if (h->tile != 0) return h->tile;
   return (h->nx % 4 == 0 && h->ny * h->nx >= (1 << 20)) ? 6 : 1;
 }
-bool heat2d_is_tile(int v) { return (v >= 2 && v <= 7) || (v >= 15 && v <= 21); }   // temporal blocking
+bool heat2d_is_tile(int v) { return (v >= 2 && v <= 7) || (v >= 15 && v <= 23); }   // temporal blocking
 
 // Many-grid variants 3 to 6 (and the default, 3) block in time.
 bool multi_is_tb(const kb_problem *h) { return h->tile == 0 || (h->tile >= 3 && h->tile <= 6); }
@@ -269,6 +269,7 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
         make_heat2d_direct(L[0], a);
         return 1;
       }
+      if (v >= 22) return make_heat2d_strip(L[0], a, v) ? 1 : -1;
       if (v >= 18) return make_heat2d_region(L[0], a, v) ? 1 : -1;
       if (v >= 15) return make_heat2d_strip(L[0], a, v) ? 1 : -1;
       if (heat2d_is_tile(v)) return make_heat2d_tile(L[0], a, v) ? 1 : -1;
@@ -780,7 +781,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
     case KB_OPT_TILE: {
       bool ok = false;
       if (h->kind == KB_HEAT2D)
-        ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0) || (value >= 15 && value <= 21);
+        ok = (value >= 0 && value <= 7) || (value >= 8 && value <= 14 && h->nx % 4 == 0) || (value >= 15 && value <= 23);
       else if (h->kind == KB_HEAT3D)
         ok = value == 0 || value == 1 || (((value >= 2 && value <= 4) || (value >= 6 && value <= 10)) && h->nx % 4 == 0) ||
              ((value == 5 || value == 11) && h->nz <= 8);

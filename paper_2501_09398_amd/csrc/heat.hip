@@ -136,23 +136,27 @@ int heat2d_tile_max_depth() { return kMaxDepth; }
 // cell per step and never reaches the tile.  Same update, same bits as
 // every other variant.
 // ---------------------------------------------------------------------------
-constexpr int kStX = 16, kStY = 16, kStMaxDepth = 8;
+constexpr int kStMaxDepth = 8;                // 32-column regions
 
-template <int RPT>
-__global__ __launch_bounds__(32 * (32 / RPT)) void heat2d_strip_tb_kernel(const Heat2DArgs a) {
-  constexpr int NG = 32 / RPT;                 // row groups
-  __shared__ float ends[2][2][NG][32];         // [buffer][top, bottom][group][column]
+// CWID = region columns (32 or 64); tiles of CWID/2 x CWID/2 cells, so
+// t <= CWID/4; CWID/RPT row groups of CWID lanes.  With CWID = 64 a wave is
+// one row group, and the 32 x 32 tiles allow 16 steps per launch.
+template <int RPT, int CWID>
+__global__ __launch_bounds__(CWID * (CWID / RPT)) void heat2d_strip_tb_kernel(const Heat2DArgs a) {
+  constexpr int NG = CWID / RPT;               // row groups
+  constexpr int TX = CWID / 2;                 // tile side
+  __shared__ float ends[2][2][NG][CWID];       // [buffer][top, bottom][group][column]
   if (a.flag && *a.flag == 0) return;          // predicated launch (whole grid)
   const int t = a.tdepth;
-  const int tiles_x = (a.nx + kStX - 1) / kStX, tiles_y = (a.ny + kStY - 1) / kStY;
+  const int tiles_x = (a.nx + TX - 1) / TX, tiles_y = (a.ny + TX - 1) / TX;
   const int nb = tiles_x * tiles_y;
   const int lb = xcd_logical_block(nb);
   if (lb >= nb) return;
-  const int x0 = (lb % tiles_x) * kStX, y0 = (lb / tiles_x) * kStY;
-  const int rx_lo = max(x0 - t, 0), rx_hi = min(x0 + kStX + t, a.nx);
-  const int ry_lo = max(y0 - t, 0), ry_hi = min(y0 + kStY + t, a.ny);
+  const int x0 = (lb % tiles_x) * TX, y0 = (lb / tiles_x) * TX;
+  const int rx_lo = max(x0 - t, 0), rx_hi = min(x0 + TX + t, a.nx);
+  const int ry_lo = max(y0 - t, 0), ry_hi = min(y0 + TX + t, a.ny);
   const int W = rx_hi - rx_lo, H = ry_hi - ry_lo;
-  const int cx = threadIdx.x & 31, g = threadIdx.x >> 5, r0 = RPT * g;
+  const int cx = threadIdx.x % CWID, g = threadIdx.x / CWID, r0 = RPT * g;
   const int col = cx < W ? cx : W - 1;
   const size_t nx = (size_t)a.nx;
   float v[RPT], pw[RPT];
@@ -194,19 +198,24 @@ __global__ __launch_bounds__(32 * (32 / RPT)) void heat2d_strip_tb_kernel(const 
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int gy = ry_lo + r0 + i;
-      if (r0 + i < H && gy >= y0 && gy < y0 + kStY && gx >= x0 && gx < x0 + kStX) a.out[(size_t)gy * nx + gx] = v[i];
+      if (r0 + i < H && gy >= y0 && gy < y0 + TX && gx >= x0 && gx < x0 + TX) a.out[(size_t)gy * nx + gx] = v[i];
     }
   }
 }
 
-// variant 15: 4 rows per thread, 16: 2, 17: 1
+// variant 15: 4 rows per thread, 16: 2, 17: 1 (32-column regions, t <= 8);
+// 22: 4 rows per thread, 23: 8 (64-column regions, t <= 16)
 bool make_heat2d_strip(Launch &L, const Heat2DArgs &a, int variant) {
-  if (a.tdepth < 1 || a.tdepth > kStMaxDepth) return false;
-  const int nb = ((a.nx + kStX - 1) / kStX) * ((a.ny + kStY - 1) / kStY);
+  const int cw = variant >= 22 ? 64 : 32;
+  if (a.tdepth < 1 || a.tdepth > cw / 4) return false;
+  const int tx = cw / 2;
+  const int nb = ((a.nx + tx - 1) / tx) * ((a.ny + tx - 1) / tx);
   const dim3 grid(xcd_padded_grid(nb));
-  if (variant == 15) L.set((const void *)heat2d_strip_tb_kernel<4>, grid, dim3(256), 0, a);
-  else if (variant == 16) L.set((const void *)heat2d_strip_tb_kernel<2>, grid, dim3(512), 0, a);
-  else if (variant == 17) L.set((const void *)heat2d_strip_tb_kernel<1>, grid, dim3(1024), 0, a);
+  if (variant == 15) L.set((const void *)heat2d_strip_tb_kernel<4, 32>, grid, dim3(256), 0, a);
+  else if (variant == 16) L.set((const void *)heat2d_strip_tb_kernel<2, 32>, grid, dim3(512), 0, a);
+  else if (variant == 17) L.set((const void *)heat2d_strip_tb_kernel<1, 32>, grid, dim3(1024), 0, a);
+  else if (variant == 22) L.set((const void *)heat2d_strip_tb_kernel<4, 64>, grid, dim3(1024), 0, a);
+  else if (variant == 23) L.set((const void *)heat2d_strip_tb_kernel<8, 64>, grid, dim3(512), 0, a);
   else return false;
   return true;
 }

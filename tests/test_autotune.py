@@ -13,12 +13,12 @@ class FakeKB:
     Temporal depth counts only for the temporal-blocking variants of the
     problem the fake was created for."""
     HEAT2D, HEAT3D, SKELETON, FDTD3D, HEAT2D_MULTI = 1, 2, 3, 4, 5
-    TB = {1: {2, 3, 4, 5, 6, 7, 15, 16, 17, 18, 19, 20, 21}, 2: {5, 11}, 5: {3, 4, 5, 6}}
+    TB = {1: {2, 3, 4, 5, 6, 7, 15, 16, 17, 18, 19, 20, 21, 22, 23}, 2: {5, 11}, 5: {3, 4, 5, 6}}
     OPT_BUILDER, OPT_TILE, OPT_TDEPTH, OPT_GRAPH_CACHE, OPT_MAX_NODES = 1, 2, 3, 4, 5
     # per-launch kernel time (s) per variant; variant 6 with depth 8 is best
     T_K = {1: 3e-6, 2: 4e-6, 3: 3.5e-6, 4: 3.6e-6, 5: 3.4e-6, 6: 3.2e-6, 7: 3.9e-6,
            8: 2.9e-6, 9: 2.95e-6, 10: 3.1e-6, 11: 3.3e-6, 12: 3.5e-6, 13: 2.8e-6, 14: 2.85e-6,
-           15: 3.3e-6, 16: 3.25e-6, 17: 3.35e-6, 18: 3.3e-6, 19: 3.4e-6, 20: 3.3e-6, 21: 3.4e-6}
+           15: 3.3e-6, 16: 3.25e-6, 17: 3.35e-6, 18: 3.3e-6, 19: 3.4e-6, 20: 3.3e-6, 21: 3.4e-6, 22: 3.3e-6, 23: 3.35e-6}
     T_I, T_A, K_C, B_C = 0.5e-6, 8e-6, 3e-6, 2e-4
 
     class Problem:

@@ -30,8 +30,8 @@ def configs():
         kind = ("HEAT2D", "HEAT3D", "SKELETON", "FDTD3D", "HEAT2D_MULTI")[case % 5]
         if kind == "HEAT2D":
             shape = (int(rng.integers(1, 90)), int(rng.integers(1, 90)) * 4)
-            variant = int(rng.choice([1, 2, 5, 6, 9, 13, 15, 16, 17, 18, 19, 20, 21]))
-            depth = int(rng.integers(1, 9)) if variant in (2, 5, 6, 15, 16, 17, 18, 19, 20, 21) else 1
+            variant = int(rng.choice([1, 2, 5, 6, 9, 13, 15, 16, 17, 18, 19, 20, 21, 22, 23]))
+            depth = int(rng.integers(1, 9)) if variant in (2, 5, 6, 15, 16, 17, 18, 19, 20, 21, 22, 23) else 1
         elif kind == "HEAT3D":
             shape = (int(rng.integers(1, 9)), int(rng.integers(1, 50)), int(rng.integers(1, 30)) * 4)
             variant = int(rng.choice([1, 2, 5, 6, 11]))

@@ -139,6 +139,23 @@ def test_heat2d_strip_temporal_variant_bitwise(kb, shape, tdepth, tile):
     assert np.array_equal(base, run_heat2d(kb, shape, steps, b=3, seed=8, tile=tile, tdepth=tdepth))
 
 
+@pytest.mark.parametrize("shape", [(70, 133), (256, 256), (33, 65), (1, 40), (40, 1), (3, 5), (100, 9), (130, 200)])
+@pytest.mark.parametrize("tdepth", [1, 3, 8, 12, 16])
+@pytest.mark.parametrize("tile", [22, 23])
+def test_heat2d_wide_strip_temporal_variant_bitwise(kb, shape, tdepth, tile):
+    """Variants 22 and 23 (32x32 tiles in regions of up to 64 x 64 cells, 4
+    or 8 rows per thread, a wave per row group, up to 16 steps per launch):
+    same bits as the one-cell kernel per launch and in graph batches (37
+    steps leave a remainder), and within 1e-5 of the float32 oracle."""
+    announce(f"heat2d wide strip {shape} variant {tile} t={tdepth}")
+    steps = 37
+    base = run_heat2d(kb, shape, steps, seed=11)
+    assert np.array_equal(base, run_heat2d(kb, shape, steps, seed=11, tile=tile, tdepth=tdepth))
+    assert np.array_equal(base, run_heat2d(kb, shape, steps, b=3, seed=11, tile=tile, tdepth=tdepth))
+    T0, P = synth.heat2d_init(11, *shape)
+    assert rel_maxnorm(base, oracle.heat2d(T0, P, steps, dtype=np.float32)) < 1e-5
+
+
 @pytest.mark.parametrize("tile", [15, 16, 17])
 def test_heat2d_strip_depth_limit(kb, tile):
     with kb.Problem(kb.HEAT2D, (64, 64), coeffs(HEAT), 0) as p:
