@@ -196,8 +196,11 @@ int sg_fill_iter(const kb_problem *h, int cur, Launch *L) {
     sg_make_check(L[n], L[n + 1], k);
     n += 2;
   }
+  // fallback: the k plain steps in one predicated launch of the register
+  // strips over 32x32 tiles (512 threads per block; a predicated-off launch
+  // of the 64x16 LDS tiles, 1024 threads per block, costs more)
   Heat2DArgs f{Tc, Tn, h->P, H, W, h->hk, S.ksteps, S.at<int>(S.L.flag)};
-  if (!make_heat2d_tile(L[n++], f, 4)) return -1;
+  if (!make_heat2d_strip(L[n++], f, 23)) return -1;
   return n;
 }
 
