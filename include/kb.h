@@ -218,8 +218,10 @@ extern "C" {
 #define KB_OPT_TILE      2
 /* KB_OPT_TDEPTH: temporal-blocking depth t >= 1: one launch of a
  *   temporal-blocking variant advances t steps (KB_HEAT2D LDS tile 1..16,
- *   register strips 1..8; KB_HEAT3D variant 5 1..6, variant 11 1..8; KB_HEAT2D_MULTI
- *   variants 3, 4 1..8).  Other variants ignore it.  kb_run advances
+ *   register strips 15..17 1..8, register regions 18..21 1..8, register
+ *   strips 22, 23 1..16; KB_HEAT3D variant 5 1..6, variant 11 1..8;
+ *   KB_HEAT2D_MULTI variants 3..6 1..8; a launch whose variant does not
+ *   allow t fails with KB_EINVAL).  Other variants ignore it.  kb_run advances
  *   floor(n_steps / t) iterations of t steps, then n_steps mod t single
  *   steps per launch.                                                      */
 #define KB_OPT_TDEPTH    3

@@ -338,8 +338,8 @@ constexpr int kMaxK = 16;
 int launch_iter(kb_problem *h, int depth, hipStream_t s) {
   Launch L[kMaxK];
   const int k = fill_iter(h, h->cur, depth, L, reduce_due(h, h->step_count, depth));
-  h->step_count += depth;
   if (k < 0) return fail(KB_EINVAL, "invalid kernel variant %d / depth %d", h->tile, depth);
+  h->step_count += depth;
   for (int q = 0; q < k; ++q) {
     HIPCHK(hipLaunchKernel(L[q].func, L[q].grid, L[q].block, L[q].params(), L[q].lds, s));
   }
