@@ -167,31 +167,39 @@ __global__ __launch_bounds__(CWID * (CWID / RPT)) void heat2d_strip_tb_kernel(co
     v[i] = a.T[gi];
     pw[i] = a.P[gi];
   }
-  int b = 0;
   ends[0][0][g][cx] = v[0];
   ends[0][1][g][cx] = v[RPT - 1];
   __syncthreads();
-  for (int s = 0; s < t; ++s) {
+  // one step from x to o, strip ends read from LDS buffer b, written to b^1
+  auto step = [&](const float (&x)[RPT], float (&o)[RPT], int b) {
     // north of row r0 and south of row r0+RPT-1 (clamped at the region edge)
-    const float top = g > 0 ? ends[b][1][g - 1][cx] : v[0];
-    const float bot = g < NG - 1 ? ends[b][0][g + 1][cx] : v[RPT - 1];
-    float nv[RPT];
+    const float top = g > 0 ? ends[b][1][g - 1][cx] : x[0];
+    const float bot = g < NG - 1 ? ends[b][0][g + 1][cx] : x[RPT - 1];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = r0 + i;
-      float wv = lane_west_open(v[i]), ev = lane_east_open(v[i]);
-      if (cx == 0) wv = v[i];
-      if (cx >= W - 1) ev = v[i];
-      const float n = r == 0 ? v[i] : (i == 0 ? top : v[i - 1]);
-      const float so = r >= H - 1 ? v[i] : (i == RPT - 1 ? bot : v[i + 1]);
-      nv[i] = heat_update(v[i], n, so, wv, ev, pw[i], a.k);
+      float wv = lane_west_open(x[i]), ev = lane_east_open(x[i]);
+      if (cx == 0) wv = x[i];
+      if (cx >= W - 1) ev = x[i];
+      const float n = r == 0 ? x[i] : (i == 0 ? top : x[i - 1]);
+      const float so = r >= H - 1 ? x[i] : (i == RPT - 1 ? bot : x[i + 1]);
+      o[i] = heat_update(x[i], n, so, wv, ev, pw[i], a.k);
     }
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) v[i] = nv[i];
-    b ^= 1;
-    ends[b][0][g][cx] = v[0];
-    ends[b][1][g][cx] = v[RPT - 1];
+    ends[b ^ 1][0][g][cx] = o[0];
+    ends[b ^ 1][1][g][cx] = o[RPT - 1];
     __syncthreads();
+  };
+  // two steps at a time between two register sets (no register copies)
+  float u[RPT];
+  int s = 0;
+  for (; s + 2 <= t; s += 2) {
+    step(v, u, 0);
+    step(u, v, 1);
+  }
+  if (s < t) {
+    step(v, u, 0);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) v[i] = u[i];
   }
   if (cx < W) {
     const int gx = rx_lo + cx;
