@@ -75,7 +75,7 @@ KERNEL_RUNS = {
     # name: (problem, shape, coeffs-attr, variant, steps per launch loop[, temporal depth])
     "skeleton_2p16": ("SKELETON", (N_ELEM,), None, 1, 100),
     "heat2d_16384": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 13, 5),
-    "heat3d_8x4096": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 6, 5),
+    "heat3d_8x4096": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 9, 5),
     "fdtd_256": ("FDTD3D", (256, 64), "FDTD_COEFFS", 2, 5),
     "fdtd_256_fused": ("FDTD3D", (256, 64), "FDTD_COEFFS", 7, 10),
     "surrogate_512": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 1, 160),
@@ -466,7 +466,7 @@ def workloads(kb, pm, autotune, np):
     for name, prob, shp, var, bytes_per_cell in (
             ("heat2d_16384^2", kb.HEAT2D, (16384, 16384), 13, 12.0),
             ("heat2d_8192^2", kb.HEAT2D, (8192, 8192), 13, 12.0),
-            ("heat3d_8x4096^2", kb.HEAT3D, (8, 4096, 4096), 6, 8.5)):
+            ("heat3d_8x4096^2", kb.HEAT3D, (8, 4096, 4096), 9, 8.5)):
         with kb.Problem(prob, shp, kb.HEAT_COEFFS, SEED) as p:
             p.set_option(kb.OPT_TILE, var)
             t = arm(p, 20, 0, 2) / 20

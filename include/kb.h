@@ -188,7 +188,7 @@ extern "C" {
  *              streaming stores and P loads (nx % 4 == 0); 9, 10 = 2, 4 rows with the
  *              layer after next loaded one layer ahead; 11 = temporal
  *              blocking with every layer of a region column's rows in
- *              registers (KB_OPT_TDEPTH 1..8; nz <= 8).  Default: 6 if nx % 4 == 0
+ *              registers (KB_OPT_TDEPTH 1..8; nz <= 8).  Default: 9 if nx % 4 == 0
  *              and ny*nx >= 2^20, else 1.
  *   KB_SKELETON: 1 = 4 elements per thread (default), 2 = 1, 3 = 8.
  *   KB_FDTD3D: separate H and E kernels (3 kernels per iteration with the

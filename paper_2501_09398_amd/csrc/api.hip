@@ -202,7 +202,7 @@ int heat2d_variant(const kb_problem *h) {
 }
 int heat3d_variant(const kb_problem *h) {
   if (h->tile != 0) return h->tile;
-  return (h->nx % 4 == 0 && h->ny * h->nx >= (1 << 20)) ? 6 : 1;
+  return (h->nx % 4 == 0 && h->ny * h->nx >= (1 << 20)) ? 9 : 1;
 }
 bool heat2d_is_tile(int v) { return (v >= 2 && v <= 7) || (v >= 15 && v <= 23); }   // temporal blocking
 
