@@ -50,6 +50,35 @@ def _setup(L):
         f.restype = C.c_int
     L.or_fdtd_pulse.argtypes = [C.c_double, C.c_double, C.c_long, C.c_void_p, C.c_void_p]
     L.or_fdtd_pulse.restype = None
+    L.or_set_threads.argtypes = [C.c_int]
+    L.or_set_threads.restype = None
+    L.or_get_threads.restype = C.c_int
+
+
+def set_threads(n):
+    """Threads of the oracle's loops over independent rows, planes and
+    elements (the results are the same bits for every count)."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().or_get_threads())
+
+
+class threads:
+    """Context manager: run the oracle with n threads, then restore."""
+
+    def __init__(self, n):
+        self.n = int(n)
+
+    def __enter__(self):
+        self.old = get_threads()
+        set_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.old)
+        return False
 
 
 def _sfx(dtype):
@@ -162,6 +191,12 @@ def _setup_sg(L):
     L.or_sg_conv3x3.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_long, C.c_long,
                                 C.c_void_p]
     L.or_sg_conv3x3.restype = None
+    L.or_sg_conv3x3_adjoint_input.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_long, C.c_long,
+                                              C.c_void_p]
+    L.or_sg_conv3x3_adjoint_input.restype = None
+    L.or_sg_conv3x3_adjoint_weights.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_long,
+                                                C.c_long, C.c_void_p, C.c_void_p]
+    L.or_sg_conv3x3_adjoint_weights.restype = None
     L.or_sg_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_long, C.c_long, C.c_int, C.c_void_p]
     L.or_sg_forward.restype = C.c_int
     L.or_sg_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_long, C.c_long,
@@ -205,6 +240,36 @@ def sg_conv3x3(W, b, x):
         bp = _ptr(b)
     _sg().or_sg_conv3x3(_ptr(W), bp, _ptr(x), ci, co, H, Wd, _ptr(out))
     return out
+
+
+def sg_conv3x3_adjoint_input(W, g):
+    """Adjoint of sg_conv3x3 in its input: W[co][ci][3][3], g[co][H][W] ->
+    din[ci][H][W] = sum over (co, tap, pixel p) with clamp(p + tap) = q of
+    W[co][ci][tap] g[co][p], float64."""
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    co, ci = W.shape[:2]
+    assert g.shape[0] == co
+    _, H, Wd = g.shape
+    out = np.empty((ci, H, Wd), np.float64)
+    _sg().or_sg_conv3x3_adjoint_input(_ptr(W), _ptr(g), ci, co, H, Wd, _ptr(out))
+    return out
+
+
+def sg_conv3x3_adjoint_weights(x, g, gb=None):
+    """Adjoint of sg_conv3x3 in its weights and bias: x[ci][H][W] (the
+    layer input), g[co][H][W] (gradient of its output; gb, default g, is
+    the one summed into the bias) -> (dW[co][ci][3][3], db[co]), float64."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    gb = g if gb is None else np.ascontiguousarray(gb, dtype=np.float64)
+    ci, H, Wd = x.shape
+    co = g.shape[0]
+    assert g.shape == (co, H, Wd) and gb.shape == g.shape
+    dW = np.zeros((co, ci, 3, 3), np.float64)
+    db = np.zeros(co, np.float64)
+    _sg().or_sg_conv3x3_adjoint_weights(_ptr(x), _ptr(g), _ptr(gb), ci, co, H, Wd, _ptr(dW), _ptr(db))
+    return dW, db
 
 
 def sg_forward(w, T0, P, round_bf16=True):

@@ -15,6 +15,7 @@
  *   or_fdtd_pulse  the soft-source amplitude table
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -48,4 +49,9 @@ void or_fdtd_pulse(double n0, double w, long count, double *g64, float *g32)
     }
 }
 
-int or_abi_version(void) { return 1; }
+/* Threads of the loops that split independent rows, planes or elements
+ * (n >= 1; the results are the same bits for every n).                   */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }
+
+int or_abi_version(void) { return 2; }

@@ -7,8 +7,11 @@
  * GPU library.  Every loop follows the definition it cites; there is no
  * blocking, fusion or reordering beyond that definition.
  *
- * Build: gcc -O2 -ffp-contract=off, so that no multiply-add is fused unless
- * the source calls fma explicitly.
+ * Build: gcc -O2 -ffp-contract=off -fopenmp, so that no multiply-add is
+ * fused unless the source calls fma explicitly.  OpenMP threads only split
+ * loops whose iterations are independent (rows, planes, elements); every
+ * value is computed by the same operations in the same order whatever the
+ * thread count, so the results do not depend on it (or_set_threads).
  */
 
 /* ------------------------------------------------------------------------ */
@@ -22,6 +25,8 @@ static void SFX(heat2d_step)(const REAL *T, const REAL *P, REAL *out,
                              long ny, long nx, REAL c, REAL Rx, REAL Ry,
                              REAL Rz, REAL Tamb)
 {
+    /* rows are independent within a step (threads only split the rows) */
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < ny; ++i) {
         long in = i > 0 ? i - 1 : 0;
         long is = i < ny - 1 ? i + 1 : ny - 1;
@@ -70,10 +75,11 @@ static void SFX(heat3d_step)(const REAL *T, const REAL *P, REAL *out,
                              REAL Ry, REAL Rz, REAL Tamb)
 {
     long plane = ny * nx;
+#pragma omp parallel for collapse(2) schedule(static)
     for (long z = 0; z < nz; ++z) {
-        long zd = z > 0 ? z - 1 : 0;
-        long zu = z < nz - 1 ? z + 1 : nz - 1;
         for (long i = 0; i < ny; ++i) {
+            long zd = z > 0 ? z - 1 : 0;
+            long zu = z < nz - 1 ? z + 1 : nz - 1;
             long in = i > 0 ? i - 1 : 0;
             long is = i < ny - 1 ? i + 1 : ny - 1;
             for (long j = 0; j < nx; ++j) {
@@ -124,11 +130,16 @@ int SFX(or_heat3d)(const REAL *T0, const REAL *P, long nz, long ny, long nx,
 int SFX(or_skeleton)(const REAL *x0, long n, const REAL *a, const REAL *b,
                      int K, long iters, REAL *out)
 {
-    memcpy(out, x0, sizeof(REAL) * n);
-    for (long it = 0; it < iters; ++it)
-        for (int k = 0; k < K; ++k)
-            for (long e = 0; e < n; ++e)
-                out[e] = SKEL_AXPB(a[k], out[e], b[k]);
+    /* every element runs its own chain: iteration by iteration, kernel by
+     * kernel, the same operations as the kernel-major loop of the method */
+#pragma omp parallel for schedule(static)
+    for (long e = 0; e < n; ++e) {
+        REAL x = x0[e];
+        for (long it = 0; it < iters; ++it)
+            for (int k = 0; k < K; ++k)
+                x = SKEL_AXPB(a[k], x, b[k]);
+        out[e] = x;
+    }
     return 0;
 }
 
@@ -148,6 +159,8 @@ static void SFX(fdtd_h)(REAL *Hx, REAL *Hy, REAL *Hz, const REAL *Ex,
                         const REAL *Ey, const REAL *Ez, long N, REAL dt)
 {
     long M = N + 1;
+    /* each H node reads only E: the planes are independent */
+#pragma omp parallel for schedule(static)
     for (long k = 0; k <= N; ++k)
         for (long j = 0; j <= N; ++j)
             for (long i = 0; i <= N; ++i) {
@@ -167,6 +180,8 @@ static void SFX(fdtd_e)(REAL *Ex, REAL *Ey, REAL *Ez, const REAL *Hx,
                         const REAL *Hy, const REAL *Hz, long N, REAL dt)
 {
     long M = N + 1;
+    /* each E node reads only H: the planes are independent */
+#pragma omp parallel for schedule(static)
     for (long k = 0; k <= N; ++k)
         for (long j = 0; j <= N; ++j)
             for (long i = 0; i <= N; ++i) {

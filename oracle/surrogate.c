@@ -13,6 +13,12 @@
  * that enter the weight- and data-gradient products.  Biases, pre-
  * activations, GELU and its derivative, and all sums stay in double.
  *
+ * The single convolution and its two adjoints (in the input, in the
+ * weights) are exported as well, so that each layer of a GPU evaluation can
+ * be checked on its own operands.  OpenMP threads split output channels
+ * (input channels for the input adjoint); every sum runs in the same order
+ * for any thread count.
+ *
  * Weight vector (19393 doubles), canonical order:
  *   W1[32][2][3][3], b1[32], W2[32][32][3][3], b2[32],
  *   W3[32][32][3][3], b3[32], W4[1][32][3][3], b4[1]
@@ -69,6 +75,7 @@ static long clampi(long v, long n) { return v < 0 ? 0 : (v > n - 1 ? n - 1 : v);
 void or_sg_conv3x3(const double *W, const double *b, const double *in, int cin, int cout,
                    long H, long Wd, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int co = 0; co < cout; ++co)
         for (long y = 0; y < H; ++y)
             for (long x = 0; x < Wd; ++x) {
@@ -82,30 +89,34 @@ void or_sg_conv3x3(const double *W, const double *b, const double *in, int cin, 
             }
 }
 
-/* Adjoint of or_sg_conv3x3 in its input: din[ci][q] += sum over (co, tap,
- * pixel) with clamp(pixel + tap) = q of W[co][ci][tap] * g[co][pixel].    */
-static void conv3x3_adjoint_input(const double *W, const double *g, int cin, int cout, long H, long Wd,
-                                  double *din)
+/* Adjoint of or_sg_conv3x3 in its input: din[ci][q] = sum over (co, tap,
+ * pixel) with clamp(pixel + tap) = q of W[co][ci][tap] * g[co][pixel].
+ * Each input channel is accumulated by one thread, in (co, pixel, tap)
+ * order.                                                                  */
+void or_sg_conv3x3_adjoint_input(const double *W, const double *g, int cin, int cout, long H, long Wd,
+                                 double *din)
 {
     memset(din, 0, sizeof(double) * cin * H * Wd);
-    for (int co = 0; co < cout; ++co)
-        for (long y = 0; y < H; ++y)
-            for (long x = 0; x < Wd; ++x) {
-                double gv = g[(co * H + y) * Wd + x];
-                if (gv == 0.0) continue;
-                for (int ci = 0; ci < cin; ++ci)
+#pragma omp parallel for schedule(static)
+    for (int ci = 0; ci < cin; ++ci)
+        for (int co = 0; co < cout; ++co)
+            for (long y = 0; y < H; ++y)
+                for (long x = 0; x < Wd; ++x) {
+                    double gv = g[(co * H + y) * Wd + x];
+                    if (gv == 0.0) continue;
                     for (int ky = 0; ky < 3; ++ky)
                         for (int kx = 0; kx < 3; ++kx)
                             din[(ci * H + clampi(y + ky - 1, H)) * Wd + clampi(x + kx - 1, Wd)] +=
                                 W[((co * cin + ci) * 3 + ky) * 3 + kx] * gv;
-            }
+                }
 }
 
 /* Gradient in the weights: dW[co][ci][tap] += sum_pixel g[co][pixel] *
  * in[ci][clamp(pixel + tap)], db[co] += sum_pixel gb[co][pixel].        */
-static void conv3x3_adjoint_weights(const double *in, const double *g, const double *gb, int cin, int cout,
-                                    long H, long Wd, double *dW, double *db)
+void or_sg_conv3x3_adjoint_weights(const double *in, const double *g, const double *gb, int cin, int cout,
+                                   long H, long Wd, double *dW, double *db)
 {
+#pragma omp parallel for schedule(static)
     for (int co = 0; co < cout; ++co)
         for (long y = 0; y < H; ++y)
             for (long x = 0; x < Wd; ++x) {
@@ -195,9 +206,9 @@ int or_sg_loss_grad(const double *w, const float *T0, const float *P, const doub
     *loss = L / norm;
     for (int l = 3; l >= 0; --l) {
         const double *in = l == 0 ? t.x : t.a[l - 1];
-        conv3x3_adjoint_weights(in, g, gb, SG_CIN[l], SG_COUT[l], H, Wd, grad + wo[l], grad + bo[l]);
+        or_sg_conv3x3_adjoint_weights(in, g, gb, SG_CIN[l], SG_COUT[l], H, Wd, grad + wo[l], grad + bo[l]);
         if (l == 0) break;
-        conv3x3_adjoint_input(t.w + wo[l], g, SG_CIN[l], SG_COUT[l], H, Wd, da);
+        or_sg_conv3x3_adjoint_input(t.w + wo[l], g, SG_CIN[l], SG_COUT[l], H, Wd, da);
         for (long i = 0; i < SG_C * n; ++i) {
             gb[i] = da[i] * gelu_d(t.z[l - 1][i]);
             g[i] = rnd(gb[i], round);
