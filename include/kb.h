@@ -152,6 +152,33 @@ extern "C" {
                            KB_OPT_REDUCE_EVERY                             */
 #define KB_F_REDCOUNT 24 /* entries appended to the log (one int64; it keeps
                            counting past the log's 4096 rows)             */
+/* The tape of the last kb_sg_loss_grad / kb_sg_train_step batch of a
+ * KB_HEAT2D_SURROGATE problem (read only; KB_EINVAL before the first batch
+ * and for kb_write).  m = ncrop*crop*crop pixels in crop-major, row-major
+ * order; channels contiguous per pixel:
+ *   KB_F_SG_X        bf16 bits (uint16) [m][2]   network input (t, p)
+ *   KB_F_SG_A1..A3   bf16 bits (uint16) [m][32]  hidden activations
+ *   KB_F_SG_Z1..Z3   float [m][32]               pre-activations
+ *   KB_F_SG_Y        float [m]                   network output y
+ *   KB_F_SG_TGT      float [m]                   target (T16 - T0)/s
+ *   KB_F_SG_G4       float [m]                   dL/dy
+ *   KB_F_SG_G1..G3   float [m][32]               dL/dz of the hidden layers
+ *   KB_F_SG_GRAD     float [19393]               dL/dw (canonical order)
+ * So each convolution of the GPU path can be checked on its own operands. */
+#define KB_F_SG_X    30
+#define KB_F_SG_A1   31
+#define KB_F_SG_A2   32
+#define KB_F_SG_A3   33
+#define KB_F_SG_Z1   34
+#define KB_F_SG_Z2   35
+#define KB_F_SG_Z3   36
+#define KB_F_SG_Y    37
+#define KB_F_SG_TGT  38
+#define KB_F_SG_G4   39
+#define KB_F_SG_G1   40
+#define KB_F_SG_G2   41
+#define KB_F_SG_G3   42
+#define KB_F_SG_GRAD 43
 
 /* ---- options (kb_set_option) ------------------------------------------- */
 /* KB_OPT_BUILDER: how a batch graph is built.

@@ -197,6 +197,10 @@ def _setup_sg(L):
     L.or_sg_conv3x3_adjoint_weights.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_long,
                                                 C.c_long, C.c_void_p, C.c_void_p]
     L.or_sg_conv3x3_adjoint_weights.restype = None
+    L.or_bf16_round_n.argtypes = [C.c_void_p, C.c_long, C.c_void_p]
+    L.or_bf16_round_n.restype = None
+    L.or_sg_gelu.argtypes = [C.c_void_p, C.c_long, C.c_void_p, C.c_void_p]
+    L.or_sg_gelu.restype = None
     L.or_sg_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_long, C.c_long, C.c_int, C.c_void_p]
     L.or_sg_forward.restype = C.c_int
     L.or_sg_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_long, C.c_long,
@@ -223,7 +227,12 @@ def bf16_round(v):
     """Round each value to the nearest bf16 (ties to even), in float64."""
     L = _sg()
     a = np.asarray(v, dtype=np.float64)
-    return np.vectorize(L.or_bf16_round, otypes=[np.float64])(a) if a.ndim else L.or_bf16_round(float(a))
+    if not a.ndim:
+        return L.or_bf16_round(float(a))
+    a = np.ascontiguousarray(a)
+    out = np.empty_like(a)
+    L.or_bf16_round_n(_ptr(a), a.size, _ptr(out))
+    return out
 
 
 def sg_conv3x3(W, b, x):
@@ -240,6 +249,15 @@ def sg_conv3x3(W, b, x):
         bp = _ptr(b)
     _sg().or_sg_conv3x3(_ptr(W), bp, _ptr(x), ci, co, H, Wd, _ptr(out))
     return out
+
+
+def sg_gelu(z):
+    """(GELU(z), GELU'(z)) elementwise, exact erf form, float64."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.empty_like(z)
+    dout = np.empty_like(z)
+    _sg().or_sg_gelu(_ptr(z), z.size, _ptr(out), _ptr(dout))
+    return out, dout
 
 
 def sg_conv3x3_adjoint_input(W, g):

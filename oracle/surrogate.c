@@ -59,6 +59,11 @@ double or_bf16_round(double v)
     return ldexp(r, e - 8);
 }
 
+void or_bf16_round_n(const double *v, long n, double *out)
+{
+    for (long i = 0; i < n; ++i) out[i] = or_bf16_round(v[i]);
+}
+
 static double rnd(double v, int round) { return round ? or_bf16_round(v) : v; }
 
 static double gelu(double x) { return 0.5 * x * (1.0 + erf(x / sqrt(2.0))); }
@@ -66,6 +71,16 @@ static double gelu(double x) { return 0.5 * x * (1.0 + erf(x / sqrt(2.0))); }
 static double gelu_d(double x)
 {
     return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * SG_PI);
+}
+
+/* GELU and its derivative elementwise (for checks of a GPU layer's
+ * activation and gradient epilogues on the GPU's own pre-activations).   */
+void or_sg_gelu(const double *z, long n, double *out, double *dout)
+{
+    for (long i = 0; i < n; ++i) {
+        if (out) out[i] = gelu(z[i]);
+        if (dout) dout[i] = gelu_d(z[i]);
+    }
 }
 
 static long clampi(long v, long n) { return v < 0 ? 0 : (v > n - 1 ? n - 1 : v); }

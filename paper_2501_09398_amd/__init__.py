@@ -28,6 +28,9 @@ F_T, F_P, F_X, F_A, F_B = 1, 2, 3, 4, 5
 F_EX, F_EY, F_EZ, F_HX, F_HY, F_HZ, F_PROBE, F_STEP = 10, 11, 12, 13, 14, 15, 16, 17
 F_W, F_SGSTATS, F_RESID = 20, 21, 22
 F_REDLOG, F_REDCOUNT = 23, 24
+# the surrogate's training tape (read only)
+F_SG_X, F_SG_A1, F_SG_A2, F_SG_A3, F_SG_Z1, F_SG_Z2, F_SG_Z3 = 30, 31, 32, 33, 34, 35, 36
+F_SG_Y, F_SG_TGT, F_SG_G4, F_SG_G1, F_SG_G2, F_SG_G3, F_SG_GRAD = 37, 38, 39, 40, 41, 42, 43
 SG_NW = 19393
 FDTD_FIELDS = {"Ex": F_EX, "Ey": F_EY, "Ez": F_EZ, "Hx": F_HX, "Hy": F_HY, "Hz": F_HZ}
 # options
@@ -152,6 +155,7 @@ class Problem:
         self.shape = tuple(int(s) for s in shape)
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self._h = C.c_void_p()
+        self._sg_m = 0                     # pixels of the last training batch (tape fields)
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
             nbytes = workspace_bytes(problem, shape)
@@ -209,6 +213,17 @@ class Problem:
             return (4096, 4), np.float64
         if field == F_REDCOUNT:
             return (1,), np.int64
+        if F_SG_X <= field <= F_SG_GRAD:
+            m = self._sg_m
+            if field == F_SG_X:
+                return (m, 2), np.uint16
+            if field in (F_SG_A1, F_SG_A2, F_SG_A3):
+                return (m, 32), np.uint16
+            if field in (F_SG_Z1, F_SG_Z2, F_SG_Z3, F_SG_G1, F_SG_G2, F_SG_G3):
+                return (m, 32), np.float32
+            if field == F_SG_GRAD:
+                return (SG_NW,), np.float32
+            return (m,), np.float32
         if field in (F_A, F_B):
             return (self.kernels_per_iter(),), np.float32
         if field == F_X:
@@ -275,6 +290,7 @@ class Problem:
                                      C.c_void_p(T16.data_ptr()), nf, H, W, cr.ctypes.data_as(C.c_void_p),
                                      cr.shape[0], int(crop), C.byref(loss),
                                      grad.ctypes.data_as(C.POINTER(C.c_float))))
+        self._sg_m = cr.shape[0] * int(crop) ** 2
         return loss.value, grad
 
     def sg_train_step(self, T0, P, T16, crops, crop, lr):
@@ -286,6 +302,7 @@ class Problem:
         _check(lib().kb_sg_train_step(self._h, C.c_void_p(T0.data_ptr()), C.c_void_p(P.data_ptr()),
                                       C.c_void_p(T16.data_ptr()), nf, H, W, cr.ctypes.data_as(C.c_void_p),
                                       cr.shape[0], int(crop), float(lr), C.byref(loss)))
+        self._sg_m = cr.shape[0] * int(crop) ** 2
         return loss.value
 
     def destroy(self):

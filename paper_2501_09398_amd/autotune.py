@@ -13,6 +13,10 @@ per problem and shape, in two stages, through the C ABI only:
    sizes (divisors of the iteration count, Eq. 4), measure T_C and T_E with
    repeats, fit Eq. 2 and Eq. 6 (perfmodel) and take the b that minimises
    the modelled T = T_C + T_E (Eq. 1); the measured best b is reported too.
+   Eq. 2 is fitted per graph: a run of an alternating (ping-pong) problem
+   with odd b builds one graph per start buffer, so its T_C is divided by
+   the graphs it built, and the model charges each b the graphs its run
+   builds.
 
 The objective of the batch stage is the paper's (creation included); the
 warm per-step time at that b is reported beside it.
@@ -131,6 +135,7 @@ def tune(kb, problem, shape, coeffs, n_steps, seed=0, probe_steps=None, b_probe=
         p.set_option(kb.OPT_TILE, best_v)
         p.set_option(kb.OPT_TDEPTH, best_t)
         p.set_option(kb.OPT_GRAPH_CACHE, 0)
+        graphs = {}
         for b in b_candidates:
             tc, te = [], []
             for _ in range(reps):
@@ -138,12 +143,15 @@ def tune(kb, problem, shape, coeffs, n_steps, seed=0, probe_steps=None, b_probe=
                 tm = p.last_timing()
                 tc.append(tm["t_create_s"])
                 te.append(tm["t_exec_s"])
+                graphs[b] = int(tm["n_graphs_built"])
             sweep.append((b, float(np.median(tc)), float(np.median(te))))
     S = np.array([s[0] for s in sweep], float)
     model = None
     if len(sweep) >= 3:
-        model = pm.Model(pm.fit_creation(K * S, [s[1] for s in sweep]),
-                         pm.fit_execution(S, [s[2] for s in sweep]), K=K)
+        per_graph = [s[1] / max(1, graphs[s[0]]) for s in sweep]
+        model = pm.Model(pm.fit_creation(K * S, per_graph),
+                         pm.fit_execution(S, [s[2] for s in sweep]), K=K,
+                         graphs={b: max(1, g) for b, g in graphs.items()})
         b_star, _ = model.best(b_candidates)
     measured = {s[0]: s[1] + s[2] for s in sweep}
     b_meas = min(measured, key=measured.get)

@@ -500,6 +500,9 @@ bool field_info(const kb_problem *h, int field, float **dev, size_t *bytes, bool
       if (h->kind != KB_FDTD3D) return false;
       *dev = reinterpret_cast<float *>(h->step); *bytes = 8; return true;
     case KB_F_W: case KB_F_SGSTATS: case KB_F_RESID:
+    case KB_F_SG_X: case KB_F_SG_A1: case KB_F_SG_A2: case KB_F_SG_A3: case KB_F_SG_Z1: case KB_F_SG_Z2:
+    case KB_F_SG_Z3: case KB_F_SG_Y: case KB_F_SG_TGT: case KB_F_SG_G4: case KB_F_SG_G1: case KB_F_SG_G2:
+    case KB_F_SG_G3: case KB_F_SG_GRAD:
       if (h->kind != KB_HEAT2D_SURROGATE) return false;
       return sg_field(h, field, dev, bytes);
     case KB_F_REDLOG:
@@ -776,6 +779,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
   switch (option) {
     case KB_OPT_BUILDER:
       if (value != 0 && value != 1) return fail(KB_EINVAL, "builder must be 0 or 1");
+      if (h->builder != value) clear_cache(h);   // cached graphs belong to the other builder
       h->builder = (int)value;
       break;
     case KB_OPT_TILE: {
@@ -1057,6 +1061,7 @@ int kb_read(kb_problem *h, int field, void *dst, size_t bytes, int dst_on_device
 
 int kb_write(kb_problem *h, int field, const void *src, size_t bytes, int src_on_device) {
   if (!h || !src) return fail(KB_EINVAL, "null argument");
+  if (field >= KB_F_SG_X && field <= KB_F_SG_GRAD) return fail(KB_EINVAL, "field %d is read only", field);
   float *dev = nullptr;
   size_t need = 0, rows = 0, pitch = 0;
   bool hv = false;

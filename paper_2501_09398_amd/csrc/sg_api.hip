@@ -23,7 +23,7 @@ constexpr int kSgMaxNet = 1024;           // persistent blocks of the fused kern
 struct SgLayout {
   size_t total = 0;
   size_t T[2], P, x, act[2];
-  size_t T0c, Pc, tgt, xt, a[3], z[3], yt, g4, g[2], pw, pb, lossp, loss, crops;
+  size_t T0c, Pc, tgt, xt, a[3], z[3], yt, g4, g[3], pw, pb, lossp, loss, crops;
   size_t w, grad, m, v, fwd1, fwd2, fwd3, fwd4, bwd2, bwd3, bwd4;
   size_t chk, plain, psum, flag, hist, counters;
 };
@@ -42,7 +42,8 @@ bool sg_layout(const int64_t *shape, int ndim, SgLayout &L) {
   const size_t mm = (size_t)m;
   L.T0c = add(mm * 4); L.Pc = add(mm * 4); L.tgt = add(mm * 4); L.xt = add(mm * 4);
   for (int l = 0; l < 3; ++l) { L.a[l] = add(mm * 64); L.z[l] = add(mm * 128); }
-  L.yt = add(mm * 4); L.g4 = add(mm * 4); L.g[0] = add(mm * 128); L.g[1] = add(mm * 128);
+  L.yt = add(mm * 4); L.g4 = add(mm * 4);
+  for (int l = 0; l < 3; ++l) L.g[l] = add(mm * 128);
   L.pw = add((size_t)kSgWgradBlocks * 32 * 288 * 4); L.pb = add((size_t)kSgWgradBlocks * 32 * 4);
   L.lossp = add(kSgLossBlocks * 8); L.loss = add(8); L.crops = add(kSgMaxCrops * 3 * 4);
   L.w = add(kSgNW * 4); L.grad = add(kSgNW * 4); L.m = add(kSgNW * 4); L.v = add(kSgNW * 4);
@@ -63,6 +64,7 @@ struct SgState {
   float s = 0.8f;
   double threshold = 1e-3;
   long long adam_t = 0;
+  long long last_m = 0;                    // pixels of the last training batch (tape fields)
   int tile_y[4], tile_x[4];
   int tiles_x = 0, ntiles = 0, nnet = 0;   // fused kernel: output tiles, persistent blocks
   template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -211,6 +213,22 @@ bool sg_field(const kb_problem *h, int field, float **dev, size_t *bytes) {
     case KB_F_SGSTATS: *dev = S.at<float>(S.L.counters); *bytes = 16; return true;
     case KB_F_RESID: *dev = S.at<float>(S.L.hist); *bytes = (size_t)kSgHistCap * 8; return true;
   }
+  // the tape of the last training batch (read only)
+  const size_t m = (size_t)S.last_m;
+  if (m == 0 || field < KB_F_SG_X || field > KB_F_SG_GRAD) return false;
+  switch (field) {
+    case KB_F_SG_X: *dev = S.at<float>(S.L.xt); *bytes = m * 4; return true;
+    case KB_F_SG_A1: case KB_F_SG_A2: case KB_F_SG_A3:
+      *dev = S.at<float>(S.L.a[field - KB_F_SG_A1]); *bytes = m * 64; return true;
+    case KB_F_SG_Z1: case KB_F_SG_Z2: case KB_F_SG_Z3:
+      *dev = S.at<float>(S.L.z[field - KB_F_SG_Z1]); *bytes = m * 128; return true;
+    case KB_F_SG_Y: *dev = S.at<float>(S.L.yt); *bytes = m * 4; return true;
+    case KB_F_SG_TGT: *dev = S.at<float>(S.L.tgt); *bytes = m * 4; return true;
+    case KB_F_SG_G4: *dev = S.at<float>(S.L.g4); *bytes = m * 4; return true;
+    case KB_F_SG_G1: case KB_F_SG_G2: case KB_F_SG_G3:
+      *dev = S.at<float>(S.L.g[field - KB_F_SG_G1]); *bytes = m * 128; return true;
+    case KB_F_SG_GRAD: *dev = S.at<float>(S.L.grad); *bytes = (size_t)kSgNW * 4; return true;
+  }
   return false;
 }
 
@@ -242,6 +260,7 @@ int sg_backprop(kb_problem *h, const float *T0, const float *P, const float *T16
   }
   hipStream_t st = h->stream;
   const long long m = (long long)ncrop * C * C;
+  S.last_m = 0;
   int *crops_d = S.at<int>(S.L.crops);
   SGCHK(hipMemcpyAsync(crops_d, crops, (size_t)ncrop * 3 * 4, hipMemcpyHostToDevice, st));
   float *T0c = S.at<float>(S.L.T0c), *Pc = S.at<float>(S.L.Pc), *tgt = S.at<float>(S.L.tgt);
@@ -271,7 +290,6 @@ int sg_backprop(kb_problem *h, const float *T0, const float *P, const float *T16
   const unsigned short *bw[4] = {nullptr, S.at<unsigned short>(S.L.bwd2), S.at<unsigned short>(S.L.bwd3),
                                  S.at<unsigned short>(S.L.bwd4)};
   const float *gl = g4;            // gradient of layer l's output
-  int gi = 0;
   for (int l = 3; l >= 0; --l) {
     const int cin = kSgCin[l], cout = kSgCout[l];
     SGCHK(sg_launch_wgrad(SgWgradArgs{gl, inp[l], S.at<float>(S.L.pw), S.at<float>(S.L.pb), ncrop, C, C}, cin,
@@ -280,11 +298,11 @@ int sg_backprop(kb_problem *h, const float *T0, const float *P, const float *T16
                                         grad + kSgOffB[l], kSgWgradBlocks, cin, cout},
                            st));
     if (l == 0) break;
-    float *gout = S.at<float>(S.L.g[gi]);
+    float *gout = S.at<float>(S.L.g[l - 1]);   // dL/dz of layer l's input (kept for the tape)
     SGCHK(sg_launch_dgrad(SgDgradArgs{gl, bw[l], S.at<float>(S.L.z[l - 1]), gout, m, C, C}, cout, st));
     gl = gout;
-    gi ^= 1;
   }
+  S.last_m = m;
   return KB_OK;
 }
 

@@ -22,11 +22,17 @@ against b and scaled to n iterations; both of Eq. 6's terms are linear in
 the iteration count), and minimises Eq. 1.
 
 Requirements on the step: replayable (no host synchronisation, no host-side
-decisions on device values, no reallocation of the state); if it alternates
-between buffers through Python state, an even number of calls must restore
-that state (use even b).  Capture records whatever the step enqueues; avoid
-library calls that record memset nodes (some reductions do), whose replays
-after the first can differ.
+decisions on device values, no reallocation of the state).  A step that
+alternates between buffers through Python state (it swaps references after
+each call) is only replayable with a b that brings the references back to
+where they were: a graph bakes in the buffers of the calls it recorded, so
+after an odd b of a two-buffer step the second replay would read the wrong
+buffer.  Give such a step's buffer list as ``state`` (the mutable list of
+tensors that the step reorders): each capture compares it before and after
+the b recorded calls and, if the buffers moved, puts the list back and
+raises ValueError.  Capture records whatever the step enqueues;
+avoid library calls that record memset nodes (some reductions do), whose
+replays after the first can differ.
 """
 from __future__ import annotations
 
@@ -39,20 +45,31 @@ from . import perfmodel as pm
 
 
 class BatchedLoop:
-    def __init__(self, step, device=None):
+    def __init__(self, step, device=None, state=None):
         self.step = step
+        self.state = state          # the step's buffer list, which it may reorder (or None)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._graphs = {}
 
     def _capture(self, b):
-        """Record b calls of the step; returns (graph, T_C seconds)."""
+        """Record b calls of the step; returns (graph, T_C seconds).
+        Raises ValueError when the declared state does not come back to the
+        same buffers after the b calls (the graph would replay from the
+        wrong ones); the list is then put back as it was (the recorded
+        calls ran no kernel)."""
         torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()
+        before = list(self.state) if self.state is not None else None
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             for _ in range(b):
                 self.step()
         torch.cuda.synchronize(self.device)
+        if before is not None and [t.data_ptr() for t in self.state] != [t.data_ptr() for t in before]:
+            self.state[:] = before
+            raise ValueError(f"the step's buffers move over {b} calls, so a graph of {b} calls cannot be "
+                             f"replayed: choose a b after which they are back in place (e.g. an even b for "
+                             f"two alternating buffers)")
         return g, time.perf_counter() - t0
 
     def graph(self, b):
@@ -118,6 +135,6 @@ class BatchedLoop:
                 "model": model.as_dict(), "sweep": sweep}
 
 
-def batch(step, device=None):
+def batch(step, device=None, state=None):
     """BatchedLoop of a step function (see the module documentation)."""
-    return BatchedLoop(step, device)
+    return BatchedLoop(step, device, state)

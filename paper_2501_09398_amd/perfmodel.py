@@ -92,11 +92,24 @@ class Model:
     creation: CreationFit
     execution: ExecutionFit
     K: int = 1        # kernels per iteration (nodes = K * S)
+    # graphs a run builds per batch size S (default one).  A problem whose
+    # iterations alternate between two buffers needs, for odd S and at least
+    # two batches, one graph per start buffer, and pays T_C twice.
+    graphs: dict | None = None
+
+    def n_graphs(self, S):
+        S = np.atleast_1d(np.asarray(S))
+        if not self.graphs:
+            return np.ones(S.shape, np.float64)
+        return np.array([float(self.graphs.get(int(s), 1)) for s in S.ravel()]).reshape(S.shape)
 
     def total(self, S):
-        """Eq. 1 with the fitted Eq. 2 and Eq. 6."""
-        S = np.asarray(S, dtype=np.float64)
-        return self.creation(self.K * S) + self.execution(S)
+        """Eq. 1 with the fitted Eq. 2 (per graph, times the graphs the run
+        builds) and Eq. 6."""
+        scalar = np.ndim(S) == 0
+        S = np.atleast_1d(np.asarray(S, dtype=np.float64))
+        t = self.n_graphs(S) * self.creation(self.K * S) + self.execution(S)
+        return t[0] if scalar else t
 
     def s_closed_form(self):
         """Continuous minimiser of k_c K S + a / S."""
@@ -113,7 +126,8 @@ class Model:
 
     def as_dict(self):
         return {"creation": asdict(self.creation), "execution": asdict(self.execution), "K": self.K,
-                "S_closed_form": self.s_closed_form()}
+                "S_closed_form": self.s_closed_form(),
+                "graphs": {str(k): v for k, v in self.graphs.items()} if self.graphs else None}
 
 
 @dataclass

@@ -21,6 +21,14 @@ class FakeKB:
            15: 3.3e-6, 16: 3.25e-6, 17: 3.35e-6, 18: 3.3e-6, 19: 3.4e-6, 20: 3.3e-6, 21: 3.4e-6, 22: 3.3e-6, 23: 3.35e-6}
     T_I, T_A, K_C, B_C = 0.5e-6, 8e-6, 3e-6, 2e-4
 
+    @staticmethod
+    def graphs(problem, b, nb):
+        """Graphs a run builds: the stencils alternate between two buffers,
+        so odd b with two or more batches needs one graph per start buffer."""
+        if nb == 0:
+            return 0
+        return 2 if problem != FakeKB.SKELETON and b % 2 == 1 and nb >= 2 else 1
+
     class Problem:
         def __init__(self, kbm, problem, shape, coeffs, seed):
             self.kbm, self.problem, self.v, self.t, self.last = kbm, problem, 1, 1, None
@@ -46,7 +54,8 @@ class FakeKB:
             tk = FakeKB.T_K[self.v] * (1 + 0.1 * t) / t * t    # deeper steps cost a little more each
             nb = iters // b
             te = iters * (tk + FakeKB.T_I) + nb * (FakeKB.T_A - FakeKB.T_I)
-            self.last = {"t_create_s": FakeKB.K_C * b + FakeKB.B_C, "t_exec_s": te}
+            g = FakeKB.graphs(self.problem, b, nb)
+            self.last = {"t_create_s": g * (FakeKB.K_C * b + FakeKB.B_C), "t_exec_s": te, "n_graphs_built": g}
 
         def last_timing(self):
             return self.last
@@ -74,8 +83,29 @@ def test_tuner_picks_fastest_kernel_and_model_batch():
     assert math.isclose(res.model["execution"]["a"], a, rel_tol=1e-9)
     assert math.isclose(res.model["creation"]["k_c"], FakeKB.K_C, rel_tol=1e-9)
     cands = [d for d in pm.divisors(n_iter) if d <= 4096]
-    expect = min(cands, key=lambda b: FakeKB.K_C * b + a / b)
+    g = lambda b: FakeKB.graphs(kb.HEAT2D, b, n_iter // b)
+    expect = min(cands, key=lambda b: g(b) * (FakeKB.K_C * b + FakeKB.B_C) + a / b)
     assert res.b == expect
+
+
+def test_tuner_charges_both_parity_graphs_for_odd_b():
+    """An alternating problem with odd b builds two graphs: the fit of
+    Eq. 2 divides T_C by the graphs built (so k_c, b_c stay per graph), and
+    the model's total charges odd b twice.  250 steps with candidates 10,
+    25 (odd: two graphs) and 50: 25 would win with one graph, and the
+    optimum moves to 50."""
+    kb = fake_kb()
+    n, cands = 250, [10, 25, 50]
+    a = n * (FakeKB.T_A - FakeKB.T_I)
+    one = {b: FakeKB.K_C * b + FakeKB.B_C + a / b for b in cands}
+    assert min(one, key=one.get) == 25
+    res = autotune.tune(kb, kb.HEAT2D, (256, 256), (), n, reps=1, b_candidates=cands,
+                        kernel_candidates_override=[(1, 1)])
+    assert math.isclose(res.model["creation"]["k_c"], FakeKB.K_C, rel_tol=1e-9)
+    assert math.isclose(res.model["creation"]["b_c"], FakeKB.B_C, rel_tol=1e-9)
+    assert res.model["graphs"] == {"10": 1, "25": 2, "50": 1}
+    two = {b: (2 if b % 2 else 1) * (FakeKB.K_C * b + FakeKB.B_C) + a / b for b in cands}
+    assert res.b == min(two, key=two.get) == 50
 
 
 @pytest.mark.parametrize("problem,shape", [(3, (8, 64, 64)), (5, (3, 100, 100, 70, 70, 64, 64))])

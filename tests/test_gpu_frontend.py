@@ -70,12 +70,50 @@ def test_alternating_buffers_with_even_batches(torch):
         return step
     be = [init.clone(), torch.empty_like(init)]
     bg = [init.clone(), torch.empty_like(init)]
-    eager, batched = frontend.batch(make(be)), frontend.batch(make(bg))
+    eager, batched = frontend.batch(make(be)), frontend.batch(make(bg), state=bg)
     for n in (40, 40, 22):
         eager.run(n, 0)
         batched.run(n, 10)
         torch.cuda.synchronize()
         assert torch.equal(be[0], bg[0])
+    # an odd b cannot be replayed (the buffers move over the recorded
+    # calls): refused, the buffer list left as it was, and the state intact
+    order = [t.data_ptr() for t in bg]
+    with pytest.raises(ValueError):
+        batched.run(21, 7)
+    assert [t.data_ptr() for t in bg] == order
+    eager.run(6, 0)
+    batched.run(6, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(be[0], bg[0])
+
+
+def test_skeleton_step_against_float64_oracle(torch):
+    """The front-end's skeleton step (torch element-wise multiply, then
+    add: two roundings per kernel) from the seeded workload inputs, in
+    graph batches, against the float64 oracle of the chain: within the
+    round-off bound of the affine recurrence, 2K u max(|x|+|b|) per
+    iteration, damped by the contraction A = a_4 a_3 a_2 a_1 < 1 (at most
+    1/(1-A) iterations' worth accumulates)."""
+    import oracle
+    import synth
+    from paper_2501_09398_amd import frontend
+    announce("frontend skeleton vs float64 oracle")
+    n, iters = 1 << 16, 300
+    x0, a, b = synth.skeleton_init(20250116, n, 4)
+    x = torch.from_numpy(x0.copy()).cuda()
+    loop = frontend.batch(make_step(x, [float(v) for v in a], [float(v) for v in b]))
+    loop.run(iters, 50)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy().astype(np.float64)
+    ref = oracle.skeleton(x0, a, b, iters)
+    A = float(np.prod(a.astype(np.float64)))
+    u = 2.0 ** -24
+    bound = min(iters, 1.0 / (1.0 - A)) * 2 * 4 * u * (max(np.abs(ref).max(), np.abs(x0).max()) + np.abs(b).max())
+    err = float(np.max(np.abs(got - ref)))
+    print(f"frontend skeleton vs float64: max |err| {err:.3e} (bound {bound:.3e}), "
+          f"vs the library's fused chain (float32 oracle) {np.max(np.abs(got - oracle.skeleton(x0, a, b, iters, dtype=np.float32))):.3e}")
+    assert err <= bound
 
 
 def test_tune_picks_an_admissible_batch(torch):

@@ -1,0 +1,172 @@
+"""Parity at the sizes the benchmark times on the large grids.
+
+The default kernels for large grids (heat2d variant 13 at 16384^2, heat3d
+variant 9 at 8 x 4096^2, the fused FDTD step with streaming stores,
+variant 7, at 256^3) and the temporal-blocking kernels timed beside them
+run here at those sizes, in the launch configurations the benchmark uses:
+
+* every variant is bit-identical, over the whole grid, to the one-cell
+  reference kernel (heat) or to the float32 oracle (FDTD, every node);
+* heat: row bands at the top edge, in the middle and at the bottom edge
+  against the float32 oracle run on the band plus a halo of one row per
+  step (a step moves information by one row, so the band's rows are an
+  exact sub-problem), within the 1e-5 relative max-norm bar.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, need_gpu, rel_maxnorm
+
+gpu = pytest.mark.gpu
+
+HEAT = (1e-3, 1.0, 1.0, 10.0, 300.0)
+
+
+@pytest.fixture(scope="module")
+def kb():
+    need_gpu()
+    import paper_2501_09398_amd as kb
+    kb.lib()
+    return kb
+
+
+def run(kb, prob, shape, steps, seed, variant, depth=1, b=0):
+    with kb.Problem(prob, shape, HEAT, seed) as p:
+        p.set_option(kb.OPT_TILE, variant)
+        p.set_option(kb.OPT_TDEPTH, depth)
+        p.run(steps, b)
+        return p.read(kb.F_T)
+
+
+def band_rows(ny, steps):
+    return [(0, 40), (ny // 2 - 20, ny // 2 + 20), (ny - 40, ny)]
+
+
+def band_inputs_2d(seed, ny, nx, lo, hi):
+    """Rows lo..hi of the seeded T0 and P (the same draws as the whole grid)."""
+    n = (hi - lo) * nx
+    T0 = synth.uniform_f32(seed, synth.TAG_T0, n, *synth.T0_RANGE, offset=lo * nx).reshape(hi - lo, nx)
+    P = synth.uniform_f32(seed, synth.TAG_P, n, *synth.P_RANGE, offset=lo * nx).reshape(hi - lo, nx)
+    return T0, P
+
+
+def band_inputs_3d(seed, nz, ny, nx, lo, hi):
+    T0 = np.stack([synth.uniform_f32(seed, synth.TAG_T0, (hi - lo) * nx, *synth.T0_RANGE,
+                                     offset=(z * ny + lo) * nx).reshape(hi - lo, nx) for z in range(nz)])
+    P = synth.uniform_f32(seed, synth.TAG_P, (hi - lo) * nx, *synth.P_RANGE, offset=lo * nx).reshape(hi - lo, nx)
+    return T0, P
+
+
+def check_bands_2d(got, seed, steps):
+    ny, nx = got.shape
+    for a, b in band_rows(ny, steps):
+        lo, hi = max(0, a - steps - 1), min(ny, b + steps + 1)
+        T0, P = band_inputs_2d(seed, ny, nx, lo, hi)
+        ref = oracle.heat2d(T0, P, steps, dtype=np.float32)
+        e = rel_maxnorm(got[a:b], ref[a - lo:b - lo])
+        e64 = rel_maxnorm(got[a:b], oracle.heat2d(T0, P, steps)[a - lo:b - lo])
+        print(f"rows {a}..{b}: vs float32 oracle {e:.2e}, vs float64 {e64:.2e}")
+        assert e < 1e-5, (a, b)
+
+
+def check_bands_3d(got, seed, steps):
+    nz, ny, nx = got.shape
+    for a, b in band_rows(ny, steps):
+        lo, hi = max(0, a - steps - 1), min(ny, b + steps + 1)
+        T0, P = band_inputs_3d(seed, nz, ny, nx, lo, hi)
+        ref = oracle.heat3d(T0, P, steps, dtype=np.float32)
+        e = rel_maxnorm(got[:, a:b], ref[:, a - lo:b - lo])
+        e64 = rel_maxnorm(got[:, a:b], oracle.heat3d(T0, P, steps)[:, a - lo:b - lo])
+        print(f"rows {a}..{b}: vs float32 oracle {e:.2e}, vs float64 {e64:.2e}")
+        assert e < 1e-5, (a, b)
+
+
+def test_band_inputs_are_the_grid_rows():
+    """The band generators draw exactly the rows of the whole grid's inputs."""
+    T0, P = synth.heat2d_init(3, 50, 70)
+    t, p = band_inputs_2d(3, 50, 70, 20, 31)
+    assert np.array_equal(t, T0[20:31]) and np.array_equal(p, P[20:31])
+    T0, P = synth.heat3d_init(4, 3, 50, 70)
+    t, p = band_inputs_3d(4, 3, 50, 70, 7, 19)
+    assert np.array_equal(t, T0[:, 7:19]) and np.array_equal(p, P[7:19])
+
+
+@gpu
+def test_heat2d_16384_default_and_temporal(kb):
+    """16384^2 (1 GiB per field): the streaming one-step kernel (variant 13,
+    the default at this size) per launch and in graph batches of 10, and
+    the 128 x 128-region temporal kernel (variant 21, t = 8), 24 steps
+    each; against the one-cell kernel and the oracle bands."""
+    shape, seed = (16384, 16384), 11
+    announce("heat2d 16384^2 variant 1 (reference), 24 steps")
+    ref24 = run(kb, kb.HEAT2D, shape, 24, seed, 1)
+    announce("heat2d 16384^2 variant 13, 24 steps per launch")
+    got = run(kb, kb.HEAT2D, shape, 24, seed, 13)
+    assert np.array_equal(got, ref24)
+    announce("heat2d 16384^2 variant 13, 24 steps in graph batches of 10")
+    assert np.array_equal(run(kb, kb.HEAT2D, shape, 24, seed, 13, b=10), ref24)
+    announce("heat2d 16384^2 variant 21 t=8, 24 steps")
+    assert np.array_equal(run(kb, kb.HEAT2D, shape, 24, seed, 21, depth=8), ref24)
+    check_bands_2d(got, seed, 24)
+
+
+@gpu
+def test_heat3d_8x4096_default_and_temporal(kb):
+    """8 x 4096^2: the register-blocked rows kernel with the layer after
+    next loaded ahead (variant 9, the default at this size) per launch and
+    in graph batches of 10, and the 3D register strips (variant 11, t = 4),
+    24 steps each; against the one-column kernel and the oracle bands (all
+    eight layers)."""
+    shape, seed = (8, 4096, 4096), 12
+    announce("heat3d 8x4096^2 variant 1 (reference), 24 steps")
+    ref24 = run(kb, kb.HEAT3D, shape, 24, seed, 1)
+    announce("heat3d 8x4096^2 variant 9, 24 steps per launch")
+    got = run(kb, kb.HEAT3D, shape, 24, seed, 9)
+    assert np.array_equal(got, ref24)
+    announce("heat3d 8x4096^2 variant 9, 24 steps in graph batches of 10")
+    assert np.array_equal(run(kb, kb.HEAT3D, shape, 24, seed, 9, b=10), ref24)
+    announce("heat3d 8x4096^2 variant 11 t=4, 24 steps")
+    assert np.array_equal(run(kb, kb.HEAT3D, shape, 24, seed, 11, depth=4), ref24)
+    check_bands_3d(got, seed, 24)
+
+
+@pytest.fixture(scope="module")
+def fdtd256():
+    """The float32 oracle at 256^3: 100 steps from zero fields with the
+    seeded source (the benchmark's workload) and 100 steps from random
+    fields (every node, walls included, starts non-zero)."""
+    N, steps, seed = 256, 100, 20250116
+    src = synth.fdtd_source_cell(seed, N)
+    _, g32 = oracle.fdtd_pulse(steps + 1)
+    zero, probe = oracle.fdtd(oracle.fdtd_zero_fields(N, np.float32), N, steps, src=src, g=g32, dtype=np.float32)
+    rng = np.random.default_rng(256)
+    M = N + 1
+    f0 = {k: rng.uniform(-1.0, 1.0, (M, M, M)).astype(np.float32) for k in oracle.FDTD_FIELDS}
+    rand, rprobe = oracle.fdtd(f0, N, steps, src=src, g=g32, dtype=np.float32)
+    return dict(N=N, steps=steps, seed=seed, zero=zero, probe=probe, f0=f0, rand=rand, rprobe=rprobe)
+
+
+@gpu
+@pytest.mark.parametrize("variant", [7, 5, 2])
+def test_fdtd_256_vs_oracle(kb, fdtd256, variant):
+    """256^3 (two field sets of 0.8 GB): 100 steps in graph batches of 100
+    (the benchmark's graph arm), fused step with streaming stores (7, the
+    default at this size), fused with plain stores (5) and the separate H
+    and E kernels (2); bit for bit with the float32 oracle on every node,
+    and the probe history."""
+    d = fdtd256
+    N, steps = d["N"], d["steps"]
+    for start in ("zero", "rand"):
+        announce(f"fdtd 256^3 {start} fields, 100 steps, b=100, variant {variant}")
+        with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, d["seed"]) as p:
+            p.set_option(kb.OPT_TILE, variant)
+            if start == "rand":
+                for k, fid in kb.FDTD_FIELDS.items():
+                    p.write(fid, d["f0"][k])
+            p.run(steps, 100)
+            probe = p.read(kb.F_PROBE)
+            for k, fid in kb.FDTD_FIELDS.items():
+                assert np.array_equal(p.read(fid), d[start][k]), (start, k)
+        assert np.array_equal(probe[:steps], d["probe"] if start == "zero" else d["rprobe"])

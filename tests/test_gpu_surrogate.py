@@ -119,6 +119,43 @@ def test_gradient_matches_oracle(kb):
         assert e < 5e-3, nm     # measured <= 2e-4 (float32 sums of bf16 products)
 
 
+def test_gradient_matches_oracle_training_batch(kb):
+    """The training batch (16 crops of 128^2, the split-K weight gradient at
+    its full size) end to end against the oracle's own forward and
+    backward on each crop.  End to end a hidden activation within float32
+    accumulation error of a bf16 tie can round the other way on one side,
+    so this is a report with a loose bound; each layer's products are
+    checked on the GPU's own operands at float32-summation tolerance in
+    test_gpu_surrogate_layers.py."""
+    announce("surrogate gradient 16 crops of 128^2")
+    (T0, P, T16), (dT0, dP, dT16) = make_fields(kb, 4, 256, 256, 52)
+    rng = np.random.default_rng(53)
+    crops = np.array([[rng.integers(0, 4), rng.integers(0, 129), rng.integers(0, 129)] for _ in range(12)]
+                     + [[0, 0, 0], [1, 128, 128], [2, 0, 128], [3, 128, 0]], np.int32)
+    w = random_weights(54)
+    C = 128
+    with kb.Problem(kb.HEAT2D_SURROGATE, (64, 64, 16 * C * C), HEAT, 0) as p:
+        p.write(kb.F_W, w)
+        loss, g = p.sg_loss_grad(dT0, dP, dT16, crops, C)
+    norm = crops.shape[0] * C * C
+    lref, gref = 0.0, np.zeros(oracle.SG_NW)
+    for f, y0, x0 in crops:
+        t0 = T0[f, y0:y0 + C, x0:x0 + C]
+        pp = P[f, y0:y0 + C, x0:x0 + C]
+        tgt = (T16[f, y0:y0 + C, x0:x0 + C].astype(np.float32) - t0).astype(np.float32) / np.float32(S)
+        l, gg = oracle.sg_loss_grad(w, t0, pp, tgt.astype(np.float64), norm=norm, round_bf16=True)
+        lref += l
+        gref += gg
+    print(f"loss gpu {loss:.6e} oracle {lref:.6e}")
+    assert abs(loss - lref) <= 1e-2 * lref
+    bounds = [0, 576, 608, 9824, 9856, 19072, 19104, 19392, 19393]
+    names = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"]
+    for nm, a, b in zip(names, bounds[:-1], bounds[1:]):
+        e = rel_maxnorm(g[a:b], gref[a:b])
+        print(f"grad {nm}: rel max err {e:.3e}")
+        assert e < 5e-3, nm
+
+
 def test_training_lowers_loss(kb):
     announce("surrogate training steps")
     import torch
@@ -282,8 +319,14 @@ def test_shipped_weights_accuracy_vs_float64(kb, seed):
         return (np.max(np.abs(a - ref)) / np.max(np.abs(ref)),
                 np.max(np.abs((a - T0) - inc)) / np.max(np.abs(inc)))
     (eT, eI), (pT, pI), (uT, uI) = err(T16), err(T0), err(euler)
-    print(f"surrogate T {eT:.2e} inc {eI:.3f} | persistence T {pT:.2e} | big Euler T {uT:.2e} inc {uI:.3f} "
-          f"| residual {resid[0]:.2e} fallbacks {stats[1]}")
+    print(f"surrogate T {eT:.2e} inc {eI:.3f} | persistence T {pT:.2e} inc {pI:.3f} | big Euler T {uT:.2e} "
+          f"inc {uI:.3f} | residual {resid[0]:.2e} fallbacks {stats[1]}")
     assert stats[0] == 1
+    assert stats[1] == 0                # the network's own output was kept (no fallback)
     assert eT <= 1e-3
-    assert eT < pT                      # better than doing nothing
+    # what the network gains over the methods without it: against doing
+    # nothing it gains (persistence misses the whole increment); against the
+    # cheapest plain alternative, one explicit step of 16*c, it loses on the
+    # increment (measured 12-18% vs 5%, printed above), and the 16 plain
+    # steps it replaces are exact -- the loss is the recorded result
+    assert eT < pT and eI < 0.5 * pI
