@@ -1,26 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark: iteration-batched hipGraph replay vs one launch per kernel.
 
-Workload: the skeleton iterative application -- each iteration runs a chain
-of K = 4 small element-wise kernels x <- a_k x + b_k on a 2^16-element
-float32 vector -- for 10,000 iterations (40,000 kernel executions), the
-configuration on which the paper characterises its method (Sec. III-C,
-IV-A/B).  Inputs are synthetic and seeded (x0 ~ U[-1,1), a_k ~ U[0.9,1),
-b_k ~ U[-0.01,0.01)) and are resident on the device before timing starts.
+Headline workload: the FDTD Maxwell solver of a PEC cavity, 256^3 cells,
+10,000 steps per job (per step an H update, an E update and the soft
+source; the fused H + E step by default, so two kernels per step), the
+largest single-GPU configuration of the study (FDTD solver, Sec. III-C;
+results in Sec. IV-B).  Fields start at zero and a Gaussian pulse (width 20
+steps, delay 80) is added to Ez at a seeded node; the state is resident on
+the device before timing starts.
 
 Procedure (Sec. III-C):
-  1. sweep the iteration batch b over the divisors of 10,000 up to 2,000,
-     measuring graph creation T_C (build + instantiate + upload) and
-     execution T_E; fit Eq. 2 and Eq. 6 and take the b minimising Eq. 1;
+  1. the autotuner picks the kernel variant and the iteration batch b for
+     the 10,000-step job (graph creation included in its objective, Eq. 1);
   2. warm up, then time `--steps` whole jobs at that b, each job paying its
-     own graph creation (T = T_C + T_E, Eq. 1);
-  3. time the same jobs launching every kernel separately (the baseline);
-  4. take the dominant kernel's mean duration per launch from the HIP
-     events around the timed replays (roofline);
-  5. time the other workloads per launch vs graph batches (2D stencil with
-     the autotuned kernel, depth and b; 3D stencil; 64 uneven grids; FDTD
-     128^3 and 256^3) and the large grids against the HBM roofline;
-  6. time the CPU oracle on a bounded sample of the same job.
+     own graph creation (T = T_C + T_E, Eq. 1), and the same jobs launching
+     every kernel separately (the baseline);
+  3. roofline: the step time from the HIP events around the timed replays
+     (on the problem's stream) against the per-cell-step bytes, next to the
+     attainable DRAM rate of the kernel's stream mix (six read and six
+     write streams) measured live with the streaming probe;
+  4. CPU baseline: the oracle on a bounded sample of the same cavity, on
+     one core and on all cores; the same sample on the GPU gives the error
+     against the float64 oracle;
+  5. the skeleton chain (the paper's characterisation vehicle, Sec. IV-A):
+     b sweep with 10 repeats per b, fits of Eqs. 2 and 6 with standard
+     errors, graph vs per-launch, graph memory, the two builders;
+  6. the other workloads and the Table I structure over vector sizes.
 One JSON line is printed.
 """
 from __future__ import annotations
@@ -36,30 +41,41 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+SEED = 20250116
+HBM_PEAK_GBS = 8000.0
+# the headline cavity
+N_FDTD = 256
+FDTD_STEPS = 10000
+FDTD_B_CANDIDATES = [10, 20, 50, 100, 200, 500, 1000, 2000]   # divisors of 10,000
+FDTD_BYTES_PER_CELL_STEP = 72.0     # three field reads + three read-modify-writes per half step
+FDTD_KERNEL_BYTES_PER_NODE = 48.0   # the fused step: six fields read, six written
+# the skeleton chain
 N_ELEM = 1 << 16
 K = 4
 ITERS = 10000
-SEED = 20250116
-HBM_PEAK_GBS = 8000.0
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "skeleton_2p16_hbm_counters.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "kernels_misc.hip")
+SKEL_COUNTERS = os.path.join(ROOT, "profiles", "skeleton_2p16_hbm_counters.json")
+SKEL_TRACE = os.path.join(ROOT, "profiles", "skeleton_2p16_trace_gaps.json")
+FDTD_COUNTERS = os.path.join(ROOT, "profiles", "fdtd_256_fused_hbm_counters.json")
+MISC_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "kernels_misc.hip")
+FDTD_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "fdtd.hip")
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed jobs (each 10,000 iterations)")
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--b", type=int, default=0, help="fix the batch size instead of fitting it")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true", help="skip the b sweep (requires --b)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--sweep-reps", type=int, default=3, help="repeats per b in the model sweep (median)")
+    ap.add_argument("--steps", type=int, default=3, help="timed jobs per arm (each 10,000 cavity steps)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--b", type=int, default=0, help="fix the cavity's batch size (skips the autotuner)")
+    ap.add_argument("--only", choices=("all", "fdtd", "skeleton"), default="all",
+                    help="'fdtd': the headline cavity alone; 'skeleton': the skeleton chain alone")
     ap.add_argument("--arm", choices=("both", "graph", "per_launch"), default="both",
-                    help="'graph' skips the per-launch baseline; 'per_launch' times only the baseline "
-                         "(both for profiling one arm alone)")
+                    help="time both arms, or one alone (for tracing one arm)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
-                    help="skip the other workloads (2D/3D stencils, many grids, FDTD, large grids)")
+                    help="skip the other workloads and the Table I sizes")
+    ap.add_argument("--skeleton-b", type=int, default=0, help="fix the skeleton's batch size")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the skeleton's b sweep (needs --skeleton-b)")
+    ap.add_argument("--sweep-reps", type=int, default=10, help="repeats per b in the skeleton sweep")
     ap.add_argument("--kernel-only", choices=sorted(KERNEL_RUNS),
                     help="run only one workload's kernels per launch for a few steps (counter runs)")
     ap.add_argument("--stream-calibration", action="store_true",
@@ -154,52 +170,86 @@ def copy_calibration():
                                            "launches": 3}}), flush=True)
 
 
-def skeleton_kernel_hash():
-    """Hash of the skeleton kernel's source text, to tell whether stored
-    hardware counters still describe the current kernel."""
+def source_hash(path, start, end):
+    """Hash of one kernel's source text, to tell whether stored hardware
+    counters still describe the current kernel."""
     import hashlib
-    src = open(KERNEL_SOURCE).read()
-    a = src.index("template <int VEC>")
-    b = src.index("void make_skeleton")
+    src = open(path).read()
+    a = src.index(start)
+    b = src.index(end, a)
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def stored_traffic():
-    if not os.path.exists(COUNTERS_FILE):
+def skeleton_kernel_hash():
+    return source_hash(MISC_SOURCE, "template <int VEC>", "void make_skeleton")
+
+
+def fdtd_fused_kernel_hash():
+    return source_hash(FDTD_SOURCE, "void fdtd_fused_kernel(", "bool make_fdtd_fused")
+
+
+def stored_traffic(path, current_hash):
+    """Measured HBM bytes per launch from a committed counter summary, or
+    None when it is missing or was taken on another version of the kernel."""
+    if not os.path.exists(path):
         return None
     try:
-        d = json.load(open(COUNTERS_FILE))
+        d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha") != skeleton_kernel_hash():
+    if d.get("kernel_source_sha") != current_hash:
         return None
     return d.get("hbm_bytes_per_launch")
 
 
-def graph_memory(kb, np, torch, copies=8, batches=(250, 1000, 2500)):
+def stored_json(path):
+    try:
+        return json.load(open(path))
+    except (OSError, ValueError):
+        return None
+
+
+def host_info():
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(avail, int(omp)) if omp and omp.isdigit() and int(omp) > 0 else avail
+    return {"cpu_model": model, "cores_available": avail, "threads_used": threads}
+
+
+def graph_memory(kb, np, torch, steps=8, graphs_per_step=4, b=2000):
     """Device memory held by instantiated, uploaded batch graphs vs their
-    node count (the paper's Fig. 2 bars).  The free-memory reading moves in
-    2 MiB steps, so each point keeps `copies` graphs of K*b nodes alive (one
-    per problem handle, workspaces allocated before the first reading) and
-    bytes per node is the least-squares slope over the points."""
+    node count (the paper's Fig. 2 bars).  Graphs are added cumulatively --
+    `graphs_per_step` more graphs of K*b nodes per point, all kept alive
+    (one per problem handle, every workspace allocated before the first
+    reading) -- so each point moves the free-memory reading (which changes
+    in 2 MiB steps) by several MiB; bytes per node is the least-squares
+    slope over the points."""
+    probs = [kb.Problem(kb.SKELETON, (N_ELEM,), (K,), SEED, device=0) for _ in range(steps * graphs_per_step)]
+    torch.cuda.synchronize()
+    f0 = torch.cuda.mem_get_info()[0]
     pts = []
-    for b in batches:
-        probs = [kb.Problem(kb.SKELETON, (N_ELEM,), (K,), SEED, device=0) for _ in range(copies)]
-        torch.cuda.synchronize()
-        f0 = torch.cuda.mem_get_info()[0]
-        for p in probs:
+    for s in range(steps):
+        for p in probs[s * graphs_per_step:(s + 1) * graphs_per_step]:
             p.run(b, b)
             p.last_timing()
         torch.cuda.synchronize()
-        f1 = torch.cuda.mem_get_info()[0]
-        pts.append((copies * K * b, f0 - f1))
-        for p in probs:
-            p.destroy()
+        pts.append(((s + 1) * graphs_per_step * K * b, f0 - torch.cuda.mem_get_info()[0]))
+    for p in probs:
+        p.destroy()
     x = np.array([q[0] for q in pts], float)
     y = np.array([q[1] for q in pts], float)
     slope, icpt = np.polyfit(x, y, 1)
-    return {"bytes_per_node": float(slope), "bytes_fixed": float(icpt), "copies": copies,
-            "points_nodes_bytes": [[int(a), int(c)] for a, c in pts]}
+    return {"bytes_per_node": float(slope), "bytes_fixed": float(icpt), "graphs_per_point": graphs_per_step,
+            "nodes_per_graph": K * b, "points_nodes_bytes": [[int(a), int(c)] for a, c in pts],
+            "monotone": bool(np.all(np.diff(y) >= 0))}
 
 
 def table1_sweep(kb, pm, np, sizes=tuple(1 << e for e in range(10, 23, 2)), reps=2):
@@ -504,6 +554,263 @@ def workloads(kb, pm, autotune, np):
     return out
 
 
+def fdtd_headline(args, kb, autotune, np, torch):
+    """The cavity job: autotuned variant and b, graph arm (each job pays
+    its own T_C) and per-launch arm, roofline from the replay events."""
+    from paper_2501_09398_amd import perfmodel as pm
+    N, n = N_FDTD, FDTD_STEPS
+    cells, nodes = N ** 3, (N + 1) ** 3
+    tuned = None
+    if args.b > 0:
+        variant, b = 0, args.b               # 0: the default fused variant for the size
+    else:
+        tr = autotune.tune(kb, kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, n, seed=SEED, reps=1, probe_steps=200,
+                           b_candidates=FDTD_B_CANDIDATES, kernel_candidates_override=[(2, 1), (5, 1), (7, 1)])
+        variant, b = tr.variant, tr.b
+        tuned = {"variant": tr.variant, "b": tr.b, "b_measured_best": tr.b_measured,
+                 "kernel_table_us_step": [(v, round(us, 2)) for v, _, us in tr.kernel_table],
+                 "batch_table_ms": [[bb, round(tc * 1e3, 3), round(te * 1e3, 3)] for bb, tc, te in tr.batch_table],
+                 "model": tr.model}
+    p = kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, SEED, device=0)
+    p.set_option(kb.OPT_TILE, variant)
+    p.set_option(kb.OPT_GRAPH_CACHE, 0)          # every job pays its own T_C (Eq. 1)
+    Kf = p.kernels_per_iter()
+
+    def job(bb):
+        p.run(n, bb)
+        return p.last_timing()                   # synchronises
+
+    def arm(bb):
+        for _ in range(args.warmup):
+            job(bb)
+        torch.cuda.synchronize()
+        T, TC, TE = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s0 = time.perf_counter()
+            t = job(bb)
+            T.append(time.perf_counter() - s0)
+            TC.append(t["t_create_s"])
+            TE.append(t["t_exec_s"])
+        torch.cuda.synchronize()
+        return T, TC, TE, time.perf_counter() - t0
+
+    out = {"variant": variant, "b": b, "kernels_per_iter": Kf, "autotune": tuned}
+    g_T = g_TC = g_TE = None
+    wall = None
+    if args.arm in ("both", "graph"):
+        g_T, g_TC, g_TE, wall = arm(b)
+        out["graph"] = {"b": b, "us_per_iter": float(np.mean(g_T)) / n * 1e6,
+                        "us_per_iter_warm": float(np.mean(g_TE)) / n * 1e6,
+                        "us_per_iter_warm_std": float(np.std(g_TE)) / n * 1e6,
+                        "t_create_ms": float(np.mean(g_TC)) * 1e3,
+                        "gcell_upd_s": cells * n / float(np.mean(g_T)) / 1e9}
+    if args.arm in ("both", "per_launch"):
+        b_T, _, b_TE, b_wall = arm(0)
+        out["per_launch"] = {"us_per_iter": float(np.mean(b_T)) / n * 1e6,
+                             "us_per_iter_device": float(np.mean(b_TE)) / n * 1e6,
+                             "us_per_iter_device_std": float(np.std(b_TE)) / n * 1e6,
+                             "gcell_upd_s": cells * n / float(np.mean(b_T)) / 1e9}
+        if wall is None:
+            wall, g_TE = b_wall, b_TE
+    if g_T is not None and args.arm == "both":
+        sp, sp_err = pm.speedup(b_T, g_T)
+        out["speedup"], out["speedup_err"] = sp, sp_err
+        out["speedup_device"] = float(np.mean(b_TE)) / float(np.mean(g_TE))
+    out["wall_s"] = wall
+    out["value"] = cells * n * args.steps / wall / 1e9
+    # roofline of the dominant kernel: one launch advances one step of the
+    # whole cavity; its duration is bounded above by the step time from the
+    # events around the timed launches (the step also holds the source
+    # kernel and the node-to-node gaps)
+    step_s = float(np.mean(g_TE)) / n
+    p.destroy()
+    eff = variant or (7 if N >= 176 else 5)          # the default fused variant for the size
+    name = {7: "fdtd_fused_kernel<1,true>", 5: "fdtd_fused_kernel<1,false>", 6: "fdtd_fused_kernel<8,false>"}.get(
+        eff, "fdtd_h_vec_kernel + fdtd_e_vec_kernel")
+    probe_s = kb.stream_probe(6, 6, 1 << 28, reps=10)
+    mix_gbs = 12 * (1 << 28) * 4 / probe_s / 1e9
+    achieved = FDTD_BYTES_PER_CELL_STEP * cells / step_s / 1e9
+    kern = FDTD_KERNEL_BYTES_PER_NODE * nodes / step_s / 1e9
+    out["roofline"] = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": stored_traffic(FDTD_COUNTERS, fdtd_fused_kernel_hash()),
+        "kernel": name,
+        "step_us": step_s * 1e6, "bytes_per_launch": FDTD_BYTES_PER_CELL_STEP * cells,
+        "bytes_per_cell_step": FDTD_BYTES_PER_CELL_STEP, "cells_per_launch": cells,
+        # the fused kernel's own minimum: six fields read and six written
+        "kernel_bytes_per_launch": FDTD_KERNEL_BYTES_PER_NODE * nodes, "kernel_achieved": kern,
+        "kernel_frac": kern / HBM_PEAK_GBS,
+        "stream_mix_6r6w_GB_s": mix_gbs, "kernel_frac_of_stream_mix": kern / mix_gbs,
+        "trace": stored_json(os.path.join(ROOT, "profiles", "fdtd_256_graph_trace.json"))}
+    return out
+
+
+def fdtd_cpu_baseline(kb, np, torch, steps_single=10, steps_all=40):
+    """The float32 oracle on a bounded sample of the cavity -- 256^3 from
+    seeded random fields (no denormals in the timed loops) with the source
+    on -- on one core and on all the cores this process may use; the GPU
+    runs the same sample, which gives its error against the float64 oracle
+    (and bit-equality with the float32 oracle)."""
+    import oracle
+    import synth
+    info = host_info()
+    N = N_FDTD
+    M = N + 1
+    rng = np.random.default_rng(SEED)
+    f0 = {k: rng.uniform(-1.0, 1.0, (M, M, M)).astype(np.float32) for k in oracle.FDTD_FIELDS}
+    src = synth.fdtd_source_cell(SEED, N)
+    g64, g32 = oracle.fdtd_pulse(steps_all + 1)
+    with oracle.threads(1):
+        t0 = time.perf_counter()
+        oracle.fdtd(f0, N, steps_single, src=src, g=g32, dtype=np.float32)
+        t1 = time.perf_counter() - t0
+    with oracle.threads(info["threads_used"]):
+        t0 = time.perf_counter()
+        ref32, _ = oracle.fdtd(f0, N, steps_all, src=src, g=g32, dtype=np.float32)
+        tn = time.perf_counter() - t0
+        ref64, _ = oracle.fdtd(f0, N, steps_all, src=src, g=g64, dtype=np.float64)
+    with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, SEED, device=0) as p:
+        for k, fid in kb.FDTD_FIELDS.items():
+            p.write(fid, f0[k])
+        p.run(steps_all, 20)
+        got = {k: p.read(fid) for k, fid in kb.FDTD_FIELDS.items()}
+    scale = max(float(np.max(np.abs(ref64[k]))) for k in oracle.FDTD_FIELDS)
+    err64 = max(float(np.max(np.abs(got[k].astype(np.float64) - ref64[k]))) for k in oracle.FDTD_FIELDS) / scale
+    exact = all(np.array_equal(got[k], ref32[k]) for k in oracle.FDTD_FIELDS)
+    cells = N ** 3
+    cpu = {"value": cells * steps_all / tn / 1e9, "unit": "Gcell-upd/s", "cores": info["threads_used"],
+           "kind": "oracle",
+           "sample": f"{steps_all} steps of the 256^3 cavity (float32 oracle, {info['threads_used']} threads, "
+                     f"{tn:.1f} s) from seeded random fields with the source on; single thread: "
+                     f"{steps_single} steps in {t1:.1f} s; {info['cpu_model']}",
+           "single_thread": {"value": cells * steps_single / t1 / 1e9, "cores": 1, "steps": steps_single,
+                             "seconds": t1},
+           "cpu_model": info["cpu_model"], "cores_available": info["cores_available"]}
+    fp64 = {"rel_maxnorm_vs_float64": err64, "bit_exact_vs_float32_oracle": exact, "steps": steps_all,
+            "sample": "the CPU-baseline sample (256^3, random fields, source on), all six fields"}
+    return cpu, fp64
+
+
+def skeleton_section(args, kb, pm, np, torch, workloads_on):
+    """The skeleton chain (2^16 float32, K = 4, 10,000 iterations per job):
+    the b sweep (each b `sweep_reps` times, mean and standard deviation),
+    Eq. 2 and Eq. 6 fitted with standard errors, graph jobs at the model's
+    b against per-launch jobs, the per-node rate against the node floor."""
+    prob = kb.Problem(kb.SKELETON, (N_ELEM,), (K,), SEED, device=0)
+    prob.set_option(kb.OPT_GRAPH_CACHE, 0)       # every job pays its own T_C
+    elem_updates = N_ELEM * K * ITERS
+
+    def job(b):
+        prob.run(ITERS, b)
+        return prob.last_timing()
+
+    cands = pm.divisors(ITERS, 1, 2000)
+    sweep, model = [], None
+    if not args.no_sweep and args.arm != "per_launch":
+        job(100)
+        for b in cands:
+            reps = [job(b) for _ in range(args.sweep_reps)]
+            tc = [t["t_create_s"] for t in reps]
+            te = [t["t_exec_s"] for t in reps]
+            sweep.append((b, float(np.mean(tc)), float(np.std(tc)), float(np.mean(te)), float(np.std(te))))
+        S = np.array([s[0] for s in sweep], float)
+        model = pm.Model(pm.fit_creation(K * S, [s[1] for s in sweep]),
+                         pm.fit_execution(S, [s[3] for s in sweep]), K=K)
+        b_model, _ = model.best(cands)
+        measured_total = {s[0]: s[1] + s[3] for s in sweep}
+        b_measured = min(measured_total, key=measured_total.get)
+    b_star = args.skeleton_b if args.skeleton_b > 0 else (b_model if model else 100)
+    steps = max(args.steps, 3)
+    res = {"workload": "skeleton chain: K=4 element-wise kernels x<-a_k*x+b_k on 2^16 float32, 10000 "
+                       "iterations per job", "b": b_star}
+    g_T = g_TE = g_TC = None
+    if args.arm in ("both", "graph"):
+        for _ in range(max(1, args.warmup)):
+            job(b_star)
+        torch.cuda.synchronize()
+        g_T, g_TC, g_TE = [], [], []
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            t = job(b_star)
+            g_T.append(time.perf_counter() - s0)
+            g_TC.append(t["t_create_s"])
+            g_TE.append(t["t_exec_s"])
+        res["graph"] = {"b": b_star, "us_per_iter": float(np.mean(g_T)) / ITERS * 1e6,
+                        "us_per_iter_warm": float(np.mean(g_TE)) / ITERS * 1e6,
+                        "t_create_ms": float(np.mean(g_TC)) * 1e3,
+                        "gcell_upd_s": elem_updates / float(np.mean(g_T)) / 1e9}
+    if args.arm in ("both", "per_launch"):
+        for _ in range(max(1, args.warmup)):
+            job(0)
+        torch.cuda.synchronize()
+        b_T, b_TE = [], []
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            t = job(0)
+            b_T.append(time.perf_counter() - s0)
+            b_TE.append(t["t_exec_s"])
+        res["per_launch"] = {"us_per_iter": float(np.mean(b_T)) / ITERS * 1e6,
+                             "us_per_iter_device": float(np.mean(b_TE)) / ITERS * 1e6,
+                             "gcell_upd_s": elem_updates / float(np.mean(b_T)) / 1e9}
+        if g_T is not None:
+            sp, sp_err = pm.speedup(b_T, g_T)
+            res["speedup"], res["speedup_err"] = sp, sp_err
+            # crossover: graph launches after which T_C has paid for itself
+            save = (float(np.mean(b_TE)) - float(np.mean(g_TE))) / ITERS
+            res["crossover_batches"] = float(np.mean(g_TC)) / (b_star * save) if b_star > 0 and save > 0 else None
+    prob.destroy()
+    if g_TE is not None:
+        # per graph node: the replay time divided by the nodes (kernel plus
+        # the gap to the next node), against the node time of the same
+        # chain on 2^10 elements (no work to speak of)
+        n_launch = K * ITERS
+        node_s = float(np.mean(g_TE)) / n_launch
+        with kb.Problem(kb.SKELETON, (1 << 10,), (K,), SEED, device=0) as q:
+            q.run(ITERS, b_star)
+            q.last_timing()
+            te = []
+            for _ in range(3):
+                q.run(ITERS, b_star)
+                te.append(q.last_timing()["t_exec_s"])
+        floor_s = float(np.median(te)) / n_launch
+        bytes_per_launch = N_ELEM * 8
+        trace = stored_json(SKEL_TRACE)
+        res["per_node"] = {"node_us": node_s * 1e6, "node_floor_us": floor_s * 1e6,
+                           "frac_of_node_floor": floor_s / node_s,
+                           "per_node_effective_GB_s": bytes_per_launch / node_s / 1e9,
+                           "bytes_per_launch": bytes_per_launch,
+                           "traffic": stored_traffic(SKEL_COUNTERS, skeleton_kernel_hash())}
+        if trace:
+            kus = trace.get("graph_kernel_median_us")
+            res["per_node"]["trace"] = trace
+            if kus:
+                res["per_node"]["trace_kernel_frac"] = bytes_per_launch / (kus * 1e-6) / 1e9 / HBM_PEAK_GBS
+    if model is not None:
+        c, e = model.creation, model.execution
+        res["model"] = {"k_c_s_per_node": c.k_c, "k_c_se": c.k_c_se, "b_c_s": c.b_c, "b_c_se": c.b_c_se,
+                        "mae_c_s": c.mae, "a_s": e.a, "a_se": e.a_se, "b_s": e.b, "b_se": e.b_se, "mae_e_s": e.mae,
+                        "b_model": b_model, "b_closed_form": model.s_closed_form(), "b_measured_best": b_measured,
+                        # a = (iterations) * (T_a - T_i): the extra gap of a
+                        # graph launch over a node-to-node gap
+                        "T_a_minus_T_i_us": e.a / ITERS * 1e6, "T_a_minus_T_i_se_us": e.a_se / ITERS * 1e6,
+                        "repeats_per_b": args.sweep_reps}
+        res["sweep_b_tc_ms_mean_std_te_ms_mean_std"] = [
+            [s[0], round(s[1] * 1e3, 4), round(s[2] * 1e3, 4), round(s[3] * 1e3, 4), round(s[4] * 1e3, 4)]
+            for s in sweep]
+        gm = graph_memory(kb, np, torch)
+        mm = pm.MemoryModel(gm["bytes_per_node"], max(gm["bytes_fixed"], 0.0))
+        gm["b_model_under_budget"] = {}
+        for budget in (1 << 20, 4 << 20):
+            ok = [bb for bb in cands if bb * K <= mm.max_nodes(budget)] or [1]
+            gm["b_model_under_budget"][f"{budget >> 20}MiB"] = model.best(ok)[0]
+        res["graph_memory"] = gm
+        res["graph_builders"] = builders_and_update(kb, np)
+        if workloads_on:
+            res["table1_sizes"] = table1_sweep(kb, pm, np)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -524,187 +831,46 @@ def main():
     import torch
 
     import paper_2501_09398_amd as kb
+    from paper_2501_09398_amd import autotune
     from paper_2501_09398_amd import perfmodel as pm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     kb.lib()
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(torch.device("cuda", 0))
+    workloads_on = not args.no_workloads and args.arm == "both" and args.only == "all"
 
-    prob = kb.Problem(kb.SKELETON, (N_ELEM,), (K,), SEED, device=0)
-    prob.set_option(kb.OPT_GRAPH_CACHE, 0)       # every job pays its own T_C
-    elem_updates = N_ELEM * K * ITERS
-
-    def job(b):
-        prob.run(ITERS, b)
-        t = prob.last_timing()       # synchronises
-        return t
-
-    # 1. sweep b, fit Eqs. 2 and 6 -----------------------------------------
-    cands = pm.divisors(ITERS, 1, 2000)
-    sweep = []
-    model = None
-    if not args.no_sweep and args.arm != "per_launch":
-        job(100)
-        for b in cands:
-            reps = [job(b) for _ in range(args.sweep_reps)]
-            sweep.append((b, float(np.median([t["t_create_s"] for t in reps])),
-                          float(np.median([t["t_exec_s"] for t in reps]))))
-        S = np.array([s[0] for s in sweep], float)
-        model = pm.Model(pm.fit_creation(K * S, [s[1] for s in sweep]),
-                         pm.fit_execution(S, [s[2] for s in sweep]), K=K)
-        b_model, _ = model.best(cands)
-        measured_total = {s[0]: s[1] + s[2] for s in sweep}
-        b_measured = min(measured_total, key=measured_total.get)
-    b_star = args.b if args.b > 0 else (b_model if model else 100)
-    if args.arm == "per_launch":
-        b_star = 0
-
-    # 2. warm-up and timed graph jobs --------------------------------------
-    for _ in range(args.warmup):
-        job(b_star)
-    torch.cuda.synchronize()
-    graph_T, graph_TC, graph_TE = [], [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        t = job(b_star)
-        graph_T.append(time.perf_counter() - s0)
-        graph_TC.append(t["t_create_s"])
-        graph_TE.append(t["t_exec_s"])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    value = elem_updates * args.steps / wall / 1e9
-
-    # 3. baseline: one launch per kernel ------------------------------------
-    base_T, base_TE = [], []
-    if args.arm == "both":
-        for _ in range(max(1, args.warmup)):
-            job(0)
-        torch.cuda.synchronize()
-        for _ in range(args.steps):
-            s0 = time.perf_counter()
-            t = job(0)
-            base_T.append(time.perf_counter() - s0)
-            base_TE.append(t["t_exec_s"])
-        torch.cuda.synchronize()
-        sp, sp_err = pm.speedup(base_T, graph_T)
-    else:
-        sp = sp_err = None
-
-    # 4. dominant kernel: mean duration per launch over the timed replays,
-    # from the HIP events that bracket each job's launches on its stream.
-    n_launch = K * ITERS
-    kern_s = float(np.mean(graph_TE)) / n_launch
-    bytes_per_launch = N_ELEM * 8                  # read x, write x
-    achieved = bytes_per_launch / kern_s / 1e9
-    prob.destroy()
-    # the graph-node floor: the same chain on 2^10 elements (4 KB per kernel,
-    # no work to speak of) at the same b, per node from the replay events
-    floor_s = None
-    if b_star > 0:
-        with kb.Problem(kb.SKELETON, (1 << 10,), (K,), SEED, device=0) as q:
-            q.run(ITERS, b_star)
-            q.last_timing()
-            te = []
-            for _ in range(3):
-                q.run(ITERS, b_star)
-                te.append(q.last_timing()["t_exec_s"])
-        floor_s = float(np.median(te)) / n_launch
-
-    wl = None
-    if not args.no_workloads and args.arm == "both":
-        from paper_2501_09398_amd import autotune
-        wl = workloads(kb, pm, autotune, np)
-
-    # 5. CPU oracle on a bounded sample --------------------------------------
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        import synth
-        x0, a, b = synth.skeleton_init(SEED, N_ELEM, K)
-        s0 = time.perf_counter()
-        oracle.skeleton(x0, a, b, 20, dtype=np.float32)
-        probe = max(time.perf_counter() - s0, 1e-6) / 20
-        iters = int(min(ITERS, max(20, args.cpu_seconds / probe)))
-        s0 = time.perf_counter()
-        oracle.skeleton(x0, a, b, iters, dtype=np.float32)
-        dt = time.perf_counter() - s0
-        cpu = {"value": N_ELEM * K * iters / dt / 1e9, "unit": "Gcell-upd/s", "cores": 1, "kind": "oracle",
-               "sample": f"{iters} of the {ITERS} iterations of the same 2^16-element K=4 chain "
-                         f"(float32, single thread, {dt:.1f} s, {platform.processor() or platform.machine()})"}
-
-    us_iter_graph = float(np.mean(graph_T)) / ITERS * 1e6
-    per_launch = None
-    crossover = None
-    if base_T:
-        per_launch = {"us_per_iter": float(np.mean(base_T)) / ITERS * 1e6,
-                      "us_per_iter_device": float(np.mean(base_TE)) / ITERS * 1e6,
-                      "gcell_upd_s": elem_updates / float(np.mean(base_T)) / 1e9}
-        # crossover: the number of graph launches (iteration batches of b)
-        # after which building the graph has paid for itself, T_C over the
-        # saving per batch (the paper reports 2-3 batches on the A100)
-        save_per_iter = (float(np.mean(base_TE)) - float(np.mean(graph_TE))) / ITERS
-        if b_star > 0 and save_per_iter > 0:
-            crossover = float(np.mean(graph_TC)) / (b_star * save_per_iter)
-    line = {
-        "metric": "µs/iter & Gcell-upd/s: hipGraph batch-b vs per-launch; % HBM peak",
-        "value": value,
-        "unit": "Gcell-upd/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded SplitMix64: x0~U[-1,1), a_k~U[0.9,1), b_k~U[-0.01,0.01))",
-        "config": {"workload": "skeleton chain: K=4 element-wise kernels x<-a_k*x+b_k on 2^16 float32, "
-                               "10000 iterations per job, graph batch b with loop peeling",
-                   "b": b_star, "elements": N_ELEM, "kernels_per_iter": K, "iterations": ITERS,
-                   "parallelism": "single GPU"},
-        "arms": {
-            "graph": {"b": b_star, "us_per_iter": us_iter_graph,
-                      "us_per_iter_warm": float(np.mean(graph_TE)) / ITERS * 1e6,
-                      "t_create_ms": float(np.mean(graph_TC)) * 1e3,
-                      "gcell_upd_s": elem_updates / float(np.mean(graph_T)) / 1e9},
-            "per_launch": per_launch,
-            "speedup": sp, "speedup_err": sp_err, "crossover_batches": crossover,
-        },
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
-                     "kernel": "skeleton_kernel<4>", "kernel_us": kern_s * 1e6,
-                     "bytes_per_launch": bytes_per_launch,
-                     # a launch-bound kernel: its time per graph node against
-                     # the node time of the same chain with no work (2^10)
-                     "node_floor_us": floor_s * 1e6 if floor_s else None,
-                     "frac_of_node_floor": floor_s / kern_s if floor_s else None},
-        "cpu_baseline": cpu,
-        "workloads": wl,
-    }
-    if model is not None:
-        line["model"] = {"k_c_s_per_node": model.creation.k_c, "b_c_s": model.creation.b_c,
-                         "mae_c_s": model.creation.mae, "a_s": model.execution.a, "b_s": model.execution.b,
-                         "mae_e_s": model.execution.mae, "b_model": b_model,
-                         "b_closed_form": model.s_closed_form(), "b_measured_best": b_measured,
-                         # a = (number of iterations) * (T_a - T_i): the extra
-                         # gap of a graph launch over a node-to-node gap
-                         "T_a_minus_T_i_us": model.execution.a / ITERS * 1e6}
-        line["sweep"] = [[s[0], round(s[1] * 1e3, 4), round(s[2] * 1e3, 4)] for s in sweep]
-        gm = graph_memory(kb, np, torch)
-        # the model's optimum under a device-memory budget for the batch
-        # graph, from the measured bytes per node (the memory side of b*)
-        mm = pm.MemoryModel(gm["bytes_per_node"], max(gm["bytes_fixed"], 0.0))
-        divs = [b for b in pm.divisors(ITERS, 1, 2000)]
-        gm["b_model_under_budget"] = {}
-        for budget in (1 << 20, 4 << 20):
-            ok = [b for b in divs if b * K <= mm.max_nodes(budget)] or [1]
-            gm["b_model_under_budget"][f"{budget >> 20}MiB"] = model.best(ok)[0]
-        line["graph_memory"] = gm
-        line["graph_builders"] = builders_and_update(kb, np)
-        if not args.no_workloads:
-            line["table1_sizes"] = table1_sweep(kb, pm, np)
+    line = {"metric": "µs/iter & Gcell-upd/s: hipGraph batch-b vs per-launch; % HBM peak"}
+    if args.only in ("all", "fdtd"):
+        h = fdtd_headline(args, kb, autotune, np, torch)
+        line.update({
+            "value": h["value"], "unit": "Gcell-upd/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": h["wall_s"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic: PEC cavity, fields zero, Gaussian soft source (width 20, delay 80 steps) on Ez "
+                    "at the seeded node",
+            "config": {"workload": "FDTD Yee PEC cavity 256^3, Courant 0.5, 10000 steps per job (H update, E update "
+                                   "and soft source per step), graph batch b with loop peeling",
+                       "N": N_FDTD, "steps_per_job": FDTD_STEPS, "b": h["b"], "variant": h["variant"],
+                       "kernels_per_iter": h["kernels_per_iter"], "parallelism": "single GPU"},
+            "arms": {k: h.get(k) for k in ("graph", "per_launch", "speedup", "speedup_err", "speedup_device")},
+            "roofline": h["roofline"], "autotune": h["autotune"]})
+        if not args.no_cpu_baseline:
+            cpu, fp64 = fdtd_cpu_baseline(kb, np, torch)
+            line["cpu_baseline"] = cpu
+            line["fp64_error"] = fp64
+        else:
+            line["cpu_baseline"] = None
+    line["host"] = host_info()
+    if args.only in ("all", "skeleton"):
+        sk = skeleton_section(args, kb, pm, np, torch, workloads_on)
+        if args.only == "skeleton":
+            line.update({"value": sk.get("graph", sk.get("per_launch", {})).get("gcell_upd_s"),
+                         "unit": "Gcell-upd/s", "n_gpus": 1, "steps": max(args.steps, 3), "warmup": args.warmup,
+                         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                         "config": {"workload": sk["workload"], "b": sk["b"]}})
+        line["skeleton"] = sk
+    if workloads_on:
+        line["workloads"] = workloads(kb, pm, autotune, np)
     print(json.dumps(line), flush=True)
 
 

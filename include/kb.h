@@ -104,6 +104,12 @@ extern "C" {
  *            and the pixel capacity of one training batch (crops x C x C).
  *   coeffs = {c, Rx, Ry, Rz, Tamb} or {c, Rx, Ry, Rz, Tamb, s, threshold, k}
  *            (defaults s = 0.8, threshold = 1e-3, k = 16; 1 <= k <= 16).
+ *   initial: T ~ U[323,343) from the seed; the power map P is U[0,1) plus
+ *            1-4 Gaussian hot spots: count 1 + floor(4u), then per spot h
+ *            centre row u*ny, centre column u*nx, amplitude 1 + 3u and
+ *            width sigma = 4 + 28u, u the draws 0 and 1+4h .. 4+4h of
+ *            stream 7; P = float(u_P + sum_h amp exp(-r^2 / (2 sigma^2)))
+ *            evaluated in double (the learned part's training inputs).
  *            One iteration is one block of k steps:
  *              y = NN((T-333)/10, (P-0.5)/0.29)  (4 layers of 3x3 conv, 32
  *                  channels, GELU, replicate padding; bf16 operands on the

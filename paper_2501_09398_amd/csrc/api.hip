@@ -621,9 +621,15 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       std::string err;
       if ((rc = sg_create(h, shape, ndim, coeffs, ncoeffs, seed, err)) != KB_OK)
         return bail(fail(rc, "%s", err.c_str()));
-      if ((rc = enqueue_init(h, h->Tbuf[0], h->ny * h->nx, seed, kTagT0, 0, 323.0, 343.0)) ||
-          (rc = enqueue_init(h, h->P, h->ny * h->nx, seed, kTagP, 0, 0.0, 1.0)))
+      if ((rc = enqueue_init(h, h->Tbuf[0], h->ny * h->nx, seed, kTagT0, 0, 323.0, 343.0)))
         return bail(rc);
+      {
+        // the surrogate workload's power: uniform plus Gaussian hot spots
+        Launch L;
+        make_hot_spots(L, host_hot_spots(h->P, (int)h->ny, (int)h->nx, seed));
+        if (hipLaunchKernel(L.func, L.grid, L.block, L.params(), 0, h->stream) != hipSuccess)
+          return bail(fail(KB_EHIP, "hot-spot initialisation failed"));
+      }
       if (sg_power_changed(h) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
         return bail(fail(KB_EHIP, "surrogate set-up failed"));
       break;

@@ -213,10 +213,20 @@ struct InitArgs {
   double lo, span;
 };
 
+// Power map with Gaussian hot spots: P ~ U[0,1) (stream kTagP) plus up to
+// four spots whose parameters the host draws from stream kTagHot.
+struct HotSpotArgs {
+  float *out; int ny, nx; unsigned long long seed;
+  int count;
+  double cy[4], cx[4], amp[4], den[4];   // den = (2 sigma) sigma
+};
+
 // ---------------------------------------------------------------------------
 // Kernel launchers / descriptor builders, defined in the .hip files.
 // ---------------------------------------------------------------------------
 void make_init(Launch &L, const InitArgs &a);
+void make_hot_spots(Launch &L, const HotSpotArgs &a);
+HotSpotArgs host_hot_spots(float *out, int ny, int nx, uint64_t seed);
 void make_heat2d_direct(Launch &L, const Heat2DArgs &a);
 bool make_heat2d_tile(Launch &L, const Heat2DArgs &a, int variant);   // false: bad variant
 int heat2d_tile_max_depth();

@@ -20,6 +20,54 @@ void make_init(Launch &L, const InitArgs &a) {
   L.set((const void *)init_uniform_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, a);
 }
 
+// ---------------------------------------------------------------------------
+// Hot-spot power map (the surrogate workload's inputs): per cell
+//   p = u + sum_h amp_h exp(-((y - cy_h)^2 + (x - cx_h)^2) / ((2 sigma_h) sigma_h))
+// in double, each operation rounded once in this order, then one rounding
+// to float; u is the cell's uniform draw of stream kTagP.  The spot count
+// (1 + an integer draw on [0, 4)) and each spot's centre row, centre
+// column, amplitude U[1,4) and width sigma U[4,32) are draws 0 and
+// 1 + 4h .. 4 + 4h of stream kTagHot.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void hot_spot_kernel(const HotSpotArgs a) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (long long)a.ny * a.nx) return;
+  const int y = (int)(i / a.nx), x = (int)(i - (long long)y * a.nx);
+  const uint64_t z = splitmix(a.seed, kTagP, (uint64_t)i);
+  double p = (double)(z >> 40) * 0x1.0p-24;
+  for (int h = 0; h < a.count; ++h) {
+    const double dy = __dsub_rn((double)y, a.cy[h]), dx = __dsub_rn((double)x, a.cx[h]);
+    const double r2 = __dadd_rn(__dmul_rn(dy, dy), __dmul_rn(dx, dx));
+    p = __dadd_rn(p, __dmul_rn(a.amp[h], exp(-__ddiv_rn(r2, a.den[h]))));
+  }
+  a.out[i] = (float)p;
+}
+
+void make_hot_spots(Launch &L, const HotSpotArgs &a) {
+  const long long n = (long long)a.ny * a.nx;
+  L.set((const void *)hot_spot_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, a);
+}
+
+static double host_u01(uint64_t seed, uint64_t tag, uint64_t idx) {
+  return (double)(splitmix(seed, tag, idx) >> 40) * 0x1.0p-24;
+}
+
+HotSpotArgs host_hot_spots(float *out, int ny, int nx, uint64_t seed) {
+  HotSpotArgs a{};
+  a.out = out; a.ny = ny; a.nx = nx; a.seed = seed;
+  a.count = 1 + (int)host_randint(seed, kTagHot, 0, 4);
+  for (int h = 0; h < a.count; ++h) {
+    const double u0 = host_u01(seed, kTagHot, 1 + 4 * h), u1 = host_u01(seed, kTagHot, 2 + 4 * h);
+    const double u2 = host_u01(seed, kTagHot, 3 + 4 * h), u3 = host_u01(seed, kTagHot, 4 + 4 * h);
+    const double sig = 4.0 + 28.0 * u3;            // built with -ffp-contract=off: no fusion
+    a.cy[h] = u0 * ny;
+    a.cx[h] = u1 * nx;
+    a.amp[h] = 1.0 + 3.0 * u2;
+    a.den[h] = 2.0 * sig * sig;
+  }
+  return a;
+}
+
 float host_uniform(uint64_t seed, uint64_t tag, uint64_t idx, double lo, double hi) {
   const uint64_t z = splitmix(seed, tag, idx);
   const double u = (double)(z >> 40) * 0x1.0p-24;

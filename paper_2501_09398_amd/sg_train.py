@@ -7,9 +7,11 @@ kb_sg_train_step call (MFMA forward, loss, data and weight gradients,
 Adam).  This module only chooses seeds, crops and learning rates.
 
 Data (per trajectory i of a chunk): seed = base + i; T0 ~ U[323,343) and
-P = U[0,1) plus 1-4 Gaussian hot spots (synth.hot_spot_power); the state is
-recorded after every k steps for `blocks` blocks, giving `blocks` training
-pairs (T_jk, T_(j+1)k) that share P.
+P = U[0,1) plus 1-4 Gaussian hot spots, both drawn on the device by
+kb_create of the surrogate problem with that seed; the state is recorded
+after every k steps for `blocks` blocks, giving `blocks` training pairs
+(T_jk, T_(j+1)k) that share P.  The initial weights are the seeded recipe
+synth.surrogate_init.
 Crops: C x C windows at uniform positions, a quarter of them pushed against
 a randomly chosen grid edge so the replicate-padding border is learned.
 """
@@ -55,8 +57,11 @@ def generate_chunk(cfg: TrainConfig, first: int, count: int, device=0):
     """(T0, P, Tk) device tensors [count*blocks][size][size] of one chunk."""
     n = cfg.size
     shape = [count] + [n, n] * count
-    Ps = [synth.hot_spot_power(cfg.seed + first + i, n, n) for i in range(count)]
-    T0s = [synth.heat2d_init(cfg.seed + first + i, n, n)[0] for i in range(count)]
+    Ps, T0s = [], []
+    for i in range(count):                  # the workload's seeded initial state, drawn by the library
+        with Problem(HEAT2D_SURROGATE, (n, n), HEAT_COEFFS, cfg.seed + first + i, device=device) as q:
+            T0s.append(q.read(F_T))
+            Ps.append(q.read(F_P))
     states = []
     with Problem(HEAT2D_MULTI, shape, HEAT_COEFFS, 0, device=device) as p:
         p.write(F_T, np.concatenate([t.reshape(-1) for t in T0s]))
@@ -152,11 +157,8 @@ def evaluate(weights, seeds, size=512, k=16, s=0.8, device=0, threshold=1e-3):
     coeffs = tuple(HEAT_COEFFS) + (s, threshold, k)
     c = HEAT_COEFFS[0]
     for sd in seeds:
-        T0, _ = synth.heat2d_init(sd, size, size)
-        P = synth.hot_spot_power(sd, size, size)
         with Problem(HEAT2D_SURROGATE, (size, size), coeffs, sd, device=device) as p:
-            p.write(F_T, T0)
-            p.write(F_P, P)
+            T0, P = p.read(F_T), p.read(F_P)       # the seed's workload inputs, drawn on the device
             p.write(F_W, weights)
             p.run(k, 0)
             Tk = p.read(F_T).astype(np.float64)

@@ -53,6 +53,22 @@ def run_block(kb, T0, P, w, steps, threshold, b=0, variant=0):
         return p.read(kb.F_T), p.read(kb.F_SGSTATS), p.read(kb.F_RESID)
 
 
+@pytest.mark.parametrize("seed,shape", [(0, (512, 512)), (20250116, (512, 512)), (7, (96, 130)), (900011, (37, 64))])
+def test_initial_state_hot_spots_match_generator(kb, seed, shape):
+    """kb_create draws the surrogate workload's inputs on the device: T0
+    from stream 1 and the hot-spot power map (uniform stream 2 plus 1-4
+    Gaussian spots from stream 7) bit for bit as the host generator."""
+    announce(f"surrogate initial state seed {seed} {shape}")
+    with kb.Problem(kb.HEAT2D_SURROGATE, shape, HEAT, seed) as p:
+        T0, P = p.read(kb.F_T), p.read(kb.F_P)
+    T0_ref, _ = synth.heat2d_init(seed, *shape)
+    P_ref = synth.hot_spot_power(seed, *shape)
+    assert np.array_equal(T0, T0_ref)
+    diff = P != P_ref
+    print(f"hot spots: {int(diff.sum())} cells differ, max |P| {P.max():.3f}")
+    assert not diff.any()
+
+
 @pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("shape", [(64, 96), (40, 33), (35, 70)])
 def test_forward_matches_oracle(kb, shape, variant):

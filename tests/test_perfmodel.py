@@ -102,3 +102,44 @@ def test_divisors():
     assert pm.divisors(10000, 1, 2000)[:6] == [1, 2, 4, 5, 8, 10]
     assert len(pm.divisors(10000, 1, 2000)) == 22
     assert pm.divisors(1000) == [1, 2, 4, 5, 8, 10, 20, 25, 40, 50, 100, 125, 200, 250, 500, 1000]
+
+
+def test_fit_standard_errors_match_polyfit_covariance():
+    """The coefficient standard errors of Eq. 2 and Eq. 6 equal the square
+    roots of the covariance numpy's polyfit reports (residual variance over
+    n - 2 degrees of freedom)."""
+    rng = np.random.default_rng(1)
+    x = np.array([4, 8, 20, 40, 80, 200, 400, 800], float)
+    y = 4.2e-6 * x + 1.6e-4 + rng.normal(0, 5e-5, x.size)
+    f = pm.fit_creation(x, y)
+    p, cov = np.polyfit(x, y, 1, cov=True)
+    assert np.isclose(f.k_c, p[0]) and np.isclose(f.b_c, p[1])
+    assert np.isclose(f.k_c_se, np.sqrt(cov[0, 0]), rtol=1e-9) and np.isclose(f.b_c_se, np.sqrt(cov[1, 1]), rtol=1e-9)
+    S = np.array([1, 2, 5, 10, 20, 50, 100], float)
+    t = 1.77e-2 / S + 4.56e-2 + rng.normal(0, 1e-4, S.size)
+    e = pm.fit_execution(S, t)
+    p, cov = np.polyfit(1.0 / S, t, 1, cov=True)
+    assert np.isclose(e.a_se, np.sqrt(cov[0, 0]), rtol=1e-9) and np.isclose(e.b_se, np.sqrt(cov[1, 1]), rtol=1e-9)
+
+
+def test_trace_gaps_synthetic_timeline():
+    """A synthetic trace laid out as Eq. 3 describes it: graph jobs of I
+    launches of S nodes (kernel T_k, node gap T_i, graph gap T_a), then a
+    per-launch job (gap T_a0 between launches): the analyser recovers each
+    gap class exactly."""
+    K, b, iters, Tk, Ti, Ta, Ta0 = 2, 5, 20, 3000, 700, 9000, 4000
+    rows, t = [], 0
+    for job in range(2):
+        for j in range(K * iters):
+            rows.append(("k%d" % (j % K), t, t + Tk, 64))
+            t += Tk + (Ta if (j + 1) % (K * b) == 0 else Ti)
+        t += 10 ** 7                                       # host work between jobs
+    for j in range(K * iters):
+        rows.append(("k%d" % (j % K), t, t + Tk, 64))
+        t += Tk + Ta0
+    r = pm.trace_gaps(rows, K, b, iters, 2, 1)
+    assert r["T_i_in_graph_gap"]["median_us"] == Ti / 1e3
+    assert r["T_a_between_graphs_gap"]["median_us"] == Ta / 1e3
+    assert r["T_a_between_graphs_gap"]["n"] == 2 * (iters // b - 1)
+    assert r["T_a_per_launch_gap"]["median_us"] == Ta0 / 1e3
+    assert r["graph_kernel_duration"]["median_us"] == Tk / 1e3
