@@ -721,7 +721,7 @@ def skeleton_section(args, kb, pm, np, torch, workloads_on):
         measured_total = {s[0]: s[1] + s[3] for s in sweep}
         b_measured = min(measured_total, key=measured_total.get)
     b_star = args.skeleton_b if args.skeleton_b > 0 else (b_model if model else 100)
-    steps = max(args.steps, 3)
+    steps = max(args.steps, 1)
     res = {"workload": "skeleton chain: K=4 element-wise kernels x<-a_k*x+b_k on 2^16 float32, 10000 "
                        "iterations per job", "b": b_star}
     g_T = g_TE = g_TC = None
@@ -865,7 +865,7 @@ def main():
         sk = skeleton_section(args, kb, pm, np, torch, workloads_on)
         if args.only == "skeleton":
             line.update({"value": sk.get("graph", sk.get("per_launch", {})).get("gcell_upd_s"),
-                         "unit": "Gcell-upd/s", "n_gpus": 1, "steps": max(args.steps, 3), "warmup": args.warmup,
+                         "unit": "Gcell-upd/s", "n_gpus": 1, "steps": max(args.steps, 1), "warmup": args.warmup,
                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
                          "config": {"workload": sk["workload"], "b": sk["b"]}})
         line["skeleton"] = sk

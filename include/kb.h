@@ -389,6 +389,26 @@ int kb_write(kb_problem *h, int field, const void *src, size_t bytes,
  * Errors: KB_EINVAL, KB_EHIP.                                              */
 int kb_reduce(kb_problem *h, double *out, int nout);
 
+/* kb_reduce without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same deterministic two-pass sum (the same kernels,
+ * chunks and summation order as kb_reduce, so the same bits for the same n)
+ * over caller arrays, with the per-block partials in a static device array
+ * of the library (1024 doubles = 8 KiB per GPU, held until the process
+ * ends).
+ *   x      : host array of nx (1..6) device pointers, each to n floats
+ *   n      : elements per array, 0 <= n <= 2^40
+ *   square : 0 = sum of all elements, 1 = sum of their squares
+ *   out    : device pointer to one double, written on the stream
+ *   stream : hipStream_t (as void*); work is enqueued, not waited for
+ * Allocates nothing: no hipMalloc, no hipFree, no memset.  The first call on
+ * a device resolves the static array's address there (make it outside a
+ * graph capture).  Calls on one GPU share its array: calls whose work
+ * overlaps on that GPU (other streams, other threads) race and must be
+ * ordered by the caller.  The current device must be the stream's device.
+ * Errors: KB_EINVAL (counts, n, null pointers), KB_EHIP.                  */
+int kb_reduce_noalloc(const float *const *x, int nx, int64_t n, int square, double *out, void *stream);
+
 /* Timing of the last kb_run() (synchronises the stream).                   */
 int kb_last_timing(kb_problem *h, kb_timing *out);
 

@@ -79,6 +79,8 @@ def lib():
         L.kb_set_option.restype = C.c_int
         L.kb_run.argtypes = [vp, C.c_int64, C.c_int64]
         L.kb_run.restype = C.c_int
+        L.kb_reduce_noalloc.argtypes = [C.POINTER(vp), C.c_int, C.c_int64, C.c_int, vp, vp]
+        L.kb_reduce_noalloc.restype = C.c_int
         L.kb_read.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
         L.kb_read.restype = C.c_int
         L.kb_write.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
@@ -122,6 +124,26 @@ def _shape_arr(shape):
 def workspace_bytes(problem, shape):
     arr, nd = _shape_arr(shape)
     return int(lib().kb_workspace_bytes(problem, arr, nd))
+
+
+def reduce_noalloc(arrays, square=False, out=None, stream=None):
+    """kb_reduce_noalloc: deterministic sum (or sum of squares) over 1..6
+    contiguous float32 device tensors of equal size into a float64 device
+    tensor of one element (`out`, a new one unless given), enqueued on
+    `stream` (torch's current stream by default); the library's static
+    scratch holds the partials, nothing is allocated by the call."""
+    arrays = list(arrays)
+    n = arrays[0].numel()
+    for a in arrays:
+        assert a.is_cuda and a.dtype == torch.float32 and a.is_contiguous() and a.numel() == n
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=arrays[0].device)
+    s = stream if stream is not None else torch.cuda.current_stream(arrays[0].device)
+    ptrs = (C.c_void_p * len(arrays))(*[a.data_ptr() for a in arrays])
+    with torch.cuda.device(arrays[0].device):
+        _check(lib().kb_reduce_noalloc(ptrs, len(arrays), n, int(bool(square)), C.c_void_p(out.data_ptr()),
+                                       C.c_void_p(s.cuda_stream)))
+    return out
 
 
 def stream_probe(nin, nout, n, reps=10, device=0):

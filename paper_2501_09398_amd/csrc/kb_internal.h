@@ -280,6 +280,11 @@ RedLogArgs reduce_log_args(const float *const *fields, int nf, int ngroups, int 
 // Deterministic reductions (enqueued on s; partials has >= reduce_max_blocks doubles).
 int reduce_max_blocks();
 hipError_t reduce_sum(const float *x, long long n, double *partials, double *result, hipStream_t s);
+// Sum (square = 0) or sum of squares (1) over nf <= 6 arrays of n floats
+// into *result; partials holds >= reduce_max_blocks doubles.
+hipError_t reduce_impl(const float *const *f, int nf, int square, long long n, double *partials, double *result,
+                       hipStream_t s);
+constexpr long long kReduceNoallocMaxN = 1LL << 40;
 hipError_t stream_probe(int nin, int nout, long long n, float *ws, hipStream_t s, int reps, double *seconds);
 hipError_t reduce_sumsq(const float *const *fields, int nf, long long n, double *partials, double *result,
                         hipStream_t s);

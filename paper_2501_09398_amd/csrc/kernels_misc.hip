@@ -1,4 +1,6 @@
 // Seeded initial state, the skeleton chain and the deterministic reductions.
+#include <mutex>
+
 #include "kb_internal.h"
 
 namespace kb {
@@ -217,8 +219,8 @@ void make_reduce_log(Launch &L1, Launch &L2, const RedLogArgs &a) {
   L2.set((const void *)reduce_log_pass2, dim3(1), dim3(256), 0, a);
 }
 
-static hipError_t reduce_impl(const float *const *f, int nf, int square, long long n, double *partials,
-                              double *result, hipStream_t s) {
+hipError_t reduce_impl(const float *const *f, int nf, int square, long long n, double *partials, double *result,
+                       hipStream_t s) {
   long long chunk = (n + kRedBlocks - 1) / kRedBlocks;
   chunk = ((chunk + 1023) / 1024) * 1024;
   if (chunk < 1024) chunk = 1024;
@@ -242,6 +244,62 @@ hipError_t reduce_sumsq(const float *const *fields, int nf, long long n, double 
                         hipStream_t s) {
   return reduce_impl(fields, nf, 1, n, partials, result, s);
 }
+
+}  // namespace kb
+
+// ---------------------------------------------------------------------------
+// The reduction without a workspace (kb_reduce_noalloc): the per-block
+// partials live in this file-scope device array, one copy per GPU, held
+// until the process ends (kRedBlocks doubles = 8 KiB).  Host code never
+// passes the array's name to a kernel: the name is a host-side stand-in.
+// Its device address is resolved once per device with hipGetSymbolAddress
+// and kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kb::kRedBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on the current device (resolved on the first call
+// there); nullptr and a message on failure.
+double *scratch_on_current_device(const char **why) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *why = "no current HIP device (or device index >= 64)";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *why = "hipGetSymbolAddress of the scratch array failed";
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int kb_reduce_noalloc(const float *const *x, int nx, int64_t n, int square, double *out, void *stream) {
+  if (!x || !out || nx < 1 || nx > 6 || n < 0 || (square != 0 && square != 1))
+    return kb::kb_set_error(KB_EINVAL, "kb_reduce_noalloc: need 1..6 arrays, n >= 0, square 0 or 1, an output");
+  if (n > kb::kReduceNoallocMaxN)
+    return kb::kb_set_error(KB_EINVAL, "kb_reduce_noalloc: n exceeds the 2^40 elements per array it accepts");
+  for (int q = 0; q < nx; ++q)
+    if (!x[q] && n > 0) return kb::kb_set_error(KB_EINVAL, "kb_reduce_noalloc: null array");
+  const char *why = "";
+  double *partials = scratch_on_current_device(&why);
+  if (!partials) return kb::kb_set_error(KB_EHIP, why);
+  const hipError_t e = kb::reduce_impl(x, nx, square, n, partials, out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return kb::kb_set_error(KB_EHIP, hipGetErrorString(e));
+  return KB_OK;
+}
+
+namespace kb {
 
 // ---------------------------------------------------------------------------
 // Streaming calibration: out_j[i] = sum_k in_k[i], one float4 i per thread
