@@ -56,6 +56,7 @@ ITERS = 10000
 SKEL_COUNTERS = os.path.join(ROOT, "profiles", "skeleton_2p16_hbm_counters.json")
 SKEL_TRACE = os.path.join(ROOT, "profiles", "skeleton_2p16_trace_gaps.json")
 FDTD_COUNTERS = os.path.join(ROOT, "profiles", "fdtd_256_fused_hbm_counters.json")
+FDTD_TB2_COUNTERS = os.path.join(ROOT, "profiles", "fdtd_256_tb2_hbm_counters.json")
 MISC_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "kernels_misc.hip")
 FDTD_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "fdtd.hip")
 
@@ -66,6 +67,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3, help="timed jobs per arm (each 10,000 cavity steps)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--b", type=int, default=0, help="fix the cavity's batch size (skips the autotuner)")
+    ap.add_argument("--fdtd-variant", type=int, default=8, help="cavity kernel variant with --b")
+    ap.add_argument("--fdtd-depth", type=int, default=2, help="steps per launch of that variant with --b")
     ap.add_argument("--only", choices=("all", "fdtd", "skeleton"), default="all",
                     help="'fdtd': the headline cavity alone; 'skeleton': the skeleton chain alone")
     ap.add_argument("--arm", choices=("both", "graph", "per_launch"), default="both",
@@ -94,6 +97,7 @@ KERNEL_RUNS = {
     "heat3d_8x4096": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 9, 5),
     "fdtd_256": ("FDTD3D", (256, 64), "FDTD_COEFFS", 2, 5),
     "fdtd_256_fused": ("FDTD3D", (256, 64), "FDTD_COEFFS", 7, 10),
+    "fdtd_256_tb2": ("FDTD3D", (256, 64), "FDTD_COEFFS", 8, 10, 2),     # 5 launches of 2 steps
     "surrogate_512": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 1, 160),
     "surrogate_512_layered": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 2, 160),
     # 64 square grids of side round(64 * 16^u) (shape filled in from the seed)
@@ -186,6 +190,10 @@ def skeleton_kernel_hash():
 
 def fdtd_fused_kernel_hash():
     return source_hash(FDTD_SOURCE, "void fdtd_fused_kernel(", "bool make_fdtd_fused")
+
+
+def fdtd_tb2_kernel_hash():
+    return source_hash(FDTD_SOURCE, "void fdtd_tb2_kernel(", "bool make_fdtd_tb2")
 
 
 def stored_traffic(path, current_hash):
@@ -562,17 +570,19 @@ def fdtd_headline(args, kb, autotune, np, torch):
     cells, nodes = N ** 3, (N + 1) ** 3
     tuned = None
     if args.b > 0:
-        variant, b = 0, args.b               # 0: the default fused variant for the size
+        variant, depth, b = args.fdtd_variant, args.fdtd_depth, args.b
     else:
         tr = autotune.tune(kb, kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, n, seed=SEED, reps=1, probe_steps=200,
-                           b_candidates=FDTD_B_CANDIDATES, kernel_candidates_override=[(2, 1), (5, 1), (7, 1)])
-        variant, b = tr.variant, tr.b
-        tuned = {"variant": tr.variant, "b": tr.b, "b_measured_best": tr.b_measured,
-                 "kernel_table_us_step": [(v, round(us, 2)) for v, _, us in tr.kernel_table],
+                           b_candidates=FDTD_B_CANDIDATES,
+                           kernel_candidates_override=[(2, 1), (5, 1), (7, 1), (8, 2)])
+        variant, depth, b = tr.variant, tr.depth, tr.b
+        tuned = {"variant": tr.variant, "depth": tr.depth, "b": tr.b, "b_measured_best": tr.b_measured,
+                 "kernel_table_us_step": [(v, t, round(us, 2)) for v, t, us in tr.kernel_table],
                  "batch_table_ms": [[bb, round(tc * 1e3, 3), round(te * 1e3, 3)] for bb, tc, te in tr.batch_table],
                  "model": tr.model}
     p = kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, SEED, device=0)
     p.set_option(kb.OPT_TILE, variant)
+    p.set_option(kb.OPT_TDEPTH, depth)
     p.set_option(kb.OPT_GRAPH_CACHE, 0)          # every job pays its own T_C (Eq. 1)
     Kf = p.kernels_per_iter()
 
@@ -595,7 +605,7 @@ def fdtd_headline(args, kb, autotune, np, torch):
         torch.cuda.synchronize()
         return T, TC, TE, time.perf_counter() - t0
 
-    out = {"variant": variant, "b": b, "kernels_per_iter": Kf, "autotune": tuned}
+    out = {"variant": variant, "depth": depth, "b": b, "kernels_per_iter": Kf, "autotune": tuned}
     g_T = g_TC = g_TE = None
     wall = None
     if args.arm in ("both", "graph"):
@@ -626,17 +636,26 @@ def fdtd_headline(args, kb, autotune, np, torch):
     step_s = float(np.mean(g_TE)) / n
     p.destroy()
     eff = variant or (7 if N >= 176 else 5)          # the default fused variant for the size
-    name = {7: "fdtd_fused_kernel<1,true>", 5: "fdtd_fused_kernel<1,false>", 6: "fdtd_fused_kernel<8,false>"}.get(
-        eff, "fdtd_h_vec_kernel + fdtd_e_vec_kernel")
+    if eff == 8 and depth == 2:
+        name = "fdtd_tb2_kernel<true>"
+    else:
+        name = {7: "fdtd_fused_kernel<1,true>", 5: "fdtd_fused_kernel<1,false>", 6: "fdtd_fused_kernel<8,false>",
+                8: "fdtd_fused_kernel<1,true>"}.get(eff, "fdtd_h_vec_kernel + fdtd_e_vec_kernel")
+    steps_per_launch = depth if eff == 8 else 1
     probe_s = kb.stream_probe(6, 6, 1 << 28, reps=10)
     mix_gbs = 12 * (1 << 28) * 4 / probe_s / 1e9
     achieved = FDTD_BYTES_PER_CELL_STEP * cells / step_s / 1e9
-    kern = FDTD_KERNEL_BYTES_PER_NODE * nodes / step_s / 1e9
+    # the dominant kernel's own bytes: six fields read and six written per
+    # launch, a launch advancing steps_per_launch steps
+    kern = FDTD_KERNEL_BYTES_PER_NODE * nodes / (step_s * steps_per_launch) / 1e9
     out["roofline"] = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-        "traffic": stored_traffic(FDTD_COUNTERS, fdtd_fused_kernel_hash()),
+        "traffic": (stored_traffic(FDTD_TB2_COUNTERS, fdtd_tb2_kernel_hash()) if name.startswith("fdtd_tb2")
+                    else stored_traffic(FDTD_COUNTERS, fdtd_fused_kernel_hash())),
         "kernel": name,
-        "step_us": step_s * 1e6, "bytes_per_launch": FDTD_BYTES_PER_CELL_STEP * cells,
+        "step_us": step_s * 1e6, "steps_per_launch": steps_per_launch,
+        "launch_us_upper": step_s * steps_per_launch * 1e6,
+        "bytes_per_launch": FDTD_BYTES_PER_CELL_STEP * cells,
         "bytes_per_cell_step": FDTD_BYTES_PER_CELL_STEP, "cells_per_launch": cells,
         # the fused kernel's own minimum: six fields read and six written
         "kernel_bytes_per_launch": FDTD_KERNEL_BYTES_PER_NODE * nodes, "kernel_achieved": kern,
@@ -851,6 +870,7 @@ def main():
             "config": {"workload": "FDTD Yee PEC cavity 256^3, Courant 0.5, 10000 steps per job (H update, E update "
                                    "and soft source per step), graph batch b with loop peeling",
                        "N": N_FDTD, "steps_per_job": FDTD_STEPS, "b": h["b"], "variant": h["variant"],
+                       "steps_per_iter": h["depth"],
                        "kernels_per_iter": h["kernels_per_iter"], "parallelism": "single GPU"},
             "arms": {k: h.get(k) for k in ("graph", "per_launch", "speedup", "speedup_err", "speedup_device")},
             "roofline": h["roofline"], "autotune": h["autotune"]})

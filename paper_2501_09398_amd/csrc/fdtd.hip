@@ -15,6 +15,8 @@
 //
 // Both kernels are HBM-bound: 36 algorithmic bytes per node (three fields
 // read, three read and written).
+#include <algorithm>
+
 #include "kb_internal.h"
 
 namespace kb {
@@ -577,6 +579,191 @@ bool make_fdtd_fused(Launch &L, const FdtdFusedArgs &a, int kc, bool nt) {
 // Soft source (the third kernel of a step): reads the device step counter n,
 // adds g[n] to Ez at the source node, records the probe, increments n.  The
 // counter lives on the device so a replayed graph sees the absolute step.
+// ---------------------------------------------------------------------------
+// Two steps per launch (temporal blocking, variant 8 with depth 2).
+//
+// A block owns an output tile of 60 nodes along i x 13 rows along j x tk
+// planes along k and marches through its planes.  Lane l of wave w holds
+// node (i0 - 2 + l, j0 - 2 + w): each step's H update needs E at i+1, j+1,
+// k+1 and its E update H at i-1, j-1, k-1, so two steps need two nodes /
+// rows of halo below the tile and one above; halo nodes are recomputed by
+// the neighbouring blocks as well (60 of 64 lanes and 13 of 16 rows are
+// outputs).  Along i the neighbour is the adjacent lane (DPP); along j the
+// rows of the intermediate fields that other waves need pass through LDS;
+// along k a thread keeps the previous plane of each field in registers.
+// Iteration m of the march computes, for the wave's row:
+//   A  H^{n+1/2} of plane m      (E^n of planes m, m+1; rows j, j+1)
+//   B  E^{n+1}   of plane m      (+ the source of step n), from H^{n+1/2}
+//                                of planes m-1, m and rows j-1, j
+//   C  H^{n+3/2} of plane m-1    from E^{n+1} of planes m-1, m, rows j, j+1
+//   D  E^{n+2}   of plane m-1    (+ the source of step n+1), from H^{n+3/2}
+//                                of planes m-2, m-1 and rows j-1, j
+// and stores plane m-1 of the outputs.  Two barriers per plane: after A
+// (B reads row j-1 of H^{n+1/2}) and after C (D reads row j-1 of
+// H^{n+3/2}); C reads row j+1 of E^{n+1} of plane m-1, written in the
+// previous iteration (double-buffered by plane parity).  Every update is the
+// one-step kernels' expression with the same operand order, and a node that
+// a step does not update keeps its value, so two launches of the fused step
+// and one launch of this kernel give the same bits.
+// ---------------------------------------------------------------------------
+constexpr int kTbNW = 16;              // waves (rows) per block
+constexpr int kTbTJ = kTbNW - 3;       // output rows per block
+constexpr int kTbTI = 60;              // output nodes along i per block
+
+template <bool NT>
+__device__ __forceinline__ void st1(float *p, float v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <bool NT>
+__global__ __launch_bounds__(1024) void fdtd_tb2_kernel(const FdtdTbArgs a) {
+  __shared__ float sH1[2][kTbNW][64];      // H^{n+1/2} x, z of the current plane
+  __shared__ float sE1[2][2][kTbNW][64];   // [plane parity][x, z] E^{n+1}
+  __shared__ float sH2[2][kTbNW][64];      // H^{n+3/2} x, z
+  const int nb = a.ni * a.nj * a.nk;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;                    // the whole block: before any barrier
+  const int ti = lb % a.ni, tj = (lb / a.ni) % a.nj, tkk = lb / (a.ni * a.nj);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int N = a.N, M = N + 1;
+  const int i = ti * kTbTI - 2 + lane;
+  const int j = tj * kTbTJ - 2 + w;
+  const int kb = tkk * a.tk, ke = min(kb + a.tk, M);   // output planes [kb, ke)
+  const bool iv = i >= 0 && i <= N, jv = j >= 0 && j <= N, vld = iv && jv;
+  const bool jup = vld && j + 1 <= N;
+  const bool out_ij = vld && lane >= 2 && lane < 2 + kTbTI && w >= 2 && w < 2 + kTbTJ;
+  const bool ii = i >= 1 && i <= N - 1, jj = j >= 1 && j <= N - 1;
+  const bool ilt = i < N, jlt = j < N;
+  const int wm = w > 0 ? w - 1 : 0, wp = w < kTbNW - 1 ? w + 1 : kTbNW - 1;
+  const size_t sk = (size_t)M * a.P;
+  const size_t cij = vld ? (size_t)j * a.P + i : 0;
+  const float dt = a.dt;
+  const long long n = *a.step;
+  const bool add0 = n >= 0 && n < a.glen, add1 = n + 1 >= 0 && n + 1 < a.glen;
+  const float g0 = add0 ? a.g[n] : 0.f, g1 = add1 ? a.g[n + 1] : 0.f;
+  const bool srcij = i == a.si && j == a.sj;
+
+  auto ld = [&](const float *f, int k, bool ok) -> float { return ok && k >= 0 && k <= N ? f[k * sk + cij] : 0.f; };
+  auto ldj = [&](const float *f, int k) -> float {           // row j+1
+    return jup && k >= 0 && k <= N ? f[k * sk + cij + a.P] : 0.f;
+  };
+
+  const int m0 = max(kb - 2, 0);
+  // E^n of plane m0 (own row)
+  float ex = ld(a.Ex, m0, vld), ey = ld(a.Ey, m0, vld), ez = ld(a.Ez, m0, vld);
+  float h1x_p = 0.f, h1y_p = 0.f, h1z_p = 0.f;      // H^{n+1/2} of plane m-1
+  float e1x_p = 0.f, e1y_p = 0.f, e1z_p = 0.f;      // E^{n+1} of plane m-1
+  float h2x_p = 0.f, h2y_p = 0.f;                   // H^{n+3/2} of plane m-2
+  for (int m = m0; m <= ke; ++m) {
+    const bool pm = m <= N;                          // plane m exists
+    // ---- A: H^{n+1/2} of plane m
+    const float exk = ld(a.Ex, m + 1, vld), eyk = ld(a.Ey, m + 1, vld), ezk = ld(a.Ez, m + 1, vld);
+    const float ex_j = ldj(a.Ex, m), ez_j = ldj(a.Ez, m);
+    const float hx = ld(a.Hx, m, vld), hy = ld(a.Hy, m, vld), hz = ld(a.Hz, m, vld);
+    const float ey_e = lane_east_open(ey), ez_e = lane_east_open(ez);
+    const bool mlt = m < N;
+    const float h1x = (jlt && mlt) ? hx - dt * ((ez_j - ez) - (eyk - ey)) : hx;
+    const float h1y = (ilt && mlt) ? hy - dt * ((exk - ex) - (ez_e - ez)) : hy;
+    const float h1z = (ilt && jlt) ? hz - dt * ((ey_e - ey) - (ex_j - ex)) : hz;
+    sH1[0][w][lane] = h1x;
+    sH1[1][w][lane] = h1z;
+    __syncthreads();
+    // ---- B: E^{n+1} of plane m
+    const float h1x_jm = sH1[0][wm][lane], h1z_jm = sH1[1][wm][lane];
+    const float h1z_w = lane_west_open(h1z), h1y_w = lane_west_open(h1y);
+    const bool kk = m >= 1 && m <= N - 1;
+    const float e1x = (ilt && jj && kk) ? ex + dt * ((h1z - h1z_jm) - (h1y - h1y_p)) : ex;
+    const float e1y = (jlt && ii && kk) ? ey + dt * ((h1x - h1x_p) - (h1z - h1z_w)) : ey;
+    float e1z = (mlt && ii && jj) ? ez + dt * ((h1y - h1y_w) - (h1x - h1x_jm)) : ez;
+    if (srcij && m == a.sk) {
+      if (add0) e1z = e1z + g0;
+      if (out_ij && m >= kb && m < ke && n >= 0 && n < a.pcap) a.probe[n] = e1z;
+    }
+    sE1[m & 1][0][w][lane] = pm ? e1x : 0.f;
+    sE1[m & 1][1][w][lane] = pm ? e1z : 0.f;
+    // ---- C: H^{n+3/2} of plane q = m-1 (E^{n+1} of row j+1, plane q, from
+    // the previous iteration's buffer)
+    const int q = m - 1;
+    const bool doC = q >= 0 && q >= kb - 1 && q <= ke - 1;
+    float h2x = 0.f, h2y = 0.f, h2z = 0.f;
+    if (doC) {
+      const float e1x_jq = sE1[q & 1][0][wp][lane], e1z_jq = sE1[q & 1][1][wp][lane];
+      const float e1xn = pm ? e1x : 0.f, e1yn = pm ? e1y : 0.f;   // E^{n+1} of plane q+1
+      const bool qlt = q < N;
+      h2x = (jlt && qlt) ? h1x_p - dt * ((e1z_jq - e1z_p) - (e1yn - e1y_p)) : h1x_p;
+      h2y = (ilt && qlt) ? h1y_p - dt * ((e1xn - e1x_p) - (lane_east_open(e1z_p) - e1z_p)) : h1y_p;
+      h2z = (ilt && jlt) ? h1z_p - dt * ((lane_east_open(e1y_p) - e1y_p) - (e1x_jq - e1x_p)) : h1z_p;
+    }
+    sH2[0][w][lane] = h2x;
+    sH2[1][w][lane] = h2z;
+    __syncthreads();
+    // ---- D: E^{n+2} of plane q, and the outputs of plane q
+    if (q >= kb && q <= ke - 1) {
+      const float h2x_jm = sH2[0][wm][lane], h2z_jm = sH2[1][wm][lane];
+      const float h2z_w = lane_west_open(h2z), h2y_w = lane_west_open(h2y);
+      const bool kq = q >= 1 && q <= N - 1;
+      const float e2x = (ilt && jj && kq) ? e1x_p + dt * ((h2z - h2z_jm) - (h2y - h2y_p)) : e1x_p;
+      const float e2y = (jlt && ii && kq) ? e1y_p + dt * ((h2x - h2x_p) - (h2z - h2z_w)) : e1y_p;
+      float e2z = (q < N && ii && jj) ? e1z_p + dt * ((h2y - h2y_w) - (h2x - h2x_jm)) : e1z_p;
+      if (srcij && q == a.sk) {
+        if (add1) e2z = e2z + g1;
+        if (out_ij && n + 1 >= 0 && n + 1 < a.pcap) a.probe[n + 1] = e2z;
+      }
+      if (out_ij) {
+        const size_t c = (size_t)q * sk + cij;
+        st1<NT>(a.oEx + c, e2x);
+        st1<NT>(a.oEy + c, e2y);
+        st1<NT>(a.oEz + c, e2z);
+        st1<NT>(a.oHx + c, h2x);
+        st1<NT>(a.oHy + c, h2y);
+        st1<NT>(a.oHz + c, h2z);
+      }
+    }
+    // ---- rotate: plane m becomes the previous plane
+    h2x_p = h2x;
+    h2y_p = h2y;
+    h1x_p = h1x;
+    h1y_p = h1y;
+    h1z_p = h1z;
+    e1x_p = e1x;
+    e1y_p = e1y;
+    e1z_p = e1z;
+    ex = exk;
+    ey = eyk;
+    ez = ezk;
+  }
+}
+
+bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a0, bool nt) {
+  FdtdTbArgs a = a0;
+  const int M = a.N + 1;
+  a.ni = (M + kTbTI - 1) / kTbTI;
+  a.nj = (M + kTbTJ - 1) / kTbTJ;
+  // plane segments of about 32 planes, equal in length
+  a.nk = std::max(1, (M + 16) / 32);
+  a.tk = (M + a.nk - 1) / a.nk;
+  a.nk = (M + a.tk - 1) / a.tk;
+  const int nb = a.ni * a.nj * a.nk;
+  const dim3 grid((unsigned)xcd_padded_grid(nb));
+  if (nt) L.set((const void *)fdtd_tb2_kernel<true>, grid, dim3(64 * kTbNW), 0, a);
+  else L.set((const void *)fdtd_tb2_kernel<false>, grid, dim3(64 * kTbNW), 0, a);
+  return true;
+}
+
+struct StepAddArgs {
+  long long *step;
+  int d;
+};
+
+__global__ void fdtd_step_add_kernel(const StepAddArgs a) {
+  if (threadIdx.x == 0) *a.step += a.d;
+}
+
+void make_fdtd_step_add(Launch &L, long long *step, int d) {
+  L.set((const void *)fdtd_step_add_kernel, dim3(1), dim3(64), 0, StepAddArgs{step, d});
+}
+
 __global__ void fdtd_src_kernel(const SrcArgs s) {
   if (threadIdx.x != 0) return;
   const long long n = *s.step;

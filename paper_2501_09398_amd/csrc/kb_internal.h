@@ -201,6 +201,24 @@ struct FdtdFusedArgs {
 };
 bool make_fdtd_fused(Launch &L, const FdtdFusedArgs &a, int kc, bool nt);   // kc: planes per thread (1, 8); nt: streaming stores (kc 1)
 
+// Two steps per launch (temporal blocking): reads E^n, H^{n-1/2} from one
+// buffer set and writes E^{n+2}, H^{n+3/2} to the other, applying the soft
+// source (and recording the probe) after each of the two E updates; the
+// device step counter is advanced by a separate launch.
+struct FdtdTbArgs {
+  const float *Ex, *Ey, *Ez, *Hx, *Hy, *Hz;
+  float *oEx, *oEy, *oEz, *oHx, *oHy, *oHz;
+  int N, P;
+  float dt;
+  int tk, ni, nj, nk;           // planes per block; tiles along i, j, k
+  int si, sj, sk;               // source node (i, j, k)
+  const float *g; int glen;     // amplitude per absolute step
+  float *probe; int pcap;
+  const long long *step;
+};
+bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a, bool nt);   // fills tk..nk itself
+void make_fdtd_step_add(Launch &L, long long *step, int d);
+
 struct SrcArgs {
   float *Ez; long long src;     // flat index of the source node
   const float *g; int glen;     // amplitude per absolute step

@@ -149,6 +149,28 @@ def fdtd256():
 
 
 @gpu
+def test_fdtd_256_two_step_vs_oracle(kb, fdtd256):
+    """The two-step kernel (variant 8, depth 2, streaming stores at this
+    size) at 256^3: 100 steps in graph batches of 50 two-step iterations,
+    bit for bit with the float32 oracle on every node, and the probe."""
+    d = fdtd256
+    N, steps = d["N"], d["steps"]
+    for start in ("zero", "rand"):
+        announce(f"fdtd 256^3 {start} fields, 100 steps, two-step kernel, b=50")
+        with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, d["seed"]) as p:
+            p.set_option(kb.OPT_TILE, 8)
+            p.set_option(kb.OPT_TDEPTH, 2)
+            if start == "rand":
+                for k, fid in kb.FDTD_FIELDS.items():
+                    p.write(fid, d["f0"][k])
+            p.run(steps, 50)
+            probe = p.read(kb.F_PROBE)
+            for k, fid in kb.FDTD_FIELDS.items():
+                assert np.array_equal(p.read(fid), d[start][k]), (start, k)
+        assert np.array_equal(probe[:steps], d["probe"] if start == "zero" else d["rprobe"])
+
+
+@gpu
 @pytest.mark.parametrize("variant", [7, 5, 2])
 def test_fdtd_256_vs_oracle(kb, fdtd256, variant):
     """256^3 (two field sets of 0.8 GB): 100 steps in graph batches of 100

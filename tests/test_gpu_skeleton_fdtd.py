@@ -137,6 +137,48 @@ def test_fdtd_bitwise_vs_oracle(kb, N, steps, variant):
     assert np.all(probe[steps:] == 0)
 
 
+@pytest.mark.parametrize("N,steps", [(4, 61), (5, 60), (8, 150), (17, 121), (33, 40), (70, 23), (75, 100)])
+def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps):
+    """Variant 8 with depth 2 (two steps per launch, temporal blocking):
+    from zero fields with the source on and from random fields on every
+    node, per launch and in graph batches (an odd step count ends with one
+    fused step), bit for bit with the float32 oracle, probe included.
+    N = 70 and 75 span several tiles along i (60 nodes), j (13 rows) and k
+    (plane segments)."""
+    announce(f"fdtd two-step N={N} steps={steps}")
+    seed = 36
+    src = synth.fdtd_source_cell(seed, N)
+    _, g32 = oracle.fdtd_pulse(steps + 1)
+    M = N + 1
+    rng = np.random.default_rng(N)
+    f0 = {k: rng.uniform(-1.0, 1.0, (M, M, M)).astype(np.float32) for k in oracle.FDTD_FIELDS}
+    for start in ("zero", "rand"):
+        init = oracle.fdtd_zero_fields(N, np.float32) if start == "zero" else f0
+        ref, probe_ref = oracle.fdtd(init, N, steps, src=src, g=g32, dtype=np.float32)
+        for b in (0, 3):
+            with kb.Problem(kb.FDTD3D, (N, 512), kb.FDTD_COEFFS, seed) as p:
+                p.set_option(kb.OPT_TILE, 8)
+                p.set_option(kb.OPT_TDEPTH, 2)
+                if start == "rand":
+                    for k, fid in kb.FDTD_FIELDS.items():
+                        p.write(fid, f0[k])
+                p.run(steps, b)
+                got = gpu_fields(kb, p)
+                probe = p.read(kb.F_PROBE)
+                assert p.read(kb.F_STEP)[0] == steps
+            for k in oracle.FDTD_FIELDS:
+                assert np.array_equal(got[k], ref[k]), (start, b, k)
+            assert np.array_equal(probe[:steps], probe_ref), (start, b)
+
+
+def test_fdtd_two_step_depth_limits(kb):
+    with kb.Problem(kb.FDTD3D, (8, 64), kb.FDTD_COEFFS, 0) as p:
+        p.set_option(kb.OPT_TILE, 8)
+        p.set_option(kb.OPT_TDEPTH, 3)
+        with pytest.raises(kb.KBError):
+            p.run(6, 0)
+
+
 @pytest.mark.parametrize("b", [1, 7, 40])
 @pytest.mark.parametrize("builder", [0, 1])
 @pytest.mark.parametrize("variant", [2, 5])
