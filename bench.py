@@ -61,6 +61,11 @@ MISC_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "kernels_misc.h
 FDTD_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "fdtd.hip")
 
 
+def note(msg):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +376,7 @@ def workloads(kb, pm, autotune, np):
         return t["t_create_s"] + t["t_exec_s"]
 
     # 2D thermal stencil, 256x256, 1000 steps (launch-bound)
+    note("workloads: heat2d 256^2")
     n = 1000
     d = {"steps": n, "cells": 256 * 256}
     with kb.Problem(kb.HEAT2D, (256, 256), kb.HEAT_COEFFS, SEED) as p:
@@ -389,6 +395,7 @@ def workloads(kb, pm, autotune, np):
     out["heat2d_256x256_1000"] = d
 
     # 3D stencil 8x512x512, 2000 steps
+    note("workloads: heat3d 8x512^2")
     n = 2000
     d = {"steps": n, "cells": 8 * 512 * 512}
     with kb.Problem(kb.HEAT3D, (8, 512, 512), kb.HEAT_COEFFS, SEED) as p:
@@ -412,6 +419,7 @@ def workloads(kb, pm, autotune, np):
     out["heat3d_8x512x512_2000"] = d
 
     # many uneven grids, one kernel per step over all of them
+    note("workloads: 64 uneven grids")
     import synth
     sides = synth.multigrid_sides(SEED, 64)
     shape = [64] + [v for s in sides for v in (s, s)]
@@ -464,6 +472,7 @@ def workloads(kb, pm, autotune, np):
     out["multigrid_64_2000"] = d
 
     # FDTD cavities
+    note("workloads: FDTD cavities")
     # (separate H and E kernels: 72 B per node-step; the fused step: 48 B)
     for N, n in ((128, 10000), (256, 2000)):
         d = {"steps": n, "cells": N ** 3}
@@ -484,6 +493,7 @@ def workloads(kb, pm, autotune, np):
                               "t_create_ms": tr.t_create_s * 1e3, "b_measured_best": tr.b_measured}
         out[f"fdtd_{N}^3_{n}"] = d
 
+    note("workloads: surrogate")
     # learned 16-step surrogate at 512^2 (network, residual check and the
     # predicated fallback in every block) vs the plain stencil
     from paper_2501_09398_amd import sg_train
@@ -520,6 +530,7 @@ def workloads(kb, pm, autotune, np):
         out["surrogate_512_k16"] = d
 
     # large grids against the HBM roofline (working sets >> 256 MB cache)
+    note("workloads: large grids")
     big = {}
     for name, prob, shp, var, bytes_per_cell in (
             ("heat2d_16384^2", kb.HEAT2D, (16384, 16384), 13, 12.0),
@@ -572,6 +583,7 @@ def fdtd_headline(args, kb, autotune, np, torch):
     if args.b > 0:
         variant, depth, b = args.fdtd_variant, args.fdtd_depth, args.b
     else:
+        note("cavity: autotuning the kernel variant and b")
         tr = autotune.tune(kb, kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, n, seed=SEED, reps=1, probe_steps=200,
                            b_candidates=FDTD_B_CANDIDATES,
                            kernel_candidates_override=[(2, 1), (5, 1), (7, 1), (8, 2)])
@@ -609,6 +621,7 @@ def fdtd_headline(args, kb, autotune, np, torch):
     g_T = g_TC = g_TE = None
     wall = None
     if args.arm in ("both", "graph"):
+        note(f"cavity: graph arm, variant {variant} depth {depth} b {b}")
         g_T, g_TC, g_TE, wall = arm(b)
         out["graph"] = {"b": b, "us_per_iter": float(np.mean(g_T)) / n * 1e6,
                         "us_per_iter_warm": float(np.mean(g_TE)) / n * 1e6,
@@ -616,6 +629,7 @@ def fdtd_headline(args, kb, autotune, np, torch):
                         "t_create_ms": float(np.mean(g_TC)) * 1e3,
                         "gcell_upd_s": cells * n / float(np.mean(g_T)) / 1e9}
     if args.arm in ("both", "per_launch"):
+        note("cavity: per-launch arm")
         b_T, _, b_TE, b_wall = arm(0)
         out["per_launch"] = {"us_per_iter": float(np.mean(b_T)) / n * 1e6,
                              "us_per_iter_device": float(np.mean(b_TE)) / n * 1e6,
@@ -875,6 +889,7 @@ def main():
             "arms": {k: h.get(k) for k in ("graph", "per_launch", "speedup", "speedup_err", "speedup_device")},
             "roofline": h["roofline"], "autotune": h["autotune"]})
         if not args.no_cpu_baseline:
+            note("cavity: CPU oracle baseline and the float64 error")
             cpu, fp64 = fdtd_cpu_baseline(kb, np, torch)
             line["cpu_baseline"] = cpu
             line["fp64_error"] = fp64
@@ -882,6 +897,7 @@ def main():
             line["cpu_baseline"] = None
     line["host"] = host_info()
     if args.only in ("all", "skeleton"):
+        note("skeleton chain: b sweep, fits, arms")
         sk = skeleton_section(args, kb, pm, np, torch, workloads_on)
         if args.only == "skeleton":
             line.update({"value": sk.get("graph", sk.get("per_launch", {})).get("gcell_upd_s"),
@@ -890,6 +906,7 @@ def main():
                          "config": {"workload": sk["workload"], "b": sk["b"]}})
         line["skeleton"] = sk
     if workloads_on:
+        note("other workloads")
         line["workloads"] = workloads(kb, pm, autotune, np)
     print(json.dumps(line), flush=True)
 
