@@ -489,7 +489,7 @@ def workloads(kb, pm, autotune, np):
         if N == 128:
             tr = autotune.tune(kb, kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, n, seed=SEED, reps=2,
                                b_candidates=[10, 20, 50, 100, 200, 500, 1000, 2000])
-            d["autotuned"] = {"variant": tr.variant, "b": tr.b, "us_step": tr.us_per_step_warm,
+            d["autotuned"] = {"variant": tr.variant, "depth": tr.depth, "b": tr.b, "us_step": tr.us_per_step_warm,
                               "t_create_ms": tr.t_create_s * 1e3, "b_measured_best": tr.b_measured}
         out[f"fdtd_{N}^3_{n}"] = d
 
@@ -571,6 +571,157 @@ def workloads(kb, pm, autotune, np):
                                      "gcell_upd_s": 256 ** 3 / d[f"{name}_graph_b100_us_step"] / 1e3}
     out["large_grids_hbm"] = big
     return out
+
+
+def workloads_cpu_baseline(kb, np, out):
+    """CPU-baseline leg of the other workloads: the oracle timed on this
+    host's cores (one thread, then every thread this process may use) on a
+    stated sample of each workload, and the GPU's result on that same
+    sample (the configuration the autotuner chose) against the float32
+    oracle (0.0 = the same bits) and the float64 oracle (relative max-norm;
+    for the surrogate also on the increment T - T0)."""
+    import oracle
+    import synth
+    info = host_info()
+    nt = info["threads_used"]
+    res = {"host": info}
+
+    def rel(a, b):
+        a = np.asarray(a, np.float64)
+        return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+    def timed(fn, threads):
+        with oracle.threads(threads):
+            t0 = time.perf_counter()
+            r = fn()
+            return r, time.perf_counter() - t0
+
+    def gpu_run(prob, shape, coeffs, seed, tuned, steps, writes=()):
+        with kb.Problem(prob, shape, coeffs, seed) as p:
+            for fid, v in writes:
+                p.write(fid, v)
+            if tuned:
+                p.set_option(kb.OPT_TILE, tuned["variant"])
+                p.set_option(kb.OPT_TDEPTH, tuned.get("depth", 1))
+                p.run(steps, tuned["b"])
+            else:
+                p.run(steps, 100)
+            return p.read(kb.F_T)
+
+    def entry(cell_steps_1, t1, cell_steps_n, tn, sample, got, r32, r64, **extra):
+        d = {"cpu_value_gcell_upd_s": cell_steps_n / tn / 1e9, "cores": nt, "seconds": tn,
+             "single_thread_gcell_upd_s": cell_steps_1 / t1 / 1e9, "single_thread_seconds": t1,
+             "sample": sample, "kind": "oracle",
+             "gpu_rel_maxnorm_vs_float32_oracle": rel(got, r32),
+             "gpu_bit_exact_vs_float32_oracle": bool(np.array_equal(got, r32)),
+             "gpu_rel_maxnorm_vs_float64_oracle": rel(got, r64),
+             "float32_oracle_rel_maxnorm_vs_float64": rel(r32, r64)}
+        d.update(extra)
+        return d
+
+    # 2D thermal stencil 256^2, the whole 1000-step job
+    note("cpu baseline: heat2d 256^2")
+    n = 1000
+    T0, P = synth.heat2d_init(SEED, 256, 256)
+    got = gpu_run(kb.HEAT2D, (256, 256), kb.HEAT_COEFFS, SEED, out["heat2d_256x256_1000"]["autotuned"], n)
+    r32, t1 = timed(lambda: oracle.heat2d(T0, P, n, dtype=np.float32), 1)
+    _, tn = timed(lambda: oracle.heat2d(T0, P, n, dtype=np.float32), nt)
+    r64, _ = timed(lambda: oracle.heat2d(T0, P, n, dtype=np.float64), nt)
+    cs = 256 * 256 * n
+    res["heat2d_256x256_1000"] = entry(cs, t1, cs, tn, "the whole job: 256^2, 1000 steps from the seeded state",
+                                       got, r32, r64)
+
+    # 3D stencil 8 x 512^2, the whole 2000-step job (one thread: 200 steps)
+    note("cpu baseline: heat3d 8x512^2")
+    n, n1 = 2000, 200
+    T0, P = synth.heat3d_init(SEED, 8, 512, 512)
+    got = gpu_run(kb.HEAT3D, (8, 512, 512), kb.HEAT_COEFFS, SEED, out["heat3d_8x512x512_2000"]["autotuned"], n)
+    _, t1 = timed(lambda: oracle.heat3d(T0, P, n1, dtype=np.float32), 1)
+    r32, tn = timed(lambda: oracle.heat3d(T0, P, n, dtype=np.float32), nt)
+    r64, _ = timed(lambda: oracle.heat3d(T0, P, n, dtype=np.float64), nt)
+    c = 8 * 512 * 512
+    res["heat3d_8x512x512_2000"] = entry(c * n1, t1, c * n, tn,
+                                         "the whole job: 8x512^2, 2000 steps (single thread: the first 200)",
+                                         got, r32, r64)
+
+    # 64 uneven grids: the first 200 steps of the job (one thread: 20)
+    note("cpu baseline: 64 uneven grids")
+    sides = synth.multigrid_sides(SEED, 64)
+    shape = [64] + [v for sd in sides for v in (sd, sd)]
+    n, n1 = 200, 20
+    T0s, Ps = synth.multigrid_init(SEED, sides)
+    got = gpu_run(kb.HEAT2D_MULTI, shape, kb.HEAT_COEFFS, SEED, out["multigrid_64_2000"]["autotuned"], n)
+    _, t1 = timed(lambda: [oracle.heat2d(a, b, n1, dtype=np.float32) for a, b in zip(T0s, Ps)], 1)
+    r32, tn = timed(lambda: [oracle.heat2d(a, b, n, dtype=np.float32) for a, b in zip(T0s, Ps)], nt)
+    r64, _ = timed(lambda: [oracle.heat2d(a, b, n, dtype=np.float64) for a, b in zip(T0s, Ps)], nt)
+    cells = sum(sd * sd for sd in sides)
+    r32 = np.concatenate([r.ravel() for r in r32])
+    r64 = np.concatenate([r.ravel() for r in r64])
+    res["multigrid_64_2000"] = entry(cells * n1, t1, cells * n, tn,
+                                     f"the first {n} steps of the job ({cells} cells in 64 grids; single thread: "
+                                     f"{n1} steps)", got, r32, r64)
+
+    # FDTD cavity 128^3: the first 100 steps of the job, source on
+    note("cpu baseline: FDTD 128^3")
+    N, n, n1 = 128, 100, 20
+    src = synth.fdtd_source_cell(SEED, N)
+    g64, g32 = oracle.fdtd_pulse(n + 1)
+    tuned = out["fdtd_128^3_10000"].get("autotuned")
+    with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, SEED) as p:
+        if tuned:
+            p.set_option(kb.OPT_TILE, tuned["variant"])
+            p.set_option(kb.OPT_TDEPTH, tuned.get("depth", 1))
+        p.run(n, 20)
+        gotf = {k: p.read(fid) for k, fid in kb.FDTD_FIELDS.items()}
+    z32, z64 = oracle.fdtd_zero_fields(N, np.float32), oracle.fdtd_zero_fields(N, np.float64)
+    _, t1 = timed(lambda: oracle.fdtd(z32, N, n1, src=src, g=g32, dtype=np.float32), 1)
+    (f32, _), tn = timed(lambda: oracle.fdtd(z32, N, n, src=src, g=g32, dtype=np.float32), nt)
+    (f64, _), _ = timed(lambda: oracle.fdtd(z64, N, n, src=src, g=g64, dtype=np.float64), nt)
+    keys = list(oracle.FDTD_FIELDS)
+    got = np.concatenate([gotf[k].ravel() for k in keys])
+    r32 = np.concatenate([f32[k].ravel() for k in keys])
+    r64 = np.concatenate([f64[k].ravel() for k in keys])
+    res["fdtd_128^3_10000"] = entry(N ** 3 * n1, t1, N ** 3 * n, tn,
+                                    f"the first {n} steps of the job (all six fields; single thread: {n1})",
+                                    got, r32, r64)
+
+    # learned surrogate 512^2: ten blocks of 16 steps against the plain
+    # stencil in float64; the CPU leg is the float64 network oracle (one
+    # application) and the plain float64 stencil
+    from paper_2501_09398_amd import sg_train
+    if os.path.exists(sg_train.WEIGHTS_FILE):
+        note("cpu baseline: surrogate 512^2")
+        w = sg_train.load_weights()
+        N, k, n = 512, 16, 160
+        T0, _ = synth.heat2d_init(SEED, N, N)
+        P = synth.hot_spot_power(SEED, N, N)
+        with kb.Problem(kb.HEAT2D_SURROGATE, (N, N), kb.HEAT_COEFFS + (0.8, 1e-3, k), SEED) as p:
+            p.set_option(kb.OPT_TILE, 1)
+            p.write(kb.F_T, T0)
+            p.write(kb.F_P, P)
+            p.write(kb.F_W, w)
+            p.run(n, 10)
+            got = p.read(kb.F_T).astype(np.float64)
+            st = p.read(kb.F_SGSTATS)
+        plain = gpu_run(kb.HEAT2D, (N, N), kb.HEAT_COEFFS, SEED, None, n, writes=((kb.F_T, T0), (kb.F_P, P)))
+        r64, tp = timed(lambda: oracle.heat2d(T0, P, n, dtype=np.float64), nt)
+        _, tnet = timed(lambda: oracle.sg_forward(w.astype(np.float64), T0, P), nt)
+        inc = r64 - T0
+        e_inc = lambda a: float(np.max(np.abs((np.asarray(a, np.float64) - T0) - inc)) / np.max(np.abs(inc)))
+        # one explicit step of 16c per block: the method's cheapest stand-in
+        eul = T0.astype(np.float64)
+        for _ in range(n // k):
+            eul = oracle.heat2d(eul, P, 1, c=k * 1e-3, dtype=np.float64)
+        res["surrogate_512_k16"] = {
+            "sample": f"{n // k} blocks of {k} steps at 512^2 from the seeded state with hot spots",
+            "surrogate_rel_maxnorm_vs_float64": rel(got, r64), "surrogate_inc_rel_maxnorm_vs_float64": e_inc(got),
+            "plain_gpu_rel_maxnorm_vs_float64": rel(plain, r64), "plain_gpu_inc_rel_maxnorm_vs_float64": e_inc(plain),
+            "euler16c_rel_maxnorm_vs_float64": rel(eul, r64), "euler16c_inc_rel_maxnorm_vs_float64": e_inc(eul),
+            "persistence_rel_maxnorm_vs_float64": rel(T0, r64),
+            "fallbacks": int(st[1]), "blocks": int(st[0]),
+            "cpu_plain_float64_gcell_upd_s": N * N * n / tp / 1e9,
+            "cpu_network_float64_s_per_application": tnet, "cores": nt, "kind": "oracle"}
+    return res
 
 
 def fdtd_headline(args, kb, autotune, np, torch):
@@ -908,6 +1059,8 @@ def main():
     if workloads_on:
         note("other workloads")
         line["workloads"] = workloads(kb, pm, autotune, np)
+        if not args.no_cpu_baseline:
+            line["workloads_cpu_baseline"] = workloads_cpu_baseline(kb, np, line["workloads"])
     print(json.dumps(line), flush=True)
 
 

@@ -229,7 +229,11 @@ extern "C" {
  *              float4 rows, each thread walking 8 / 16 planes in k;
  *              fused H + E step (2 kernels per iteration): 5 = float4 rows,
  *              one plane per thread, 6 = walking 8 planes, 7 = as 5 with
- *              streaming (non-temporal) stores.  Default: 7 when the two
+ *              streaming (non-temporal) stores; 8 = two steps per launch
+ *              with KB_OPT_TDEPTH 2 (blocks march along k, the intermediate
+ *              E and H rows shared through LDS; streaming stores when the
+ *              sets exceed 256 MiB), the fused step with depth 1 (and for
+ *              the last step of an odd count).  Default: 7 when the two
  *              field sets exceed 256 MiB (N >= 176), else 5.  The
  *              fused step reads one set of six fields and writes the other
  *              (48 instead of 72 bytes per node-step), so the state
@@ -253,7 +257,8 @@ extern "C" {
  *   temporal-blocking variant advances t steps (KB_HEAT2D LDS tile 1..16,
  *   register strips 15..17 1..8, register regions 18..21 1..8, register
  *   strips 22, 23 1..16; KB_HEAT3D variant 5 1..6, variant 11 1..8;
- *   KB_HEAT2D_MULTI variants 3..6 1..8; a launch whose variant does not
+ *   KB_HEAT2D_MULTI variants 3..6 1..8; KB_FDTD3D variant 8 1..2, the
+ *   option taking 1..2 for every cavity variant; a launch whose variant does not
  *   allow t fails with KB_EINVAL).  Other variants ignore it.  kb_run advances
  *   floor(n_steps / t) iterations of t steps, then n_steps mod t single
  *   steps per launch.                                                      */

@@ -4,7 +4,8 @@
  *   2 -> 32 (+GELU) -> 32 (+GELU) -> 32 (+GELU) -> 1,
  * on the normalised inputs t = (T0 - 333)/10, p = (P - 0.5)/0.29; its
  * output y is the normalised k-step increment, T_k = T0 + s*y.
- * GELU is the exact form 0.5 x (1 + erf(x / sqrt 2)).
+ * GELU is the exact form x Phi(x), Phi(x) = erfc(-x / sqrt 2) / 2 (the normal
+ * distribution function; no cancellation for negative x).
  *
  * Everything is evaluated in double.  With round = 1 the operands that the
  * GPU path feeds to its bf16 matrix cores are first rounded to bf16 (round
@@ -66,11 +67,16 @@ void or_bf16_round_n(const double *v, long n, double *out)
 
 static double rnd(double v, int round) { return round ? or_bf16_round(v) : v; }
 
-static double gelu(double x) { return 0.5 * x * (1.0 + erf(x / sqrt(2.0))); }
+/* Phi, the standard normal distribution function, as erfc(-x/sqrt 2)/2:
+ * the same function as (1 + erf(x/sqrt 2))/2 without its cancellation for
+ * negative x. */
+static double norm_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+static double gelu(double x) { return x * norm_cdf(x); }
 
 static double gelu_d(double x)
 {
-    return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * SG_PI);
+    return norm_cdf(x) + x * exp(-0.5 * x * x) / sqrt(2.0 * SG_PI);
 }
 
 /* GELU and its derivative elementwise (for checks of a GPU layer's

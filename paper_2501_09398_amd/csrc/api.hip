@@ -825,10 +825,14 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       break;
     }
     case KB_OPT_TDEPTH: {
-      if (h->kind != KB_HEAT2D && h->kind != KB_HEAT3D && h->kind != KB_HEAT2D_MULTI && value != 1)
-        return fail(KB_EINVAL, "temporal depth > 1 only for KB_HEAT2D, KB_HEAT3D and KB_HEAT2D_MULTI");
+      if (h->kind != KB_HEAT2D && h->kind != KB_HEAT3D && h->kind != KB_HEAT2D_MULTI && h->kind != KB_FDTD3D &&
+          value != 1)
+        return fail(KB_EINVAL, "temporal depth > 1 only for KB_HEAT2D, KB_HEAT3D, KB_HEAT2D_MULTI and KB_FDTD3D");
+      // FDTD: two steps per launch at most (variant 8; the other variants
+      // advance one step per launch whatever the depth)
       const int maxd = h->kind == KB_HEAT3D ? heat3d_tb_max_depth()
-                     : h->kind == KB_HEAT2D_MULTI ? kMtMaxDepth : heat2d_tile_max_depth();
+                     : h->kind == KB_HEAT2D_MULTI ? kMtMaxDepth
+                     : h->kind == KB_FDTD3D ? 2 : heat2d_tile_max_depth();
       if (value < 1 || value > maxd) return fail(KB_EINVAL, "temporal depth must be 1..%d", maxd);
       if (h->tdepth != value) clear_cache(h);
       h->tdepth = (int)value;

@@ -52,9 +52,14 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// GELU(x) = x Phi(x), Phi the standard normal distribution function, and
+// GELU'(x) = Phi(x) + x phi(x).  Phi is taken as erfc(-x / sqrt 2) / 2, which
+// keeps its relative accuracy for negative x, where 1 + erf(x / sqrt 2)
+// would cancel.
+__device__ __forceinline__ float norm_cdf(float x) { return 0.5f * erfcf(-x * 0.70710678118654752f); }
+__device__ __forceinline__ float gelu(float x) { return x * norm_cdf(x); }
 __device__ __forceinline__ float gelu_d(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+  return norm_cdf(x) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
 __device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v > n - 1 ? n - 1 : v); }
@@ -226,7 +231,11 @@ __global__ __launch_bounds__(256) void sg_loss_kernel(const SgLossArgs a) {
 // 32 channels of its input, times GELU'(z_{l-1}):
 //   gout[q][cin] = gelu'(z[q][cin]) * sum_(tap, cout) W[cout][cin][tap] *
 //                  sum_{p : clamp(p + tap) = q} bf16(g[p][cout])
-// The inner sum over source pixels has one term away from the edges.
+// The inner sum over source pixels has one term away from the edges and up
+// to four at an image corner.  Each source pixel enters the matrix cores as
+// its own bf16 operand (one MFMA per source slot), so every product is exact
+// and only float32 sums follow, as in the convolution's other products;
+// slots beyond the first run only where a lane of the wave lies on an edge.
 // ---------------------------------------------------------------------------
 // Pixels p along one axis with clamp(p + d) == q (at most two).
 __device__ __forceinline__ int adj_src(int q, int d, int n, int *out) {
@@ -269,21 +278,21 @@ __global__ __launch_bounds__(256) void sg_dgrad_kernel(const SgDgradArgs a) {
         int ys[3], xs[3];
         const int ny = adj_src(pg[g].y, dy, a.H, ys);
         const int nx = adj_src(pg[g].x, dx, a.W, xs);
-        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        for (int iy = 0; iy < ny; ++iy)
-          for (int ix = 0; ix < nx; ++ix) {
-            const float *gp = a.g + pix_at(pg[g], ys[iy], xs[ix], a.H, a.W) * 32 + kq * 8;
+        const int ns = ny * nx;
+        for (int k = 0; k < 4; ++k) {
+          if (k > 0 && !__any(k < ns)) break;          // wave-uniform
+          unsigned short v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+          if (k < ns) {
+            const float *gp = a.g + pix_at(pg[g], ys[k / nx], xs[k % nx], a.H, a.W) * 32 + kq * 8;
             const float4 v0 = *reinterpret_cast<const float4 *>(gp);
             const float4 v1 = *reinterpret_cast<const float4 *>(gp + 4);
-            s[0] += bf2f(f2bf(v0.x)); s[1] += bf2f(f2bf(v0.y)); s[2] += bf2f(f2bf(v0.z)); s[3] += bf2f(f2bf(v0.w));
-            s[4] += bf2f(f2bf(v1.x)); s[5] += bf2f(f2bf(v1.y)); s[6] += bf2f(f2bf(v1.z)); s[7] += bf2f(f2bf(v1.w));
+            v[0] = f2bf(v0.x); v[1] = f2bf(v0.y); v[2] = f2bf(v0.z); v[3] = f2bf(v0.w);
+            v[4] = f2bf(v1.x); v[5] = f2bf(v1.y); v[6] = f2bf(v1.z); v[7] = f2bf(v1.w);
           }
-        unsigned short v[8];
+          const bf16x8 B = make_frag(v);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = f2bf(s[i]);
-        const bf16x8 B = make_frag(v);
-#pragma unroll
-        for (int m = 0; m < 2; ++m) acc[m][g] = mfma(A[m], B, acc[m][g]);
+          for (int m = 0; m < 2; ++m) acc[m][g] = mfma(A[m], B, acc[m][g]);
+        }
       }
     }
   } else {
@@ -292,23 +301,37 @@ __global__ __launch_bounds__(256) void sg_dgrad_kernel(const SgDgradArgs a) {
     for (int m = 0; m < 2; ++m) A[m] = ld_frag(a.w + (size_t)(m * 16 + r) * 32 + kq * 8);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      unsigned short v[8];
+      // K runs over the taps (kq*8 + i < 9); slot k of tap i is its k-th
+      // source pixel
+      int nmax = 0;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int tap = kq * 8 + i;
-        float s = 0.f;
         if (tap < 9) {
           int ys[3], xs[3];
-          const int ny = adj_src(pg[g].y, tap / 3 - 1, a.H, ys);
-          const int nx = adj_src(pg[g].x, tap % 3 - 1, a.W, xs);
-          for (int iy = 0; iy < ny; ++iy)
-            for (int ix = 0; ix < nx; ++ix) s += bf2f(f2bf(a.g[pix_at(pg[g], ys[iy], xs[ix], a.H, a.W)]));
+          const int ns = adj_src(pg[g].y, tap / 3 - 1, a.H, ys) * adj_src(pg[g].x, tap % 3 - 1, a.W, xs);
+          nmax = ns > nmax ? ns : nmax;
         }
-        v[i] = f2bf(s);
       }
-      const bf16x8 B = make_frag(v);
+      for (int k = 0; k < 4; ++k) {
+        if (k > 0 && !__any(k < nmax)) break;          // wave-uniform
+        unsigned short v[8];
 #pragma unroll
-      for (int m = 0; m < 2; ++m) acc[m][g] = mfma(A[m], B, acc[m][g]);
+        for (int i = 0; i < 8; ++i) {
+          const int tap = kq * 8 + i;
+          float val = 0.f;
+          if (tap < 9) {
+            int ys[3], xs[3];
+            const int ny = adj_src(pg[g].y, tap / 3 - 1, a.H, ys);
+            const int nx = adj_src(pg[g].x, tap % 3 - 1, a.W, xs);
+            if (k < ny * nx) val = a.g[pix_at(pg[g], ys[k / nx], xs[k % nx], a.H, a.W)];
+          }
+          v[i] = f2bf(val);
+        }
+        const bf16x8 B = make_frag(v);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) acc[m][g] = mfma(A[m], B, acc[m][g]);
+      }
     }
   }
 

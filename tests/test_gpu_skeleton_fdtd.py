@@ -172,11 +172,15 @@ def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps):
 
 
 def test_fdtd_two_step_depth_limits(kb):
+    """Depth 1 or 2 for the cavity; depth 1 of variant 8 is the fused step."""
     with kb.Problem(kb.FDTD3D, (8, 64), kb.FDTD_COEFFS, 0) as p:
         p.set_option(kb.OPT_TILE, 8)
-        p.set_option(kb.OPT_TDEPTH, 3)
-        with pytest.raises(kb.KBError):
-            p.run(6, 0)
+        for bad in (0, 3):
+            with pytest.raises(kb.KBError):
+                p.set_option(kb.OPT_TDEPTH, bad)
+        p.set_option(kb.OPT_TDEPTH, 1)
+        p.run(6, 0)
+        assert p.read(kb.F_STEP)[0] == 6
 
 
 @pytest.mark.parametrize("b", [1, 7, 40])

@@ -294,3 +294,27 @@ def test_oracle_threads_do_not_change_bits():
         yb = oracle.sg_forward(w, T0, P)
         lb, gb = oracle.sg_loss_grad(w, T0, P, np.zeros((40, 70)))
     assert np.array_equal(a, b) and np.array_equal(ya, yb) and la == lb and np.array_equal(ga, gb)
+
+
+def test_gelu_relative_accuracy_in_the_negative_tail():
+    """GELU(x) = x Phi(x) and GELU'(x) = Phi(x) + x phi(x) with Phi the normal
+    distribution function: against scipy's ndtr (a library routine, not the
+    oracle's formula) over [-30, 8], where the form (1 + erf(x/sqrt 2))/2
+    loses every digit below x = -8, to 1e-14 (1 + x^2) relative (x^2: the
+    condition number of Phi in the tail).  Two table values as well:
+    Phi(-5) = 2.866515718791939e-7 and Phi(-10) = 7.619853024160527e-24."""
+    from scipy.special import ndtr
+    x = np.linspace(-30.0, 8.0, 3801)
+    g, dg = oracle.sg_gelu(x)
+    phi = np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+    ref_g = x * ndtr(x)
+    ref_dg = ndtr(x) + x * phi
+    nz = ref_g != 0
+    assert np.all(np.abs(g[nz] / ref_g[nz] - 1.0) < 1e-14 * (1.0 + x[nz] ** 2))
+    ok = np.abs(ref_dg) > 1e-300
+    # GELU' changes sign near x = -0.75: relative there to its two terms
+    scale = np.abs(ndtr(x)) + np.abs(x * phi)
+    assert np.all(np.abs(dg[ok] - ref_dg[ok]) <= 1e-14 * (1.0 + x[ok] ** 2) * scale[ok])
+    g5, _ = oracle.sg_gelu(np.array([-5.0, -10.0]))
+    assert abs(g5[0] / (-5.0 * 2.866515718791939e-7) - 1.0) < 1e-13
+    assert abs(g5[1] / (-10.0 * 7.619853024160527e-24) - 1.0) < 1e-13
