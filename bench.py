@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--skeleton-b", type=int, default=0, help="fix the skeleton's batch size")
     ap.add_argument("--no-sweep", action="store_true", help="skip the skeleton's b sweep (needs --skeleton-b)")
     ap.add_argument("--sweep-reps", type=int, default=10, help="repeats per b in the skeleton sweep")
+    ap.add_argument("--kernel-only-b", type=int, default=0,
+                    help="with --kernel-only: run the steps twice in graph batches of this b (the first run "
+                         "builds the graphs; traces then show warm replays)")
     ap.add_argument("--kernel-only", choices=sorted(KERNEL_RUNS),
                     help="run only one workload's kernels per launch for a few steps (counter runs)")
     ap.add_argument("--stream-calibration", action="store_true",
@@ -111,12 +114,18 @@ KERNEL_RUNS = {
     "multigrid_64_tb": ("HEAT2D_MULTI", None, "HEAT_COEFFS", 3, 60, 6),    # 10 launches of 6 steps
     "heat2d_16384_region": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 21, 40, 8),   # 5 launches of 8 steps
     "heat3d_8x4096_strip_tb": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 11, 20, 4),   # 5 launches of 4
+    # the launch-bound configurations, for traces of graph replays
+    "heat2d_256": ("HEAT2D", (256, 256), "HEAT_COEFFS", 1, 1000),
+    "heat3d_8x512": ("HEAT3D", (8, 512, 512), "HEAT_COEFFS", 0, 2000),
+    "fdtd_128": ("FDTD3D", (128, 64), "FDTD_COEFFS", 0, 1000),
 }
 
 
-def kernel_only(name):
+def kernel_only(name, b=0):
     """Run one workload's kernels per launch for a few steps and nothing else
-    (for hardware-counter runs, which serialise every dispatch)."""
+    (for hardware-counter runs, which serialise every dispatch); with b > 0
+    run the steps twice in graph batches of b (for kernel traces of warm
+    replays: the second run replays the graphs the first one built)."""
     import torch
     import paper_2501_09398_amd as kb
     prob, shape, co, var, steps = KERNEL_RUNS[name][:5]
@@ -137,10 +146,11 @@ def kernel_only(name):
             w = synth.surrogate_init(SEED)
             w[19104:19393] = synth.uniform_f32(SEED, 9, 289, -0.06, 0.06)
             p.write(kb.F_W, w.astype(np.float32))
-        p.run(steps, 0)
-        p.last_timing()
+        for _ in range(2 if b > 0 else 1):
+            p.run(steps, b)
+            p.last_timing()
     torch.cuda.synchronize()
-    print(json.dumps({"kernel_only": name, "steps": steps}), flush=True)
+    print(json.dumps({"kernel_only": name, "steps": steps, "b": b}), flush=True)
 
 
 # (reads, writes) of the kernels whose HBM fraction the benchmark reports:
@@ -1008,7 +1018,7 @@ def main():
         copy_calibration()
         return
     if args.kernel_only:
-        kernel_only(args.kernel_only)
+        kernel_only(args.kernel_only, args.kernel_only_b)
         return
 
     import numpy as np

@@ -655,12 +655,17 @@ __global__ __launch_bounds__(1024) void fdtd_tb2_kernel(const FdtdTbArgs a) {
   float h1x_p = 0.f, h1y_p = 0.f, h1z_p = 0.f;      // H^{n+1/2} of plane m-1
   float e1x_p = 0.f, e1y_p = 0.f, e1z_p = 0.f;      // E^{n+1} of plane m-1
   float h2x_p = 0.f, h2y_p = 0.f;                   // H^{n+3/2} of plane m-2
+  // loads one plane ahead: E^n of plane m+1, row j+1 of E^n and H of plane m
+  float exk = ld(a.Ex, m0 + 1, vld), eyk = ld(a.Ey, m0 + 1, vld), ezk = ld(a.Ez, m0 + 1, vld);
+  float ex_j = ldj(a.Ex, m0), ez_j = ldj(a.Ez, m0);
+  float hx = ld(a.Hx, m0, vld), hy = ld(a.Hy, m0, vld), hz = ld(a.Hz, m0, vld);
   for (int m = m0; m <= ke; ++m) {
     const bool pm = m <= N;                          // plane m exists
+    // the next iteration's operands, in flight during this one
+    const float nexk = ld(a.Ex, m + 2, vld), neyk = ld(a.Ey, m + 2, vld), nezk = ld(a.Ez, m + 2, vld);
+    const float nex_j = ldj(a.Ex, m + 1), nez_j = ldj(a.Ez, m + 1);
+    const float nhx = ld(a.Hx, m + 1, vld), nhy = ld(a.Hy, m + 1, vld), nhz = ld(a.Hz, m + 1, vld);
     // ---- A: H^{n+1/2} of plane m
-    const float exk = ld(a.Ex, m + 1, vld), eyk = ld(a.Ey, m + 1, vld), ezk = ld(a.Ez, m + 1, vld);
-    const float ex_j = ldj(a.Ex, m), ez_j = ldj(a.Ez, m);
-    const float hx = ld(a.Hx, m, vld), hy = ld(a.Hy, m, vld), hz = ld(a.Hz, m, vld);
     const float ey_e = lane_east_open(ey), ez_e = lane_east_open(ez);
     const bool mlt = m < N;
     const float h1x = (jlt && mlt) ? hx - dt * ((ez_j - ez) - (eyk - ey)) : hx;
@@ -690,10 +695,14 @@ __global__ __launch_bounds__(1024) void fdtd_tb2_kernel(const FdtdTbArgs a) {
     if (doC) {
       const float e1x_jq = sE1[q & 1][0][wp][lane], e1z_jq = sE1[q & 1][1][wp][lane];
       const float e1xn = pm ? e1x : 0.f, e1yn = pm ? e1y : 0.f;   // E^{n+1} of plane q+1
+      // the i+1 neighbours, taken on every lane before the selects below
+      // (inside a select arm only the lanes of that arm would run the lane
+      // shift, and the lane before one of the others would read 0)
+      const float e1z_e = lane_east_open(e1z_p), e1y_e = lane_east_open(e1y_p);
       const bool qlt = q < N;
       h2x = (jlt && qlt) ? h1x_p - dt * ((e1z_jq - e1z_p) - (e1yn - e1y_p)) : h1x_p;
-      h2y = (ilt && qlt) ? h1y_p - dt * ((e1xn - e1x_p) - (lane_east_open(e1z_p) - e1z_p)) : h1y_p;
-      h2z = (ilt && jlt) ? h1z_p - dt * ((lane_east_open(e1y_p) - e1y_p) - (e1x_jq - e1x_p)) : h1z_p;
+      h2y = (ilt && qlt) ? h1y_p - dt * ((e1xn - e1x_p) - (e1z_e - e1z_p)) : h1y_p;
+      h2z = (ilt && jlt) ? h1z_p - dt * ((e1y_e - e1y_p) - (e1x_jq - e1x_p)) : h1z_p;
     }
     sH2[0][w][lane] = h2x;
     sH2[1][w][lane] = h2z;
@@ -732,6 +741,14 @@ __global__ __launch_bounds__(1024) void fdtd_tb2_kernel(const FdtdTbArgs a) {
     ex = exk;
     ey = eyk;
     ez = ezk;
+    exk = nexk;
+    eyk = neyk;
+    ezk = nezk;
+    ex_j = nex_j;
+    ez_j = nez_j;
+    hx = nhx;
+    hy = nhy;
+    hz = nhz;
   }
 }
 
@@ -740,8 +757,10 @@ bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a0, bool nt) {
   const int M = a.N + 1;
   a.ni = (M + kTbTI - 1) / kTbTI;
   a.nj = (M + kTbTJ - 1) / kTbTJ;
-  // plane segments of about 32 planes, equal in length
-  a.nk = std::max(1, (M + 16) / 32);
+  // plane segments of equal length, as many as fill the chip in one round
+  // (two blocks of 16 waves per compute unit), at least 8 planes each
+  const int slots = 2 * kCUs;
+  a.nk = std::max(1, std::min((slots + a.ni * a.nj / 2) / (a.ni * a.nj), M / 8));
   a.tk = (M + a.nk - 1) / a.nk;
   a.nk = (M + a.tk - 1) / a.tk;
   const int nb = a.ni * a.nj * a.nk;

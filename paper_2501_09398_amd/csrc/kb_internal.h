@@ -68,6 +68,7 @@ struct Launch {
 // multiple of 8; logical ids past the end return.
 // ---------------------------------------------------------------------------
 constexpr int kXcds = 8;
+constexpr int kCUs = 256;                 // compute units of the MI355X (32 per XCD)
 
 __device__ __forceinline__ int xcd_logical_block(int nblocks) {
   const int hw = blockIdx.x;

@@ -53,10 +53,56 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 // GELU(x) = x Phi(x), Phi the standard normal distribution function, and
-// GELU'(x) = Phi(x) + x phi(x).  Phi is taken as erfc(-x / sqrt 2) / 2, which
-// keeps its relative accuracy for negative x, where 1 + erf(x / sqrt 2)
-// would cancel.
-__device__ __forceinline__ float norm_cdf(float x) { return 0.5f * erfcf(-x * 0.70710678118654752f); }
+// GELU'(x) = Phi(x) + x phi(x).  Phi(x) = erfc(-x / sqrt 2) / 2 is evaluated
+// so that it keeps its relative accuracy for negative x, where
+// (1 + erf(x / sqrt 2)) / 2 would cancel:
+//   |x| <= 1: Phi = 1/2 + x S(x^2), S a degree-5 polynomial;
+//   |x| >  1: erfc(v) = exp(-v^2) R(v), v = |x| / sqrt 2, R the scaled
+//             complementary error function as a (4, 5) rational function
+//             fitted on [0, 10]; exp(-x^2 / 2) = 2^(-x^2 log2(e) / 2) with
+//             x^2 and the product carried to about twice float32 precision
+//             (an error in the exponent would be amplified by x^2).
+// Phi = erfc/2 for x < 0 and 1 - erfc/2 for x > 0.  Coefficients: minimax
+// fits in relative error (gelu_coeffs.py).  Error, in float32 arithmetic:
+// at most about 8 units of 2^-24 relative (mean 1) over [-13, 8]; below
+// x = -13 the exponential leaves the normal float range and GELU returns -0.
+// The polynomial piece runs for the lanes with |x| <= 1, the rest only where
+// a lane of the wave needs it.
+constexpr float kPhiS[6] = {3.989422917e-01f, -6.649035960e-02f, 9.973322973e-03f, -1.186329755e-03f, 1.134861304e-04f, -7.654097317e-06f};
+constexpr float kErfcxP[5] = {1.000000000e+00f, 1.237535715e+00f, 7.306861281e-01f, 2.287804782e-01f, 3.270421550e-02f};
+constexpr float kErfcxQ[6] = {1.000000000e+00f, 2.365915537e+00f, 2.400326729e+00f, 1.323654652e+00f, 4.055296779e-01f, 5.796599761e-02f};
+
+__device__ __forceinline__ float norm_cdf_tail(float x) {
+  constexpr float kC = 0.7213475108146667f;                  // log2(e) / 2, rounded to float
+  constexpr float kCl = 9.62981494545545e-09f;               // log2(e) / 2 - kC
+  constexpr float kLn2 = 0.6931471805599453f;
+  const float sq = x * x, se = fmaf(x, x, -sq);               // x^2 = sq + se exactly
+  const float yh = sq * kC;
+  const float yl = fmaf(se, kC, fmaf(sq, kCl, fmaf(sq, kC, -yh)));
+  const float e2 = __builtin_amdgcn_exp2f(-yh);
+  const float ex = fmaf(e2, -yl * kLn2, e2);                  // exp(-x^2 / 2)
+  const float v = fabsf(x) * 0.70710678118654752f;
+  float p = kErfcxP[4], q = kErfcxQ[5];
+#pragma unroll
+  for (int i = 3; i >= 0; --i) p = fmaf(p, v, kErfcxP[i]);
+#pragma unroll
+  for (int i = 4; i >= 0; --i) q = fmaf(q, v, kErfcxQ[i]);
+  const float rq = __builtin_amdgcn_rcpf(q);
+  float R = p * rq;
+  R = fmaf(fmaf(-q, R, p), rq, R);                            // one correction of the quotient
+  const float E = ex * R;                                     // erfc(v)
+  return x < 0.f ? 0.5f * E : fmaf(-0.5f, E, 1.0f);
+}
+__device__ __forceinline__ float norm_cdf(float x) {
+  if (fabsf(x) <= 1.0f) {
+    const float w = x * x;
+    float s = kPhiS[5];
+#pragma unroll
+    for (int i = 4; i >= 0; --i) s = fmaf(s, w, kPhiS[i]);
+    return fmaf(x, s, 0.5f);
+  }
+  return norm_cdf_tail(x);
+}
 __device__ __forceinline__ float gelu(float x) { return x * norm_cdf(x); }
 __device__ __forceinline__ float gelu_d(float x) {
   return norm_cdf(x) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
