@@ -115,8 +115,8 @@ KERNEL_RUNS = {
     "heat2d_16384_region": ("HEAT2D", (16384, 16384), "HEAT_COEFFS", 21, 40, 8),   # 5 launches of 8 steps
     "heat3d_8x4096_strip_tb": ("HEAT3D", (8, 4096, 4096), "HEAT_COEFFS", 11, 20, 4),   # 5 launches of 4
     # the launch-bound configurations, for traces of graph replays
-    "heat2d_256": ("HEAT2D", (256, 256), "HEAT_COEFFS", 1, 1000),
-    "heat3d_8x512": ("HEAT3D", (8, 512, 512), "HEAT_COEFFS", 0, 2000),
+    "heat2d_256": ("HEAT2D", (256, 256), "HEAT_COEFFS", 16, 1000, 8),        # register strips, 8 steps
+    "heat3d_8x512": ("HEAT3D", (8, 512, 512), "HEAT_COEFFS", 11, 2000, 5),   # register strips, 5 steps
     "fdtd_128": ("FDTD3D", (128, 64), "FDTD_COEFFS", 0, 1000),
 }
 
