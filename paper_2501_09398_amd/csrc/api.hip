@@ -216,7 +216,7 @@ int iter_depth(const kb_problem *h) {
   if (h->kind == KB_HEAT2D_SURROGATE) return sg_iter_depth(h);
   if (h->kind == KB_HEAT3D && (heat3d_variant(h) == 5 || heat3d_variant(h) == 11)) return h->tdepth;
   if (h->kind == KB_HEAT2D_MULTI && multi_is_tb(h)) return h->tdepth;
-  if (h->kind == KB_FDTD3D && fdtd_variant(h) == 8) return h->tdepth;
+  if (h->kind == KB_FDTD3D && fdtd_variant(h) >= 8) return h->tdepth;
   return (h->kind == KB_HEAT2D && heat2d_is_tile(heat2d_variant(h))) ? h->tdepth : 1;
 }
 
@@ -319,22 +319,29 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
         // once the sets outgrow the last-level cache), its single steps the
         // fused step
         const bool nt8 = 12.0 * (h->N + 1) * (h->N + 1) * h->pitch * 4 > 256.0 * (1 << 20);
-        if (v == 8 && depth == 2) {
+        if (v >= 8 && depth == 2) {
           FdtdTbArgs t{};
           t.Ex = A[0]; t.Ey = A[1]; t.Ez = A[2]; t.Hx = A[3]; t.Hy = A[4]; t.Hz = A[5];
           t.oEx = B[0]; t.oEy = B[1]; t.oEz = B[2]; t.oHx = B[3]; t.oHy = B[4]; t.oHz = B[5];
           t.N = h->N; t.P = h->pitch; t.dt = h->dt;
           t.si = h->src_ijk[0]; t.sj = h->src_ijk[1]; t.sk = h->src_ijk[2];
           t.g = h->g; t.glen = h->glen; t.probe = h->probe; t.pcap = h->pcap; t.step = h->step;
+          // variants 9, 10: whole rows up to N = 256 (above that, as 8)
+          if (v >= 9 && h->N <= 256) {
+            if (!make_fdtd_tb2_rows(L[0], t, nt8, v - 9)) return -1;
+            if (h->N == 256) make_fdtd_column(L[1], t);
+            else make_fdtd_step_add(L[1], h->step, 2);
+            return 2;
+          }
           if (!make_fdtd_tb2(L[0], t, nt8)) return -1;
           make_fdtd_step_add(L[1], h->step, 2);
           return 2;
         }
-        if (v == 8 && depth != 1) return -1;
+        if (v >= 8 && depth != 1) return -1;
         FdtdFusedArgs f{A[0], A[1], A[2], A[3], A[4], A[5], B[0], B[1], B[2], B[3], B[4], B[5],
                         h->N, h->pitch, h->dt};
         // variant 5: one plane per thread; 6: 8 planes; 7: one plane, streaming stores
-        if (!make_fdtd_fused(L[0], f, v == 6 ? 8 : 1, v == 7 || (v == 8 && nt8))) return -1;
+        if (!make_fdtd_fused(L[0], f, v == 6 ? 8 : 1, v == 7 || (v >= 8 && nt8))) return -1;
         SrcArgs s{B[2], h->src, h->g, h->glen, h->probe, h->pcap, h->step};
         make_fdtd_src(L[1], s);
         return 2;
@@ -813,7 +820,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
         ok = value == 0 || value == 1 || (((value >= 2 && value <= 4) || (value >= 6 && value <= 10)) && h->nx % 4 == 0) ||
              ((value == 5 || value == 11) && h->nz <= 8);
       else if (h->kind == KB_SKELETON) ok = value >= 0 && value <= 3;
-      else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 8;
+      else if (h->kind == KB_FDTD3D) ok = value >= 0 && value <= 10;
       else if (h->kind == KB_HEAT2D_SURROGATE) ok = value >= 0 && value <= 2;
       else if (h->kind == KB_HEAT2D_MULTI) ok = value >= 0 && value <= 6;
       else ok = value == 0;

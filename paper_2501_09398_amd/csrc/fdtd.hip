@@ -770,6 +770,310 @@ bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a0, bool nt) {
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Two steps per launch over whole rows (variant 9 with depth 2, N <= 256).
+//
+// The scheme of the kernel above (blocks march along k; phases A-D per
+// plane, two barriers; rows j-1 / j+1 of the intermediate fields through
+// LDS; two rows below and one above the 13 output rows recomputed) with a
+// wave holding a whole row: lane l keeps nodes 4l .. 4l+3, read and written
+// as 16-byte vectors, so no node along i is computed twice and a wave issues
+// a quarter of the memory instructions.  A node's i+1 neighbour is the next
+// element of the lane, or element 0 of the next lane (lane shift); its i-1
+// neighbour likewise.  Elements past N (row padding) take no update and
+// keep their values.
+//
+// At N = 256 a row has 257 nodes and lane 63 ends at i = 255.  The node at
+// i = N takes part only through its E values, the i+1 neighbours of node
+// N-1: no E component at i = N is ever updated (Ex there is row padding, Ey
+// and Ez are tangential to the wall), so E^{n+1} = E^n there and lane 63
+// reads them from the input set.  The column's own outputs (E, Hy and Hz
+// copied, Hx updated twice) are written by fdtd_column_kernel, which runs
+// after this kernel in the same iteration.
+// ---------------------------------------------------------------------------
+
+struct Q4 {
+  float v[4];
+};
+__device__ __forceinline__ Q4 q4ld(const float *p) {
+  const float4 a = *reinterpret_cast<const float4 *>(p);
+  return Q4{{a.x, a.y, a.z, a.w}};
+}
+__device__ __forceinline__ float4 f4of(const Q4 &a) { return make_float4(a.v[0], a.v[1], a.v[2], a.v[3]); }
+__device__ __forceinline__ Q4 q4of(const float4 &a) { return Q4{{a.x, a.y, a.z, a.w}}; }
+// i+1 and i-1 neighbours of the lane's four nodes (whole-wave lane shifts:
+// call from code every lane of the wave runs)
+__device__ __forceinline__ Q4 q4east(const Q4 &a, bool last, float ext) {
+  float t = lane_east_open(a.v[0]);
+  if (last) t = ext;
+  return Q4{{a.v[1], a.v[2], a.v[3], t}};
+}
+__device__ __forceinline__ Q4 q4west(const Q4 &a) {
+  return Q4{{lane_west_open(a.v[3]), a.v[0], a.v[1], a.v[2]}};
+}
+template <bool NT>
+__device__ __forceinline__ void st4q(float *p, const Q4 &a) {
+  st4o<NT>(p, a.v[0], a.v[1], a.v[2], a.v[3]);
+}
+
+// NW waves (rows) per block, NW - 3 output rows; PF: operands loaded one
+// plane ahead (the register room for it needs NW <= 12)
+template <bool NT, int NW, bool PF>
+__global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs a) {
+  constexpr int kTrNW = NW, kTrTJ = NW - 3;
+  __shared__ float4 sH1[2][kTrNW][64];      // H^{n+1/2} x, z of the current plane
+  __shared__ float4 sE1[2][2][kTrNW][64];   // [plane parity][x, z] E^{n+1}
+  __shared__ float4 sH2[2][kTrNW][64];      // H^{n+3/2} x, z
+  const int nb = a.nj * a.nk;
+  const int lb = xcd_logical_block(nb);
+  if (lb >= nb) return;                     // the whole block: before any barrier
+  const int tj = lb % a.nj, tkk = lb / a.nj;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int N = a.N, M = N + 1;
+  const int i0 = 4 * lane;
+  const int j = tj * kTrTJ - 2 + w;
+  const int kb = tkk * a.tk, ke = min(kb + a.tk, M);   // output planes [kb, ke)
+  const bool jv = j >= 0 && j <= N;
+  const bool vld = jv && i0 <= N;                      // the lane holds a node of the row
+  const bool jup = vld && j + 1 <= N;
+  const bool out = vld && w >= 2 && w < 2 + kTrTJ;
+  const bool jj = j >= 1 && j <= N - 1, jlt = j < N;
+  const bool last = lane == 63;
+  const bool xn = last && jv && N == 4 * 64;            // lane 63 reads E at i = N
+  // per-node conditions, evaluated where used (kept as lane masks they
+  // would tie up scalar registers the kernel needs)
+  auto iN = [&](int e) { return i0 + e <= N; };
+  auto ilt = [&](int e) { return i0 + e < N; };
+  auto ii = [&](int e) { return i0 + e >= 1 && i0 + e <= N - 1; };
+  const bool srow = j == a.sj && a.si >= i0 && a.si < i0 + 4;   // the source node is in this lane
+  const int wm = w > 0 ? w - 1 : 0, wp = w < kTrNW - 1 ? w + 1 : kTrNW - 1;
+  const size_t sk = (size_t)M * a.P;
+  const size_t cij = vld ? (size_t)j * a.P + i0 : 0;
+  const size_t cN = xn ? (size_t)j * a.P + N : 0;
+  const float dt = a.dt;
+  const long long n = *a.step;
+  const bool add0 = n >= 0 && n < a.glen, add1 = n + 1 >= 0 && n + 1 < a.glen;
+  const float g0 = add0 ? a.g[n] : 0.f, g1 = add1 ? a.g[n + 1] : 0.f;
+  const Q4 z4{{0.f, 0.f, 0.f, 0.f}};
+
+  auto ld = [&](const float *f, int k) -> Q4 { return vld && k >= 0 && k <= N ? q4ld(f + k * sk + cij) : z4; };
+  auto ldj = [&](const float *f, int k) -> Q4 {           // row j+1
+    return jup && k >= 0 && k <= N ? q4ld(f + k * sk + cij + a.P) : z4;
+  };
+  auto ldN = [&](const float *f, int k) -> float { return xn && k >= 0 && k <= N ? f[k * sk + cN] : 0.f; };
+
+  const int m0 = max(kb - 2, 0);
+  Q4 ex = ld(a.Ex, m0), ey = ld(a.Ey, m0), ez = ld(a.Ez, m0);   // E^n of plane m
+  float eyN = ldN(a.Ey, m0), ezN = ldN(a.Ez, m0);               // E at i = N, plane m
+  float eyN_p = 0.f, ezN_p = 0.f;                               // ... plane m-1
+  Q4 h1x_p = z4, h1y_p = z4, h1z_p = z4;       // H^{n+1/2} of plane m-1
+  Q4 e1x_p = z4, e1y_p = z4, e1z_p = z4;       // E^{n+1} of plane m-1
+  Q4 h2x_p = z4, h2y_p = z4;                   // H^{n+3/2} of plane m-2
+  // with PF: E^n of plane m+1, row j+1 of E^n and H of plane m are loaded
+  // one iteration ahead
+  Q4 pexk = z4, peyk = z4, pezk = z4, pex_j = z4, pez_j = z4, phx = z4, phy = z4, phz = z4;
+  float peyNk = 0.f, pezNk = 0.f;
+  if constexpr (PF) {
+    pexk = ld(a.Ex, m0 + 1); peyk = ld(a.Ey, m0 + 1); pezk = ld(a.Ez, m0 + 1);
+    pex_j = ldj(a.Ex, m0); pez_j = ldj(a.Ez, m0);
+    phx = ld(a.Hx, m0); phy = ld(a.Hy, m0); phz = ld(a.Hz, m0);
+    peyNk = ldN(a.Ey, m0 + 1); pezNk = ldN(a.Ez, m0 + 1);
+  }
+  for (int m = m0; m <= ke; ++m) {
+    const bool pm = m <= N;                          // plane m exists
+    Q4 exk, eyk, ezk, ex_j, ez_j, hx, hy, hz;
+    float eyNk, ezNk;
+    if constexpr (PF) {
+      exk = pexk; eyk = peyk; ezk = pezk; ex_j = pex_j; ez_j = pez_j; hx = phx; hy = phy; hz = phz;
+      eyNk = peyNk; ezNk = pezNk;
+      pexk = ld(a.Ex, m + 2); peyk = ld(a.Ey, m + 2); pezk = ld(a.Ez, m + 2);
+      pex_j = ldj(a.Ex, m + 1); pez_j = ldj(a.Ez, m + 1);
+      phx = ld(a.Hx, m + 1); phy = ld(a.Hy, m + 1); phz = ld(a.Hz, m + 1);
+      peyNk = ldN(a.Ey, m + 2); pezNk = ldN(a.Ez, m + 2);
+    } else {
+      exk = ld(a.Ex, m + 1); eyk = ld(a.Ey, m + 1); ezk = ld(a.Ez, m + 1);
+      ex_j = ldj(a.Ex, m); ez_j = ldj(a.Ez, m);
+      hx = ld(a.Hx, m); hy = ld(a.Hy, m); hz = ld(a.Hz, m);
+      eyNk = ldN(a.Ey, m + 1); ezNk = ldN(a.Ez, m + 1);
+    }
+    // ---- A: H^{n+1/2} of plane m
+    const bool mlt = m < N;
+    const Q4 ey_e = q4east(ey, last, eyN), ez_e = q4east(ez, last, ezN);
+    Q4 h1x, h1y, h1z;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      h1x.v[e] = (iN(e) && jlt && mlt) ? hx.v[e] - dt * ((ez_j.v[e] - ez.v[e]) - (eyk.v[e] - ey.v[e])) : hx.v[e];
+      h1y.v[e] = (ilt(e) && mlt) ? hy.v[e] - dt * ((exk.v[e] - ex.v[e]) - (ez_e.v[e] - ez.v[e])) : hy.v[e];
+      h1z.v[e] = (ilt(e) && jlt) ? hz.v[e] - dt * ((ey_e.v[e] - ey.v[e]) - (ex_j.v[e] - ex.v[e])) : hz.v[e];
+    }
+    sH1[0][w][lane] = f4of(h1x);
+    sH1[1][w][lane] = f4of(h1z);
+    __syncthreads();
+    // ---- B: E^{n+1} of plane m
+    const Q4 h1x_jm = q4of(sH1[0][wm][lane]), h1z_jm = q4of(sH1[1][wm][lane]);
+    const Q4 h1z_w = q4west(h1z), h1y_w = q4west(h1y);
+    const bool kk = m >= 1 && m <= N - 1;
+    Q4 e1x, e1y, e1z;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      e1x.v[e] = (ilt(e) && jj && kk) ? ex.v[e] + dt * ((h1z.v[e] - h1z_jm.v[e]) - (h1y.v[e] - h1y_p.v[e])) : ex.v[e];
+      e1y.v[e] = (jlt && ii(e) && kk) ? ey.v[e] + dt * ((h1x.v[e] - h1x_p.v[e]) - (h1z.v[e] - h1z_w.v[e])) : ey.v[e];
+      e1z.v[e] = (mlt && ii(e) && jj) ? ez.v[e] + dt * ((h1y.v[e] - h1y_w.v[e]) - (h1x.v[e] - h1x_jm.v[e])) : ez.v[e];
+    }
+    if (m == a.sk) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (srow && i0 + e == a.si) {
+          if (add0) e1z.v[e] = e1z.v[e] + g0;
+          if (out && m >= kb && m < ke && n >= 0 && n < a.pcap) a.probe[n] = e1z.v[e];
+        }
+    }
+    sE1[m & 1][0][w][lane] = pm ? f4of(e1x) : make_float4(0.f, 0.f, 0.f, 0.f);
+    sE1[m & 1][1][w][lane] = pm ? f4of(e1z) : make_float4(0.f, 0.f, 0.f, 0.f);
+    // ---- C: H^{n+3/2} of plane q = m-1 (E^{n+1} of row j+1, plane q, from
+    // the previous iteration's buffer)
+    const int q = m - 1;
+    const bool doC = q >= 0 && q >= kb - 1 && q <= ke - 1;
+    Q4 h2x = z4, h2y = z4, h2z = z4;
+    if (doC) {
+      const Q4 e1x_jq = q4of(sE1[q & 1][0][wp][lane]), e1z_jq = q4of(sE1[q & 1][1][wp][lane]);
+      const Q4 e1xn = pm ? e1x : z4, e1yn = pm ? e1y : z4;   // E^{n+1} of plane q+1
+      // i+1 neighbours (at i = N: E^{n+1} = E^n of plane q)
+      const Q4 e1z_e = q4east(e1z_p, last, ezN_p), e1y_e = q4east(e1y_p, last, eyN_p);
+      const bool qlt = q < N;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        h2x.v[e] = (iN(e) && jlt && qlt)
+                       ? h1x_p.v[e] - dt * ((e1z_jq.v[e] - e1z_p.v[e]) - (e1yn.v[e] - e1y_p.v[e])) : h1x_p.v[e];
+        h2y.v[e] = (ilt(e) && qlt)
+                       ? h1y_p.v[e] - dt * ((e1xn.v[e] - e1x_p.v[e]) - (e1z_e.v[e] - e1z_p.v[e])) : h1y_p.v[e];
+        h2z.v[e] = (ilt(e) && jlt)
+                       ? h1z_p.v[e] - dt * ((e1y_e.v[e] - e1y_p.v[e]) - (e1x_jq.v[e] - e1x_p.v[e])) : h1z_p.v[e];
+      }
+    }
+    sH2[0][w][lane] = f4of(h2x);
+    sH2[1][w][lane] = f4of(h2z);
+    __syncthreads();
+    // ---- D: E^{n+2} of plane q, and the outputs of plane q
+    if (q >= kb && q <= ke - 1) {
+      const Q4 h2x_jm = q4of(sH2[0][wm][lane]), h2z_jm = q4of(sH2[1][wm][lane]);
+      const Q4 h2z_w = q4west(h2z), h2y_w = q4west(h2y);
+      const bool kq = q >= 1 && q <= N - 1;
+      Q4 e2x, e2y, e2z;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        e2x.v[e] = (ilt(e) && jj && kq) ? e1x_p.v[e] + dt * ((h2z.v[e] - h2z_jm.v[e]) - (h2y.v[e] - h2y_p.v[e]))
+                                        : e1x_p.v[e];
+        e2y.v[e] = (jlt && ii(e) && kq) ? e1y_p.v[e] + dt * ((h2x.v[e] - h2x_p.v[e]) - (h2z.v[e] - h2z_w.v[e]))
+                                        : e1y_p.v[e];
+        e2z.v[e] = (q < N && ii(e) && jj) ? e1z_p.v[e] + dt * ((h2y.v[e] - h2y_w.v[e]) - (h2x.v[e] - h2x_jm.v[e]))
+                                          : e1z_p.v[e];
+      }
+      if (q == a.sk) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (srow && i0 + e == a.si) {
+            if (add1) e2z.v[e] = e2z.v[e] + g1;
+            if (out && n + 1 >= 0 && n + 1 < a.pcap) a.probe[n + 1] = e2z.v[e];
+          }
+      }
+      if (out) {
+        const size_t c = (size_t)q * sk + cij;
+        st4q<NT>(a.oEx + c, e2x);
+        st4q<NT>(a.oEy + c, e2y);
+        st4q<NT>(a.oEz + c, e2z);
+        st4q<NT>(a.oHx + c, h2x);
+        st4q<NT>(a.oHy + c, h2y);
+        st4q<NT>(a.oHz + c, h2z);
+      }
+    }
+    // ---- rotate: plane m becomes the previous plane
+    h2x_p = h2x;
+    h2y_p = h2y;
+    h1x_p = h1x;
+    h1y_p = h1y;
+    h1z_p = h1z;
+    e1x_p = e1x;
+    e1y_p = e1y;
+    e1z_p = e1z;
+    ex = exk;
+    ey = eyk;
+    ez = ezk;
+    eyN_p = eyN;
+    ezN_p = ezN;
+    eyN = eyNk;
+    ezN = ezNk;
+  }
+}
+
+bool make_fdtd_tb2_rows(Launch &L, const FdtdTbArgs &a0, bool nt, int form) {
+  FdtdTbArgs a = a0;
+  const int M = a.N + 1;
+  if (a.N > 4 * 64 || a.P % 4 != 0) return false;
+  // form 0: 16 waves per block, operands loaded in the iteration that uses
+  // them; form 1: 12 waves, loaded one plane ahead
+  const int nw = form == 0 ? 16 : 12;
+  a.ni = 1;
+  a.nj = (M + nw - 4) / (nw - 3);
+  // plane segments of equal length, as many as fill the chip with one
+  // block (up to 128 KiB of LDS) per compute unit, at least 8 planes each
+  a.nk = std::max(1, std::min(kCUs / a.nj, M / 8));
+  a.tk = (M + a.nk - 1) / a.nk;
+  a.nk = (M + a.tk - 1) / a.tk;
+  const int nb = a.nj * a.nk;
+  const dim3 grid((unsigned)xcd_padded_grid(nb));
+  const void *f = form == 0 ? (nt ? (const void *)fdtd_tb2_rows_kernel<true, 16, false>
+                                  : (const void *)fdtd_tb2_rows_kernel<false, 16, false>)
+                            : (nt ? (const void *)fdtd_tb2_rows_kernel<true, 12, true>
+                                  : (const void *)fdtd_tb2_rows_kernel<false, 12, true>);
+  L.set(f, grid, dim3(64 * nw), 0, a);
+  return true;
+}
+
+// The column i = N = 256 of the whole-row kernel's launch (see above),
+// launched after it in the same iteration: E, Hy and Hz copied to the
+// output set, Hx updated twice with the column's unchanging E (the same
+// expression as every other Hx update); thread 0 also advances the device
+// step counter by the launch's two steps (this kernel does not read it).
+// One thread per (j, k) node of the column.
+struct ColumnArgs {
+  const float *Ex, *Ey, *Ez, *Hx, *Hy, *Hz;
+  float *oEx, *oEy, *oEz, *oHx, *oHy, *oHz;
+  int N, P;
+  float dt;
+  long long *step;
+};
+
+__global__ __launch_bounds__(256) void fdtd_column_kernel(const ColumnArgs a) {
+  const int N = a.N, M = N + 1;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t == 0) *a.step += 2;
+  if (t >= (long long)M * M) return;
+  const int k = (int)(t / M), j = (int)(t - (long long)k * M);
+  const size_t sk = (size_t)M * a.P;
+  const size_t c = (size_t)k * sk + (size_t)j * a.P + N;
+  const float ey = a.Ey[c], ez = a.Ez[c], hx = a.Hx[c];
+  a.oEx[c] = a.Ex[c];
+  a.oEy[c] = ey;
+  a.oEz[c] = ez;
+  a.oHy[c] = a.Hy[c];
+  a.oHz[c] = a.Hz[c];
+  float h = hx;
+  if (j < N && k < N) {
+    const float d = (a.Ez[c + a.P] - ez) - (a.Ey[c + sk] - ey);
+    h = h - a.dt * d;                // H^{n+1/2}
+    h = h - a.dt * d;                // H^{n+3/2}: the column's E has not changed
+  }
+  a.oHx[c] = h;
+}
+
+void make_fdtd_column(Launch &L, const FdtdTbArgs &t) {
+  ColumnArgs c{t.Ex, t.Ey, t.Ez, t.Hx, t.Hy, t.Hz, t.oEx, t.oEy, t.oEz, t.oHx, t.oHy, t.oHz, t.N, t.P, t.dt,
+               const_cast<long long *>(t.step)};
+  const long long n = (long long)(t.N + 1) * (t.N + 1);
+  L.set((const void *)fdtd_column_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c);
+}
+
 struct StepAddArgs {
   long long *step;
   int d;

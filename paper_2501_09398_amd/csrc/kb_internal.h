@@ -218,6 +218,11 @@ struct FdtdTbArgs {
   const long long *step;
 };
 bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a, bool nt);   // fills tk..nk itself
+// Whole-row form (N <= 256, false otherwise); at N = 256 its iteration's
+// second kernel is make_fdtd_column (the i = N column and the step counter),
+// else make_fdtd_step_add.
+bool make_fdtd_tb2_rows(Launch &L, const FdtdTbArgs &a, bool nt, int form);   // form 0: 16 waves; 1: 12 waves, operands one plane ahead
+void make_fdtd_column(Launch &L, const FdtdTbArgs &a);
 void make_fdtd_step_add(Launch &L, long long *step, int d);
 
 struct SrcArgs {

@@ -149,16 +149,20 @@ def fdtd256():
 
 
 @gpu
-def test_fdtd_256_two_step_vs_oracle(kb, fdtd256):
-    """The two-step kernel (variant 8, depth 2, streaming stores at this
-    size) at 256^3: 100 steps in graph batches of 50 two-step iterations,
-    bit for bit with the float32 oracle on every node, and the probe."""
+@pytest.mark.parametrize("variant", [10, 9, 8])
+def test_fdtd_256_two_step_vs_oracle(kb, fdtd256, variant):
+    """The two-step kernels (depth 2, streaming stores at this size) at
+    256^3 -- whole rows of four nodes per lane with the i = N column on its
+    own (9: 16 rows per block; 10: 12 rows, operands loaded a plane ahead),
+    60-node tiles (8) -- 100 steps in graph batches of 50 two-step
+    iterations, bit for bit with the float32 oracle on every node, and the
+    probe."""
     d = fdtd256
     N, steps = d["N"], d["steps"]
     for start in ("zero", "rand"):
-        announce(f"fdtd 256^3 {start} fields, 100 steps, two-step kernel, b=50")
+        announce(f"fdtd 256^3 {start} fields, 100 steps, two-step kernel {variant}, b=50")
         with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, d["seed"]) as p:
-            p.set_option(kb.OPT_TILE, 8)
+            p.set_option(kb.OPT_TILE, variant)
             p.set_option(kb.OPT_TDEPTH, 2)
             if start == "rand":
                 for k, fid in kb.FDTD_FIELDS.items():

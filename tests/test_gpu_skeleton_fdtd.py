@@ -137,15 +137,20 @@ def test_fdtd_bitwise_vs_oracle(kb, N, steps, variant):
     assert np.all(probe[steps:] == 0)
 
 
-@pytest.mark.parametrize("N,steps", [(4, 61), (5, 60), (8, 150), (17, 121), (33, 40), (70, 23), (75, 100)])
-def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps):
-    """Variant 8 with depth 2 (two steps per launch, temporal blocking):
-    from zero fields with the source on and from random fields on every
-    node, per launch and in graph batches (an odd step count ends with one
-    fused step), bit for bit with the float32 oracle, probe included.
-    N = 70 and 75 span several tiles along i (60 nodes), j (13 rows) and k
-    (plane segments)."""
-    announce(f"fdtd two-step N={N} steps={steps}")
+@pytest.mark.parametrize("variant", [8, 9, 10])
+@pytest.mark.parametrize("N,steps", [(4, 61), (5, 60), (8, 150), (17, 121), (33, 40), (70, 23), (75, 100),
+                                     (129, 12), (253, 6), (255, 7)])
+def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps, variant):
+    """Variants 8, 9 and 10 with depth 2 (two steps per launch, temporal
+    blocking): from zero fields with the source on and from random fields
+    on every node, per launch and in graph batches (an odd step count ends
+    with one fused step), bit for bit with the float32 oracle, probe
+    included.  Variant 8: N = 70 and 75 span several tiles along i (60
+    nodes), j (13 rows) and k (plane segments).  Variants 9, 10 (whole rows, four
+    nodes per lane): N = 253 and 255 end the row inside and at the end of
+    lane 63 (row padding in the last vector, none), N = 129 at element 1 of
+    lane 32."""
+    announce(f"fdtd two-step variant {variant} N={N} steps={steps}")
     seed = 36
     src = synth.fdtd_source_cell(seed, N)
     _, g32 = oracle.fdtd_pulse(steps + 1)
@@ -157,7 +162,7 @@ def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps):
         ref, probe_ref = oracle.fdtd(init, N, steps, src=src, g=g32, dtype=np.float32)
         for b in (0, 3):
             with kb.Problem(kb.FDTD3D, (N, 512), kb.FDTD_COEFFS, seed) as p:
-                p.set_option(kb.OPT_TILE, 8)
+                p.set_option(kb.OPT_TILE, variant)
                 p.set_option(kb.OPT_TDEPTH, 2)
                 if start == "rand":
                     for k, fid in kb.FDTD_FIELDS.items():
