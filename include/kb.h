@@ -378,19 +378,27 @@ int kb_set_option(kb_problem *h, int option, int64_t value);
  *          ran per launch instead.                                        */
 int kb_run(kb_problem *h, int64_t n_steps, int64_t batch_b);
 
-/* Copy one field out.  Synchronises the stream first.  dst is host memory
- * (dst_on_device = 0) or device memory (1); bytes must equal the field's
- * size.  Errors: KB_EINVAL (field or size), KB_EHIP.                      */
+/* Copy one field out: the state an iterative application has after its
+ * loop of kernel iterations (Sec. III-A, the iteration loop of Listings
+ * 1-2; the applications' outputs of Sec. III-C).  Synchronises the stream
+ * first.  dst is host memory (dst_on_device = 0) or device memory (1);
+ * bytes must equal the field's size.  Errors: KB_EINVAL (field or size),
+ * KB_EHIP.                                                                 */
 int kb_read(kb_problem *h, int field, void *dst, size_t bytes,
             int dst_on_device);
 
-/* Overwrite one field (for resume and for prescribed initial states).
- * Synchronises the stream after the copy.  Same errors as kb_read.        */
+/* Overwrite one field: the application's input state before its loop
+ * (Sec. III-A; prescribed initial states, and resuming a loop split across
+ * kb_run calls, which must equal one run of the total count).  Synchronises
+ * the stream after the copy.  Same errors as kb_read.                      */
 int kb_write(kb_problem *h, int field, const void *src, size_t bytes,
              int src_on_device);
 
 /* Deterministic device reduction of the current state (fixed-order wave64
- * tree, double accumulation across blocks), synchronous.
+ * tree, double accumulation across blocks), synchronous: the checks an
+ * application makes of its state (mean T against the heat equation's
+ * closed-form mean, the FDTD cavity's discrete energy); the paper's
+ * applications check their results, its method does not define them.
  *   KB_HEAT2D/3D/MULTI: out[0] = sum of T
  *   KB_SKELETON       : out[0] = sum of x
  *   KB_FDTD3D         : out[0] = sum of E.E, out[1] = sum of H.H
@@ -447,7 +455,9 @@ int kb_sg_train_step(kb_problem *h, const float *T0, const float *P, const float
 /* Number of kernels per iteration (K) of the problem, or < 0 on error.    */
 int kb_kernels_per_iter(const kb_problem *h);
 
-/* Destroy graphs, events and the handle; the workspace stays the caller's.
+/* Destroy graphs, events and the handle; the workspace stays the caller's
+ * (the end of the application, after which its graphs are destroyed, as in
+ * the measurement of a graph's memory before that point, Sec. III-C).
  * Synchronises the stream.  NULL is accepted.                              */
 int kb_destroy(kb_problem *h);
 
