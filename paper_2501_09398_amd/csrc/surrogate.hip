@@ -818,14 +818,17 @@ int sg_check_tile() { return kTile; }
 // reads taps at clamped coordinates, which is replicate padding at every
 // layer (a clamped tap always lies inside the previous, larger region).
 // Layers 1-3 are the forward implicit GEMM of sg_conv_fwd_kernel with the
-// B fragments read from LDS; the weight fragments of layers 2 and 3 stay in
-// registers for the whole launch.  Layer 4 (one output channel) is done in
-// transposed form: one MFMA per 16 pixels of layer 3 gives every pixel's
-// contribution to each of the 9 taps, D[pixel][tap], and an output pixel
-// sums the 9 entries of its clamped neighbours.
-// Activations are pixel-major, 64 bytes per pixel, with the four 16-byte
-// channel chunks of pixel p rotated by (p >> 2) & 3 so that the 16 pixels
-// of a fragment load hit distinct banks.
+// B fragments read from LDS.  The weight fragments of layers 2 and 3 are
+// kept in LDS in fragment order (a wave's load of one fragment is 1 KiB of
+// consecutive bytes) and a wave takes the current layer's 18 fragments into
+// registers when the layer starts, which leaves room for three waves per
+// SIMD (12 per block).  Layer 4 (one output channel) is done in transposed
+// form: one MFMA per 16 pixels of layer 3 gives every pixel's contribution
+// to each of the 9 taps, D[pixel][tap], and an output pixel sums the 9
+// entries of its clamped neighbours.
+// Activations are pixel-major, 64 bytes per pixel; the 16-byte channel
+// chunk c of pixel p sits in slot (c + (p >> 1)) & 3, so that the eight
+// consecutive pixels of a 128-byte load pass use eight distinct slots.
 // Blocks 0..3 run the plain check tiles; blocks 4.. are persistent over the
 // output tiles (tile i goes to block 4 + i % nnet) and write the check
 // partials of the tiles they produced.
@@ -837,15 +840,23 @@ constexpr int H1 = TH + 6, W1 = TW + 6, N1 = H1 * W1;
 constexpr int H2 = TH + 4, W2 = TW + 4, N2 = H2 * W2;
 constexpr int H3 = TH + 2, W3 = TW + 2, N3 = H3 * W3;
 constexpr int G1 = (N1 + 15) / 16, G2 = (N2 + 15) / 16, G3 = (N3 + 15) / 16;
-constexpr int kPix = 80;                              // bytes per pixel: 64 of channels + 16 pad
+constexpr int kPix = 64;                              // bytes per pixel (32 bf16 channels)
+constexpr int kW = 12;                                // waves per block
+constexpr int kT = 64 * kW;                           // threads per block
 constexpr int kIn = 0;                                // N0 uint
 constexpr int kA = kIn + N0 * 4;                      // N1 * kPix bytes
 constexpr int kB = kA + N1 * kPix;                    // N2 * kPix bytes
-constexpr int kBytes = kB + N2 * kPix;
+constexpr int kWt = kB + N2 * kPix;                   // weight fragments, 16 bytes per lane:
+constexpr int kWf2 = 0, kWf3 = 9 * 2 * 64, kWf1 = 2 * 9 * 2 * 64, kWf4 = kWf1 + 2 * 64;   //  layers 2, 3 [tap][m][lane]; 1 [m][lane]; 4 [lane]
+constexpr int kNWf = kWf4 + 64;
+constexpr int kBytes = kWt + kNWf * 16;
 static_assert(N3 * 9 * 4 <= N2 * kPix, "layer-4 partials must fit buffer B");
-static_assert(2 * kRegion * kRegion * 4 <= kBytes, "check tile must fit");
-static_assert(kA % 16 == 0 && kB % 16 == 0, "16-byte aligned buffers");
-static_assert(N0 <= 2 * kNT, "two input pixels per thread");
+static_assert(2 * kRegion * kRegion * 4 <= kWt, "check tile must fit");
+static_assert(kA % 16 == 0 && kB % 16 == 0 && kWt % 16 == 0, "16-byte aligned buffers");
+static_assert(N0 <= 2 * kT, "two input pixels per thread");
+static_assert(TH * TW <= kT, "one output pixel per thread");
+// byte offset of the 16-byte channel chunk c of pixel p
+__device__ __forceinline__ int chunk(int p, int c) { return p * kPix + (((c + (p >> 1)) & 3) << 4); }
 }  // namespace fz
 
 // Source pixel (in the previous region) of tap (dy, dx) for region pixel p.
@@ -884,7 +895,9 @@ __device__ __forceinline__ void store_act(unsigned char *dst, int p, int kq, con
     uint2 packed;
     packed.x = f2bf2(gelu(acc[m][0]), gelu(acc[m][1]));
     packed.y = f2bf2(gelu(acc[m][2]), gelu(acc[m][3]));
-    *reinterpret_cast<uint2 *>(dst + p * fz::kPix + m * 32 + kq * 8) = packed;
+    // channels m*16 + kq*4 .. +3: chunk 2m + kq/2, bytes (kq & 1) * 8
+    *reinterpret_cast<uint2 *>(dst + fz::chunk(p, 2 * m + (kq >> 1)) + (kq & 1) * 8) = packed;
+    __builtin_amdgcn_sched_barrier(0);   // four activations at a time (registers)
   }
 }
 
@@ -893,45 +906,51 @@ __device__ __forceinline__ void bias_init(f32x4 (&acc)[2], const float *bias, in
   acc[1] = *reinterpret_cast<const f32x4 *>(bias + 16 + kq * 4);
 }
 
-// One 32 -> 32 layer over a region (Wr wide, N pixels, G groups of 16).
+// One 32 -> 32 layer over a region (Wr wide, N pixels, G groups of 16);
+// wf: the layer's weight fragments in LDS, [tap][m][lane].
 template <int Wr, int N, int G, bool EDGE>
-__device__ __forceinline__ void fused_layer32(const unsigned char *src, unsigned char *dst, const bf16x8 (&wa)[9][2],
+__device__ __forceinline__ void fused_layer32(const unsigned char *src, unsigned char *dst, const bf16x8 *wf,
                                               const float *bias, int oy, int ox, int H, int W) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
-  for (int g = wave; g < G; g += kNW) {
+  bf16x8 wa[9][2];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) wa[tap][m] = wf[(tap * 2 + m) * 64 + lane];
+  for (int g = wave; g < G; g += fz::kW) {
     const int p = min(g * 16 + r, N - 1);
     const TapSrc<Wr, EDGE> ts(p, oy, ox, H, W);
     f32x4 acc[2];
     bias_init(acc, bias, kq);
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-      const bf16x8 B = ld_frag(reinterpret_cast<const unsigned short *>(src + ts(tap) * fz::kPix + kq * 16));
+      const bf16x8 B = ld_frag(reinterpret_cast<const unsigned short *>(src + fz::chunk(ts(tap), kq)));
       acc[0] = mfma(wa[tap][0], B, acc[0]);
       acc[1] = mfma(wa[tap][1], B, acc[1]);
+      // at most three taps' operands in flight (register room for three
+      // waves per SIMD)
+      if (tap % 3 == 2) __builtin_amdgcn_sched_barrier(0);
     }
     const int po = g * 16 + r;
     if (po < N) store_act(dst, po, kq, acc);
   }
 }
 
-struct FusedRegs {
-  bf16x8 w1[2], w2[9][2], w3[9][2], w4;
-};
-
 // The network on one 16x32 output tile; in0 holds the tile's input region.
 // Returns after the last barrier that orders this tile's LDS use; the
 // output phase follows in the caller.
 template <bool EDGE>
-__device__ __forceinline__ void fused_tile(const SgFusedArgs &a, const FusedRegs &R, unsigned char *sm,
-                                           const float *sbias, int y0, int x0) {
+__device__ __forceinline__ void fused_tile(const SgFusedArgs &a, unsigned char *sm, const float *sbias, int y0,
+                                           int x0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
   const unsigned *in0 = reinterpret_cast<const unsigned *>(sm + fz::kIn);
   unsigned char *bA = sm + fz::kA, *bB = sm + fz::kB;
+  const bf16x8 *wf = reinterpret_cast<const bf16x8 *>(sm + fz::kWt);
   float *Dl = reinterpret_cast<float *>(bB);
   // layer 1 (2 -> 32): k = tap*2 + cin; lane kq gathers taps kq*4 .. kq*4+3
-  for (int g = wave; g < fz::G1; g += kNW) {
+  for (int g = wave; g < fz::G1; g += fz::kW) {
     const int p = min(g * 16 + r, fz::N1 - 1);
     const TapSrc<fz::W1, EDGE> ts(p, y0 - 3, x0 - 3, a.H, a.W);
     unsigned u[4];
@@ -943,21 +962,21 @@ __device__ __forceinline__ void fused_tile(const SgFusedArgs &a, const FusedRegs
     const bf16x8 B = __builtin_bit_cast(bf16x8, uint4{u[0], u[1], u[2], u[3]});
     f32x4 acc[2];
     bias_init(acc, sbias, kq);
-    acc[0] = mfma(R.w1[0], B, acc[0]);
-    acc[1] = mfma(R.w1[1], B, acc[1]);
+    acc[0] = mfma(wf[fz::kWf1 + lane], B, acc[0]);
+    acc[1] = mfma(wf[fz::kWf1 + 64 + lane], B, acc[1]);
     const int po = g * 16 + r;
     if (po < fz::N1) store_act(bA, po, kq, acc);
   }
   __syncthreads();
-  fused_layer32<fz::W2, fz::N2, fz::G2, EDGE>(bA, bB, R.w2, sbias + 32, y0 - 2, x0 - 2, a.H, a.W);
+  fused_layer32<fz::W2, fz::N2, fz::G2, EDGE>(bA, bB, wf + fz::kWf2, sbias + 32, y0 - 2, x0 - 2, a.H, a.W);
   __syncthreads();
-  fused_layer32<fz::W3, fz::N3, fz::G3, EDGE>(bB, bA, R.w3, sbias + 64, y0 - 1, x0 - 1, a.H, a.W);
+  fused_layer32<fz::W3, fz::N3, fz::G3, EDGE>(bB, bA, wf + fz::kWf3, sbias + 64, y0 - 1, x0 - 1, a.H, a.W);
   __syncthreads();
   // layer 4, transposed: D[pixel][tap] = sum_cin act3[pixel][cin] W4[tap][cin]
-  for (int g = wave; g < fz::G3; g += kNW) {
+  for (int g = wave; g < fz::G3; g += fz::kW) {
     const int p = min(g * 16 + r, fz::N3 - 1);
-    const bf16x8 A = ld_frag(reinterpret_cast<const unsigned short *>(bA + p * fz::kPix + kq * 16));
-    const f32x4 d = mfma(A, R.w4, f32x4{0.f, 0.f, 0.f, 0.f});
+    const bf16x8 A = ld_frag(reinterpret_cast<const unsigned short *>(bA + fz::chunk(p, kq)));
+    const f32x4 d = mfma(A, wf[fz::kWf4 + lane], f32x4{0.f, 0.f, 0.f, 0.f});
     if (r < 9) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -989,13 +1008,13 @@ __device__ __forceinline__ float fused_out(const SgFusedArgs &a, const float *Dl
   return acc;
 }
 
-__global__ __launch_bounds__(kNT) void sg_fused_kernel(const SgFusedArgs a) {
+__global__ __launch_bounds__(fz::kT) void sg_fused_kernel(const SgFusedArgs a) {
   __shared__ __align__(16) unsigned char sm[fz::kBytes];
   __shared__ __align__(16) float sbias[100];
   __shared__ float t0s[2][fz::TH * fz::TW];   // by tile parity: written before the
                                               // previous tile's output is read out
-  __shared__ double dsh[kNW];
-  __shared__ float fsh[kNW];
+  __shared__ double dsh[fz::kW];
+  __shared__ float fsh[fz::kW];
   if (blockIdx.x < 4) {
     const int t = blockIdx.x;
     check_plain_tile(a.T0, a.P, a.H, a.W, a.ksteps, a.k, a.tile_y[t], a.tile_x[t], reinterpret_cast<float *>(sm),
@@ -1010,19 +1029,26 @@ __global__ __launch_bounds__(kNT) void sg_fused_kernel(const SgFusedArgs a) {
   if (threadIdx.x < 96) sbias[threadIdx.x] = a.bias[kSgOffB[threadIdx.x >> 5] + (threadIdx.x & 31)];
   if (threadIdx.x == 96) sbias[96] = a.bias[kSgOffB[3]];
 
-  // weights: layer-1 and layer-2/3 A fragments, layer-4 B fragment (kept
-  // in registers for the whole launch)
-  FusedRegs R;
-#pragma unroll
-  for (int m = 0; m < 2; ++m) R.w1[m] = ld_frag(a.w1 + (m * 16 + r) * 32 + kq * 8);
-#pragma unroll
-  for (int tap = 0; tap < 9; ++tap)
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      R.w2[tap][m] = ld_frag(a.w2 + (tap * 32 + m * 16 + r) * 32 + kq * 8);
-      R.w3[tap][m] = ld_frag(a.w3 + (tap * 32 + m * 16 + r) * 32 + kq * 8);
+  // weight fragments in LDS in fragment order (one wave's fragment = 1 KiB
+  // of consecutive bytes): layers 2, 3 [tap][m][lane] (A operands), layer 1
+  // [m][lane] (A), layer 4 [lane] (the B operand of the transposed layer)
+  {
+    bf16x8 *wf = reinterpret_cast<bf16x8 *>(sm + fz::kWt);
+    for (int e = threadIdx.x; e < fz::kNWf; e += fz::kT) {
+      const int ln = e % 64, rr = ln & 15, qq = ln >> 4;
+      bf16x8 v;
+      if (e < fz::kWf1) {
+        const int l = e / fz::kWf3, tap = (e / (2 * 64)) % 9, m = (e / 64) % 2;
+        v = ld_frag((l == 0 ? a.w2 : a.w3) + (tap * 32 + m * 16 + rr) * 32 + qq * 8);
+      } else if (e < fz::kWf4) {
+        const int m = (e - fz::kWf1) / 64;
+        v = ld_frag(a.w1 + (m * 16 + rr) * 32 + qq * 8);
+      } else {
+        v = rr < 9 ? ld_frag(a.w4 + rr * 32 + qq * 8) : __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+      }
+      wf[e] = v;
     }
-  R.w4 = r < 9 ? ld_frag(a.w4 + r * 32 + kq * 8) : __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+  }
 
   // input values of the 24 x 40 region, two per thread, loaded one tile ahead
   float pT[2], pP[2];
@@ -1030,7 +1056,7 @@ __global__ __launch_bounds__(kNT) void sg_fused_kernel(const SgFusedArgs a) {
     const int y0 = (tile / a.tiles_x) * fz::TH, x0 = (tile % a.tiles_x) * fz::TW;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int p = min((int)threadIdx.x + q * kNT, fz::N0 - 1);
+      const int p = min((int)threadIdx.x + q * fz::kT, fz::N0 - 1);
       const int i = p / fz::W0, j = p - (p / fz::W0) * fz::W0;
       const long long g = (long long)clampi(y0 - 4 + i, a.H) * a.W + clampi(x0 - 4 + j, a.W);
       pT[q] = a.T0[g];
@@ -1047,7 +1073,7 @@ __global__ __launch_bounds__(kNT) void sg_fused_kernel(const SgFusedArgs a) {
     // network input; the tile's own T0 values are kept for the output
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int p = threadIdx.x + q * kNT;
+      const int p = threadIdx.x + q * fz::kT;
       if (p < fz::N0) {
         const float t = (pT[q] - 333.0f) / 10.0f;
         const float u = (pP[q] - 0.5f) / 0.29f;
@@ -1059,12 +1085,12 @@ __global__ __launch_bounds__(kNT) void sg_fused_kernel(const SgFusedArgs a) {
     __syncthreads();
     if (tile + a.nnet < a.ntiles) fetch(tile + a.nnet);
     const bool interior = y0 >= 4 && x0 >= 4 && y0 + fz::TH + 4 <= a.H && x0 + fz::TW + 4 <= a.W;
-    if (interior) fused_tile<false>(a, R, sm, sbias, y0, x0);
-    else fused_tile<true>(a, R, sm, sbias, y0, x0);
+    if (interior) fused_tile<false>(a, sm, sbias, y0, x0);
+    else fused_tile<true>(a, sm, sbias, y0, x0);
     // output (one pixel per thread)
     const int i = threadIdx.x >> 5, j = threadIdx.x & 31;
     const int yy = y0 + i, xx = x0 + j;
-    if (yy < a.H && xx < a.W) {
+    if (i < fz::TH && yy < a.H && xx < a.W) {
       const float acc = interior ? fused_out<false>(a, Dl, y0, x0, i, j) : fused_out<true>(a, Dl, y0, x0, i, j);
       const float y = acc + sbias[96];
       const float t0 = t0s[par][i * fz::TW + j];
@@ -1077,9 +1103,9 @@ __global__ __launch_bounds__(kNT) void sg_fused_kernel(const SgFusedArgs a) {
     // buffer B (D) is next written after two more barriers, t0s[par] after
     // three; in0 and buffer A are no longer read by this tile.
   }
-  const double s1 = block_sum_w<kNW>(s_cur, dsh);
-  const double s2 = block_sum_w<kNW>(s_new, dsh);
-  const float m = block_max_w<kNW>(mx, fsh);
+  const double s1 = block_sum_w<fz::kW>(s_cur, dsh);
+  const double s2 = block_sum_w<fz::kW>(s_new, dsh);
+  const float m = block_max_w<fz::kW>(mx, fsh);
   if (threadIdx.x == 0) {
     a.partial[nb * 3 + 0] = s1;
     a.partial[nb * 3 + 1] = s2;
@@ -1088,7 +1114,7 @@ __global__ __launch_bounds__(kNT) void sg_fused_kernel(const SgFusedArgs a) {
 }
 
 void sg_make_fused(Launch &L, const SgFusedArgs &a) {
-  L.set((const void *)sg_fused_kernel, dim3(a.nnet + 4), dim3(kNT), 0, a);
+  L.set((const void *)sg_fused_kernel, dim3(a.nnet + 4), dim3(fz::kT), 0, a);
 }
 
 int sg_fused_tiles(int H, int W, int *tiles_x) {
