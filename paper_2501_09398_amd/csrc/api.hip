@@ -1121,6 +1121,14 @@ int kb_write(kb_problem *h, int field, const void *src, size_t bytes, int src_on
   } else {
     HIPCHK(hipMemcpy(dev, src, bytes, kind));
   }
+  if (h->kind == KB_FDTD3D && field >= KB_F_EX && field <= KB_F_HZ) {
+    // the cavity's i = N column is kept equal in both field sets (no step
+    // changes E, Hy or Hz there, and every kernel that writes a whole set
+    // copies them): mirror the written column into the other set
+    float *other = h->F[1 - h->cur][field - KB_F_EX];
+    HIPCHK(hipMemcpy2D(other + h->N, pitch * sizeof(float), dev + h->N, pitch * sizeof(float), sizeof(float), rows,
+                       hipMemcpyDeviceToDevice));
+  }
   if (h->kind == KB_HEAT2D_SURROGATE && (field == KB_F_W || field == KB_F_P)) {
     // derived device data: the packed bf16 weights, the power sum
     HIPCHK(field == KB_F_W ? sg_repack(h) : sg_power_changed(h));

@@ -787,9 +787,11 @@ bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a0, bool nt) {
 // i = N takes part only through its E values, the i+1 neighbours of node
 // N-1: no E component at i = N is ever updated (Ex there is row padding, Ey
 // and Ez are tangential to the wall), so E^{n+1} = E^n there and lane 63
-// reads them from the input set.  The column's own outputs (E, Hy and Hz
-// copied, Hx updated twice) are written by fdtd_column_kernel, which runs
-// after this kernel in the same iteration.
+// reads them from the input set.  Nor do Hy and Hz there change, and the
+// library keeps the column's E, Hy and Hz equal in both field sets (every
+// kernel that writes a whole set copies them, kb_write mirrors them), so of
+// the column only Hx, updated twice, is written: by fdtd_column_kernel,
+// which runs after this kernel in the same iteration.
 // ---------------------------------------------------------------------------
 
 struct Q4 {
@@ -1031,11 +1033,11 @@ bool make_fdtd_tb2_rows(Launch &L, const FdtdTbArgs &a0, bool nt, int form) {
 }
 
 // The column i = N = 256 of the whole-row kernel's launch (see above),
-// launched after it in the same iteration: E, Hy and Hz copied to the
-// output set, Hx updated twice with the column's unchanging E (the same
-// expression as every other Hx update); thread 0 also advances the device
-// step counter by the launch's two steps (this kernel does not read it).
-// One thread per (j, k) node of the column.
+// launched after it in the same iteration: Hx updated twice with the
+// column's unchanging E (the same expression as every other Hx update; E,
+// Hy and Hz there already hold the same values in both sets); thread 0 also
+// advances the device step counter by the launch's two steps (this kernel
+// does not read it).  One thread per (j, k) node of the column.
 struct ColumnArgs {
   const float *Ex, *Ey, *Ez, *Hx, *Hy, *Hz;
   float *oEx, *oEy, *oEz, *oHx, *oHy, *oHz;
@@ -1052,14 +1054,9 @@ __global__ __launch_bounds__(256) void fdtd_column_kernel(const ColumnArgs a) {
   const int k = (int)(t / M), j = (int)(t - (long long)k * M);
   const size_t sk = (size_t)M * a.P;
   const size_t c = (size_t)k * sk + (size_t)j * a.P + N;
-  const float ey = a.Ey[c], ez = a.Ez[c], hx = a.Hx[c];
-  a.oEx[c] = a.Ex[c];
-  a.oEy[c] = ey;
-  a.oEz[c] = ez;
-  a.oHy[c] = a.Hy[c];
-  a.oHz[c] = a.Hz[c];
-  float h = hx;
+  float h = a.Hx[c];
   if (j < N && k < N) {
+    const float ey = a.Ey[c], ez = a.Ez[c];
     const float d = (a.Ez[c + a.P] - ez) - (a.Ey[c + sk] - ey);
     h = h - a.dt * d;                // H^{n+1/2}
     h = h - a.dt * d;                // H^{n+3/2}: the column's E has not changed
