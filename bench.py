@@ -859,7 +859,7 @@ def fdtd_headline(args, kb, autotune, np, torch):
     return out
 
 
-def fdtd_cpu_baseline(kb, np, torch, steps_single=10, steps_all=40):
+def fdtd_cpu_baseline(kb, np, torch, steps_single=100, steps_all=1000):
     """The float32 oracle on a bounded sample of the cavity -- 256^3 from
     seeded random fields (no denormals in the timed loops) with the source
     on -- on one core and on all the cores this process may use; the GPU

@@ -797,9 +797,18 @@ bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a0, bool nt) {
 struct Q4 {
   float v[4];
 };
+// a 16-byte load through a global-memory pointer: a generic pointer could
+// be merged with the address of a register-free zero and become a flat load,
+// which shares the LDS wait counter and so holds every LDS wait until it
+// returns
+typedef float V4f __attribute__((ext_vector_type(4)));
+typedef const V4f __attribute__((address_space(1))) *GlobalV4f;
 __device__ __forceinline__ Q4 q4ld(const float *p) {
-  const float4 a = *reinterpret_cast<const float4 *>(p);
+  const V4f a = *(GlobalV4f)p;
   return Q4{{a.x, a.y, a.z, a.w}};
+}
+__device__ __forceinline__ float f1ld(const float *p) {
+  return *(const float __attribute__((address_space(1))) *)p;
 }
 __device__ __forceinline__ float4 f4of(const Q4 &a) { return make_float4(a.v[0], a.v[1], a.v[2], a.v[3]); }
 __device__ __forceinline__ Q4 q4of(const float4 &a) { return Q4{{a.x, a.y, a.z, a.w}}; }
@@ -846,7 +855,7 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
   // would tie up scalar registers the kernel needs)
   auto iN = [&](int e) { return i0 + e <= N; };
   auto ilt = [&](int e) { return i0 + e < N; };
-  auto ii = [&](int e) { return i0 + e >= 1 && i0 + e <= N - 1; };
+  auto ii = [&](int e) { return (i0 + e >= 1) & (i0 + e <= N - 1); };
   const bool srow = j == a.sj && a.si >= i0 && a.si < i0 + 4;   // the source node is in this lane
   const int wm = w > 0 ? w - 1 : 0, wp = w < kTrNW - 1 ? w + 1 : kTrNW - 1;
   const size_t sk = (size_t)M * a.P;
@@ -858,11 +867,22 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
   const float g0 = add0 ? a.g[n] : 0.f, g1 = add1 ? a.g[n + 1] : 0.f;
   const Q4 z4{{0.f, 0.f, 0.f, 0.f}};
 
-  auto ld = [&](const float *f, int k) -> Q4 { return vld && k >= 0 && k <= N ? q4ld(f + k * sk + cij) : z4; };
-  auto ldj = [&](const float *f, int k) -> Q4 {           // row j+1
-    return jup && k >= 0 && k <= N ? q4ld(f + k * sk + cij + a.P) : z4;
+  // operands outside the domain read as zero (exec-masked loads)
+  auto ld = [&](const float *f, int k) -> Q4 {
+    Q4 r{{0.f, 0.f, 0.f, 0.f}};
+    if (vld && k >= 0 && k <= N) r = q4ld(f + k * sk + cij);
+    return r;
   };
-  auto ldN = [&](const float *f, int k) -> float { return xn && k >= 0 && k <= N ? f[k * sk + cN] : 0.f; };
+  auto ldj = [&](const float *f, int k) -> Q4 {           // row j+1
+    Q4 r{{0.f, 0.f, 0.f, 0.f}};
+    if (jup && k >= 0 && k <= N) r = q4ld(f + k * sk + cij + a.P);
+    return r;
+  };
+  auto ldN = [&](const float *f, int k) -> float {
+    float r = 0.f;
+    if (xn && k >= 0 && k <= N) r = f1ld(f + k * sk + cN);
+    return r;
+  };
 
   const int m0 = max(kb - 2, 0);
   Q4 ex = ld(a.Ex, m0), ey = ld(a.Ey, m0), ez = ld(a.Ez, m0);   // E^n of plane m
@@ -902,11 +922,17 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
     const bool mlt = m < N;
     const Q4 ey_e = q4east(ey, last, eyN), ez_e = q4east(ez, last, ezN);
     Q4 h1x, h1y, h1z;
+    // (every update is computed and then selected, its condition combined
+    // without short-circuits: a conditional expression would become a
+    // branch per node and component)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      h1x.v[e] = (iN(e) && jlt && mlt) ? hx.v[e] - dt * ((ez_j.v[e] - ez.v[e]) - (eyk.v[e] - ey.v[e])) : hx.v[e];
-      h1y.v[e] = (ilt(e) && mlt) ? hy.v[e] - dt * ((exk.v[e] - ex.v[e]) - (ez_e.v[e] - ez.v[e])) : hy.v[e];
-      h1z.v[e] = (ilt(e) && jlt) ? hz.v[e] - dt * ((ey_e.v[e] - ey.v[e]) - (ex_j.v[e] - ex.v[e])) : hz.v[e];
+      const float ux = hx.v[e] - dt * ((ez_j.v[e] - ez.v[e]) - (eyk.v[e] - ey.v[e]));
+      const float uy = hy.v[e] - dt * ((exk.v[e] - ex.v[e]) - (ez_e.v[e] - ez.v[e]));
+      const float uz = hz.v[e] - dt * ((ey_e.v[e] - ey.v[e]) - (ex_j.v[e] - ex.v[e]));
+      h1x.v[e] = (iN(e) & jlt & mlt) ? ux : hx.v[e];
+      h1y.v[e] = (ilt(e) & mlt) ? uy : hy.v[e];
+      h1z.v[e] = (ilt(e) & jlt) ? uz : hz.v[e];
     }
     sH1[0][w][lane] = f4of(h1x);
     sH1[1][w][lane] = f4of(h1z);
@@ -918,9 +944,12 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
     Q4 e1x, e1y, e1z;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      e1x.v[e] = (ilt(e) && jj && kk) ? ex.v[e] + dt * ((h1z.v[e] - h1z_jm.v[e]) - (h1y.v[e] - h1y_p.v[e])) : ex.v[e];
-      e1y.v[e] = (jlt && ii(e) && kk) ? ey.v[e] + dt * ((h1x.v[e] - h1x_p.v[e]) - (h1z.v[e] - h1z_w.v[e])) : ey.v[e];
-      e1z.v[e] = (mlt && ii(e) && jj) ? ez.v[e] + dt * ((h1y.v[e] - h1y_w.v[e]) - (h1x.v[e] - h1x_jm.v[e])) : ez.v[e];
+      const float ux = ex.v[e] + dt * ((h1z.v[e] - h1z_jm.v[e]) - (h1y.v[e] - h1y_p.v[e]));
+      const float uy = ey.v[e] + dt * ((h1x.v[e] - h1x_p.v[e]) - (h1z.v[e] - h1z_w.v[e]));
+      const float uz = ez.v[e] + dt * ((h1y.v[e] - h1y_w.v[e]) - (h1x.v[e] - h1x_jm.v[e]));
+      e1x.v[e] = (ilt(e) & jj & kk) ? ux : ex.v[e];
+      e1y.v[e] = (jlt & ii(e) & kk) ? uy : ey.v[e];
+      e1z.v[e] = (mlt & ii(e) & jj) ? uz : ez.v[e];
     }
     if (m == a.sk) {
 #pragma unroll
@@ -945,12 +974,12 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
       const bool qlt = q < N;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        h2x.v[e] = (iN(e) && jlt && qlt)
-                       ? h1x_p.v[e] - dt * ((e1z_jq.v[e] - e1z_p.v[e]) - (e1yn.v[e] - e1y_p.v[e])) : h1x_p.v[e];
-        h2y.v[e] = (ilt(e) && qlt)
-                       ? h1y_p.v[e] - dt * ((e1xn.v[e] - e1x_p.v[e]) - (e1z_e.v[e] - e1z_p.v[e])) : h1y_p.v[e];
-        h2z.v[e] = (ilt(e) && jlt)
-                       ? h1z_p.v[e] - dt * ((e1y_e.v[e] - e1y_p.v[e]) - (e1x_jq.v[e] - e1x_p.v[e])) : h1z_p.v[e];
+        const float ux = h1x_p.v[e] - dt * ((e1z_jq.v[e] - e1z_p.v[e]) - (e1yn.v[e] - e1y_p.v[e]));
+        const float uy = h1y_p.v[e] - dt * ((e1xn.v[e] - e1x_p.v[e]) - (e1z_e.v[e] - e1z_p.v[e]));
+        const float uz = h1z_p.v[e] - dt * ((e1y_e.v[e] - e1y_p.v[e]) - (e1x_jq.v[e] - e1x_p.v[e]));
+        h2x.v[e] = (iN(e) & jlt & qlt) ? ux : h1x_p.v[e];
+        h2y.v[e] = (ilt(e) & qlt) ? uy : h1y_p.v[e];
+        h2z.v[e] = (ilt(e) & jlt) ? uz : h1z_p.v[e];
       }
     }
     sH2[0][w][lane] = f4of(h2x);
@@ -964,12 +993,12 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
       Q4 e2x, e2y, e2z;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        e2x.v[e] = (ilt(e) && jj && kq) ? e1x_p.v[e] + dt * ((h2z.v[e] - h2z_jm.v[e]) - (h2y.v[e] - h2y_p.v[e]))
-                                        : e1x_p.v[e];
-        e2y.v[e] = (jlt && ii(e) && kq) ? e1y_p.v[e] + dt * ((h2x.v[e] - h2x_p.v[e]) - (h2z.v[e] - h2z_w.v[e]))
-                                        : e1y_p.v[e];
-        e2z.v[e] = (q < N && ii(e) && jj) ? e1z_p.v[e] + dt * ((h2y.v[e] - h2y_w.v[e]) - (h2x.v[e] - h2x_jm.v[e]))
-                                          : e1z_p.v[e];
+        const float ux = e1x_p.v[e] + dt * ((h2z.v[e] - h2z_jm.v[e]) - (h2y.v[e] - h2y_p.v[e]));
+        const float uy = e1y_p.v[e] + dt * ((h2x.v[e] - h2x_p.v[e]) - (h2z.v[e] - h2z_w.v[e]));
+        const float uz = e1z_p.v[e] + dt * ((h2y.v[e] - h2y_w.v[e]) - (h2x.v[e] - h2x_jm.v[e]));
+        e2x.v[e] = (ilt(e) & jj & kq) ? ux : e1x_p.v[e];
+        e2y.v[e] = (jlt & ii(e) & kq) ? uy : e1y_p.v[e];
+        e2z.v[e] = ((q < N) & ii(e) & jj) ? uz : e1z_p.v[e];
       }
       if (q == a.sk) {
 #pragma unroll
