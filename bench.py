@@ -215,7 +215,8 @@ def fdtd_tb2_kernel_hash():
 
 
 def fdtd_tb2_rows_kernel_hash():
-    return source_hash(FDTD_SOURCE, "void fdtd_tb2_rows_kernel(", "bool make_fdtd_tb2_rows")
+    # the kernel and the access helpers above it
+    return source_hash(FDTD_SOURCE, "struct Q4 {", "bool make_fdtd_tb2_rows")
 
 
 def stored_traffic(path, current_hash):
@@ -816,8 +817,8 @@ def fdtd_headline(args, kb, autotune, np, torch):
     # node), whether the launch advances one step (the fused step) or two
     # (the two-step kernels).  Its duration is bounded above by the launch's
     # share of the step time from the events around the timed replays (the
-    # share also holds the iteration's second kernel -- source, or the i = N
-    # column and step counter -- and the node-to-node gaps); the committed
+    # share also holds the iteration's second kernel, if any -- the source or
+    # the step counter's advance -- and the node-to-node gaps); the committed
     # kernel trace gives the kernel's own duration.  The one-step figure of
     # the method (72 B per cell-step with separate H and E kernels) over the
     # step time is reported beside it as the effective rate.
@@ -826,8 +827,8 @@ def fdtd_headline(args, kb, autotune, np, torch):
     eff = variant or (7 if N >= 176 else 5)          # the default fused variant for the size
     two_step = eff >= 8 and depth == 2
     if two_step:
-        name = {8: "fdtd_tb2_kernel<true>", 9: "fdtd_tb2_rows_kernel<true,16,false>",
-                10: "fdtd_tb2_rows_kernel<true,12,true>"}[eff]
+        name = {8: "fdtd_tb2_kernel<true>", 9: "fdtd_tb2_rows_kernel<true,16,false,true>",
+                10: "fdtd_tb2_rows_kernel<true,12,true,true>"}[eff]
     else:
         name = {7: "fdtd_fused_kernel<1,true>", 5: "fdtd_fused_kernel<1,false>", 6: "fdtd_fused_kernel<8,false>",
                 8: "fdtd_fused_kernel<1,true>", 9: "fdtd_fused_kernel<1,true>",

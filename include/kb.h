@@ -236,7 +236,8 @@ extern "C" {
  *              the last step of an odd count); 9, 10 = as 8 with a wave
  *              holding a whole row, four nodes per lane (N <= 256, else as
  *              8; 9: 16 rows per block, 10: 12 rows per block with the
- *              next plane's operands loaded ahead).  Default: 7 when the two
+ *              next plane's operands loaded ahead; one kernel per two-step
+ *              iteration, which also advances the step counter).  Default: 7 when the two
  *              field sets exceed 256 MiB (N >= 176), else 5.  The
  *              fused step reads one set of six fields and writes the other
  *              (48 instead of 72 bytes per node-step), so the state

@@ -122,7 +122,7 @@ bool layout(int problem, const int64_t *shape, int ndim, Layout &L, size_t *off)
       for (int f = 0; f < 6; ++f) off[23 + f] = L.add(M * M * fdtd_pitch(shape[0]) * 4);
       off[11] = L.add(kGCap * 4);
       off[12] = L.add((pcap > 0 ? pcap : 1) * 4);
-      off[13] = L.add(8);
+      off[13] = L.add(16);              // step counter, finished-block counter
       common();
       return true;
     }
@@ -183,6 +183,15 @@ int fdtd_variant(const kb_problem *h) {
   if (h->tile != 0) return h->tile;
   const double sets = 12.0 * (h->N + 1) * (h->N + 1) * h->pitch * 4;
   return sets > 256.0 * (1 << 20) ? 7 : 5;
+}
+
+// Kernels per FDTD iteration: separate H, E and source (variants < 5); one
+// whole-row launch of two steps (9, 10 at depth 2 up to N = 256); else a
+// step kernel (fused, or the two-step tiles) and the source or step advance.
+int fdtd_kernels_per_iter(const kb_problem *h) {
+  const int v = fdtd_variant(h);
+  if (v < 5) return 3;
+  return v >= 9 && h->tdepth == 2 && h->N <= 256 ? 1 : 2;
 }
 
 // Does an iteration move the state to the other buffer set?  The stencils'
@@ -328,10 +337,9 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
           t.g = h->g; t.glen = h->glen; t.probe = h->probe; t.pcap = h->pcap; t.step = h->step;
           // variants 9, 10: whole rows up to N = 256 (above that, as 8)
           if (v >= 9 && h->N <= 256) {
-            if (!make_fdtd_tb2_rows(L[0], t, nt8, v - 9)) return -1;
-            if (h->N == 256) make_fdtd_column(L[1], t);
-            else make_fdtd_step_add(L[1], h->step, 2);
-            return 2;
+            t.step_w = h->step;
+            t.done = h->done;
+            return make_fdtd_tb2_rows(L[0], t, nt8, v - 9) ? 1 : -1;
           }
           if (!make_fdtd_tb2(L[0], t, nt8)) return -1;
           make_fdtd_step_add(L[1], h->step, 2);
@@ -758,6 +766,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
       h->probe = P(off[12]);
       h->pcap = (int)(ndim == 2 ? shape[1] : kDefaultProbe);
       h->step = reinterpret_cast<long long *>(h->ws + off[13]);
+      h->done = reinterpret_cast<unsigned *>(h->ws + off[13] + 8);
       int si, sj, sk;
       if (ncoeffs == 6) {
         si = (int)coeffs[3]; sj = (int)coeffs[4]; sk = (int)coeffs[5];
@@ -790,7 +799,7 @@ int kb_create(int problem, const int64_t *shape, int ndim, const double *coeffs,
           if (hipMemsetAsync(h->F[q][f], 0, M * M * h->pitch * 4, h->stream) != hipSuccess)
             return bail(fail(KB_EHIP, "hipMemsetAsync failed"));
       if (hipMemsetAsync(h->probe, 0, (size_t)(h->pcap > 0 ? h->pcap : 1) * 4, h->stream) != hipSuccess ||
-          hipMemsetAsync(h->step, 0, 8, h->stream) != hipSuccess)
+          hipMemsetAsync(h->step, 0, 16, h->stream) != hipSuccess)
         return bail(fail(KB_EHIP, "hipMemsetAsync failed"));
       if (h->glen > 0 && hipMemcpyAsync(h->g, gt.data(), gt.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return bail(fail(KB_EHIP, "source table upload failed"));
@@ -828,7 +837,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       if (h->tile != value) clear_cache(h);
       h->tile = (int)value;
       if (h->kind == KB_HEAT2D_SURROGATE) h->K = sg_kernels_per_block(h);
-      if (h->kind == KB_FDTD3D) h->K = fdtd_variant(h) >= 5 ? 2 : 3;
+      if (h->kind == KB_FDTD3D) h->K = fdtd_kernels_per_iter(h);
       break;
     }
     case KB_OPT_TDEPTH: {
@@ -843,6 +852,7 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       if (value < 1 || value > maxd) return fail(KB_EINVAL, "temporal depth must be 1..%d", maxd);
       if (h->tdepth != value) clear_cache(h);
       h->tdepth = (int)value;
+      if (h->kind == KB_FDTD3D) h->K = fdtd_kernels_per_iter(h);
       break;
     }
     case KB_OPT_GRAPH_CACHE:

@@ -790,25 +790,47 @@ bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a0, bool nt) {
 // reads them from the input set.  Nor do Hy and Hz there change, and the
 // library keeps the column's E, Hy and Hz equal in both field sets (every
 // kernel that writes a whole set copies them, kb_write mirrors them), so of
-// the column only Hx, updated twice, is written: by fdtd_column_kernel,
-// which runs after this kernel in the same iteration.
+// the column only Hx is written: lane 63 updates it twice with the
+// column's unchanging E (E_z of row j+1 from the next wave through LDS).
+//
+// The block that finishes last (a counter of finished blocks, reset by
+// that block) advances the device step counter by the launch's two steps:
+// every other block has read it by then.
 // ---------------------------------------------------------------------------
 
 struct Q4 {
   float v[4];
 };
-// a 16-byte load through a global-memory pointer: a generic pointer could
-// be merged with the address of a register-free zero and become a flat load,
-// which shares the LDS wait counter and so holds every LDS wait until it
-// returns
+// Plane accesses through buffer resources: the plane's address and byte
+// size in scalar registers, a lane's 32-bit byte offset in a vector
+// register.  The hardware range check does the domain masking: a load
+// outside the plane (offset kOff, or a plane of size 0 for k outside
+// 0..N) returns zero and a store there is dropped.  So every path issues
+// the same memory instructions (a wait for an earlier load then need not
+// wait for all), no lane keeps a 64-bit address, and no zero has to be
+// written into the destination first.
 typedef float V4f __attribute__((ext_vector_type(4)));
-typedef const V4f __attribute__((address_space(1))) *GlobalV4f;
-__device__ __forceinline__ Q4 q4ld(const float *p) {
-  const V4f a = *(GlobalV4f)p;
+typedef unsigned V4u __attribute__((ext_vector_type(4)));   // the buffer builtins' data type
+constexpr unsigned kOff = 0x80000000u;        // an offset beyond every plane
+constexpr int kRsrcWord3 = 0x00020000;        // raw buffer, 32-bit data (gfx9 family)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *plane, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(plane), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ Q4 q4ld(__amdgpu_buffer_rsrc_t r, unsigned ob) {
+  const V4f a = __builtin_bit_cast(V4f, __builtin_amdgcn_raw_buffer_load_b128(r, ob, 0, 0));
   return Q4{{a.x, a.y, a.z, a.w}};
 }
-__device__ __forceinline__ float f1ld(const float *p) {
-  return *(const float __attribute__((address_space(1))) *)p;
+__device__ __forceinline__ float f1ld(__amdgpu_buffer_rsrc_t r, unsigned ob) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, ob, 0, 0));
+}
+__device__ __forceinline__ void f1st(__amdgpu_buffer_rsrc_t r, unsigned ob, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, ob, 0, 0);
+}
+// NT: non-temporal (streaming) store
+template <bool NT>
+__device__ __forceinline__ void q4st(__amdgpu_buffer_rsrc_t r, unsigned ob, const Q4 &a) {
+  const V4f v = {a.v[0], a.v[1], a.v[2], a.v[3]};
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4u, v), r, ob, 0, NT ? 2 : 0);
 }
 __device__ __forceinline__ float4 f4of(const Q4 &a) { return make_float4(a.v[0], a.v[1], a.v[2], a.v[3]); }
 __device__ __forceinline__ Q4 q4of(const float4 &a) { return Q4{{a.x, a.y, a.z, a.w}}; }
@@ -822,67 +844,75 @@ __device__ __forceinline__ Q4 q4east(const Q4 &a, bool last, float ext) {
 __device__ __forceinline__ Q4 q4west(const Q4 &a) {
   return Q4{{lane_west_open(a.v[3]), a.v[0], a.v[1], a.v[2]}};
 }
-template <bool NT>
-__device__ __forceinline__ void st4q(float *p, const Q4 &a) {
-  st4o<NT>(p, a.v[0], a.v[1], a.v[2], a.v[3]);
-}
 
 // NW waves (rows) per block, NW - 3 output rows; PF: operands loaded one
-// plane ahead (the register room for it needs NW <= 12)
-template <bool NT, int NW, bool PF>
+// plane ahead (the register room for it needs NW <= 12); FR: N = 256, every
+// lane's four nodes lie in the row (the per-node conditions fold away)
+template <bool NT, int NW, bool PF, bool FR>
 __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs a) {
   constexpr int kTrNW = NW, kTrTJ = NW - 3;
   __shared__ float4 sH1[2][kTrNW][64];      // H^{n+1/2} x, z of the current plane
   __shared__ float4 sE1[2][2][kTrNW][64];   // [plane parity][x, z] E^{n+1}
   __shared__ float4 sH2[2][kTrNW][64];      // H^{n+3/2} x, z
+  __shared__ float sEzN[kTrNW];             // E_z at i = N of each row, current plane
   const int nb = a.nj * a.nk;
   const int lb = xcd_logical_block(nb);
-  if (lb >= nb) return;                     // the whole block: before any barrier
+  // the last block of the grid to finish advances the step counter (no
+  // fence: the block's read of the counter has returned before this)
+  auto finish = [&]() {
+    if (threadIdx.x == 0) {
+      if (atomicAdd(a.done, 1u) == gridDim.x - 1) {
+        atomicExch(a.done, 0u);
+        *a.step_w += 2;
+      }
+    }
+  };
+  if (lb >= nb) {                           // the whole block: before any barrier
+    finish();
+    return;
+  }
   const int tj = lb % a.nj, tkk = lb / a.nj;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // w is the same in the whole wave: read once, so that everything that
+  // depends on the row only sits in scalar registers
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int N = a.N, M = N + 1;
   const int i0 = 4 * lane;
   const int j = tj * kTrTJ - 2 + w;
   const int kb = tkk * a.tk, ke = min(kb + a.tk, M);   // output planes [kb, ke)
   const bool jv = j >= 0 && j <= N;
-  const bool vld = jv && i0 <= N;                      // the lane holds a node of the row
+  const bool vld = jv && (FR || i0 <= N);              // the lane holds a node of the row
   const bool jup = vld && j + 1 <= N;
   const bool out = vld && w >= 2 && w < 2 + kTrTJ;
   const bool jj = j >= 1 && j <= N - 1, jlt = j < N;
   const bool last = lane == 63;
-  const bool xn = last && jv && N == 4 * 64;            // lane 63 reads E at i = N
+  const bool xn = FR && last && jv;                     // lane 63 reads E at i = N
   // per-node conditions, evaluated where used (kept as lane masks they
   // would tie up scalar registers the kernel needs)
-  auto iN = [&](int e) { return i0 + e <= N; };
-  auto ilt = [&](int e) { return i0 + e < N; };
-  auto ii = [&](int e) { return (i0 + e >= 1) & (i0 + e <= N - 1); };
+  auto iN = [&](int e) { return FR || i0 + e <= N; };
+  auto ilt = [&](int e) { return FR || i0 + e < N; };
+  auto ii = [&](int e) { return FR ? (e > 0 || lane > 0) : (i0 + e >= 1) & (i0 + e <= N - 1); };
   const bool srow = j == a.sj && a.si >= i0 && a.si < i0 + 4;   // the source node is in this lane
   const int wm = w > 0 ? w - 1 : 0, wp = w < kTrNW - 1 ? w + 1 : kTrNW - 1;
   const size_t sk = (size_t)M * a.P;
-  const size_t cij = vld ? (size_t)j * a.P + i0 : 0;
-  const size_t cN = xn ? (size_t)j * a.P + N : 0;
+  // byte offsets within a plane (a plane has at most 257 x 260 floats);
+  // kOff where the lane has no such node
+  const unsigned pbytes = (unsigned)(M * a.P * 4);
+  const unsigned ob = vld ? (unsigned)((j * a.P + i0) * 4) : kOff;
+  const unsigned obj = jup ? (unsigned)(((j + 1) * a.P + i0) * 4) : kOff;
+  const unsigned obN = xn ? (unsigned)((j * a.P + N) * 4) : kOff;
+  auto plane = [&](const float *f, int k) {   // plane k of a field (size 0 outside 0..N)
+    return plane_rsrc(f + (size_t)k * sk, k >= 0 && k <= N ? pbytes : 0u);
+  };
   const float dt = a.dt;
   const long long n = *a.step;
   const bool add0 = n >= 0 && n < a.glen, add1 = n + 1 >= 0 && n + 1 < a.glen;
   const float g0 = add0 ? a.g[n] : 0.f, g1 = add1 ? a.g[n + 1] : 0.f;
   const Q4 z4{{0.f, 0.f, 0.f, 0.f}};
 
-  // operands outside the domain read as zero (exec-masked loads)
-  auto ld = [&](const float *f, int k) -> Q4 {
-    Q4 r{{0.f, 0.f, 0.f, 0.f}};
-    if (vld && k >= 0 && k <= N) r = q4ld(f + k * sk + cij);
-    return r;
-  };
-  auto ldj = [&](const float *f, int k) -> Q4 {           // row j+1
-    Q4 r{{0.f, 0.f, 0.f, 0.f}};
-    if (jup && k >= 0 && k <= N) r = q4ld(f + k * sk + cij + a.P);
-    return r;
-  };
-  auto ldN = [&](const float *f, int k) -> float {
-    float r = 0.f;
-    if (xn && k >= 0 && k <= N) r = f1ld(f + k * sk + cN);
-    return r;
-  };
+  // operands outside the domain read as zero
+  auto ld = [&](const float *f, int k) -> Q4 { return q4ld(plane(f, k), ob); };
+  auto ldj = [&](const float *f, int k) -> Q4 { return q4ld(plane(f, k), obj); };   // row j+1
+  auto ldN = [&](const float *f, int k) -> float { return f1ld(plane(f, k), obN); };
 
   const int m0 = max(kb - 2, 0);
   Q4 ex = ld(a.Ex, m0), ey = ld(a.Ey, m0), ez = ld(a.Ez, m0);   // E^n of plane m
@@ -894,29 +924,29 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
   // with PF: E^n of plane m+1, row j+1 of E^n and H of plane m are loaded
   // one iteration ahead
   Q4 pexk = z4, peyk = z4, pezk = z4, pex_j = z4, pez_j = z4, phx = z4, phy = z4, phz = z4;
-  float peyNk = 0.f, pezNk = 0.f;
+  float peyNk = 0.f, pezNk = 0.f, phxN = 0.f;
   if constexpr (PF) {
     pexk = ld(a.Ex, m0 + 1); peyk = ld(a.Ey, m0 + 1); pezk = ld(a.Ez, m0 + 1);
     pex_j = ldj(a.Ex, m0); pez_j = ldj(a.Ez, m0);
     phx = ld(a.Hx, m0); phy = ld(a.Hy, m0); phz = ld(a.Hz, m0);
-    peyNk = ldN(a.Ey, m0 + 1); pezNk = ldN(a.Ez, m0 + 1);
+    peyNk = ldN(a.Ey, m0 + 1); pezNk = ldN(a.Ez, m0 + 1); phxN = ldN(a.Hx, m0);
   }
   for (int m = m0; m <= ke; ++m) {
     const bool pm = m <= N;                          // plane m exists
     Q4 exk, eyk, ezk, ex_j, ez_j, hx, hy, hz;
-    float eyNk, ezNk;
+    float eyNk, ezNk, hxN;                           // hxN: Hx at i = N (lane 63 at N = 256)
     if constexpr (PF) {
       exk = pexk; eyk = peyk; ezk = pezk; ex_j = pex_j; ez_j = pez_j; hx = phx; hy = phy; hz = phz;
-      eyNk = peyNk; ezNk = pezNk;
+      eyNk = peyNk; ezNk = pezNk; hxN = phxN;
       pexk = ld(a.Ex, m + 2); peyk = ld(a.Ey, m + 2); pezk = ld(a.Ez, m + 2);
       pex_j = ldj(a.Ex, m + 1); pez_j = ldj(a.Ez, m + 1);
       phx = ld(a.Hx, m + 1); phy = ld(a.Hy, m + 1); phz = ld(a.Hz, m + 1);
-      peyNk = ldN(a.Ey, m + 2); pezNk = ldN(a.Ez, m + 2);
+      peyNk = ldN(a.Ey, m + 2); pezNk = ldN(a.Ez, m + 2); phxN = ldN(a.Hx, m + 1);
     } else {
       exk = ld(a.Ex, m + 1); eyk = ld(a.Ey, m + 1); ezk = ld(a.Ez, m + 1);
       ex_j = ldj(a.Ex, m); ez_j = ldj(a.Ez, m);
       hx = ld(a.Hx, m); hy = ld(a.Hy, m); hz = ld(a.Hz, m);
-      eyNk = ldN(a.Ey, m + 1); ezNk = ldN(a.Ez, m + 1);
+      eyNk = ldN(a.Ey, m + 1); ezNk = ldN(a.Ez, m + 1); hxN = ldN(a.Hx, m);
     }
     // ---- A: H^{n+1/2} of plane m
     const bool mlt = m < N;
@@ -936,7 +966,18 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
     }
     sH1[0][w][lane] = f4of(h1x);
     sH1[1][w][lane] = f4of(h1z);
+    if (last) sEzN[w] = ezN;
     __syncthreads();
+    // Hx at i = N of plane m (two updates with the same E; the rows j = N
+    // and the plane k = N keep it)
+    {
+      const float d = (sEzN[wp] - ezN) - (eyNk - eyN);
+      const float h1 = hxN - dt * d;
+      const float h = (jlt & mlt) ? h1 - dt * d : hxN;
+      // (only lane 63 of an output row, and planes kb .. ke-1, write)
+      const unsigned o = out && m >= kb && m < ke ? obN : kOff;
+      f1st(plane(a.oHx, m), o, h);
+    }
     // ---- B: E^{n+1} of plane m
     const Q4 h1x_jm = q4of(sH1[0][wm][lane]), h1z_jm = q4of(sH1[1][wm][lane]);
     const Q4 h1z_w = q4west(h1z), h1y_w = q4west(h1y);
@@ -1008,15 +1049,13 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
             if (out && n + 1 >= 0 && n + 1 < a.pcap) a.probe[n + 1] = e2z.v[e];
           }
       }
-      if (out) {
-        const size_t c = (size_t)q * sk + cij;
-        st4q<NT>(a.oEx + c, e2x);
-        st4q<NT>(a.oEy + c, e2y);
-        st4q<NT>(a.oEz + c, e2z);
-        st4q<NT>(a.oHx + c, h2x);
-        st4q<NT>(a.oHy + c, h2y);
-        st4q<NT>(a.oHz + c, h2z);
-      }
+      const unsigned o = out ? ob : kOff;
+      q4st<NT>(plane(a.oEx, q), o, e2x);
+      q4st<NT>(plane(a.oEy, q), o, e2y);
+      q4st<NT>(plane(a.oEz, q), o, e2z);
+      q4st<NT>(plane(a.oHx, q), o, h2x);
+      q4st<NT>(plane(a.oHy, q), o, h2y);
+      q4st<NT>(plane(a.oHz, q), o, h2z);
     }
     // ---- rotate: plane m becomes the previous plane
     h2x_p = h2x;
@@ -1035,6 +1074,7 @@ __global__ __launch_bounds__(64 * NW) void fdtd_tb2_rows_kernel(const FdtdTbArgs
     eyN = eyNk;
     ezN = ezNk;
   }
+  finish();
 }
 
 bool make_fdtd_tb2_rows(Launch &L, const FdtdTbArgs &a0, bool nt, int form) {
@@ -1053,51 +1093,18 @@ bool make_fdtd_tb2_rows(Launch &L, const FdtdTbArgs &a0, bool nt, int form) {
   a.nk = (M + a.tk - 1) / a.tk;
   const int nb = a.nj * a.nk;
   const dim3 grid((unsigned)xcd_padded_grid(nb));
-  const void *f = form == 0 ? (nt ? (const void *)fdtd_tb2_rows_kernel<true, 16, false>
-                                  : (const void *)fdtd_tb2_rows_kernel<false, 16, false>)
-                            : (nt ? (const void *)fdtd_tb2_rows_kernel<true, 12, true>
-                                  : (const void *)fdtd_tb2_rows_kernel<false, 12, true>);
+  const bool fr = a.N == 4 * 64;
+  const void *f = form == 0
+      ? (fr ? (nt ? (const void *)fdtd_tb2_rows_kernel<true, 16, false, true>
+                  : (const void *)fdtd_tb2_rows_kernel<false, 16, false, true>)
+            : (nt ? (const void *)fdtd_tb2_rows_kernel<true, 16, false, false>
+                  : (const void *)fdtd_tb2_rows_kernel<false, 16, false, false>))
+      : (fr ? (nt ? (const void *)fdtd_tb2_rows_kernel<true, 12, true, true>
+                  : (const void *)fdtd_tb2_rows_kernel<false, 12, true, true>)
+            : (nt ? (const void *)fdtd_tb2_rows_kernel<true, 12, true, false>
+                  : (const void *)fdtd_tb2_rows_kernel<false, 12, true, false>));
   L.set(f, grid, dim3(64 * nw), 0, a);
   return true;
-}
-
-// The column i = N = 256 of the whole-row kernel's launch (see above),
-// launched after it in the same iteration: Hx updated twice with the
-// column's unchanging E (the same expression as every other Hx update; E,
-// Hy and Hz there already hold the same values in both sets); thread 0 also
-// advances the device step counter by the launch's two steps (this kernel
-// does not read it).  One thread per (j, k) node of the column.
-struct ColumnArgs {
-  const float *Ex, *Ey, *Ez, *Hx, *Hy, *Hz;
-  float *oEx, *oEy, *oEz, *oHx, *oHy, *oHz;
-  int N, P;
-  float dt;
-  long long *step;
-};
-
-__global__ __launch_bounds__(256) void fdtd_column_kernel(const ColumnArgs a) {
-  const int N = a.N, M = N + 1;
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (t == 0) *a.step += 2;
-  if (t >= (long long)M * M) return;
-  const int k = (int)(t / M), j = (int)(t - (long long)k * M);
-  const size_t sk = (size_t)M * a.P;
-  const size_t c = (size_t)k * sk + (size_t)j * a.P + N;
-  float h = a.Hx[c];
-  if (j < N && k < N) {
-    const float ey = a.Ey[c], ez = a.Ez[c];
-    const float d = (a.Ez[c + a.P] - ez) - (a.Ey[c + sk] - ey);
-    h = h - a.dt * d;                // H^{n+1/2}
-    h = h - a.dt * d;                // H^{n+3/2}: the column's E has not changed
-  }
-  a.oHx[c] = h;
-}
-
-void make_fdtd_column(Launch &L, const FdtdTbArgs &t) {
-  ColumnArgs c{t.Ex, t.Ey, t.Ez, t.Hx, t.Hy, t.Hz, t.oEx, t.oEy, t.oEz, t.oHx, t.oHy, t.oHz, t.N, t.P, t.dt,
-               const_cast<long long *>(t.step)};
-  const long long n = (long long)(t.N + 1) * (t.N + 1);
-  L.set((const void *)fdtd_column_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c);
 }
 
 struct StepAddArgs {

@@ -216,13 +216,14 @@ struct FdtdTbArgs {
   const float *g; int glen;     // amplitude per absolute step
   float *probe; int pcap;
   const long long *step;
+  // whole-row kernels: the step counter they advance and the counter of
+  // finished blocks (zero between launches) that says which block does it
+  long long *step_w; unsigned *done;
 };
 bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a, bool nt);   // fills tk..nk itself
-// Whole-row form (N <= 256, false otherwise); at N = 256 its iteration's
-// second kernel is make_fdtd_column (the i = N column and the step counter),
-// else make_fdtd_step_add.
+// Whole-row form (N <= 256, false otherwise): the iteration's one kernel
+// (it also writes the i = N column at N = 256 and advances the step counter).
 bool make_fdtd_tb2_rows(Launch &L, const FdtdTbArgs &a, bool nt, int form);   // form 0: 16 waves; 1: 12 waves, operands one plane ahead
-void make_fdtd_column(Launch &L, const FdtdTbArgs &a);
 void make_fdtd_step_add(Launch &L, long long *step, int d);
 
 struct SrcArgs {
@@ -379,6 +380,7 @@ struct kb_problem {
   float *g = nullptr; int glen = 0;
   float *probe = nullptr; int pcap = 0;
   long long *step = nullptr;
+  unsigned *done = nullptr;           // finished blocks of the running whole-row launch
   long long src = 0;
   int src_ijk[3] = {0, 0, 0};
   // learned surrogate (KB_HEAT2D_SURROGATE)

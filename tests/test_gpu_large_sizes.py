@@ -152,8 +152,9 @@ def fdtd256():
 @pytest.mark.parametrize("variant", [10, 9, 8])
 def test_fdtd_256_two_step_vs_oracle(kb, fdtd256, variant):
     """The two-step kernels (depth 2, streaming stores at this size) at
-    256^3 -- whole rows of four nodes per lane with the i = N column on its
-    own (9: 16 rows per block; 10: 12 rows, operands loaded a plane ahead),
+    256^3 -- whole rows of four nodes per lane, lane 63 also writing the
+    i = N column's Hx (9: 16 rows per block; 10: 12 rows, operands loaded a
+    plane ahead),
     60-node tiles (8) -- 100 steps in graph batches of 50 two-step
     iterations, bit for bit with the float32 oracle on every node, and the
     probe."""
