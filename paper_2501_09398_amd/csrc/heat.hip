@@ -281,6 +281,28 @@ __device__ __forceinline__ void row_neighbours(const float *row, const float4 &c
   else if (lane == 63) ev = row[x + 4];
 }
 
+// The same neighbours with the two loads apart: `load_row_edges` reads the
+// value west of lane 0 and east of lane 63 (issued with the loads of the
+// next layer, so that waiting for them does not also wait for loads issued
+// after them), `edge_neighbours` combines them with the lane shifts.
+struct RowEdges {
+  float w, e;
+};
+__device__ __forceinline__ RowEdges load_row_edges(const float *row, int x, int nx, int lane) {
+  RowEdges g{0.f, 0.f};
+  if (lane == 0 && x > 0) g.w = row[x - 1];
+  if (lane == 63 && x + 4 < nx) g.e = row[x + 4];
+  return g;
+}
+__device__ __forceinline__ void edge_neighbours(const RowEdges &g, const float4 &c, int x, int nx, int lane,
+                                                float &wv, float &ev) {
+  wv = lane_west_open(c.w);
+  ev = lane_east_open(c.x);
+  if (lane == 0) wv = x > 0 ? g.w : c.x;
+  if (x + 4 >= nx) ev = c.w;
+  else if (lane == 63) ev = g.e;
+}
+
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 // Store a float4 row segment; NT = non-temporal (streaming) store that does
@@ -428,7 +450,8 @@ __global__ __launch_bounds__(256) void heat3d_vec_kernel(const Heat3DArgs a) {
 // row above and the row below them -- R + 2 row loads for R output rows,
 // where the one-row kernel issues three -- and keeps the layers below, at
 // and above the current one in registers.  NT: streaming stores.  PF: the
-// rows of the layer after next are loaded one iteration ahead.
+// rows of the layer after next, and the values beyond the wave's ends in
+// the next layer's rows, are loaded one iteration ahead.
 // ---------------------------------------------------------------------------
 template <int R, bool NT, bool PF>
 __global__ __launch_bounds__(256) void heat3d_rows_kernel(const Heat3DArgs a) {
@@ -453,6 +476,7 @@ __global__ __launch_bounds__(256) void heat3d_rows_kernel(const Heat3DArgs a) {
     rows[r] = (size_t)(yy < 0 ? 0 : (yy >= a.ny ? a.ny - 1 : yy));
   }
   float4 c[R + 2], u[R + 2], d[R], u2[R + 2];
+  RowEdges eg[R], egn[R];                       // PF: ends of layer z, z+1
 #pragma unroll
   for (int r = 0; r < R + 2; ++r) c[r] = load_row4(T, rows[r], nx, x, xin);
 #pragma unroll
@@ -460,6 +484,8 @@ __global__ __launch_bounds__(256) void heat3d_rows_kernel(const Heat3DArgs a) {
   if constexpr (PF) {                           // layer 1 rows, one layer ahead
 #pragma unroll
     for (int r = 0; r < R + 2; ++r) u2[r] = a.nz > 1 ? load_row4(T, ny + rows[r], nx, x, xin) : c[r];
+#pragma unroll
+    for (int r = 0; r < R; ++r) eg[r] = load_row_edges(T + rows[r + 1] * nx, x, a.nx, lane);
   }
   for (int z = 0; z < a.nz; ++z) {
     const size_t zr = (size_t)z * ny;
@@ -472,6 +498,10 @@ __global__ __launch_bounds__(256) void heat3d_rows_kernel(const Heat3DArgs a) {
       } else {
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) u2[r] = u[r];
+      }
+      if (z + 1 < a.nz) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) egn[r] = load_row_edges(T + (zr + ny + rows[r + 1]) * nx, x, a.nx, lane);
       }
       if (z + 1 >= a.nz) {
 #pragma unroll
@@ -494,7 +524,8 @@ __global__ __launch_bounds__(256) void heat3d_rows_kernel(const Heat3DArgs a) {
         const float4 tc = c[r + 1], tn = c[r], ts = c[r + 2], tu = u[r + 1], td = d[r];
         const float4 p = hp ? load_once4<NT>(P, (size_t)yy, nx, x, xin) : make_float4(0.f, 0.f, 0.f, 0.f);
         float wv, ev;
-        row_neighbours(T + (zr + yy) * nx, tc, x, a.nx, lane, wv, ev);
+        if constexpr (PF) edge_neighbours(eg[r], tc, x, a.nx, lane, wv, ev);
+        else row_neighbours(T + (zr + yy) * nx, tc, x, a.nx, lane, wv, ev);
         float4 o;
         o.x = heat3d_update(tc.x, tn.x, ts.x, wv, tc.y, tu.x, td.x, p.x, hp, a.k);
         o.y = heat3d_update(tc.y, tn.y, ts.y, tc.x, tc.z, tu.y, td.y, p.y, hp, a.k);
@@ -502,6 +533,10 @@ __global__ __launch_bounds__(256) void heat3d_rows_kernel(const Heat3DArgs a) {
         o.w = heat3d_update(tc.w, tn.w, ts.w, tc.z, ev, tu.w, td.w, p.w, hp, a.k);
         if (xin) store_row4<NT>(out + (zr + yy) * nx + x, o);
       }
+    }
+    if constexpr (PF) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) eg[r] = egn[r];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) d[r] = c[r + 1];
