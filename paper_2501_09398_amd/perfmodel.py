@@ -153,9 +153,11 @@ class MemoryModel:
     """Device memory an instantiated, uploaded graph holds: linear in its
     kernel nodes (the footprint the paper's Fig. 2 bars grow with).  The
     defaults are the MI355X fit of the benchmark (skeleton chain, ROCm
-    7.2): about 206 bytes per node plus about 150 KB per graph."""
-    bytes_per_node: float = 206.0
-    bytes_fixed: float = 150e3
+    7.2, eight cumulative points of four 8000-node graphs each): 262 bytes
+    per node and no fixed part -- each such graph took exactly one 2 MiB
+    allocation unit, so this is an upper bound for graphs of that size."""
+    bytes_per_node: float = 262.144
+    bytes_fixed: float = 0.0
 
     def __call__(self, nodes):
         return self.bytes_fixed + self.bytes_per_node * np.asarray(nodes, dtype=np.float64)
