@@ -176,6 +176,36 @@ def test_fdtd_256_two_step_vs_oracle(kb, fdtd256, variant):
 
 
 @gpu
+def test_fdtd_256_variant_switching(kb, fdtd256):
+    """100 steps at 256^3 from random fields, switching kernels on the way:
+    the whole-row two-step kernels (one launch per iteration, the step
+    counter advanced by the grid's last block, the i = N column's Hx in
+    lane 63) per launch and in graph batches with an odd b, the fused step
+    in between (which copies the column's unchanging values) -- bit for bit
+    with the float32 oracle, probe and step counter included."""
+    d = fdtd256
+    N, steps = d["N"], d["steps"]
+    plan = ((10, 2, 31, 5), (7, 1, 20, 0), (9, 2, 24, 0), (10, 2, 25, 3))   # variant, depth, steps, b
+    assert sum(n for _, _, n, _ in plan) == steps
+    announce("fdtd 256^3 rand fields, 100 steps switching 10 / 7 / 9 / 10")
+    with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, d["seed"]) as p:
+        for k, fid in kb.FDTD_FIELDS.items():
+            p.write(fid, d["f0"][k])
+        done = 0
+        for v, t, n, b in plan:
+            p.set_option(kb.OPT_TILE, v)
+            p.set_option(kb.OPT_TDEPTH, t)
+            assert p.kernels_per_iter() == (1 if v >= 9 and t == 2 else 2)
+            p.run(n, b)
+            done += n
+            assert p.read(kb.F_STEP)[0] == done
+        probe = p.read(kb.F_PROBE)
+        for k, fid in kb.FDTD_FIELDS.items():
+            assert np.array_equal(p.read(fid), d["rand"][k]), k
+    assert np.array_equal(probe[:steps], d["rprobe"])
+
+
+@gpu
 @pytest.mark.parametrize("variant", [7, 5, 2])
 def test_fdtd_256_vs_oracle(kb, fdtd256, variant):
     """256^3 (two field sets of 0.8 GB): 100 steps in graph batches of 100
