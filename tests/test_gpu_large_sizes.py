@@ -176,6 +176,32 @@ def test_fdtd_256_two_step_vs_oracle(kb, fdtd256, variant):
 
 
 @gpu
+def test_fdtd_256_headline_job_vs_oracle(kb, fdtd256):
+    """The benchmark's job itself: the 256^3 cavity from zero fields with
+    the seeded Gaussian source, 10,000 steps with the whole-row two-step
+    kernel (variant 10, depth 2) in graph batches of b = 100 iterations --
+    every node of the six fields and all 10,000 probe values bit for bit
+    with the float32 oracle (about a minute of oracle time on 16 threads)."""
+    d = fdtd256
+    N, seed, steps = d["N"], d["seed"], 10000
+    src = synth.fdtd_source_cell(seed, N)
+    _, g32 = oracle.fdtd_pulse(steps + 1)
+    announce("fdtd 256^3 headline job: float32 oracle, 10,000 steps")
+    ref, probe_ref = oracle.fdtd(oracle.fdtd_zero_fields(N, np.float32), N, steps, src=src, g=g32,
+                                 dtype=np.float32)
+    announce("fdtd 256^3 headline job: GPU, variant 10, b = 100")
+    with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, seed) as p:
+        p.set_option(kb.OPT_TILE, 10)
+        p.set_option(kb.OPT_TDEPTH, 2)
+        p.run(steps, 100)
+        assert p.read(kb.F_STEP)[0] == steps
+        probe = p.read(kb.F_PROBE)
+        for k, fid in kb.FDTD_FIELDS.items():
+            assert np.array_equal(p.read(fid), ref[k]), k
+    assert np.array_equal(probe[:steps], probe_ref)
+
+
+@gpu
 def test_fdtd_256_variant_switching(kb, fdtd256):
     """100 steps at 256^3 from random fields, switching kernels on the way:
     the whole-row two-step kernels (one launch per iteration, the step
