@@ -771,11 +771,12 @@ bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a0, bool nt) {
 }
 
 // ---------------------------------------------------------------------------
-// Two steps per launch over whole rows (variant 9 with depth 2, N <= 256).
+// Two steps per launch over whole rows (variants 9 and 10 with depth 2,
+// N <= 256).
 //
 // The scheme of the kernel above (blocks march along k; phases A-D per
 // plane, two barriers; rows j-1 / j+1 of the intermediate fields through
-// LDS; two rows below and one above the 13 output rows recomputed) with a
+// LDS; two rows below and one above the output rows recomputed) with a
 // wave holding a whole row: lane l keeps nodes 4l .. 4l+3, read and written
 // as 16-byte vectors, so no node along i is computed twice and a wave issues
 // a quarter of the memory instructions.  A node's i+1 neighbour is the next
