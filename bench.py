@@ -58,6 +58,7 @@ SKEL_TRACE = os.path.join(ROOT, "profiles", "skeleton_2p16_trace_gaps.json")
 FDTD_COUNTERS = os.path.join(ROOT, "profiles", "fdtd_256_fused_hbm_counters.json")
 FDTD_TB2_COUNTERS = os.path.join(ROOT, "profiles", "fdtd_256_tb2_hbm_counters.json")
 FDTD_ROWS_COUNTERS = os.path.join(ROOT, "profiles", "fdtd_256_tb2_rows_hbm_counters.json")
+FDTD_TB3_COUNTERS = os.path.join(ROOT, "profiles", "fdtd_256_tb3_rows_hbm_counters.json")
 MISC_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "kernels_misc.hip")
 FDTD_SOURCE = os.path.join(ROOT, "paper_2501_09398_amd", "csrc", "fdtd.hip")
 
@@ -109,6 +110,7 @@ KERNEL_RUNS = {
     "fdtd_256_tb2": ("FDTD3D", (256, 64), "FDTD_COEFFS", 8, 10, 2),     # 5 launches of 2 steps
     "fdtd_256_tb2_rows16": ("FDTD3D", (256, 64), "FDTD_COEFFS", 9, 10, 2),
     "fdtd_256_tb2_rows12": ("FDTD3D", (256, 64), "FDTD_COEFFS", 10, 10, 2),
+    "fdtd_256_tb3_rows": ("FDTD3D", (256, 64), "FDTD_COEFFS", 10, 9, 3),      # 3 launches of 3 steps
     "surrogate_512": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 1, 160),
     "surrogate_512_layered": ("HEAT2D_SURROGATE", (512, 512), "HEAT_COEFFS", 2, 160),
     # 64 square grids of side round(64 * 16^u) (shape filled in from the seed)
@@ -217,6 +219,11 @@ def fdtd_tb2_kernel_hash():
 def fdtd_tb2_rows_kernel_hash():
     # the kernel and the access helpers above it
     return source_hash(FDTD_SOURCE, "struct Q4 {", "bool make_fdtd_tb2_rows")
+
+
+def fdtd_tb3_rows_kernel_hash():
+    # the kernel and its access helpers (it also uses those of the two-step one)
+    return source_hash(FDTD_SOURCE, "struct Q4 {", "bool make_fdtd_tb3_rows")
 
 
 def stored_traffic(path, current_hash):
@@ -755,7 +762,7 @@ def fdtd_headline(args, kb, autotune, np, torch):
         note("cavity: autotuning the kernel variant and b")
         tr = autotune.tune(kb, kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, n, seed=SEED, reps=1, probe_steps=200,
                            b_candidates=FDTD_B_CANDIDATES,
-                           kernel_candidates_override=[(2, 1), (5, 1), (7, 1), (8, 2), (9, 2), (10, 2)])
+                           kernel_candidates_override=[(2, 1), (5, 1), (7, 1), (8, 2), (9, 2), (10, 2), (10, 3)])
         variant, depth, b = tr.variant, tr.depth, tr.b
         tuned = {"variant": tr.variant, "depth": tr.depth, "b": tr.b, "b_measured_best": tr.b_measured,
                  "kernel_table_us_step": [(v, t, round(us, 2)) for v, t, us in tr.kernel_table],
@@ -825,22 +832,26 @@ def fdtd_headline(args, kb, autotune, np, torch):
     step_s = float(np.mean(g_TE)) / n
     p.destroy()
     eff = variant or (7 if N >= 176 else 5)          # the default fused variant for the size
-    two_step = eff >= 8 and depth == 2
-    if two_step:
+    blocked = eff >= 8 and depth in (2, 3)            # two or three steps per launch
+    if blocked and depth == 3:
+        name = "fdtd_tb3_rows_kernel<true,true>"
+    elif blocked:
         name = {8: "fdtd_tb2_kernel<true>", 9: "fdtd_tb2_rows_kernel<true,16,false,true>",
                 10: "fdtd_tb2_rows_kernel<true,12,true,true>"}[eff]
     else:
         name = {7: "fdtd_fused_kernel<1,true>", 5: "fdtd_fused_kernel<1,false>", 6: "fdtd_fused_kernel<8,false>",
                 8: "fdtd_fused_kernel<1,true>", 9: "fdtd_fused_kernel<1,true>",
                 10: "fdtd_fused_kernel<1,true>"}.get(eff, "fdtd_h_vec_kernel + fdtd_e_vec_kernel")
-    steps_per_launch = 2 if two_step else 1
+    steps_per_launch = depth if blocked else 1
     probe_s = kb.stream_probe(6, 6, 1 << 28, reps=10)
     mix_gbs = 12 * (1 << 28) * 4 / probe_s / 1e9
     launch_s = step_s * steps_per_launch
     kern_bytes = FDTD_KERNEL_BYTES_PER_NODE * nodes
     kern = kern_bytes / launch_s / 1e9
     effective = FDTD_BYTES_PER_CELL_STEP * cells / step_s / 1e9
-    if name.startswith("fdtd_tb2_rows"):
+    if name.startswith("fdtd_tb3_rows"):
+        traffic = stored_traffic(FDTD_TB3_COUNTERS, fdtd_tb3_rows_kernel_hash())
+    elif name.startswith("fdtd_tb2_rows"):
         traffic = stored_traffic(FDTD_ROWS_COUNTERS, fdtd_tb2_rows_kernel_hash())
     elif name.startswith("fdtd_tb2"):
         traffic = stored_traffic(FDTD_TB2_COUNTERS, fdtd_tb2_kernel_hash())

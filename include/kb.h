@@ -237,7 +237,9 @@ extern "C" {
  *              holding a whole row, four nodes per lane (N <= 256, else as
  *              8; 9: 16 rows per block, 10: 12 rows per block with the
  *              next plane's operands loaded ahead; one kernel per two-step
- *              iteration, which also advances the step counter).  Default: 7 when the two
+ *              iteration, which also advances the step counter); with
+ *              KB_OPT_TDEPTH 3, 9 and 10 take three steps per launch (12
+ *              rows per block, 7 of them output).  Default: 7 when the two
  *              field sets exceed 256 MiB (N >= 176), else 5.  The
  *              fused step reads one set of six fields and writes the other
  *              (48 instead of 72 bytes per node-step), so the state
@@ -261,9 +263,10 @@ extern "C" {
  *   temporal-blocking variant advances t steps (KB_HEAT2D LDS tile 1..16,
  *   register strips 15..17 1..8, register regions 18..21 1..8, register
  *   strips 22, 23 1..16; KB_HEAT3D variant 5 1..6, variant 11 1..8;
- *   KB_HEAT2D_MULTI variants 3..6 1..8; KB_FDTD3D variants 8..10 1..2, the
- *   option taking 1..2 for every cavity variant; a launch whose variant does not
- *   allow t fails with KB_EINVAL).  Other variants ignore it.  kb_run advances
+ *   KB_HEAT2D_MULTI variants 3..6 1..8; KB_FDTD3D variants 8..10 1..2 and
+ *   variants 9, 10 also 3 (N <= 256), the option taking 1..3 for every
+ *   cavity variant; a launch whose variant does not allow t fails with
+ *   KB_EINVAL).  Other variants ignore it.  kb_run advances
  *   floor(n_steps / t) iterations of t steps, then n_steps mod t single
  *   steps per launch.                                                      */
 #define KB_OPT_TDEPTH    3

@@ -62,8 +62,8 @@ def kernel_candidates(kb, problem, shape):
         return [(1, 1), (2, 1), (3, 1)]
     if problem == kb.FDTD3D:
         # one step per launch; two steps per launch (60-node tiles, and the
-        # whole-row kernels up to N = 256)
-        two = [(8, 2)] + ([(9, 2), (10, 2)] if shape[0] <= 256 else [])
+        # whole-row kernels up to N = 256, which also take three)
+        two = [(8, 2)] + ([(9, 2), (10, 2), (10, 3)] if shape[0] <= 256 else [])
         return [(1, 1), (2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1)] + two
     if problem == kb.HEAT2D_MULTI:
         return [(1, 1), (2, 1)] + [(v, t) for v in (3, 4, 5, 6) for t in MULTI_DEPTHS]

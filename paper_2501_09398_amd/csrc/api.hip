@@ -186,12 +186,13 @@ int fdtd_variant(const kb_problem *h) {
 }
 
 // Kernels per FDTD iteration: separate H, E and source (variants < 5); one
-// whole-row launch of two steps (9, 10 at depth 2 up to N = 256); else a
-// step kernel (fused, or the two-step tiles) and the source or step advance.
+// whole-row launch of two or three steps (9, 10 at depth 2 or 3 up to
+// N = 256); else a step kernel (fused, or the two-step tiles) and the
+// source or step advance.
 int fdtd_kernels_per_iter(const kb_problem *h) {
   const int v = fdtd_variant(h);
   if (v < 5) return 3;
-  return v >= 9 && h->tdepth == 2 && h->N <= 256 ? 1 : 2;
+  return v >= 9 && (h->tdepth == 2 || h->tdepth == 3) && h->N <= 256 ? 1 : 2;
 }
 
 // Does an iteration move the state to the other buffer set?  The stencils'
@@ -328,20 +329,25 @@ int fill_iter_kernels(const kb_problem *h, int cur, int depth, Launch *L) {
         // once the sets outgrow the last-level cache), its single steps the
         // fused step
         const bool nt8 = 12.0 * (h->N + 1) * (h->N + 1) * h->pitch * 4 > 256.0 * (1 << 20);
-        if (v >= 8 && depth == 2) {
+        if (v >= 8 && (depth == 2 || depth == 3)) {
           FdtdTbArgs t{};
           t.Ex = A[0]; t.Ey = A[1]; t.Ez = A[2]; t.Hx = A[3]; t.Hy = A[4]; t.Hz = A[5];
           t.oEx = B[0]; t.oEy = B[1]; t.oEz = B[2]; t.oHx = B[3]; t.oHy = B[4]; t.oHz = B[5];
           t.N = h->N; t.P = h->pitch; t.dt = h->dt;
           t.si = h->src_ijk[0]; t.sj = h->src_ijk[1]; t.sk = h->src_ijk[2];
           t.g = h->g; t.glen = h->glen; t.probe = h->probe; t.pcap = h->pcap; t.step = h->step;
-          // variants 9, 10: whole rows up to N = 256 (above that, as 8)
+          // variants 9, 10: whole rows up to N = 256 (above that, as 8);
+          // three steps per launch only with whole rows
           if (v >= 9 && h->N <= 256) {
             t.step_w = h->step;
             t.done = h->done;
+            if (depth == 3) {
+              t.fs = reinterpret_cast<const char *>(A[1]) - reinterpret_cast<const char *>(A[0]);
+              return make_fdtd_tb3_rows(L[0], t, nt8) ? 1 : -1;
+            }
             return make_fdtd_tb2_rows(L[0], t, nt8, v - 9) ? 1 : -1;
           }
-          if (!make_fdtd_tb2(L[0], t, nt8)) return -1;
+          if (depth == 3 || !make_fdtd_tb2(L[0], t, nt8)) return -1;
           make_fdtd_step_add(L[1], h->step, 2);
           return 2;
         }
@@ -844,11 +850,12 @@ int kb_set_option(kb_problem *h, int option, int64_t value) {
       if (h->kind != KB_HEAT2D && h->kind != KB_HEAT3D && h->kind != KB_HEAT2D_MULTI && h->kind != KB_FDTD3D &&
           value != 1)
         return fail(KB_EINVAL, "temporal depth > 1 only for KB_HEAT2D, KB_HEAT3D, KB_HEAT2D_MULTI and KB_FDTD3D");
-      // FDTD: two steps per launch at most (variant 8; the other variants
-      // advance one step per launch whatever the depth)
+      // FDTD: two steps per launch with variants 8-10, three with 9 and 10
+      // (whole rows, N <= 256); the other variants advance one step per
+      // launch whatever the depth
       const int maxd = h->kind == KB_HEAT3D ? heat3d_tb_max_depth()
                      : h->kind == KB_HEAT2D_MULTI ? kMtMaxDepth
-                     : h->kind == KB_FDTD3D ? 2 : heat2d_tile_max_depth();
+                     : h->kind == KB_FDTD3D ? 3 : heat2d_tile_max_depth();
       if (value < 1 || value > maxd) return fail(KB_EINVAL, "temporal depth must be 1..%d", maxd);
       if (h->tdepth != value) clear_cache(h);
       h->tdepth = (int)value;

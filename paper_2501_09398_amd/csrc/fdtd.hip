@@ -1108,6 +1108,309 @@ bool make_fdtd_tb2_rows(Launch &L, const FdtdTbArgs &a0, bool nt, int form) {
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Three steps per launch over whole rows (variants 9 and 10 with depth 3,
+// N <= 256).  The two-step kernel's march with a third pair of phases: per
+// plane m, A H^{n+1/2}(m), B E^{n+1}(m), C H^{n+3/2}(m-1), D E^{n+2}(m-1),
+// E H^{n+5/2}(m-2), F E^{n+3}(m-2) and the outputs of plane m-2, with a
+// barrier after A, C and E.  Rows j-1 of each new H and j+1 of each new E
+// pass through LDS; a new E row is written after the barrier that follows
+// the reads of the previous plane's row, so each array holds one plane.
+// Three rows below and two above the output rows, and three planes below
+// each segment, are recomputed: 12 waves (rows) give 7 output rows.  Each
+// layer of the march reads and writes what the two-step kernel's does, for
+// three steps instead of two.  The i = N column's Hx (N = 256) takes its
+// three updates in lane 63; the last block advances the step counter by 3.
+// ---------------------------------------------------------------------------
+// Accesses to a plane of all six fields of a set through one buffer
+// resource: the fields lie fs bytes apart, so the field's start is the
+// instruction's scalar offset (f * fs) and the lane's offset in the plane is
+// the vector offset; the resource spans the six planes.  A lane without a
+// node (offset kOff) or a plane outside 0..N (size 0) reads zero and drops
+// its stores, whether or not the scalar offset enters the range check.
+__device__ __forceinline__ Q4 q4ld_f(__amdgpu_buffer_rsrc_t r, unsigned ob, int fo) {
+  const V4f a = __builtin_bit_cast(V4f, __builtin_amdgcn_raw_buffer_load_b128(r, ob, fo, 0));
+  return Q4{{a.x, a.y, a.z, a.w}};
+}
+__device__ __forceinline__ float f1ld_f(__amdgpu_buffer_rsrc_t r, unsigned ob, int fo) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, ob, fo, 0));
+}
+__device__ __forceinline__ void f1st_f(__amdgpu_buffer_rsrc_t r, unsigned ob, int fo, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, ob, fo, 0);
+}
+template <bool NT>
+__device__ __forceinline__ void q4st_f(__amdgpu_buffer_rsrc_t r, unsigned ob, int fo, const Q4 &a) {
+  const V4f v = {a.v[0], a.v[1], a.v[2], a.v[3]};
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4u, v), r, ob, fo, NT ? 2 : 0);
+}
+
+template <bool NT, bool FR>
+__global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) {
+  constexpr int kNW = 12, kTJ = kNW - 5;
+  __shared__ float4 sH1[2][kNW][64];   // H^{n+1/2} x, z of plane m
+  __shared__ float4 sE1[2][kNW][64];   // E^{n+1} x, z of plane m-1 (until C), then m
+  __shared__ float4 sH2[2][kNW][64];   // H^{n+3/2} x, z of plane m-1
+  __shared__ float4 sE2[2][kNW][64];   // E^{n+2} x, z of plane m-2 (until E), then m-1
+  __shared__ float4 sH3[2][kNW][64];   // H^{n+5/2} x, z of plane m-2
+  __shared__ float sEzN[kNW];          // E_z at i = N of each row, current plane
+  const int nb = a.nj * a.nk;
+  const int lb = xcd_logical_block(nb);
+  auto finish = [&]() {                // as in the two-step kernel, three steps
+    if (threadIdx.x == 0) {
+      if (atomicAdd(a.done, 1u) == gridDim.x - 1) {
+        atomicExch(a.done, 0u);
+        *a.step_w += 3;
+      }
+    }
+  };
+  if (lb >= nb) {
+    finish();
+    return;
+  }
+  const int tj = lb % a.nj, tkk = lb / a.nj;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int N = a.N, M = N + 1;
+  const int i0 = 4 * lane;
+  const int j = tj * kTJ - 3 + w;
+  const int kb = tkk * a.tk, ke = min(kb + a.tk, M);   // output planes [kb, ke)
+  const bool jv = j >= 0 && j <= N;
+  const bool vld = jv && (FR || i0 <= N);
+  const bool jup = vld && j + 1 <= N;
+  const bool out = vld && w >= 3 && w < 3 + kTJ;
+  const bool jj = j >= 1 && j <= N - 1, jlt = j < N;
+  const bool last = lane == 63;
+  const bool xn = FR && last && jv;
+  auto iN = [&](int e) { return FR || i0 + e <= N; };
+  auto ilt = [&](int e) { return FR || i0 + e < N; };
+  auto ii = [&](int e) { return FR ? (e > 0 || lane > 0) : (i0 + e >= 1) & (i0 + e <= N - 1); };
+  const bool srow = j == a.sj && a.si >= i0 && a.si < i0 + 4;
+  const int wm = w > 0 ? w - 1 : 0, wp = w < kNW - 1 ? w + 1 : kNW - 1;
+  const size_t sk = (size_t)M * a.P;
+  const unsigned pbytes = (unsigned)(M * a.P * 4);
+  const unsigned ob = vld ? (unsigned)((j * a.P + i0) * 4) : kOff;
+  const unsigned obj = jup ? (unsigned)(((j + 1) * a.P + i0) * 4) : kOff;
+  const unsigned obN = xn ? (unsigned)((j * a.P + N) * 4) : kOff;
+  // plane k of the input or output set: one resource for its six fields
+  const unsigned span = (unsigned)(5 * a.fs) + pbytes;
+  const int fs = (int)a.fs;
+  auto pin = [&](int k) { return plane_rsrc(a.Ex + (size_t)k * sk, k >= 0 && k <= N ? span : 0u); };
+  auto pout = [&](int k) { return plane_rsrc(a.oEx + (size_t)k * sk, k >= 0 && k <= N ? span : 0u); };
+  enum { kEx, kEy, kEz, kHx, kHy, kHz };
+  const float dt = a.dt;
+  const long long n = *a.step;
+  const bool add0 = n >= 0 && n < a.glen, add1 = n + 1 >= 0 && n + 1 < a.glen, add2 = n + 2 >= 0 && n + 2 < a.glen;
+  const float g0 = add0 ? a.g[n] : 0.f, g1 = add1 ? a.g[n + 1] : 0.f, g2 = add2 ? a.g[n + 2] : 0.f;
+  const Q4 z4{{0.f, 0.f, 0.f, 0.f}};
+  auto ld = [&](int f, int k) -> Q4 { return q4ld_f(pin(k), ob, f * fs); };
+  auto ldj = [&](int f, int k) -> Q4 { return q4ld_f(pin(k), obj, f * fs); };   // row j+1
+  auto ldN = [&](int f, int k) -> float { return f1ld_f(pin(k), obN, f * fs); };
+  // the source node's E_z after an E update: add the amplitude; the block
+  // that outputs plane k records the probe
+  auto source = [&](Q4 &ez_new, int k, bool add, float g, long long t) {
+    if (k == a.sk) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (srow && i0 + e == a.si) {
+          if (add) ez_new.v[e] = ez_new.v[e] + g;
+          if (out && k >= kb && k < ke && t >= 0 && t < a.pcap) a.probe[t] = ez_new.v[e];
+        }
+    }
+  };
+
+  const int m0 = max(kb - 3, 0);
+  Q4 ex = ld(kEx, m0), ey = ld(kEy, m0), ez = ld(kEz, m0);   // E^n of plane m
+  float eyN = ldN(kEy, m0), ezN = ldN(kEz, m0);               // E at i = N: plane m,
+  float eyN_p = 0.f, ezN_p = 0.f, eyN_pp = 0.f, ezN_pp = 0.f;   // m-1, m-2
+  Q4 h1x_p = z4, h1y_p = z4, h1z_p = z4;       // H^{n+1/2} of plane m-1
+  Q4 e1y_p = z4;                               // E^{n+1}_y of plane m-1 (x, z: in sE1)
+  Q4 h2x_p = z4, h2y_p = z4, h2z_p = z4;       // H^{n+3/2} of plane m-2
+  Q4 e2y_p = z4;                               // E^{n+2}_y of plane m-2 (x, z: in sE2)
+  Q4 h3x_p = z4, h3y_p = z4;                   // H^{n+5/2} of plane m-3
+  // E^n of plane m+1, row j+1 of E^n and H of plane m, loaded one iteration ahead
+  Q4 pexk = ld(kEx, m0 + 1), peyk = ld(kEy, m0 + 1), pezk = ld(kEz, m0 + 1);
+  Q4 pex_j = ldj(kEx, m0), pez_j = ldj(kEz, m0);
+  Q4 phx = ld(kHx, m0), phy = ld(kHy, m0), phz = ld(kHz, m0);
+  float peyNk = ldN(kEy, m0 + 1), pezNk = ldN(kEz, m0 + 1), phxN = ldN(kHx, m0);
+  for (int m = m0; m <= ke + 1; ++m) {
+    const bool pm = m <= N;
+    const Q4 exk = pexk, eyk = peyk, ezk = pezk, ex_j = pex_j, ez_j = pez_j, hx = phx, hy = phy, hz = phz;
+    const float eyNk = peyNk, ezNk = pezNk, hxN = phxN;
+    // ---- A: H^{n+1/2} of plane m
+    const bool mlt = m < N;
+    const Q4 ey_e = q4east(ey, last, eyN), ez_e = q4east(ez, last, ezN);
+    Q4 h1x, h1y, h1z;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float ux = hx.v[e] - dt * ((ez_j.v[e] - ez.v[e]) - (eyk.v[e] - ey.v[e]));
+      const float uy = hy.v[e] - dt * ((exk.v[e] - ex.v[e]) - (ez_e.v[e] - ez.v[e]));
+      const float uz = hz.v[e] - dt * ((ey_e.v[e] - ey.v[e]) - (ex_j.v[e] - ex.v[e]));
+      h1x.v[e] = (iN(e) & jlt & mlt) ? ux : hx.v[e];
+      h1y.v[e] = (ilt(e) & mlt) ? uy : hy.v[e];
+      h1z.v[e] = (ilt(e) & jlt) ? uz : hz.v[e];
+    }
+    sH1[0][w][lane] = f4of(h1x);
+    sH1[1][w][lane] = f4of(h1z);
+    if (last) sEzN[w] = ezN;
+    __syncthreads();                                         // ---- barrier 1
+    {   // Hx at i = N of plane m: three updates with the column's unchanging E
+      const float d = (sEzN[wp] - ezN) - (eyNk - eyN);
+      const float h1 = hxN - dt * d;
+      const float h2 = h1 - dt * d;
+      const float h = (jlt & mlt) ? h2 - dt * d : hxN;
+      const unsigned o = out && m >= kb && m < ke ? obN : kOff;
+      f1st_f(pout(m), o, kHx * fs, h);
+    }
+    // ---- B: E^{n+1} of plane m
+    const Q4 h1x_jm = q4of(sH1[0][wm][lane]), h1z_jm = q4of(sH1[1][wm][lane]);
+    const Q4 h1z_w = q4west(h1z), h1y_w = q4west(h1y);
+    const bool kk = m >= 1 && m <= N - 1;
+    Q4 e1x, e1y, e1z;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float ux = ex.v[e] + dt * ((h1z.v[e] - h1z_jm.v[e]) - (h1y.v[e] - h1y_p.v[e]));
+      const float uy = ey.v[e] + dt * ((h1x.v[e] - h1x_p.v[e]) - (h1z.v[e] - h1z_w.v[e]));
+      const float uz = ez.v[e] + dt * ((h1y.v[e] - h1y_w.v[e]) - (h1x.v[e] - h1x_jm.v[e]));
+      e1x.v[e] = (ilt(e) & jj & kk) ? ux : ex.v[e];
+      e1y.v[e] = (jlt & ii(e) & kk) ? uy : ey.v[e];
+      e1z.v[e] = (mlt & ii(e) & jj) ? uz : ez.v[e];
+    }
+    source(e1z, m, add0, g0, n);
+    if (!pm) e1x = e1y = e1z = z4;                           // no plane m
+    // ---- C: H^{n+3/2} of plane q = m-1 (E^{n+1} of row j+1, plane q, in sE1)
+    const int q = m - 1;
+    const bool doC = q >= 0 && q >= kb - 2 && q <= ke;
+    Q4 h2x = z4, h2y = z4, h2z = z4;
+    // E^{n+1} x, z of plane q: this row's from sE1 (held there until barrier 3)
+    const Q4 e1x_p = q4of(sE1[0][w][lane]), e1z_p = q4of(sE1[1][w][lane]);
+    if (doC) {
+      const Q4 e1x_jq = q4of(sE1[0][wp][lane]), e1z_jq = q4of(sE1[1][wp][lane]);
+      const Q4 e1z_e = q4east(e1z_p, last, ezN_p), e1y_e = q4east(e1y_p, last, eyN_p);
+      const bool qlt = q < N;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float ux = h1x_p.v[e] - dt * ((e1z_jq.v[e] - e1z_p.v[e]) - (e1y.v[e] - e1y_p.v[e]));
+        const float uy = h1y_p.v[e] - dt * ((e1x.v[e] - e1x_p.v[e]) - (e1z_e.v[e] - e1z_p.v[e]));
+        const float uz = h1z_p.v[e] - dt * ((e1y_e.v[e] - e1y_p.v[e]) - (e1x_jq.v[e] - e1x_p.v[e]));
+        h2x.v[e] = (iN(e) & jlt & qlt) ? ux : h1x_p.v[e];
+        h2y.v[e] = (ilt(e) & qlt) ? uy : h1y_p.v[e];
+        h2z.v[e] = (ilt(e) & jlt) ? uz : h1z_p.v[e];
+      }
+    }
+    sH2[0][w][lane] = f4of(h2x);
+    sH2[1][w][lane] = f4of(h2z);
+    __syncthreads();                                         // ---- barrier 2
+    // the next plane's operands, issued here (half an iteration ahead) to
+    // keep their registers free during A-C
+    pexk = ld(kEx, m + 2); peyk = ld(kEy, m + 2); pezk = ld(kEz, m + 2);
+    pex_j = ldj(kEx, m + 1); pez_j = ldj(kEz, m + 1);
+    phx = ld(kHx, m + 1); phy = ld(kHy, m + 1); phz = ld(kHz, m + 1);
+    peyNk = ldN(kEy, m + 2); pezNk = ldN(kEz, m + 2); phxN = ldN(kHx, m + 1);
+    // ---- D: E^{n+2} of plane q
+    Q4 e2x = z4, e2y = z4, e2z = z4;
+    if (doC && q <= N) {
+      const Q4 h2x_jm = q4of(sH2[0][wm][lane]), h2z_jm = q4of(sH2[1][wm][lane]);
+      const Q4 h2z_w = q4west(h2z), h2y_w = q4west(h2y);
+      const bool kq = q >= 1 && q <= N - 1;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float ux = e1x_p.v[e] + dt * ((h2z.v[e] - h2z_jm.v[e]) - (h2y.v[e] - h2y_p.v[e]));
+        const float uy = e1y_p.v[e] + dt * ((h2x.v[e] - h2x_p.v[e]) - (h2z.v[e] - h2z_w.v[e]));
+        const float uz = e1z_p.v[e] + dt * ((h2y.v[e] - h2y_w.v[e]) - (h2x.v[e] - h2x_jm.v[e]));
+        e2x.v[e] = (ilt(e) & jj & kq) ? ux : e1x_p.v[e];
+        e2y.v[e] = (jlt & ii(e) & kq) ? uy : e1y_p.v[e];
+        e2z.v[e] = ((q < N) & ii(e) & jj) ? uz : e1z_p.v[e];
+      }
+      source(e2z, q, add1, g1, n + 1);
+    }
+    // ---- E: H^{n+5/2} of plane r = m-2 (E^{n+2} of row j+1, plane r, in sE2)
+    const int r = m - 2;
+    const bool doE = r >= 0 && r >= kb - 1 && r <= ke - 1;
+    Q4 h3x = z4, h3y = z4, h3z = z4;
+    // E^{n+2} x, z of plane r: this row's from sE2 (held there until the end)
+    const Q4 e2x_p = q4of(sE2[0][w][lane]), e2z_p = q4of(sE2[1][w][lane]);
+    if (doE) {
+      const Q4 e2x_jr = q4of(sE2[0][wp][lane]), e2z_jr = q4of(sE2[1][wp][lane]);
+      const Q4 e2z_e = q4east(e2z_p, last, ezN_pp), e2y_e = q4east(e2y_p, last, eyN_pp);
+      const bool rlt = r < N;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float ux = h2x_p.v[e] - dt * ((e2z_jr.v[e] - e2z_p.v[e]) - (e2y.v[e] - e2y_p.v[e]));
+        const float uy = h2y_p.v[e] - dt * ((e2x.v[e] - e2x_p.v[e]) - (e2z_e.v[e] - e2z_p.v[e]));
+        const float uz = h2z_p.v[e] - dt * ((e2y_e.v[e] - e2y_p.v[e]) - (e2x_jr.v[e] - e2x_p.v[e]));
+        h3x.v[e] = (iN(e) & jlt & rlt) ? ux : h2x_p.v[e];
+        h3y.v[e] = (ilt(e) & rlt) ? uy : h2y_p.v[e];
+        h3z.v[e] = (ilt(e) & jlt) ? uz : h2z_p.v[e];
+      }
+    }
+    sH3[0][w][lane] = f4of(h3x);
+    sH3[1][w][lane] = f4of(h3z);
+    __syncthreads();                                         // ---- barrier 3
+    sE1[0][w][lane] = f4of(e1x);                             // plane m: C, D of m+1
+    sE1[1][w][lane] = f4of(e1z);
+    // ---- F: E^{n+3} of plane r, and the outputs of plane r
+    if (r >= kb && r <= ke - 1) {
+      const Q4 h3x_jm = q4of(sH3[0][wm][lane]), h3z_jm = q4of(sH3[1][wm][lane]);
+      const Q4 h3z_w = q4west(h3z), h3y_w = q4west(h3y);
+      const bool kr = r >= 1 && r <= N - 1;
+      Q4 e3x, e3y, e3z;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float ux = e2x_p.v[e] + dt * ((h3z.v[e] - h3z_jm.v[e]) - (h3y.v[e] - h3y_p.v[e]));
+        const float uy = e2y_p.v[e] + dt * ((h3x.v[e] - h3x_p.v[e]) - (h3z.v[e] - h3z_w.v[e]));
+        const float uz = e2z_p.v[e] + dt * ((h3y.v[e] - h3y_w.v[e]) - (h3x.v[e] - h3x_jm.v[e]));
+        e3x.v[e] = (ilt(e) & jj & kr) ? ux : e2x_p.v[e];
+        e3y.v[e] = (jlt & ii(e) & kr) ? uy : e2y_p.v[e];
+        e3z.v[e] = ((r < N) & ii(e) & jj) ? uz : e2z_p.v[e];
+      }
+      source(e3z, r, add2, g2, n + 2);
+      const unsigned o = out ? ob : kOff;
+      const __amdgpu_buffer_rsrc_t po = pout(r);
+      q4st_f<NT>(po, o, kEx * fs, e3x);
+      q4st_f<NT>(po, o, kEy * fs, e3y);
+      q4st_f<NT>(po, o, kEz * fs, e3z);
+      q4st_f<NT>(po, o, kHx * fs, h3x);
+      q4st_f<NT>(po, o, kHy * fs, h3y);
+      q4st_f<NT>(po, o, kHz * fs, h3z);
+    }
+    sE2[0][w][lane] = f4of(e2x);                             // plane q: E, F of m+1
+    sE2[1][w][lane] = f4of(e2z);
+    // ---- rotate: plane m becomes the previous plane
+    h3x_p = h3x; h3y_p = h3y;
+    h2x_p = h2x; h2y_p = h2y; h2z_p = h2z;
+    e2y_p = e2y;
+    h1x_p = h1x; h1y_p = h1y; h1z_p = h1z;
+    e1y_p = e1y;
+    ex = exk; ey = eyk; ez = ezk;
+    eyN_pp = eyN_p; ezN_pp = ezN_p;
+    eyN_p = eyN; ezN_p = ezN;
+    eyN = eyNk; ezN = ezNk;
+  }
+  finish();
+}
+
+bool make_fdtd_tb3_rows(Launch &L, const FdtdTbArgs &a0, bool nt) {
+  FdtdTbArgs a = a0;
+  const int M = a.N + 1;
+  if (a.N > 4 * 64 || a.P % 4 != 0) return false;
+  // the kernel addresses the fields as base + f * fs
+  const float *in[6] = {a.Ex, a.Ey, a.Ez, a.Hx, a.Hy, a.Hz}, *out[6] = {a.oEx, a.oEy, a.oEz, a.oHx, a.oHy, a.oHz};
+  for (int f = 0; f < 6; ++f)
+    if ((const char *)in[f] != (const char *)a.Ex + f * a.fs || (const char *)out[f] != (const char *)a.oEx + f * a.fs)
+      return false;
+  constexpr int nw = 12;
+  a.ni = 1;
+  a.nj = (M + nw - 6) / (nw - 5);
+  a.nk = std::max(1, std::min(kCUs / a.nj, M / 8));
+  a.tk = (M + a.nk - 1) / a.nk;
+  a.nk = (M + a.tk - 1) / a.tk;
+  const int nb = a.nj * a.nk;
+  const bool fr = a.N == 4 * 64;
+  const void *f = fr ? (nt ? (const void *)fdtd_tb3_rows_kernel<true, true> : (const void *)fdtd_tb3_rows_kernel<false, true>)
+                     : (nt ? (const void *)fdtd_tb3_rows_kernel<true, false> : (const void *)fdtd_tb3_rows_kernel<false, false>);
+  L.set(f, dim3((unsigned)xcd_padded_grid(nb)), dim3(64 * nw), 0, a);
+  return true;
+}
+
 struct StepAddArgs {
   long long *step;
   int d;

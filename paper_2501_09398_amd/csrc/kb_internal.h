@@ -219,11 +219,13 @@ struct FdtdTbArgs {
   // whole-row kernels: the step counter they advance and the counter of
   // finished blocks (zero between launches) that says which block does it
   long long *step_w; unsigned *done;
+  long long fs;                 // bytes from one field to the next within a set (three-step kernel)
 };
 bool make_fdtd_tb2(Launch &L, const FdtdTbArgs &a, bool nt);   // fills tk..nk itself
 // Whole-row form (N <= 256, false otherwise): the iteration's one kernel
 // (it also writes the i = N column at N = 256 and advances the step counter).
 bool make_fdtd_tb2_rows(Launch &L, const FdtdTbArgs &a, bool nt, int form);   // form 0: 16 waves; 1: 12 waves, operands one plane ahead
+bool make_fdtd_tb3_rows(Launch &L, const FdtdTbArgs &a, bool nt);             // three steps per launch, 12 waves
 void make_fdtd_step_add(Launch &L, long long *step, int d);
 
 struct SrcArgs {

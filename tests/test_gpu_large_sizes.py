@@ -149,26 +149,26 @@ def fdtd256():
 
 
 @gpu
-@pytest.mark.parametrize("variant", [10, 9, 8])
-def test_fdtd_256_two_step_vs_oracle(kb, fdtd256, variant):
-    """The two-step kernels (depth 2, streaming stores at this size) at
+@pytest.mark.parametrize("variant,depth", [(10, 3), (10, 2), (9, 2), (8, 2)])
+def test_fdtd_256_two_step_vs_oracle(kb, fdtd256, variant, depth):
+    """The temporal-blocking kernels (streaming stores at this size) at
     256^3 -- whole rows of four nodes per lane, lane 63 also writing the
     i = N column's Hx (9: 16 rows per block; 10: 12 rows, operands loaded a
-    plane ahead),
-    60-node tiles (8) -- 100 steps in graph batches of 50 two-step
-    iterations, bit for bit with the float32 oracle on every node, and the
+    plane ahead; depth 3: three steps per launch), 60-node tiles (8) -- 100
+    steps in graph batches of 11 iterations (the leftover steps as fused
+    steps), bit for bit with the float32 oracle on every node, and the
     probe."""
     d = fdtd256
     N, steps = d["N"], d["steps"]
     for start in ("zero", "rand"):
-        announce(f"fdtd 256^3 {start} fields, 100 steps, two-step kernel {variant}, b=50")
+        announce(f"fdtd 256^3 {start} fields, 100 steps, kernel {variant} depth {depth}, b=11")
         with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, d["seed"]) as p:
             p.set_option(kb.OPT_TILE, variant)
-            p.set_option(kb.OPT_TDEPTH, 2)
+            p.set_option(kb.OPT_TDEPTH, depth)
             if start == "rand":
                 for k, fid in kb.FDTD_FIELDS.items():
                     p.write(fid, d["f0"][k])
-            p.run(steps, 50)
+            p.run(steps, 11)
             probe = p.read(kb.F_PROBE)
             for k, fid in kb.FDTD_FIELDS.items():
                 assert np.array_equal(p.read(fid), d[start][k]), (start, k)
@@ -178,10 +178,11 @@ def test_fdtd_256_two_step_vs_oracle(kb, fdtd256, variant):
 @gpu
 def test_fdtd_256_headline_job_vs_oracle(kb, fdtd256):
     """The benchmark's job itself: the 256^3 cavity from zero fields with
-    the seeded Gaussian source, 10,000 steps with the whole-row two-step
-    kernel (variant 10, depth 2) in graph batches of b = 100 iterations --
-    every node of the six fields and all 10,000 probe values bit for bit
-    with the float32 oracle (about a minute of oracle time on 16 threads)."""
+    the seeded Gaussian source, 10,000 steps with the whole-row kernel of
+    three steps per launch (variant 10, depth 3; 3333 iterations in graph
+    batches of b = 101, the last step fused) -- every node of the six
+    fields and all 10,000 probe values bit for bit with the float32 oracle
+    (about a minute of oracle time on 16 threads)."""
     d = fdtd256
     N, seed, steps = d["N"], d["seed"], 10000
     src = synth.fdtd_source_cell(seed, N)
@@ -189,11 +190,11 @@ def test_fdtd_256_headline_job_vs_oracle(kb, fdtd256):
     announce("fdtd 256^3 headline job: float32 oracle, 10,000 steps")
     ref, probe_ref = oracle.fdtd(oracle.fdtd_zero_fields(N, np.float32), N, steps, src=src, g=g32,
                                  dtype=np.float32)
-    announce("fdtd 256^3 headline job: GPU, variant 10, b = 100")
+    announce("fdtd 256^3 headline job: GPU, variant 10 depth 3, b = 101")
     with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, seed) as p:
         p.set_option(kb.OPT_TILE, 10)
-        p.set_option(kb.OPT_TDEPTH, 2)
-        p.run(steps, 100)
+        p.set_option(kb.OPT_TDEPTH, 3)
+        p.run(steps, 101)
         assert p.read(kb.F_STEP)[0] == steps
         probe = p.read(kb.F_PROBE)
         for k, fid in kb.FDTD_FIELDS.items():
@@ -204,16 +205,17 @@ def test_fdtd_256_headline_job_vs_oracle(kb, fdtd256):
 @gpu
 def test_fdtd_256_variant_switching(kb, fdtd256):
     """100 steps at 256^3 from random fields, switching kernels on the way:
-    the whole-row two-step kernels (one launch per iteration, the step
-    counter advanced by the grid's last block, the i = N column's Hx in
-    lane 63) per launch and in graph batches with an odd b, the fused step
-    in between (which copies the column's unchanging values) -- bit for bit
-    with the float32 oracle, probe and step counter included."""
+    the whole-row kernels of two and three steps per launch (one launch per
+    iteration, the step counter advanced by the grid's last block, the
+    i = N column's Hx in lane 63) per launch and in graph batches with an
+    odd b, the fused step in between (which copies the column's unchanging
+    values) -- bit for bit with the float32 oracle, probe and step counter
+    included."""
     d = fdtd256
     N, steps = d["N"], d["steps"]
-    plan = ((10, 2, 31, 5), (7, 1, 20, 0), (9, 2, 24, 0), (10, 2, 25, 3))   # variant, depth, steps, b
+    plan = ((10, 2, 31, 5), (7, 1, 20, 0), (10, 3, 14, 3), (9, 2, 24, 0), (10, 3, 11, 0))   # variant, depth, steps, b
     assert sum(n for _, _, n, _ in plan) == steps
-    announce("fdtd 256^3 rand fields, 100 steps switching 10 / 7 / 9 / 10")
+    announce("fdtd 256^3 rand fields, 100 steps switching 10 / 7 / 10 depth 3 / 9 / 10 depth 3")
     with kb.Problem(kb.FDTD3D, (N, 16384), kb.FDTD_COEFFS, d["seed"]) as p:
         for k, fid in kb.FDTD_FIELDS.items():
             p.write(fid, d["f0"][k])
@@ -221,7 +223,7 @@ def test_fdtd_256_variant_switching(kb, fdtd256):
         for v, t, n, b in plan:
             p.set_option(kb.OPT_TILE, v)
             p.set_option(kb.OPT_TDEPTH, t)
-            assert p.kernels_per_iter() == (1 if v >= 9 and t == 2 else 2)
+            assert p.kernels_per_iter() == (1 if v >= 9 and t >= 2 else 2)
             p.run(n, b)
             done += n
             assert p.read(kb.F_STEP)[0] == done

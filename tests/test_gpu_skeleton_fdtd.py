@@ -137,20 +137,21 @@ def test_fdtd_bitwise_vs_oracle(kb, N, steps, variant):
     assert np.all(probe[steps:] == 0)
 
 
-@pytest.mark.parametrize("variant", [8, 9, 10])
+@pytest.mark.parametrize("variant,depth", [(8, 2), (9, 2), (10, 2), (10, 3)])
 @pytest.mark.parametrize("N,steps", [(4, 61), (5, 60), (8, 150), (17, 121), (33, 40), (70, 23), (75, 100),
                                      (129, 12), (253, 6), (255, 7)])
-def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps, variant):
+def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps, variant, depth):
     """Variants 8, 9 and 10 with depth 2 (two steps per launch, temporal
-    blocking): from zero fields with the source on and from random fields
-    on every node, per launch and in graph batches (an odd step count ends
-    with one fused step), bit for bit with the float32 oracle, probe
-    included.  Variant 8: N = 70 and 75 span several tiles along i (60
-    nodes), j (13 rows) and k (plane segments).  Variants 9, 10 (whole rows, four
-    nodes per lane): N = 253 and 255 end the row inside and at the end of
-    lane 63 (row padding in the last vector, none), N = 129 at element 1 of
-    lane 32."""
-    announce(f"fdtd two-step variant {variant} N={N} steps={steps}")
+    blocking), and the whole rows with depth 3 (three steps per launch):
+    from zero fields with the source on and from random fields on every
+    node, per launch and in graph batches (a step count that is not a
+    multiple of the depth ends with fused steps), bit for bit with the
+    float32 oracle, probe included.  Variant 8: N = 70 and 75 span several
+    tiles along i (60 nodes), j (13 rows) and k (plane segments).  Variants
+    9, 10 (whole rows, four nodes per lane): N = 253 and 255 end the row
+    inside and at the end of lane 63 (row padding in the last vector,
+    none), N = 129 at element 1 of lane 32."""
+    announce(f"fdtd temporal blocking variant {variant} depth {depth} N={N} steps={steps}")
     seed = 36
     src = synth.fdtd_source_cell(seed, N)
     _, g32 = oracle.fdtd_pulse(steps + 1)
@@ -163,7 +164,7 @@ def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps, variant):
         for b in (0, 3):
             with kb.Problem(kb.FDTD3D, (N, 512), kb.FDTD_COEFFS, seed) as p:
                 p.set_option(kb.OPT_TILE, variant)
-                p.set_option(kb.OPT_TDEPTH, 2)
+                p.set_option(kb.OPT_TDEPTH, depth)
                 if start == "rand":
                     for k, fid in kb.FDTD_FIELDS.items():
                         p.write(fid, f0[k])
@@ -177,15 +178,25 @@ def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps, variant):
 
 
 def test_fdtd_two_step_depth_limits(kb):
-    """Depth 1 or 2 for the cavity; depth 1 of variant 8 is the fused step."""
+    """Depth 1..3 for the cavity; depth 1 of variant 8 is the fused step;
+    three steps per launch need the whole-row kernels (variant 8 refuses
+    to run them)."""
     with kb.Problem(kb.FDTD3D, (8, 64), kb.FDTD_COEFFS, 0) as p:
         p.set_option(kb.OPT_TILE, 8)
-        for bad in (0, 3):
+        for bad in (0, 4):
             with pytest.raises(kb.KBError):
                 p.set_option(kb.OPT_TDEPTH, bad)
+        p.set_option(kb.OPT_TDEPTH, 3)
+        with pytest.raises(kb.KBError):
+            p.run(6, 0)
         p.set_option(kb.OPT_TDEPTH, 1)
         p.run(6, 0)
         assert p.read(kb.F_STEP)[0] == 6
+        p.set_option(kb.OPT_TILE, 10)
+        p.set_option(kb.OPT_TDEPTH, 3)
+        assert p.kernels_per_iter() == 1
+        p.run(6, 0)
+        assert p.read(kb.F_STEP)[0] == 12
 
 
 @pytest.mark.parametrize("b", [1, 7, 40])
