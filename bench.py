@@ -868,6 +868,14 @@ def fdtd_headline(args, kb, autotune, np, torch):
         "effective_GB_s": effective, "effective_bytes_per_cell_step": FDTD_BYTES_PER_CELL_STEP,
         "effective_frac": effective / HBM_PEAK_GBS,
         "trace": stored_json(os.path.join(ROOT, "profiles", "fdtd_256_graph_trace.json"))}
+    # the three-step kernel also spends half its launch issuing vector
+    # instructions: the committed instruction counters (same kernel source)
+    # give the issue time per SIMD, set here against the live launch time
+    if name.startswith("fdtd_tb3_rows"):
+        sq = stored_json(os.path.join(ROOT, "profiles", "fdtd_256_tb3_rows_sq_counters.json"))
+        if sq and sq.get("kernel_source_sha") == fdtd_tb3_rows_kernel_hash():
+            out["roofline"]["valu_issue_us_per_simd"] = sq["valu_issue_us_per_simd"]
+            out["roofline"]["valu_issue_frac"] = sq["valu_issue_us_per_simd"] / (launch_s * 1e6)
     return out
 
 
