@@ -177,6 +177,39 @@ def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps, variant, depth):
             assert np.array_equal(probe[:steps], probe_ref), (start, b)
 
 
+@pytest.mark.parametrize("variant,depth", [(8, 2), (9, 2), (10, 2), (10, 3), (7, 1)])
+def test_fdtd_source_on_block_edges(kb, variant, depth):
+    """The source placed (coefficients i, j, k) on the rows and planes that
+    two blocks of the blocked kernels compute -- one as output, the other as
+    recomputed halo -- and at both ends of a row: the amplitude must enter
+    every copy and the probe be recorded once.  N = 33: the three-step
+    kernel's blocks output rows 7t..7t+6 and planes 9s..9s+8 (halo rows
+    7t-3..7t-1 and 7t+7, 7t+8, halo planes 9s-3..9s-1); the two-step
+    kernels' edges lie elsewhere among the same positions.  A short pulse
+    (width 5, delay 10) makes the source large over the 40 steps; bit for
+    bit with the float32 oracle, fields and probe, per launch and in graph
+    batches."""
+    N, steps = 33, 40
+    _, g32 = oracle.fdtd_pulse(steps + 1, width=5.0, delay=10.0)
+    cells = [(1, 6, 8), (32, 7, 9), (2, 8, 0), (16, 13, 17), (31, 14, 18), (5, 4, 26), (17, 32, 27), (32, 1, 32),
+             (9, 9, 6), (24, 20, 11)]
+    for src in cells:
+        announce(f"fdtd source on block edges variant {variant} depth {depth} src={src}")
+        ref, probe_ref = oracle.fdtd(oracle.fdtd_zero_fields(N, np.float32), N, steps, src=src, g=g32,
+                                     dtype=np.float32)
+        for b in (0, 3):
+            with kb.Problem(kb.FDTD3D, (N, 64), (0.5, 5.0, 10.0) + tuple(float(c) for c in src), 0) as p:
+                p.set_option(kb.OPT_TILE, variant)
+                p.set_option(kb.OPT_TDEPTH, depth)
+                p.run(steps, b)
+                got = gpu_fields(kb, p)
+                probe = p.read(kb.F_PROBE)
+            for k in oracle.FDTD_FIELDS:
+                assert np.array_equal(got[k], ref[k]), (src, b, k)
+            assert np.array_equal(probe[:steps], probe_ref), (src, b)
+            assert np.all(probe[steps:] == 0), (src, b)
+
+
 def test_fdtd_two_step_depth_limits(kb):
     """Depth 1..3 for the cavity; depth 1 of variant 8 is the fused step;
     three steps per launch need the whole-row kernels (variant 8 refuses
