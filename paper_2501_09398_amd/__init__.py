@@ -285,6 +285,16 @@ class Problem:
         _check(lib().kb_read(self._h, field, C.c_void_p(out.data_ptr()), out.numel() * out.element_size(), 1))
         return out
 
+    def write_device(self, field, src: torch.Tensor):
+        """Copy a contiguous device tensor of the field's byte size into a
+        field (synchronous; torch's queued work is finished first)."""
+        shp, dt = self.field_shape(field)
+        assert src.is_cuda and src.is_contiguous()
+        if src.numel() * src.element_size() != int(np.prod(shp)) * np.dtype(dt).itemsize:
+            raise KBError(EINVAL, f"field {field} needs {int(np.prod(shp)) * np.dtype(dt).itemsize} bytes")
+        torch.cuda.synchronize(self.device)
+        _check(lib().kb_write(self._h, field, C.c_void_p(src.data_ptr()), src.numel() * src.element_size(), 1))
+
     def write(self, field, values):
         shp, dt = self.field_shape(field)
         arr = np.ascontiguousarray(values, dtype=dt)

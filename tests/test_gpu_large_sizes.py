@@ -255,3 +255,46 @@ def test_fdtd_256_vs_oracle(kb, fdtd256, variant):
             for k, fid in kb.FDTD_FIELDS.items():
                 assert np.array_equal(p.read(fid), d[start][k]), (start, k)
         assert np.array_equal(probe[:steps], d["probe"] if start == "zero" else d["rprobe"])
+
+
+@gpu
+@pytest.mark.parametrize("variant,depth", [(7, 1), (5, 1), (2, 1), (8, 2)])
+def test_fdtd_largest_cavity_corners(kb, variant, depth):
+    """N = 1024, the largest cavity the library accepts (two field sets of
+    52 GB): seeded random fields on every node (drawn on the device), 6
+    steps, no source.  A node after s steps depends only on nodes within s
+    of it, so the two corner cubes of 25^3 nodes (one holding the walls at
+    0, the other the walls at N and the i = N column) are exact cavities of
+    N = 24 for the oracle away from their cut faces: every node farther
+    than s + 1 from a cut face is compared, bit for bit, with the float32
+    oracle run on the cube."""
+    import torch
+    N, steps, n = 1024, 6, 24
+    M = N + 1
+    announce(f"fdtd N=1024 corners, variant {variant} depth {depth}, {steps} steps")
+    gen = torch.Generator(device="cuda").manual_seed(1000 + variant)
+    lo, hi = {}, {}
+    with kb.Problem(kb.FDTD3D, (N, 16), (0.5, 0.0, 80.0), 0) as p:   # width 0: no source
+        p.set_option(kb.OPT_TILE, variant)
+        p.set_option(kb.OPT_TDEPTH, depth)
+        buf = torch.empty((M, M, M), dtype=torch.float32, device=p.device)
+        for k, fid in kb.FDTD_FIELDS.items():
+            buf.uniform_(-1.0, 1.0, generator=gen)
+            p.write_device(fid, buf)
+            lo[k] = buf[:n + 1, :n + 1, :n + 1].cpu().numpy()
+            hi[k] = buf[N - n:, N - n:, N - n:].cpu().numpy()
+        p.run(steps, 0)
+        assert p.read(kb.F_STEP)[0] == steps
+        got_lo, got_hi = {}, {}
+        for k, fid in kb.FDTD_FIELDS.items():
+            p.read_device(fid, buf)
+            got_lo[k] = buf[:n + 1, :n + 1, :n + 1].cpu().numpy()
+            got_hi[k] = buf[N - n:, N - n:, N - n:].cpu().numpy()
+        del buf
+    ref_lo, _ = oracle.fdtd(lo, n, steps, dtype=np.float32)
+    ref_hi, _ = oracle.fdtd(hi, n, steps, dtype=np.float32)
+    a, b = n - steps - 1, steps + 2          # exact: index < a (low cube), >= b (high cube)
+    for k in oracle.FDTD_FIELDS:
+        assert np.array_equal(got_lo[k][:a, :a, :a], ref_lo[k][:a, :a, :a]), ("low corner", k)
+        assert np.array_equal(got_hi[k][b:, b:, b:], ref_hi[k][b:, b:, b:]), ("high corner", k)
+        assert not np.array_equal(got_lo[k], lo[k]) and not np.array_equal(got_hi[k], hi[k]), k   # they moved
