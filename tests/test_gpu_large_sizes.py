@@ -257,6 +257,62 @@ def test_fdtd_256_vs_oracle(kb, fdtd256, variant):
         assert np.array_equal(probe[:steps], d["probe"] if start == "zero" else d["rprobe"])
 
 
+
+@gpu
+def test_largest_grids(kb):
+    """The largest grids the library accepts (at most 2^31 - 1 cells): heat2d
+    32767 x 65536 and heat3d 2 x 32767 x 32768 (8 GiB per field; the
+    default one-step kernels, variants 13 and 9), 3 steps, row bands at the
+    top, middle and bottom edges against the float32 oracle on the band plus
+    a halo; the skeleton vector of 2^31 - 1 elements (four per thread and a
+    tail of three), 3 iterations, its first and last 4096 elements bit for
+    bit with the oracle's chain.  Fields come back through a device tensor,
+    the compared rows alone to the host."""
+    import torch
+    steps = 3
+    ny, nx, seed = 32767, 65536, 5
+    announce("heat2d 32767 x 65536, variant 13, 3 steps")
+    with kb.Problem(kb.HEAT2D, (ny, nx), HEAT, seed) as p:
+        p.set_option(kb.OPT_TILE, 13)
+        p.run(steps, 0)
+        buf = torch.empty((ny, nx), dtype=torch.float32, device=p.device)
+        p.read_device(kb.F_T, buf)
+        bands = {ab: buf[ab[0]:ab[1]].cpu().numpy() for ab in band_rows(ny, steps)}
+        del buf
+    for (a, b), got in bands.items():
+        lo, hi = max(0, a - steps - 1), min(ny, b + steps + 1)
+        T0, P = band_inputs_2d(seed, ny, nx, lo, hi)
+        e = rel_maxnorm(got, oracle.heat2d(T0, P, steps, dtype=np.float32)[a - lo:b - lo])
+        print(f"heat2d rows {a}..{b}: vs float32 oracle {e:.2e}")
+        assert e < 1e-5, (a, b)
+    nz, ny, nx, seed = 2, 32767, 32768, 6
+    announce("heat3d 2 x 32767 x 32768, variant 9, 3 steps")
+    with kb.Problem(kb.HEAT3D, (nz, ny, nx), HEAT, seed) as p:
+        p.set_option(kb.OPT_TILE, 9)
+        p.run(steps, 0)
+        buf = torch.empty((nz, ny, nx), dtype=torch.float32, device=p.device)
+        p.read_device(kb.F_T, buf)
+        bands = {ab: buf[:, ab[0]:ab[1]].cpu().numpy() for ab in band_rows(ny, steps)}
+        del buf
+    for (a, b), got in bands.items():
+        lo, hi = max(0, a - steps - 1), min(ny, b + steps + 1)
+        T0, P = band_inputs_3d(seed, nz, ny, nx, lo, hi)
+        e = rel_maxnorm(got, oracle.heat3d(T0, P, steps, dtype=np.float32)[:, a - lo:b - lo])
+        print(f"heat3d rows {a}..{b}: vs float32 oracle {e:.2e}")
+        assert e < 1e-5, (a, b)
+    n, seed, m = (1 << 31) - 1, 7, 4096
+    announce("skeleton 2^31 - 1 elements, K = 4, 3 iterations")
+    with kb.Problem(kb.SKELETON, (n,), (4,), seed) as p:
+        p.run(steps, 0)
+        a_k, b_k = p.read(kb.F_A), p.read(kb.F_B)
+        buf = torch.empty(n, dtype=torch.float32, device=p.device)
+        p.read_device(kb.F_X, buf)
+        head, tail = buf[:m].cpu().numpy(), buf[n - m:].cpu().numpy()
+        del buf
+    for got, off in ((head, 0), (tail, n - m)):
+        x0 = synth.uniform_f32(seed, synth.TAG_X0, m, *synth.X0_RANGE, offset=off)
+        assert np.array_equal(got, oracle.skeleton(x0, a_k, b_k, steps, dtype=np.float32)), off
+
 @gpu
 @pytest.mark.parametrize("variant,depth", [(7, 1), (5, 1), (2, 1), (8, 2)])
 def test_fdtd_largest_cavity_corners(kb, variant, depth):
