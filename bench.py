@@ -834,7 +834,7 @@ def fdtd_headline(args, kb, autotune, np, torch):
     eff = variant or (7 if N >= 176 else 5)          # the default fused variant for the size
     blocked = eff >= 8 and depth in (2, 3)            # two or three steps per launch
     if blocked and depth == 3:
-        name = "fdtd_tb3_rows_kernel<true,true>"
+        name = "fdtd_tb3_rows_kernel<true,true,4>"
     elif blocked:
         name = {8: "fdtd_tb2_kernel<true>", 9: "fdtd_tb2_rows_kernel<true,16,false,true>",
                 10: "fdtd_tb2_rows_kernel<true,12,true,true>"}[eff]

@@ -1108,6 +1108,29 @@ bool make_fdtd_tb2_rows(Launch &L, const FdtdTbArgs &a0, bool nt, int form) {
   return true;
 }
 
+// Two nodes per lane (rows of up to 129 nodes fill the wave): the same
+// accesses and lane shifts as Q4 with 8-byte loads, stores and LDS slots.
+struct Q2 {
+  float v[2];
+};
+typedef float V2f __attribute__((ext_vector_type(2)));
+typedef unsigned V2u __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ Q2 qeast(const Q2 &a, bool last, float ext) {
+  float t = lane_east_open(a.v[0]);
+  if (last) t = ext;
+  return Q2{{a.v[1], t}};
+}
+__device__ __forceinline__ Q2 qwest(const Q2 &a) { return Q2{{lane_west_open(a.v[1]), a.v[0]}}; }
+__device__ __forceinline__ Q4 qeast(const Q4 &a, bool last, float ext) { return q4east(a, last, ext); }
+__device__ __forceinline__ Q4 qwest(const Q4 &a) { return q4west(a); }
+__device__ __forceinline__ float2 ldsof(const Q2 &a) { return make_float2(a.v[0], a.v[1]); }
+__device__ __forceinline__ float4 ldsof(const Q4 &a) { return f4of(a); }
+__device__ __forceinline__ Q2 qof(const float2 &a) { return Q2{{a.x, a.y}}; }
+__device__ __forceinline__ Q4 qof(const float4 &a) { return q4of(a); }
+template <int NPL> struct QT;
+template <> struct QT<4> { typedef Q4 type; typedef float4 lds; };
+template <> struct QT<2> { typedef Q2 type; typedef float2 lds; };
+
 // ---------------------------------------------------------------------------
 // Three steps per launch over whole rows (variants 9 and 10 with depth 3,
 // N <= 256).  The two-step kernel's march with a third pair of phases: per
@@ -1143,15 +1166,37 @@ __device__ __forceinline__ void q4st_f(__amdgpu_buffer_rsrc_t r, unsigned ob, in
   const V4f v = {a.v[0], a.v[1], a.v[2], a.v[3]};
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4u, v), r, ob, fo, NT ? 2 : 0);
 }
+template <bool NT>
+__device__ __forceinline__ void qst_f(__amdgpu_buffer_rsrc_t r, unsigned ob, int fo, const Q4 &a) {
+  q4st_f<NT>(r, ob, fo, a);
+}
+template <bool NT>
+__device__ __forceinline__ void qst_f(__amdgpu_buffer_rsrc_t r, unsigned ob, int fo, const Q2 &a) {
+  const V2f v = {a.v[0], a.v[1]};
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2u, v), r, ob, fo, NT ? 2 : 0);
+}
+template <int NPL>
+__device__ __forceinline__ typename QT<NPL>::type qld_f(__amdgpu_buffer_rsrc_t r, unsigned ob, int fo) {
+  if constexpr (NPL == 4) {
+    return q4ld_f(r, ob, fo);
+  } else {
+    const V2f a = __builtin_bit_cast(V2f, __builtin_amdgcn_raw_buffer_load_b64(r, ob, fo, 0));
+    return Q2{{a.x, a.y}};
+  }
+}
 
-template <bool NT, bool FR>
+// NPL nodes per lane: 4 (rows up to 257 nodes), 2 (up to 129); FR: the row
+// is exactly 64 * NPL + 1 nodes (the per-node conditions fold away)
+template <bool NT, bool FR, int NPL>
 __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) {
   constexpr int kNW = 12, kTJ = kNW - 5;
-  __shared__ float4 sH1[2][kNW][64];   // H^{n+1/2} x, z of plane m
-  __shared__ float4 sE1[2][kNW][64];   // E^{n+1} x, z of plane m-1 (until C), then m
-  __shared__ float4 sH2[2][kNW][64];   // H^{n+3/2} x, z of plane m-1
-  __shared__ float4 sE2[2][kNW][64];   // E^{n+2} x, z of plane m-2 (until E), then m-1
-  __shared__ float4 sH3[2][kNW][64];   // H^{n+5/2} x, z of plane m-2
+  typedef typename QT<NPL>::type Q;            // a lane's NPL nodes of a row
+  typedef typename QT<NPL>::lds LT;
+  __shared__ LT sH1[2][kNW][64];   // H^{n+1/2} x, z of plane m
+  __shared__ LT sE1[2][kNW][64];   // E^{n+1} x, z of plane m-1 (until C), then m
+  __shared__ LT sH2[2][kNW][64];   // H^{n+3/2} x, z of plane m-1
+  __shared__ LT sE2[2][kNW][64];   // E^{n+2} x, z of plane m-2 (until E), then m-1
+  __shared__ LT sH3[2][kNW][64];   // H^{n+5/2} x, z of plane m-2
   __shared__ float sEzN[kNW];          // E_z at i = N of each row, current plane
   const int nb = a.nj * a.nk;
   const int lb = xcd_logical_block(nb);
@@ -1170,7 +1215,7 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
   const int tj = lb % a.nj, tkk = lb / a.nj;
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int N = a.N, M = N + 1;
-  const int i0 = 4 * lane;
+  const int i0 = NPL * lane;
   const int j = tj * kTJ - 3 + w;
   const int kb = tkk * a.tk, ke = min(kb + a.tk, M);   // output planes [kb, ke)
   const bool jv = j >= 0 && j <= N;
@@ -1183,7 +1228,7 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
   auto iN = [&](int e) { return FR || i0 + e <= N; };
   auto ilt = [&](int e) { return FR || i0 + e < N; };
   auto ii = [&](int e) { return FR ? (e > 0 || lane > 0) : (i0 + e >= 1) & (i0 + e <= N - 1); };
-  const bool srow = j == a.sj && a.si >= i0 && a.si < i0 + 4;
+  const bool srow = j == a.sj && a.si >= i0 && a.si < i0 + NPL;
   const int wm = w > 0 ? w - 1 : 0, wp = w < kNW - 1 ? w + 1 : kNW - 1;
   const size_t sk = (size_t)M * a.P;
   const unsigned pbytes = (unsigned)(M * a.P * 4);
@@ -1200,16 +1245,16 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
   const long long n = *a.step;
   const bool add0 = n >= 0 && n < a.glen, add1 = n + 1 >= 0 && n + 1 < a.glen, add2 = n + 2 >= 0 && n + 2 < a.glen;
   const float g0 = add0 ? a.g[n] : 0.f, g1 = add1 ? a.g[n + 1] : 0.f, g2 = add2 ? a.g[n + 2] : 0.f;
-  const Q4 z4{{0.f, 0.f, 0.f, 0.f}};
-  auto ld = [&](int f, int k) -> Q4 { return q4ld_f(pin(k), ob, f * fs); };
-  auto ldj = [&](int f, int k) -> Q4 { return q4ld_f(pin(k), obj, f * fs); };   // row j+1
+  const Q z4{};
+  auto ld = [&](int f, int k) -> Q { return qld_f<NPL>(pin(k), ob, f * fs); };
+  auto ldj = [&](int f, int k) -> Q { return qld_f<NPL>(pin(k), obj, f * fs); };   // row j+1
   auto ldN = [&](int f, int k) -> float { return f1ld_f(pin(k), obN, f * fs); };
   // the source node's E_z after an E update: add the amplitude; the block
   // that outputs plane k records the probe
-  auto source = [&](Q4 &ez_new, int k, bool add, float g, long long t) {
+  auto source = [&](Q &ez_new, int k, bool add, float g, long long t) {
     if (k == a.sk) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int e = 0; e < NPL; ++e)
         if (srow && i0 + e == a.si) {
           if (add) ez_new.v[e] = ez_new.v[e] + g;
           if (out && k >= kb && k < ke && t >= 0 && t < a.pcap) a.probe[t] = ez_new.v[e];
@@ -1218,29 +1263,29 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
   };
 
   const int m0 = max(kb - 3, 0);
-  Q4 ex = ld(kEx, m0), ey = ld(kEy, m0), ez = ld(kEz, m0);   // E^n of plane m
+  Q ex = ld(kEx, m0), ey = ld(kEy, m0), ez = ld(kEz, m0);   // E^n of plane m
   float eyN = ldN(kEy, m0), ezN = ldN(kEz, m0);               // E at i = N: plane m,
   float eyN_p = 0.f, ezN_p = 0.f, eyN_pp = 0.f, ezN_pp = 0.f;   // m-1, m-2
-  Q4 h1x_p = z4, h1y_p = z4, h1z_p = z4;       // H^{n+1/2} of plane m-1
-  Q4 e1y_p = z4;                               // E^{n+1}_y of plane m-1 (x, z: in sE1)
-  Q4 h2x_p = z4, h2y_p = z4, h2z_p = z4;       // H^{n+3/2} of plane m-2
-  Q4 e2y_p = z4;                               // E^{n+2}_y of plane m-2 (x, z: in sE2)
-  Q4 h3x_p = z4, h3y_p = z4;                   // H^{n+5/2} of plane m-3
+  Q h1x_p = z4, h1y_p = z4, h1z_p = z4;       // H^{n+1/2} of plane m-1
+  Q e1y_p = z4;                               // E^{n+1}_y of plane m-1 (x, z: in sE1)
+  Q h2x_p = z4, h2y_p = z4, h2z_p = z4;       // H^{n+3/2} of plane m-2
+  Q e2y_p = z4;                               // E^{n+2}_y of plane m-2 (x, z: in sE2)
+  Q h3x_p = z4, h3y_p = z4;                   // H^{n+5/2} of plane m-3
   // E^n of plane m+1, row j+1 of E^n and H of plane m, loaded one iteration ahead
-  Q4 pexk = ld(kEx, m0 + 1), peyk = ld(kEy, m0 + 1), pezk = ld(kEz, m0 + 1);
-  Q4 pex_j = ldj(kEx, m0), pez_j = ldj(kEz, m0);
-  Q4 phx = ld(kHx, m0), phy = ld(kHy, m0), phz = ld(kHz, m0);
+  Q pexk = ld(kEx, m0 + 1), peyk = ld(kEy, m0 + 1), pezk = ld(kEz, m0 + 1);
+  Q pex_j = ldj(kEx, m0), pez_j = ldj(kEz, m0);
+  Q phx = ld(kHx, m0), phy = ld(kHy, m0), phz = ld(kHz, m0);
   float peyNk = ldN(kEy, m0 + 1), pezNk = ldN(kEz, m0 + 1), phxN = ldN(kHx, m0);
   for (int m = m0; m <= ke + 1; ++m) {
     const bool pm = m <= N;
-    const Q4 exk = pexk, eyk = peyk, ezk = pezk, ex_j = pex_j, ez_j = pez_j, hx = phx, hy = phy, hz = phz;
+    const Q exk = pexk, eyk = peyk, ezk = pezk, ex_j = pex_j, ez_j = pez_j, hx = phx, hy = phy, hz = phz;
     const float eyNk = peyNk, ezNk = pezNk, hxN = phxN;
     // ---- A: H^{n+1/2} of plane m
     const bool mlt = m < N;
-    const Q4 ey_e = q4east(ey, last, eyN), ez_e = q4east(ez, last, ezN);
-    Q4 h1x, h1y, h1z;
+    const Q ey_e = qeast(ey, last, eyN), ez_e = qeast(ez, last, ezN);
+    Q h1x, h1y, h1z;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < NPL; ++e) {
       const float ux = hx.v[e] - dt * ((ez_j.v[e] - ez.v[e]) - (eyk.v[e] - ey.v[e]));
       const float uy = hy.v[e] - dt * ((exk.v[e] - ex.v[e]) - (ez_e.v[e] - ez.v[e]));
       const float uz = hz.v[e] - dt * ((ey_e.v[e] - ey.v[e]) - (ex_j.v[e] - ex.v[e]));
@@ -1248,8 +1293,8 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
       h1y.v[e] = (ilt(e) & mlt) ? uy : hy.v[e];
       h1z.v[e] = (ilt(e) & jlt) ? uz : hz.v[e];
     }
-    sH1[0][w][lane] = f4of(h1x);
-    sH1[1][w][lane] = f4of(h1z);
+    sH1[0][w][lane] = ldsof(h1x);
+    sH1[1][w][lane] = ldsof(h1z);
     if (last) sEzN[w] = ezN;
     __syncthreads();                                         // ---- barrier 1
     {   // Hx at i = N of plane m: three updates with the column's unchanging E
@@ -1261,12 +1306,12 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
       f1st_f(pout(m), o, kHx * fs, h);
     }
     // ---- B: E^{n+1} of plane m
-    const Q4 h1x_jm = q4of(sH1[0][wm][lane]), h1z_jm = q4of(sH1[1][wm][lane]);
-    const Q4 h1z_w = q4west(h1z), h1y_w = q4west(h1y);
+    const Q h1x_jm = qof(sH1[0][wm][lane]), h1z_jm = qof(sH1[1][wm][lane]);
+    const Q h1z_w = qwest(h1z), h1y_w = qwest(h1y);
     const bool kk = m >= 1 && m <= N - 1;
-    Q4 e1x, e1y, e1z;
+    Q e1x, e1y, e1z;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < NPL; ++e) {
       const float ux = ex.v[e] + dt * ((h1z.v[e] - h1z_jm.v[e]) - (h1y.v[e] - h1y_p.v[e]));
       const float uy = ey.v[e] + dt * ((h1x.v[e] - h1x_p.v[e]) - (h1z.v[e] - h1z_w.v[e]));
       const float uz = ez.v[e] + dt * ((h1y.v[e] - h1y_w.v[e]) - (h1x.v[e] - h1x_jm.v[e]));
@@ -1279,15 +1324,15 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
     // ---- C: H^{n+3/2} of plane q = m-1 (E^{n+1} of row j+1, plane q, in sE1)
     const int q = m - 1;
     const bool doC = q >= 0 && q >= kb - 2 && q <= ke;
-    Q4 h2x = z4, h2y = z4, h2z = z4;
+    Q h2x = z4, h2y = z4, h2z = z4;
     // E^{n+1} x, z of plane q: this row's from sE1 (held there until barrier 3)
-    const Q4 e1x_p = q4of(sE1[0][w][lane]), e1z_p = q4of(sE1[1][w][lane]);
+    const Q e1x_p = qof(sE1[0][w][lane]), e1z_p = qof(sE1[1][w][lane]);
     if (doC) {
-      const Q4 e1x_jq = q4of(sE1[0][wp][lane]), e1z_jq = q4of(sE1[1][wp][lane]);
-      const Q4 e1z_e = q4east(e1z_p, last, ezN_p), e1y_e = q4east(e1y_p, last, eyN_p);
+      const Q e1x_jq = qof(sE1[0][wp][lane]), e1z_jq = qof(sE1[1][wp][lane]);
+      const Q e1z_e = qeast(e1z_p, last, ezN_p), e1y_e = qeast(e1y_p, last, eyN_p);
       const bool qlt = q < N;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < NPL; ++e) {
         const float ux = h1x_p.v[e] - dt * ((e1z_jq.v[e] - e1z_p.v[e]) - (e1y.v[e] - e1y_p.v[e]));
         const float uy = h1y_p.v[e] - dt * ((e1x.v[e] - e1x_p.v[e]) - (e1z_e.v[e] - e1z_p.v[e]));
         const float uz = h1z_p.v[e] - dt * ((e1y_e.v[e] - e1y_p.v[e]) - (e1x_jq.v[e] - e1x_p.v[e]));
@@ -1296,8 +1341,8 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
         h2z.v[e] = (ilt(e) & jlt) ? uz : h1z_p.v[e];
       }
     }
-    sH2[0][w][lane] = f4of(h2x);
-    sH2[1][w][lane] = f4of(h2z);
+    sH2[0][w][lane] = ldsof(h2x);
+    sH2[1][w][lane] = ldsof(h2z);
     __syncthreads();                                         // ---- barrier 2
     // the next plane's operands, issued here (half an iteration ahead) to
     // keep their registers free during A-C
@@ -1306,13 +1351,13 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
     phx = ld(kHx, m + 1); phy = ld(kHy, m + 1); phz = ld(kHz, m + 1);
     peyNk = ldN(kEy, m + 2); pezNk = ldN(kEz, m + 2); phxN = ldN(kHx, m + 1);
     // ---- D: E^{n+2} of plane q
-    Q4 e2x = z4, e2y = z4, e2z = z4;
+    Q e2x = z4, e2y = z4, e2z = z4;
     if (doC && q <= N) {
-      const Q4 h2x_jm = q4of(sH2[0][wm][lane]), h2z_jm = q4of(sH2[1][wm][lane]);
-      const Q4 h2z_w = q4west(h2z), h2y_w = q4west(h2y);
+      const Q h2x_jm = qof(sH2[0][wm][lane]), h2z_jm = qof(sH2[1][wm][lane]);
+      const Q h2z_w = qwest(h2z), h2y_w = qwest(h2y);
       const bool kq = q >= 1 && q <= N - 1;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < NPL; ++e) {
         const float ux = e1x_p.v[e] + dt * ((h2z.v[e] - h2z_jm.v[e]) - (h2y.v[e] - h2y_p.v[e]));
         const float uy = e1y_p.v[e] + dt * ((h2x.v[e] - h2x_p.v[e]) - (h2z.v[e] - h2z_w.v[e]));
         const float uz = e1z_p.v[e] + dt * ((h2y.v[e] - h2y_w.v[e]) - (h2x.v[e] - h2x_jm.v[e]));
@@ -1325,15 +1370,15 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
     // ---- E: H^{n+5/2} of plane r = m-2 (E^{n+2} of row j+1, plane r, in sE2)
     const int r = m - 2;
     const bool doE = r >= 0 && r >= kb - 1 && r <= ke - 1;
-    Q4 h3x = z4, h3y = z4, h3z = z4;
+    Q h3x = z4, h3y = z4, h3z = z4;
     // E^{n+2} x, z of plane r: this row's from sE2 (held there until the end)
-    const Q4 e2x_p = q4of(sE2[0][w][lane]), e2z_p = q4of(sE2[1][w][lane]);
+    const Q e2x_p = qof(sE2[0][w][lane]), e2z_p = qof(sE2[1][w][lane]);
     if (doE) {
-      const Q4 e2x_jr = q4of(sE2[0][wp][lane]), e2z_jr = q4of(sE2[1][wp][lane]);
-      const Q4 e2z_e = q4east(e2z_p, last, ezN_pp), e2y_e = q4east(e2y_p, last, eyN_pp);
+      const Q e2x_jr = qof(sE2[0][wp][lane]), e2z_jr = qof(sE2[1][wp][lane]);
+      const Q e2z_e = qeast(e2z_p, last, ezN_pp), e2y_e = qeast(e2y_p, last, eyN_pp);
       const bool rlt = r < N;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < NPL; ++e) {
         const float ux = h2x_p.v[e] - dt * ((e2z_jr.v[e] - e2z_p.v[e]) - (e2y.v[e] - e2y_p.v[e]));
         const float uy = h2y_p.v[e] - dt * ((e2x.v[e] - e2x_p.v[e]) - (e2z_e.v[e] - e2z_p.v[e]));
         const float uz = h2z_p.v[e] - dt * ((e2y_e.v[e] - e2y_p.v[e]) - (e2x_jr.v[e] - e2x_p.v[e]));
@@ -1342,19 +1387,19 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
         h3z.v[e] = (ilt(e) & jlt) ? uz : h2z_p.v[e];
       }
     }
-    sH3[0][w][lane] = f4of(h3x);
-    sH3[1][w][lane] = f4of(h3z);
+    sH3[0][w][lane] = ldsof(h3x);
+    sH3[1][w][lane] = ldsof(h3z);
     __syncthreads();                                         // ---- barrier 3
-    sE1[0][w][lane] = f4of(e1x);                             // plane m: C, D of m+1
-    sE1[1][w][lane] = f4of(e1z);
+    sE1[0][w][lane] = ldsof(e1x);                             // plane m: C, D of m+1
+    sE1[1][w][lane] = ldsof(e1z);
     // ---- F: E^{n+3} of plane r, and the outputs of plane r
     if (r >= kb && r <= ke - 1) {
-      const Q4 h3x_jm = q4of(sH3[0][wm][lane]), h3z_jm = q4of(sH3[1][wm][lane]);
-      const Q4 h3z_w = q4west(h3z), h3y_w = q4west(h3y);
+      const Q h3x_jm = qof(sH3[0][wm][lane]), h3z_jm = qof(sH3[1][wm][lane]);
+      const Q h3z_w = qwest(h3z), h3y_w = qwest(h3y);
       const bool kr = r >= 1 && r <= N - 1;
-      Q4 e3x, e3y, e3z;
+      Q e3x, e3y, e3z;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < NPL; ++e) {
         const float ux = e2x_p.v[e] + dt * ((h3z.v[e] - h3z_jm.v[e]) - (h3y.v[e] - h3y_p.v[e]));
         const float uy = e2y_p.v[e] + dt * ((h3x.v[e] - h3x_p.v[e]) - (h3z.v[e] - h3z_w.v[e]));
         const float uz = e2z_p.v[e] + dt * ((h3y.v[e] - h3y_w.v[e]) - (h3x.v[e] - h3x_jm.v[e]));
@@ -1365,15 +1410,15 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
       source(e3z, r, add2, g2, n + 2);
       const unsigned o = out ? ob : kOff;
       const __amdgpu_buffer_rsrc_t po = pout(r);
-      q4st_f<NT>(po, o, kEx * fs, e3x);
-      q4st_f<NT>(po, o, kEy * fs, e3y);
-      q4st_f<NT>(po, o, kEz * fs, e3z);
-      q4st_f<NT>(po, o, kHx * fs, h3x);
-      q4st_f<NT>(po, o, kHy * fs, h3y);
-      q4st_f<NT>(po, o, kHz * fs, h3z);
+      qst_f<NT>(po, o, kEx * fs, e3x);
+      qst_f<NT>(po, o, kEy * fs, e3y);
+      qst_f<NT>(po, o, kEz * fs, e3z);
+      qst_f<NT>(po, o, kHx * fs, h3x);
+      qst_f<NT>(po, o, kHy * fs, h3y);
+      qst_f<NT>(po, o, kHz * fs, h3z);
     }
-    sE2[0][w][lane] = f4of(e2x);                             // plane q: E, F of m+1
-    sE2[1][w][lane] = f4of(e2z);
+    sE2[0][w][lane] = ldsof(e2x);                             // plane q: E, F of m+1
+    sE2[1][w][lane] = ldsof(e2z);
     // ---- rotate: plane m becomes the previous plane
     h3x_p = h3x; h3y_p = h3y;
     h2x_p = h2x; h2y_p = h2y; h2z_p = h2z;
@@ -1404,9 +1449,18 @@ bool make_fdtd_tb3_rows(Launch &L, const FdtdTbArgs &a0, bool nt) {
   a.tk = (M + a.nk - 1) / a.nk;
   a.nk = (M + a.tk - 1) / a.tk;
   const int nb = a.nj * a.nk;
-  const bool fr = a.N == 4 * 64;
-  const void *f = fr ? (nt ? (const void *)fdtd_tb3_rows_kernel<true, true> : (const void *)fdtd_tb3_rows_kernel<false, true>)
-                     : (nt ? (const void *)fdtd_tb3_rows_kernel<true, false> : (const void *)fdtd_tb3_rows_kernel<false, false>);
+  // two nodes per lane up to N = 128 (a row of 129 nodes fills the wave),
+  // four above
+  const void *f;
+  if (a.N <= 2 * 64) {
+    const bool fr = a.N == 2 * 64;
+    f = fr ? (nt ? (const void *)fdtd_tb3_rows_kernel<true, true, 2> : (const void *)fdtd_tb3_rows_kernel<false, true, 2>)
+           : (nt ? (const void *)fdtd_tb3_rows_kernel<true, false, 2> : (const void *)fdtd_tb3_rows_kernel<false, false, 2>);
+  } else {
+    const bool fr = a.N == 4 * 64;
+    f = fr ? (nt ? (const void *)fdtd_tb3_rows_kernel<true, true, 4> : (const void *)fdtd_tb3_rows_kernel<false, true, 4>)
+           : (nt ? (const void *)fdtd_tb3_rows_kernel<true, false, 4> : (const void *)fdtd_tb3_rows_kernel<false, false, 4>);
+  }
   L.set(f, dim3((unsigned)xcd_padded_grid(nb)), dim3(64 * nw), 0, a);
   return true;
 }

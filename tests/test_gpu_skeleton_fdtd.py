@@ -139,7 +139,7 @@ def test_fdtd_bitwise_vs_oracle(kb, N, steps, variant):
 
 @pytest.mark.parametrize("variant,depth", [(8, 2), (9, 2), (10, 2), (10, 3)])
 @pytest.mark.parametrize("N,steps", [(4, 61), (5, 60), (8, 150), (17, 121), (33, 40), (70, 23), (75, 100),
-                                     (129, 12), (253, 6), (255, 7)])
+                                     (127, 9), (128, 13), (129, 12), (253, 6), (255, 7)])
 def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps, variant, depth):
     """Variants 8, 9 and 10 with depth 2 (two steps per launch, temporal
     blocking), and the whole rows with depth 3 (three steps per launch):
@@ -150,7 +150,10 @@ def test_fdtd_two_step_kernel_vs_oracle(kb, N, steps, variant, depth):
     tiles along i (60 nodes), j (13 rows) and k (plane segments).  Variants
     9, 10 (whole rows, four nodes per lane): N = 253 and 255 end the row
     inside and at the end of lane 63 (row padding in the last vector,
-    none), N = 129 at element 1 of lane 32."""
+    none), N = 129 at element 1 of lane 32.  The three-step kernel keeps two
+    nodes per lane up to N = 128: N = 128 fills the wave exactly (the i = N
+    column in lane 63), N = 127 ends inside lane 63, the smaller sizes in
+    earlier lanes."""
     announce(f"fdtd temporal blocking variant {variant} depth {depth} N={N} steps={steps}")
     seed = 36
     src = synth.fdtd_source_cell(seed, N)
