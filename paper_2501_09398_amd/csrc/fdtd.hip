@@ -1140,7 +1140,11 @@ template <> struct QT<2> { typedef Q2 type; typedef float2 lds; };
 // pass through LDS; a new E row is written after the barrier that follows
 // the reads of the previous plane's row, so each array holds one plane.
 // Three rows below and two above the output rows, and three planes below
-// each segment, are recomputed: 12 waves (rows) give 7 output rows.  Each
+// each segment, are recomputed: 12 waves (rows) give 7 output rows.  A
+// recomputed row runs only the phases whose results an output row depends
+// on (rows w in [3, 10) output; F needs E on [2, 10), which needs D on
+// [2, 11), C on [1, 11), B on [1, 12) and A everywhere), so the outermost
+// rows skip the later phases and their LDS writes.  Each
 // layer of the march reads and writes what the two-step kernel's does, for
 // three steps instead of two.  The i = N column's Hx (N = 256) takes its
 // three updates in lane 63; the last block advances the step counter by 3.
@@ -1225,6 +1229,8 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
   const bool jj = j >= 1 && j <= N - 1, jlt = j < N;
   const bool last = lane == 63;
   const bool xn = FR && last && jv;
+  // the rows (waves) that run phases B, C, D and E; F runs on the output rows
+  const bool wB = w >= 1, wC = w >= 1 && w < kTJ + 4, wD = w >= 2 && w < kTJ + 4, wE = w >= 2 && w < kTJ + 3;
   auto iN = [&](int e) { return FR || i0 + e <= N; };
   auto ilt = [&](int e) { return FR || i0 + e < N; };
   auto ii = [&](int e) { return FR ? (e > 0 || lane > 0) : (i0 + e >= 1) & (i0 + e <= N - 1); };
@@ -1306,24 +1312,25 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
       f1st_f(pout(m), o, kHx * fs, h);
     }
     // ---- B: E^{n+1} of plane m
-    const Q h1x_jm = qof(sH1[0][wm][lane]), h1z_jm = qof(sH1[1][wm][lane]);
-    const Q h1z_w = qwest(h1z), h1y_w = qwest(h1y);
-    const bool kk = m >= 1 && m <= N - 1;
-    Q e1x, e1y, e1z;
+    Q e1x = z4, e1y = z4, e1z = z4;
+    if (wB && pm) {
+      const Q h1x_jm = qof(sH1[0][wm][lane]), h1z_jm = qof(sH1[1][wm][lane]);
+      const Q h1z_w = qwest(h1z), h1y_w = qwest(h1y);
+      const bool kk = m >= 1 && m <= N - 1;
 #pragma unroll
-    for (int e = 0; e < NPL; ++e) {
-      const float ux = ex.v[e] + dt * ((h1z.v[e] - h1z_jm.v[e]) - (h1y.v[e] - h1y_p.v[e]));
-      const float uy = ey.v[e] + dt * ((h1x.v[e] - h1x_p.v[e]) - (h1z.v[e] - h1z_w.v[e]));
-      const float uz = ez.v[e] + dt * ((h1y.v[e] - h1y_w.v[e]) - (h1x.v[e] - h1x_jm.v[e]));
-      e1x.v[e] = (ilt(e) & jj & kk) ? ux : ex.v[e];
-      e1y.v[e] = (jlt & ii(e) & kk) ? uy : ey.v[e];
-      e1z.v[e] = (mlt & ii(e) & jj) ? uz : ez.v[e];
+      for (int e = 0; e < NPL; ++e) {
+        const float ux = ex.v[e] + dt * ((h1z.v[e] - h1z_jm.v[e]) - (h1y.v[e] - h1y_p.v[e]));
+        const float uy = ey.v[e] + dt * ((h1x.v[e] - h1x_p.v[e]) - (h1z.v[e] - h1z_w.v[e]));
+        const float uz = ez.v[e] + dt * ((h1y.v[e] - h1y_w.v[e]) - (h1x.v[e] - h1x_jm.v[e]));
+        e1x.v[e] = (ilt(e) & jj & kk) ? ux : ex.v[e];
+        e1y.v[e] = (jlt & ii(e) & kk) ? uy : ey.v[e];
+        e1z.v[e] = (mlt & ii(e) & jj) ? uz : ez.v[e];
+      }
+      source(e1z, m, add0, g0, n);
     }
-    source(e1z, m, add0, g0, n);
-    if (!pm) e1x = e1y = e1z = z4;                           // no plane m
     // ---- C: H^{n+3/2} of plane q = m-1 (E^{n+1} of row j+1, plane q, in sE1)
     const int q = m - 1;
-    const bool doC = q >= 0 && q >= kb - 2 && q <= ke;
+    const bool doC = wC && q >= 0 && q >= kb - 2 && q <= ke;
     Q h2x = z4, h2y = z4, h2z = z4;
     // E^{n+1} x, z of plane q: this row's from sE1 (held there until barrier 3)
     const Q e1x_p = qof(sE1[0][w][lane]), e1z_p = qof(sE1[1][w][lane]);
@@ -1341,8 +1348,10 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
         h2z.v[e] = (ilt(e) & jlt) ? uz : h1z_p.v[e];
       }
     }
-    sH2[0][w][lane] = ldsof(h2x);
-    sH2[1][w][lane] = ldsof(h2z);
+    if (wC) {
+      sH2[0][w][lane] = ldsof(h2x);
+      sH2[1][w][lane] = ldsof(h2z);
+    }
     __syncthreads();                                         // ---- barrier 2
     // the next plane's operands, issued here (half an iteration ahead) to
     // keep their registers free during A-C
@@ -1352,7 +1361,7 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
     peyNk = ldN(kEy, m + 2); pezNk = ldN(kEz, m + 2); phxN = ldN(kHx, m + 1);
     // ---- D: E^{n+2} of plane q
     Q e2x = z4, e2y = z4, e2z = z4;
-    if (doC && q <= N) {
+    if (wD && doC && q <= N) {
       const Q h2x_jm = qof(sH2[0][wm][lane]), h2z_jm = qof(sH2[1][wm][lane]);
       const Q h2z_w = qwest(h2z), h2y_w = qwest(h2y);
       const bool kq = q >= 1 && q <= N - 1;
@@ -1369,7 +1378,7 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
     }
     // ---- E: H^{n+5/2} of plane r = m-2 (E^{n+2} of row j+1, plane r, in sE2)
     const int r = m - 2;
-    const bool doE = r >= 0 && r >= kb - 1 && r <= ke - 1;
+    const bool doE = wE && r >= 0 && r >= kb - 1 && r <= ke - 1;
     Q h3x = z4, h3y = z4, h3z = z4;
     // E^{n+2} x, z of plane r: this row's from sE2 (held there until the end)
     const Q e2x_p = qof(sE2[0][w][lane]), e2z_p = qof(sE2[1][w][lane]);
@@ -1387,13 +1396,17 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
         h3z.v[e] = (ilt(e) & jlt) ? uz : h2z_p.v[e];
       }
     }
-    sH3[0][w][lane] = ldsof(h3x);
-    sH3[1][w][lane] = ldsof(h3z);
+    if (wE) {
+      sH3[0][w][lane] = ldsof(h3x);
+      sH3[1][w][lane] = ldsof(h3z);
+    }
     __syncthreads();                                         // ---- barrier 3
-    sE1[0][w][lane] = ldsof(e1x);                             // plane m: C, D of m+1
-    sE1[1][w][lane] = ldsof(e1z);
+    if (wB) {
+      sE1[0][w][lane] = ldsof(e1x);                          // plane m: C, D of m+1
+      sE1[1][w][lane] = ldsof(e1z);
+    }
     // ---- F: E^{n+3} of plane r, and the outputs of plane r
-    if (r >= kb && r <= ke - 1) {
+    if (w >= 3 && w < kTJ + 3 && r >= kb && r <= ke - 1) {
       const Q h3x_jm = qof(sH3[0][wm][lane]), h3z_jm = qof(sH3[1][wm][lane]);
       const Q h3z_w = qwest(h3z), h3y_w = qwest(h3y);
       const bool kr = r >= 1 && r <= N - 1;
@@ -1417,8 +1430,10 @@ __global__ __launch_bounds__(768) void fdtd_tb3_rows_kernel(const FdtdTbArgs a) 
       qst_f<NT>(po, o, kHy * fs, h3y);
       qst_f<NT>(po, o, kHz * fs, h3z);
     }
-    sE2[0][w][lane] = ldsof(e2x);                             // plane q: E, F of m+1
-    sE2[1][w][lane] = ldsof(e2z);
+    if (wD) {
+      sE2[0][w][lane] = ldsof(e2x);                          // plane q: E, F of m+1
+      sE2[1][w][lane] = ldsof(e2z);
+    }
     // ---- rotate: plane m becomes the previous plane
     h3x_p = h3x; h3y_p = h3y;
     h2x_p = h2x; h2y_p = h2y; h2z_p = h2z;
