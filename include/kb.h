@@ -239,7 +239,8 @@ extern "C" {
  *              next plane's operands loaded ahead; one kernel per two-step
  *              iteration, which also advances the step counter); with
  *              KB_OPT_TDEPTH 3, 9 and 10 take three steps per launch (12
- *              rows per block, 7 of them output).  Default: 7 when the two
+ *              rows per block, 7 of them output; two nodes per lane up to
+ *              N = 128).  Default: 7 when the two
  *              field sets exceed 256 MiB (N >= 176), else 5.  The
  *              fused step reads one set of six fields and writes the other
  *              (48 instead of 72 bytes per node-step), so the state
